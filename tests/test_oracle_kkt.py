@@ -1,0 +1,181 @@
+"""Pins of the oracle's KKT system (DTO default, OTD structural checks).
+
+The DTO system must be the first-order optimality system of the discrete
+objective J_h under the Crank-Nicolson/Q1 state equation.  It is checked
+against an independent reduced-space solve (forward/adjoint marching + CG),
+against finite differences of J_h, against the forward and backward time
+marches, and by the symmetry of its Lagrangian Hessian.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import kkt, krylov, ras, reduced, fem
+from workloads.generate import make_custom, OTD, DTO
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def tiny(variant=DTO, n=(3, 2, 2), M=3, seed=11):
+    return make_custom(n, M, seed, lattice=1, variant=variant)
+
+
+def slot_swap_perm(nrows):
+    p = np.arange(nrows).reshape(-1, 3).copy()
+    p[:, [0, 1]] = p[:, [1, 0]]
+    return p.ravel()
+
+
+@pytest.mark.parametrize("shape", [((3, 2, 2), 3), ((2, 3, 4), 4), ((4, 4, 4), 5)])
+def test_dto_lagrangian_hessian_symmetric(shape):
+    prob = make_custom(shape[0], shape[1], 3, lattice=2)
+    F = kkt.assemble(prob)
+    H = F[slot_swap_perm(F.shape[0])]
+    assert abs(H - H.T).max() <= 1e-15 * abs(F).max()
+
+
+def test_dto_hessian_symmetric_cfg0(cfg0):
+    prob, _ = cfg0
+    F = kkt.assemble(prob)
+    H = F[slot_swap_perm(F.shape[0])]
+    assert abs(H - H.T).max() <= 1e-15 * abs(F).max()
+
+
+def test_apply_terms_and_box_submatrix():
+    prob = make_custom((3, 4, 2), 4, 5, lattice=2)
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    x = np.random.default_rng(0).standard_normal(F.shape[0])
+    assert np.abs(kkt.apply_terms(terms, x) - F @ x).max() < 1e-13
+    sd = ras.Subdomain(0, (1, 1, 0, 1), (3, 3, 2, 3), (0, 1, 0, 1), (4, 4, 2, 4))
+    nid = ras.box_node_ids(prob, sd)
+    gi = ras.box_global_index(prob, sd)
+    Fb = kkt.box_submatrix(terms, nid, sd.box_lo[3], sd.box_hi[3])
+    assert abs(Fb - F[gi][:, gi]).max() == 0.0
+
+
+def _solve_direct(prob):
+    F = kkt.assemble(prob)
+    b = kkt.rhs(prob)
+    return F, b, np.linalg.solve(F.toarray(), b)
+
+
+@pytest.mark.parametrize("shape", [((3, 2, 2), 3), ((4, 3, 3), 4)])
+def test_dto_matches_reduced_cg(shape):
+    prob = make_custom(shape[0], shape[1], 21, lattice=2)
+    _, _, U = _solve_direct(prob)
+    f_kkt = U.reshape(prob.M + 1, prob.N, 3)[:, :, 2]
+    f_cg, its = reduced.Reduced(prob).cg(tol=1e-13)
+    assert np.linalg.norm(f_kkt - f_cg) <= 1e-8 * np.linalg.norm(f_cg)
+
+
+def test_dto_matches_reduced_cg_cfg0(cfg0):
+    prob, s = cfg0
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    b = kkt.rhs(prob)
+    R = ras.RAS(prob, s.parts, s.overlap, terms=terms)
+    U, st = krylov.gmres(lambda v: F @ v, R.apply, b, restart=s.restart, rtol=1e-12)
+    assert st.converged
+    f_kkt = U.reshape(prob.M + 1, prob.N, 3)[:, :, 2]
+    f_cg, _ = reduced.Reduced(prob).cg(tol=1e-13)
+    assert np.linalg.norm(f_kkt - f_cg) <= 1e-8 * np.linalg.norm(f_cg)
+
+
+def test_fd_gradient_vanishes_at_kkt_solution():
+    prob = make_custom((4, 3, 3), 4, 8, lattice=2)
+    _, _, U = _solve_direct(prob)
+    f = U.reshape(prob.M + 1, prob.N, 3)[:, :, 2]
+    red = reduced.Reduced(prob)
+    rng = np.random.default_rng(3)
+    scale = np.linalg.norm(red.grad(np.zeros_like(f)))
+    for _ in range(3):
+        d = rng.standard_normal(f.shape)
+        eps = 1e-2
+        fd = (red.J(f + eps * d) - red.J(f - eps * d)) / (2 * eps)
+        assert abs(fd) <= 1e-9 * scale * np.linalg.norm(d)
+
+
+def test_fd_gradient_matches_adjoint_gradient():
+    prob = make_custom((3, 3, 2), 5, 9, lattice=2)
+    red = reduced.Reduced(prob)
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((prob.M + 1, prob.N))
+    g = red.grad(f)
+    for _ in range(3):
+        d = rng.standard_normal(f.shape)
+        eps = 1e-3
+        fd = (red.J(f + eps * d) - red.J(f - eps * d)) / (2 * eps)
+        assert abs(fd - np.sum(g * d)) <= 1e-9 * np.linalg.norm(g) * np.linalg.norm(d)
+
+
+def test_state_and_adjoint_time_marching():
+    prob = make_custom((4, 3, 3), 5, 12, lattice=2)
+    F, b, U = _solve_direct(prob)
+    X = U.reshape(prob.M + 1, prob.N, 3)
+    C, G, f = X[:, :, 0], X[:, :, 1], X[:, :, 2]
+    red = reduced.Reduced(prob)
+    Cm = red.forward(f)
+    assert np.linalg.norm(C - Cm) <= 1e-12 * np.linalg.norm(C)
+    # backward march of the multiplier: A1'^T G^n = -A2''^T G^{n+1} - w_n S (C^n - d^n)
+    g = red.w[:, None] * red.S[None, :] * (C - red.d)
+    lam = np.zeros((prob.M + 2, prob.N))
+    for n in range(prob.M, 0, -1):
+        lam[n] = red.lu.solve(-red.A2pp.T @ lam[n + 1] - g[n], trans="T")
+    P = red.ops.interior.astype(float)
+    lam[0] = P * (-(red.A2pp.T @ lam[1]) - g[0])
+    assert np.linalg.norm(G - lam[:-1]) <= 1e-11 * np.linalg.norm(G)
+
+
+def test_paper_dof_count():
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "paper_dof_counts.txt"))
+            if l.strip() and not l.startswith("#")]
+    from workloads.generate import Problem
+    for nodes, levels, dof in rows:
+        n = int(nodes) - 1
+        p = Problem(n=(n, n, n), M=int(levels) - 1, a_elem=np.ones(1), v=(0, 0, 0), beta1=1, beta2=1,
+                    sensor_node=np.zeros(0, np.int32), data=np.zeros((int(levels), 0)))
+        assert p.unknowns == int(dof)
+
+
+def test_otd_structure():
+    """OTD shares the state rows and W with DTO; its G rows are the time-shifted
+    transposed state operator (Appendix A: B1 = A1^T, B2 = A2^T), G^M = 0, and
+    the f rows couple G through the space-time mass -Tt x B."""
+    pd = make_custom((3, 3, 2), 4, 2, lattice=1, variant=DTO)
+    po = make_custom((3, 3, 2), 4, 2, lattice=1, variant=OTD)
+    Fd, Fo = kkt.assemble(pd).toarray(), kkt.assemble(po).toarray()
+    N, M = pd.N, pd.M
+    tau = pd.T / M
+    idx = lambda n, c: 3 * (n * N + np.arange(N)) + c
+    allc = lambda c: np.concatenate([idx(n, c) for n in range(M + 1)])
+    # identical state rows and f-f blocks
+    assert np.array_equal(Fd[allc(0)], Fo[allc(0)])
+    assert np.array_equal(Fd[np.ix_(allc(2), allc(2))], Fo[np.ix_(allc(2), allc(2))])
+    # G^M = 0 row
+    assert np.array_equal(Fo[idx(M, 1)][:, idx(M, 1)], np.eye(N))
+    assert np.abs(np.delete(Fo[idx(M, 1)], idx(M, 1), axis=1)).max() == 0
+    # OTD G-G block at level n equals DTO's at level n+1 shifted by one level
+    for n in range(M - 1):
+        assert np.array_equal(Fo[np.ix_(idx(n, 1), idx(n, 1))], Fd[np.ix_(idx(n + 1, 1), idx(n + 1, 1))])
+        assert np.array_equal(Fo[np.ix_(idx(n, 1), idx(n + 1, 1))], Fd[np.ix_(idx(n + 1, 1), idx(n + 2, 1))])
+    # f-G coupling is minus the space-time mass matrix (columns on Dirichlet nodes removed)
+    ops = fem.spatial_ops(po)
+    Tt = fem.time_mass(M, tau).toarray()
+    Bp = ops.B.toarray() * ops.interior[None, :]
+    for n in range(M + 1):
+        for m in range(M + 1):
+            assert np.allclose(Fo[np.ix_(idx(n, 2), idx(m, 1))], -Tt[n, m] * Bp, rtol=0, atol=1e-16)
+
+
+def test_otd_solution_close_to_dto():
+    """Both variants discretise the same continuous optimality system."""
+    pd = make_custom((4, 4, 4), 6, 30, lattice=2, variant=DTO)
+    po = make_custom((4, 4, 4), 6, 30, lattice=2, variant=OTD)
+    _, _, Ud = _solve_direct(pd)
+    _, _, Uo = _solve_direct(po)
+    Cd = Ud.reshape(-1, 3)[:, 0]
+    Co = Uo.reshape(-1, 3)[:, 0]
+    assert np.linalg.norm(Cd - Co) < 0.5 * np.linalg.norm(Cd)

@@ -1,0 +1,86 @@
+"""Pins of the oracle's interpolation, coarse operator, block LU and two-level method."""
+import dataclasses
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import kkt, krylov, ras, twolevel
+from workloads.generate import make_custom
+
+
+def test_interpolation_reproduces_multilinear():
+    prob = make_custom((4, 6, 2), 4, 1, lattice=1, sensors=np.array([2 + 7 * (3 + 7 * 1)]))
+    fac = (2, 3, 2, 2)
+    P = twolevel.prolongation(prob, fac)
+    nx, ny, nz = prob.n
+    cx, cy, cz, ct = nx // 2, ny // 3, nz // 2, prob.M // 2
+    fun = lambda x, y, z, t: (1 + 2 * x) * (3 - y) * (0.5 + z) * (2 + 0.7 * t)
+
+    def sample(nxs, nys, nzs, nts, hx, hy, hz, ht):
+        T, Z, Y, X = np.meshgrid(np.arange(nts + 1) * ht, np.arange(nzs + 1) * hz, np.arange(nys + 1) * hy,
+                                 np.arange(nxs + 1) * hx, indexing="ij")
+        v = fun(X, Y, Z, T).ravel()
+        return np.stack([v, 2 * v, -v], axis=1).ravel()
+    h = (1 / nx, 1 / ny, 1 / nz, 1 / prob.M)
+    coarse = sample(cx, cy, cz, ct, 2 * h[0], 3 * h[1], 2 * h[2], 2 * h[3])
+    fine = sample(nx, ny, nz, prob.M, *h)
+    np.testing.assert_allclose(P @ coarse, fine, rtol=1e-13)
+
+
+def test_injection_picks_coarse_nodes():
+    P = twolevel.injection_1d(3, 2).toarray()
+    assert np.array_equal(np.argmax(P, axis=0), [0, 2, 4, 6])
+    assert P.sum() == 4
+
+
+def test_coarse_problem_mean_coefficient_and_sensors():
+    nn = 9
+    sens = np.array([2 + nn * (4 + nn * 6), 6 + nn * (2 + nn * 4)], dtype=np.int32)
+    prob = make_custom((8, 8, 8), 8, 2, sensors=sens)
+    cp = twolevel.coarse_problem(prob, (2, 2, 2, 4))
+    a = prob.a_elem.reshape(8, 8, 8)
+    assert np.isclose(cp.a_elem.reshape(4, 4, 4)[1, 2, 3], a[2:4, 4:6, 6:8].mean())
+    assert list(cp.sensor_node) == [1 + 5 * (2 + 5 * 3), 3 + 5 * (1 + 5 * 2)]
+    assert cp.M == 2
+
+
+def test_block_tridiag_lu_exact():
+    prob = make_custom((4, 4, 4), 6, 3, lattice=1, sensors=np.array([2 + 5 * (2 + 5 * 2)]))
+    F = kkt.assemble(prob)
+    lu = twolevel.BlockTridiagLU(F, prob.M + 1)
+    e = np.random.default_rng(0).standard_normal(F.shape[0])
+    x = lu.solve(e)
+    assert np.linalg.norm(F @ x - e) <= 1e-10 * np.linalg.norm(e)
+    xs = spla.splu(F.tocsc()).solve(e)
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_two_level_with_identity_coarsening_is_exact():
+    """Coarse mesh = fine mesh: y = F^{-1} x and x - F y = 0, so FGMRES takes one step."""
+    prob = make_custom((3, 3, 3), 4, 5, lattice=1, sensors=np.array([1 + 4 * (2 + 4 * 1)]))
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    b = kkt.rhs(prob)
+    R = ras.RAS(prob, (2, 2, 1, 2), 1, terms=terms)
+    tl = twolevel.TwoLevel(prob, R.apply, lambda v: F @ v, (1, 1, 1, 1))
+    x, st = krylov.gmres(lambda v: F @ v, tl, b, restart=10, rtol=1e-10, flexible=True)
+    assert st.iters == 1 and st.converged
+
+
+def test_two_level_fewer_iterations_than_one_level():
+    """Paper Tables 3-4 trend: the coarse space-time correction cuts the iteration count."""
+    nn = 13
+    idx = [3, 6, 9]
+    sens = np.array([i + nn * (j + nn * k) for k in idx for j in idx for i in idx], dtype=np.int32)
+    prob = make_custom((12, 12, 12), 16, 4, sensors=sens)
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    b = kkt.rhs(prob)
+    A = lambda v: F @ v
+    R = ras.RAS(prob, (3, 3, 3, 4), 1, terms=terms)
+    _, st1 = krylov.gmres(A, R.apply, b, restart=50, rtol=1e-6)
+    tl = twolevel.TwoLevel(prob, R.apply, A, (3, 3, 3, 4))
+    x2, st2 = krylov.gmres(A, tl, b, restart=50, rtol=1e-6, flexible=True)
+    assert st1.converged and st2.converged
+    assert st2.iters < st1.iters
