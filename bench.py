@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark: KKT solves/s at FP64 relative residual 1e-6 on one MI355X.
+
+Workload (default): 32^3 hex elements x 64 time steps (7,007,715 unknowns),
+a = exp(0.5 g) with g a seeded smooth random field, two moving Gaussian
+sources, 64 lattice sensors, 1% noise, beta = 1e-4; one-level space-time RAS
+with 4x4x4x8 subdomains, overlap 2, ILU(0); GMRES(50) to rtol 1e-6; FP64.
+
+One step = one source-identification solve: new noisy sensor data for the
+same operator (fresh noise draw) -> right-hand side -> GMRES from x0 = 0 to
+rtol 1e-6.  The operator assembly and the ILU(0) setup are done once per
+operator and reported separately (setup_ms).  Inputs are resident in HBM
+when the timed region starts.
+
+Prints one JSON line.  --gpus must be 1: this build runs on a single GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "cfg1": "32^3 x 64 (7,007,715 unknowns), one-level RAS 4x4x4x8 overlap 2 ILU(0), GMRES(50), rtol 1e-6",
+    "cfg0": "8^3 x 16 (37,179 unknowns), one-level RAS 2x2x2x2 overlap 1 ILU(0), GMRES(30), rtol 1e-6",
+}
+
+
+def percentile(v, p):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), p))
+
+
+def algorithmic_apply_bytes(pre, prob):
+    """Bytes one ras_apply must move: every factor block once, r gathered on
+    every overlapping box, z written once on the owned rows."""
+    import numpy as np
+    boxes = pre.boxes()
+    vol = np.prod(boxes[:, 12:16] - boxes[:, 8:12], axis=1).astype(np.int64)
+    return int(pre.factor_bytes + 24 * int(vol.sum()) + 24 * prob.V)
+
+
+def cpu_baseline(prob, cfg, iters, sample_subs=2, seed=0):
+    """The CPU oracle on a bounded sample of the same workload, scaled to one solve.
+
+    Per Arnoldi step the oracle does one preconditioner application (all
+    subdomain ILU(0) solves), one matvec and one CGS2 orthogonalisation; the
+    sample times one full matvec, the subdomain solves of `sample_subs` seeded
+    random subdomains (scaled by the subdomain count) and one CGS2 step at
+    half the restart length, then multiplies by the GPU's iteration count.
+    """
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import kkt, ras as oras
+    with threadpool_limits(limits=1):
+        terms = kkt.kkt_terms(prob)
+        rng = np.random.default_rng(seed)
+        x = rng.standard_normal(prob.unknowns)
+        t = time.perf_counter()
+        kkt.apply_terms(terms, x)
+        t_mv = time.perf_counter() - t
+        subs = oras.subdomains(prob, cfg.parts, cfg.overlap)
+        pick = sorted(rng.choice(len(subs), size=sample_subs, replace=False).tolist())
+        R = oras.RAS(prob, cfg.parts, cfg.overlap, terms=terms, subset=pick)
+        t = time.perf_counter()
+        for sid in pick:
+            R.solve_sub(sid, x)
+        t_sub = (time.perf_counter() - t) / len(pick)
+        t_ras = t_sub * len(subs)
+        j = cfg.restart // 2
+        V = rng.standard_normal((j + 1, prob.unknowns))
+        w = rng.standard_normal(prob.unknowns)
+        t = time.perf_counter()
+        h1 = V @ w
+        w = w - V.T @ h1
+        h2 = V @ w
+        w = w - V.T @ h2
+        np.linalg.norm(w)
+        t_orth = time.perf_counter() - t
+    per_iter = t_mv + t_ras + t_orth
+    return {
+        "value": 1.0 / (iters * per_iter), "unit": "solves/s", "cores": 1, "kind": "oracle",
+        "sample": (f"one full matvec ({t_mv:.2f} s), ILU(0) solves of {len(pick)} of {len(subs)} subdomains "
+                   f"({t_sub:.2f} s each, scaled x{len(subs)}), one CGS2 step at j={j} ({t_orth:.2f} s); "
+                   f"per-iteration {per_iter:.1f} s x {iters} GPU iterations; factorisation not included"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="cfg1", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--apply-reps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is described in DESIGN.md, not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1508_06103_amd as st
+    from workloads.generate import make_problem, redraw_noise
+
+    torch.cuda.set_device(0)
+    prob, cfg = make_problem(args.config)
+    prec = st.F64 if args.precision == "f64" else st.F32
+    print(f"[bench] {args.config}: {prob.unknowns} unknowns, parts {cfg.parts}, overlap {cfg.overlap}",
+          file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = st.KKTOperator(prob)
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pre = st.RAS(op, cfg.parts, cfg.overlap, precision=prec)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    print(f"[bench] assemble {t_asm*1e3:.1f} ms, ras_setup {t_setup*1e3:.1f} ms, "
+          f"factors {pre.factor_bytes/1e9:.2f} GB", file=sys.stderr, flush=True)
+
+    b = torch.empty(op.n, dtype=torch.float64, device="cuda")
+    x = torch.zeros(op.n, dtype=torch.float64, device="cuda")
+    flexible = prec == st.F32
+
+    def step(k):
+        data = redraw_noise(prob, 1000 + k)
+        op.rhs(data, out=b)
+        x.zero_()
+        return st.solve(op, pre, b, x, restart=cfg.restart, rtol=cfg.rtol, maxit=cfg.maxit, flexible=flexible)[1]
+
+    for w in range(args.warmup):
+        s = step(w)
+        print(f"[bench] warmup {w}: {s.iters} its, {s.ms:.1f} ms, res {s.rel_res_true:.2e}", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    times, its = [], []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        s = step(args.warmup + k)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        its.append(s.iters)
+        assert s.converged and s.rel_res_true <= cfg.rtol, s
+        print(f"[bench] step {k}: {s.iters} its, {times[-1]*1e3:.1f} ms, res {s.rel_res_true:.2e}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+
+    # dominant kernel: the preconditioner application, timed with events on the launch stream
+    r = torch.randn(op.n, dtype=torch.float64, device="cuda")
+    z = torch.empty_like(r)
+    pre.apply(r, z)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.apply_reps):
+        pre.apply(r, z)
+    ev1.record()
+    ev1.synchronize()
+    apply_ms = ev0.elapsed_time(ev1) / args.apply_reps
+    apply_bytes = algorithmic_apply_bytes(pre, prob)
+    achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
+    ev0.record()
+    for _ in range(args.apply_reps):
+        op.matvec(r, z)
+    ev1.record()
+    ev1.synchronize()
+    matvec_ms = ev0.elapsed_time(ev1) / args.apply_reps
+
+    value = args.steps / total
+    mean_its = float(np.mean(its))
+    res = {
+        "metric": "KKT solves/s at FP64 rel. residual 1e-6; p50/p99 latency; GMRES iterations",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == st.F64 else "f64 outer / f32 preconditioner",
+        "data": "synthetic (seeded moving-Gaussian sources, lattice sensors, fresh 1% noise per step)",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "unknowns": prob.unknowns,
+                   "subdomains": pre.nsub, "precision": args.precision},
+        "p50_ms": 1e3 * percentile(times, 50), "p99_ms": 1e3 * percentile(times, 99),
+        "gmres_iters": mean_its, "setup_ms": {"assemble": 1e3 * t_asm, "ras_setup": 1e3 * t_setup},
+        "kernels_ms": {"ras_apply": apply_ms, "kkt_matvec": matvec_ms},
+        "roofline": {"kernel": "ras_apply", "bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                     "frac": achieved / 8000.0, "traffic": None, "algorithmic_bytes": apply_bytes},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        cfg_base = cfg
+        res["cpu_baseline"] = cpu_baseline(prob, cfg_base, int(round(mean_its)))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * stkkt -- space-time KKT solver for the unsteady inverse source problem
+ * (Deng, Cai, Zou, "Two-level space-time domain decomposition methods for
+ * unsteady inverse problems", arXiv:1508.06103) on AMD MI355X (gfx950).
+ *
+ * C ABI.  Every entry point returns an int status:
+ *   STKKT_OK (0), STKKT_NOT_CONVERGED (+1), STKKT_EINVAL (-1, bad argument),
+ *   STKKT_ENOMEM (-2, allocation failed), STKKT_EHIP (-3, HIP runtime error),
+ *   STKKT_EBREAKDOWN (-4, singular pivot block or non-finite Krylov quantity).
+ * kkt_last_error() returns a human-readable message for the calling thread's
+ * most recent failure.  No C++ exception crosses this boundary.
+ *
+ * Memory and streams.  "Device" pointers are HIP device addresses of FP64
+ * arrays owned by the caller; they are only borrowed for the stream-ordered
+ * duration of a call.  Handles (kkt_op_t, ras_t, coarse_t) own their internal
+ * device memory, obtained from the kkt_alloc_t callbacks given at assembly
+ * time (hipMalloc/hipFree when the callbacks are NULL).  Handles are immutable
+ * after setup, except for a scratch area used by ras_apply/coarse_apply/
+ * kkt_solve, so concurrent calls on the same handle must be serialised by the
+ * caller (e.g. by using one stream).  `stream` is a hipStream_t passed as a
+ * plain pointer (NULL = the null stream); all device work is enqueued on it.
+ *
+ * Vector layout (Section 3.2 of the paper): the unknown U holds, for every
+ * time level n = 0..M (slowest), every spatial node j (x fastest, then y,
+ * then z) and every slot c in (C, G, f) (fastest), the value at
+ *   index(n, j, c) = 3 * (n * N + j) + c,   N = (n0+1)(n1+1)(n2+1).
+ * Vectors have 3 * N * (M+1) doubles.
+ */
+#ifndef STKKT_H
+#define STKKT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STKKT_OK 0
+#define STKKT_NOT_CONVERGED 1
+#define STKKT_EINVAL (-1)
+#define STKKT_ENOMEM (-2)
+#define STKKT_EHIP (-3)
+#define STKKT_EBREAKDOWN (-4)
+
+/* KKT variants.  DTO: optimality system of the discrete objective (trapezoid
+ * misfit) under the Crank-Nicolson / Q1 state scheme of Section 3.1.
+ * OTD: the block system printed in Appendix A of the paper. */
+#define STKKT_DTO 0
+#define STKKT_OTD 1
+
+#define STKKT_F64 0
+#define STKKT_F32 1
+
+#define STKKT_RESTRICT_TRANSPOSE 0
+#define STKKT_RESTRICT_INJECTION 1
+
+typedef struct kkt_op kkt_op_t;
+typedef struct ras ras_t;
+typedef struct coarse coarse_t;
+
+/* Device allocator callbacks: alloc returns a device pointer (NULL on
+ * failure) of at least `bytes` bytes aligned to 256; free releases it. */
+typedef void *(*stkkt_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*stkkt_free_fn)(void *ptr, void *ctx);
+typedef struct {
+  stkkt_alloc_fn alloc;
+  stkkt_free_fn free;
+  void *ctx;
+} kkt_alloc_t;
+
+/* Problem definition (host memory, read during kkt_assemble only).
+ * Model (eq. (1)): dC/dt = div(a grad C) - div(v C) + f on the box
+ * [0,len0]x[0,len1]x[0,len2], t in (0,T), C = 0 on the Dirichlet faces,
+ * a dC/dn = 0 elsewhere, C(.,0) = 0.  Objective (eqs. (2)-(3)): point sensors
+ * and the H1-H1 space-time regularisation with weights beta1 (time) and
+ * beta2 (space). */
+typedef struct {
+  int32_t n[3];             /* elements per axis (>= 1); nodes = n + 1       */
+  int32_t nt;               /* time steps M (>= 1); levels 0..M               */
+  double len[3];            /* box edge lengths                               */
+  double T;                 /* final time                                     */
+  const double *a_elem;     /* [n2][n1][n0] diffusivity per element, > 0      */
+  double v[3];              /* constant velocity                              */
+  double beta1, beta2;      /* regularisation weights (> 0)                   */
+  int32_t n_sensors;        /* >= 1                                           */
+  const int32_t *sensor_node;  /* distinct spatial node ids, off Dirichlet faces */
+  const double *data;       /* [nt+1][n_sensors] observed concentrations      */
+  uint32_t dirichlet_faces; /* bit 0: x=0, 1: x=len0, 2: y=0, 3: y=len1,
+                               4: z=0, 5: z=len2                              */
+  int32_t variant;          /* STKKT_DTO or STKKT_OTD                         */
+} kkt_problem_t;
+
+/* One-level space-time restricted additive Schwarz (Section 3.2).
+ * p[d] subdomains along x, y, z, t (node-based split: part k of L nodes owns
+ * [k q + min(k,r), (k+1) q + min(k+1,r)), q,r = divmod(L, p)), each extended
+ * by `overlap` nodes per side and trimmed at the global box.  Subdomain
+ * solves: 3x3 point-block ILU(0) in the box's lexicographic order. */
+typedef struct {
+  int32_t p[4];
+  int32_t overlap;          /* >= 0 */
+  int32_t precision;        /* STKKT_F64 or STKKT_F32 factors and local solve */
+  int32_t ilu_level;        /* must be 0 */
+} ras_params_t;
+
+/* Two-level preconditioner (Section 3.2): nested coarse mesh with integer
+ * coarsening factors (must divide n[] and nt), linear interpolation I_c^h,
+ * restriction (I_c^h)^T or injection, coarse KKT rediscretised on the coarse
+ * mesh, solved exactly by block LU in time. */
+typedef struct {
+  int32_t factor[4];
+  int32_t precision;        /* STKKT_F64 or STKKT_F32 coarse LU */
+  int32_t restrict_kind;    /* STKKT_RESTRICT_TRANSPOSE or _INJECTION */
+} coarse_params_t;
+
+/* Restarted right-preconditioned GMRES / FGMRES (Sections 3.2 and 4). */
+typedef struct {
+  int32_t restart;          /* Krylov dimension per cycle (>= 1)        */
+  int32_t maxit;            /* total Arnoldi steps allowed               */
+  double rtol;              /* stop when ||b - F x|| <= rtol ||b||        */
+  int32_t flexible;         /* 0: GMRES, 1: FGMRES                       */
+  int32_t fixed_iters;      /* > 0: run exactly this many steps (no test) */
+} solve_params_t;
+
+typedef struct {
+  int32_t iters;            /* Arnoldi steps taken                   */
+  int32_t restarts;
+  int32_t converged;        /* 1 if the true residual met rtol       */
+  int32_t status;           /* same as the return value               */
+  double rel_res_est;       /* Givens estimate / ||b|| at the end    */
+  double rel_res_true;      /* ||b - F x|| / ||b||                   */
+  double bnorm;
+  double t_ms[4];           /* total, preconditioner, matvec, orthogonalisation */
+} kkt_stats_t;
+
+/* Build the operator handle of F_h (Appendix A block structure) and write the
+ * right-hand side b (3*N*(M+1) doubles, device) for the given data.
+ * `al` may be NULL (hipMalloc).  `b` may be NULL. */
+int kkt_assemble(const kkt_problem_t *p, const kkt_alloc_t *al, void *stream, kkt_op_t **op,
+                 double *b);
+
+/* Right-hand side for new sensor data on an existing operator.
+ * data_host: [nt+1][n_sensors] host array; b: device. */
+int kkt_rhs(const kkt_op_t *op, const double *data_host, void *stream, double *b);
+
+/* y = F_h x (device vectors, may not alias). */
+int kkt_matvec(const kkt_op_t *op, const double *x, double *y, void *stream);
+
+/* Number of unknowns 3 N (M+1). */
+int64_t kkt_size(const kkt_op_t *op);
+
+/* Partition, extract the subdomain matrices and factor them (ILU(0)). */
+int ras_setup(const kkt_op_t *op, const ras_params_t *rp, void *stream, ras_t **out);
+
+/* z = sum_i (R^0_i)^T ILU_i^{-1} R^delta_i r  (device vectors, no aliasing). */
+int ras_apply(const ras_t *ras, const double *r, double *z, void *stream);
+
+/* Subdomain count, and the box table: per subdomain 16 int32
+ * {own_lo[4], own_hi[4], box_lo[4], box_hi[4]} in (x, y, z, t) order. */
+int ras_num_subdomains(const ras_t *ras);
+int ras_query_boxes(const ras_t *ras, int32_t *host_out);
+
+/* Bytes of factor data streamed by one ras_apply (all L, U and inv(D) blocks). */
+int64_t ras_factor_bytes(const ras_t *ras);
+
+/* Copy the factors of one subdomain to host memory as [rows][81][9] doubles:
+ * slot s = (dx+1) + 3(dy+1) + 9(dz+1) + 27(dt+1) of local row rho
+ * (rho = x + lx (y + ly (z + lz t))) holds L (s < 40), inv(U_rr) (s = 40) or
+ * U (s > 40); blocks outside the box are zero. */
+int ras_export_factors(const ras_t *ras, int32_t sub, double *host_out);
+
+/* Coarse level: build F_c, its block LU and the transfer operators. */
+int coarse_setup(const kkt_op_t *fine, const coarse_params_t *cp, void *stream, coarse_t **out);
+
+/* y = I_c^h F_c^{-1} I_h^c x (device vectors of the fine size). */
+int coarse_apply(const coarse_t *c, const double *x, double *y, void *stream);
+
+/* Solve F_h x = b.  coarse == NULL selects the one-level preconditioner;
+ * otherwise M^{-1} x = y + M_one^{-1}(x - F_h y), y = coarse_apply(x).
+ * x: device, holds x0 on entry (zero it for the paper's x0 = 0) and the
+ * iterate on exit.  Synchronises `stream` before returning.  stats may be NULL. */
+int kkt_solve(const kkt_op_t *op, const ras_t *ras, const coarse_t *coarse, const solve_params_t *sp,
+              const double *b, double *x, void *stream, kkt_stats_t *stats);
+
+void kkt_op_destroy(kkt_op_t *op);
+void ras_destroy(ras_t *ras);
+void coarse_destroy(coarse_t *c);
+
+const char *kkt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STKKT_H */

@@ -1,0 +1,344 @@
+"""Python binding of libstkkt (include/stkkt.h): argument marshalling only.
+
+Every step of the solve runs in the HIP library.  PyTorch provides device
+memory (through the allocator callbacks) and the HIP stream.  If the compiled
+library is missing, importing this package raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes
+import os
+import weakref
+from dataclasses import dataclass
+
+import numpy as np
+import torch  # imported first so that the teardown below runs before torch's own
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstkkt.so")
+
+OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, EBREAKDOWN = 0, 1, -1, -2, -3, -4
+DTO, OTD = 0, 1
+F64, F32 = 0, 1
+RESTRICT_TRANSPOSE, RESTRICT_INJECTION = 0, 1
+
+
+class StkktError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_1508_06103_amd/build.py (no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_c_i32p = ctypes.POINTER(ctypes.c_int32)
+_c_dp = ctypes.POINTER(ctypes.c_double)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Alloc(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("nt", ctypes.c_int32), ("len", ctypes.c_double * 3),
+                ("T", ctypes.c_double), ("a_elem", _c_dp), ("v", ctypes.c_double * 3),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("n_sensors", ctypes.c_int32),
+                ("sensor_node", _c_i32p), ("data", _c_dp), ("dirichlet_faces", ctypes.c_uint32),
+                ("variant", ctypes.c_int32)]
+
+
+class _RasParams(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32 * 4), ("overlap", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("ilu_level", ctypes.c_int32)]
+
+
+class _CoarseParams(ctypes.Structure):
+    _fields_ = [("factor", ctypes.c_int32 * 4), ("precision", ctypes.c_int32), ("restrict_kind", ctypes.c_int32)]
+
+
+class _SolveParams(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("flexible", ctypes.c_int32), ("fixed_iters", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("rel_res_est", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+                ("bnorm", ctypes.c_double), ("t_ms", ctypes.c_double * 4)]
+
+
+_vp = ctypes.c_void_p
+_sig = {
+    "kkt_assemble": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.POINTER(_Alloc), _vp, ctypes.POINTER(_vp), _vp]),
+    "kkt_rhs": (ctypes.c_int, [_vp, _c_dp, _vp, _vp]),
+    "kkt_matvec": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "kkt_size": (ctypes.c_int64, [_vp]),
+    "ras_setup": (ctypes.c_int, [_vp, ctypes.POINTER(_RasParams), _vp, ctypes.POINTER(_vp)]),
+    "ras_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "ras_num_subdomains": (ctypes.c_int, [_vp]),
+    "ras_query_boxes": (ctypes.c_int, [_vp, _c_i32p]),
+    "ras_factor_bytes": (ctypes.c_int64, [_vp]),
+    "ras_export_factors": (ctypes.c_int, [_vp, ctypes.c_int32, _c_dp]),
+    "coarse_setup": (ctypes.c_int, [_vp, ctypes.POINTER(_CoarseParams), _vp, ctypes.POINTER(_vp)]),
+    "coarse_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "kkt_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_SolveParams), _vp, _vp, _vp,
+                                 ctypes.POINTER(_Stats)]),
+    "kkt_op_destroy": (None, [_vp]),
+    "ras_destroy": (None, [_vp]),
+    "coarse_destroy": (None, [_vp]),
+    "kkt_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+# Handles are released before the interpreter shuts down: releasing them later
+# would call the allocator callbacks into a finalising interpreter.
+_live = []
+_finalizing = False
+
+
+def _track(obj):
+    if len(_live) > 256:
+        _live[:] = [r for r in _live if r() is not None]
+    _live.append(weakref.ref(obj))
+
+
+@atexit.register
+def _release_all():
+    global _finalizing
+    for ref in reversed(_live):
+        obj = ref()
+        if obj is not None:
+            obj.close()
+    _finalizing = True
+
+
+def _check(rc, allow=(OK,)):
+    if rc not in allow:
+        raise StkktError(rc, _lib.kkt_last_error().decode(errors="replace"))
+    return rc
+
+
+def _torch():
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class TorchAllocator:
+    """Device memory for the library's handles, from torch's caching allocator."""
+
+    def __init__(self, device=None):
+        torch = _torch()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.live = {}
+
+        def _alloc(nbytes, ctx):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            except RuntimeError:
+                return None
+            p = t.data_ptr()
+            self.live[p] = t
+            return p
+
+        def _free(ptr, ctx):
+            self.live.pop(ptr, None)
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        self.struct = _Alloc(self._alloc_cb, self._free_cb, None)
+
+    @property
+    def bytes_live(self):
+        return sum(t.numel() for t in self.live.values())
+
+
+def _problem_struct(prob):
+    a = np.ascontiguousarray(prob.a_elem, dtype=np.float64)
+    sn = np.ascontiguousarray(prob.sensor_node, dtype=np.int32)
+    data = np.ascontiguousarray(prob.data, dtype=np.float64)
+    p = _Problem()
+    p.n = (ctypes.c_int32 * 3)(*prob.n)
+    p.nt = int(prob.M)
+    p.len = (ctypes.c_double * 3)(*prob.length)
+    p.T = float(prob.T)
+    p.a_elem = a.ctypes.data_as(_c_dp)
+    p.v = (ctypes.c_double * 3)(*prob.v)
+    p.beta1 = float(prob.beta1)
+    p.beta2 = float(prob.beta2)
+    p.n_sensors = int(sn.size)
+    p.sensor_node = sn.ctypes.data_as(_c_i32p)
+    p.data = data.ctypes.data_as(_c_dp)
+    p.dirichlet_faces = int(prob.dirichlet_faces)
+    p.variant = int(prob.variant)
+    return p, (a, sn, data)
+
+
+class KKTOperator:
+    """Handle of F_h (and the right-hand side b of the given data)."""
+
+    def __init__(self, prob, stream=None, allocator=None):
+        torch = _torch()
+        self.prob = prob
+        self.alloc = allocator if allocator is not None else TorchAllocator()
+        p, keep = _problem_struct(prob)
+        self.n = int(3 * (prob.M + 1) * np.prod([k + 1 for k in prob.n]))
+        self.b = torch.empty(self.n, dtype=torch.float64, device=self.alloc.device)
+        h = ctypes.c_void_p()
+        _check(_lib.kkt_assemble(ctypes.byref(p), ctypes.byref(self.alloc.struct), _stream(stream),
+                                 ctypes.byref(h), _ptr(self.b)))
+        self.handle = h
+        _track(self)
+        assert _lib.kkt_size(h) == self.n
+
+    def rhs(self, data, out=None, stream=None):
+        torch = _torch()
+        d = np.ascontiguousarray(data, dtype=np.float64)
+        out = torch.empty(self.n, dtype=torch.float64, device=self.alloc.device) if out is None else out
+        _check(_lib.kkt_rhs(self.handle, d.ctypes.data_as(_c_dp), _stream(stream), _ptr(out)))
+        return out
+
+    def matvec(self, x, y=None, stream=None):
+        torch = _torch()
+        y = torch.empty_like(x) if y is None else y
+        _check(_lib.kkt_matvec(self.handle, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.kkt_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if not _finalizing:
+            self.close()
+
+
+class RAS:
+    """One-level space-time restricted additive Schwarz preconditioner."""
+
+    def __init__(self, op: KKTOperator, parts, overlap, precision=F64, stream=None):
+        self.op = op
+        self.alloc = op.alloc   # the library frees this handle's memory through these callbacks
+        rp = _RasParams()
+        rp.p = (ctypes.c_int32 * 4)(*parts)
+        rp.overlap = int(overlap)
+        rp.precision = int(precision)
+        rp.ilu_level = 0
+        h = ctypes.c_void_p()
+        _check(_lib.ras_setup(op.handle, ctypes.byref(rp), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        _track(self)
+        self.nsub = _lib.ras_num_subdomains(h)
+
+    def apply(self, r, z=None, stream=None):
+        torch = _torch()
+        z = torch.empty_like(r) if z is None else z
+        _check(_lib.ras_apply(self.handle, _ptr(r), _ptr(z), _stream(stream)))
+        return z
+
+    def boxes(self):
+        out = np.zeros((self.nsub, 16), dtype=np.int32)
+        _check(_lib.ras_query_boxes(self.handle, out.ctypes.data_as(_c_i32p)))
+        return out
+
+    @property
+    def factor_bytes(self):
+        return int(_lib.ras_factor_bytes(self.handle))
+
+    def export_factors(self, sub):
+        b = self.boxes()[sub]
+        dims = b[12:16] - b[8:12]
+        out = np.zeros((int(np.prod(dims)), 81, 3, 3))
+        _check(_lib.ras_export_factors(self.handle, int(sub), out.ctypes.data_as(_c_dp)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.ras_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if not _finalizing:
+            self.close()
+
+
+class Coarse:
+    """Coarse space-time level of the two-level preconditioner."""
+
+    def __init__(self, op: KKTOperator, factor, precision=F64, restrict=RESTRICT_TRANSPOSE, stream=None):
+        self.op = op
+        self.alloc = op.alloc
+        cp = _CoarseParams()
+        cp.factor = (ctypes.c_int32 * 4)(*factor)
+        cp.precision = int(precision)
+        cp.restrict_kind = int(restrict)
+        h = ctypes.c_void_p()
+        _check(_lib.coarse_setup(op.handle, ctypes.byref(cp), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        _track(self)
+
+    def apply(self, x, y=None, stream=None):
+        torch = _torch()
+        y = torch.empty_like(x) if y is None else y
+        _check(_lib.coarse_apply(self.handle, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.coarse_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if not _finalizing:
+            self.close()
+
+
+@dataclass
+class SolveStats:
+    iters: int
+    restarts: int
+    converged: bool
+    status: int
+    rel_res_est: float
+    rel_res_true: float
+    bnorm: float
+    ms: float
+
+
+def solve(op: KKTOperator, ras: RAS, b=None, x=None, *, coarse: Coarse = None, restart=30, rtol=1e-6,
+          maxit=10000, flexible=False, fixed_iters=0, stream=None, raise_on_fail=True):
+    """Solve F_h x = b with right-preconditioned (F)GMRES; x holds x0 on entry."""
+    torch = _torch()
+    b = op.b if b is None else b
+    x = torch.zeros_like(b) if x is None else x
+    sp = _SolveParams(int(restart), int(maxit), float(rtol), int(bool(flexible)), int(fixed_iters))
+    st = _Stats()
+    rc = _lib.kkt_solve(op.handle, ras.handle, coarse.handle if coarse is not None else None, ctypes.byref(sp),
+                        _ptr(b), _ptr(x), _stream(stream), ctypes.byref(st))
+    if raise_on_fail:
+        _check(rc, allow=(OK, NOT_CONVERGED))
+    return x, SolveStats(st.iters, st.restarts, bool(st.converged), st.status, st.rel_res_est, st.rel_res_true,
+                         st.bnorm, st.t_ms[0])

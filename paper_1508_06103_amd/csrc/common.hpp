@@ -1,0 +1,108 @@
+// Internal helpers shared by the library's translation units: error state,
+// HIP checks, device memory through the caller's allocator, and the POD
+// operator descriptor handed to kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/stkkt.h"
+
+namespace stkkt {
+
+// Error carried from the library internals to the C ABI wrappers.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string &msg);
+
+#define STKKT_HIP(call)                                                                       \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      throw ::stkkt::Error(STKKT_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+#define STKKT_REQUIRE(cond, msg)                                                              \
+  do {                                                                                        \
+    if (!(cond)) throw ::stkkt::Error(STKKT_EINVAL, msg);                                     \
+  } while (0)
+
+// Allocation through the caller's callbacks (or hipMalloc).
+struct Allocator {
+  kkt_alloc_t cb{nullptr, nullptr, nullptr};
+  void *alloc(size_t bytes) const;
+  void free(void *p) const;
+};
+
+// Owning device buffer.
+struct DevBuf {
+  const Allocator *al = nullptr;
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const Allocator *a, size_t n) : al(a), bytes(n) { ptr = n ? a->alloc(n) : nullptr; }
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : al(o.al), ptr(o.ptr), bytes(o.bytes) { o.ptr = nullptr; o.bytes = 0; }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) { reset(); al = o.al; ptr = o.ptr; bytes = o.bytes; o.ptr = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { reset(); }
+  void reset() {
+    if (ptr && al) al->free(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Operator descriptor passed by value to kernels.
+struct OpDev {
+  int n[3];        // elements per axis
+  int nn[3];       // nodes per axis
+  int M;           // time steps
+  int N;           // spatial nodes
+  long long V;     // space-time nodes N (M+1)
+  double h[3];
+  double tau;
+  double v[3];
+  double beta1, beta2;
+  unsigned faces;  // Dirichlet face bitmask
+  int variant;
+  const double *a_elem;   // device [n2][n1][n0]
+  const double *sensor;   // device [N], 1 at sensor nodes
+};
+
+}  // namespace stkkt
+
+struct kkt_op {
+  stkkt::Allocator al;
+  stkkt::OpDev d{};
+  stkkt::DevBuf a_elem, sensor, atab;   // atab: [N][27] diffusion stiffness rows
+  std::vector<int32_t> sensor_node;   // host copy
+  double T = 1.0, len[3] = {1, 1, 1};
+  std::vector<double> a_host;         // host copy of a_elem (coarse setup)
+};
+
+namespace stkkt {
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+inline int blocks_for(long long n, int threads, int cap = 1 << 20) {
+  long long b = (n + threads - 1) / threads;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return static_cast<int>(b);
+}
+void rhs_device(const kkt_op *op, const double *data_host, hipStream_t s, double *b);
+void fill_zero(double *p, long long n, hipStream_t s);
+void stiff_table(const OpDev &d, double *tab, hipStream_t s);
+void matvec_device(const OpDev &d, const double *Atab, const double *x, double *y, hipStream_t s);
+}  // namespace stkkt

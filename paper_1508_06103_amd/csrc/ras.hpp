@@ -1,0 +1,62 @@
+// One-level space-time restricted additive Schwarz: data structures.
+#pragma once
+
+#include "common.hpp"
+
+namespace stkkt {
+
+// Per subdomain (device table).
+struct SubInfo {
+  int32_t shape;
+  int32_t org[4];        // box_lo in (x, y, z, t)
+  int32_t olo[4], ohi[4];  // owned range in local coordinates [olo, ohi)
+  int32_t pad_;
+  int64_t fbase;         // element offset of this subdomain's factors
+  int64_t sbase;         // element offset of its local vector (3 per row)
+  int64_t wbase;         // element offset in the setup working buffer
+};
+
+// Per distinct box shape (device table).  Rows of a level are in ascending
+// local lexicographic order rho = x + lx (y + ly (z + lz t)); the level of a
+// node is x + 2y + 4z + 8t (every lower neighbour of the 81-point stencil has
+// a strictly smaller level).
+struct ShapeInfo {
+  int32_t dims[4];
+  int32_t nlev, nchunk, rmax, vol;
+  int64_t lvl_off;     // into lvl_start (nlev + 1 entries, row offsets)
+  int64_t coord_off;   // into coords (vol entries, packed 16-bit x|y|z|t)
+  int64_t blk_off;     // into blkoff (nlev*81 + 1 entries, block offsets)
+  int64_t rank_off;    // into rankbase (nlev*nchunk*81 entries)
+};
+
+struct ShapeHost {
+  int dims[4];
+  int nlev = 0, nchunk = 0, rmax = 0, vol = 0;
+  std::vector<int32_t> lvl_start;
+  std::vector<uint64_t> coords;
+  std::vector<int64_t> blkoff;
+  std::vector<int32_t> rankbase;
+};
+
+}  // namespace stkkt
+
+struct ras {
+  const kkt_op *op = nullptr;   // identity only; never dereferenced after setup
+  stkkt::Allocator al;          // own copy: the handle may outlive its operator
+  stkkt::OpDev d{};             // sizes of the operator (device pointers unused)
+  ras_params_t params{};
+  int nsub = 0;
+  std::vector<stkkt::SubInfo> subs;
+  std::vector<int> shape_of;
+  std::vector<stkkt::ShapeHost> shapes;
+  std::vector<int32_t> boxes;   // nsub x 16
+  int64_t total_blocks = 0;
+  int64_t scratch_elems = 0;
+  stkkt::DevBuf d_subs, d_shapes, d_lvl, d_coords, d_blkoff, d_rank;
+  stkkt::DevBuf factors;   // double or float, 9 per block
+  stkkt::DevBuf scratch;   // local vectors
+};
+
+namespace stkkt {
+void ras_apply_device(const ras *R, const double *r, double *z, hipStream_t s);
+}

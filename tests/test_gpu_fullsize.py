@@ -1,0 +1,88 @@
+"""GPU checks at the benchmark size (32^3 x 64, 7,007,715 unknowns, 512 subdomains).
+
+The oracle cannot run the whole solve at this size in a test, so the matvec
+is compared in full (level-by-level oracle), the preconditioner and its
+factors on sampled subdomains, and the solve through its true residual.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import kkt, ras as oras
+from workloads.generate import make_problem
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def full():
+    import paper_1508_06103_amd as st
+    prob, cfg = make_problem("cfg1")
+    _say(f"cfg1: {prob.unknowns} unknowns; setting up on the GPU")
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, cfg.parts, cfg.overlap)
+    torch.cuda.synchronize()
+    terms = kkt.kkt_terms(prob)
+    return st, prob, cfg, op, pre, terms
+
+
+def test_fullsize_rhs_and_matvec(full):
+    st, prob, cfg, op, pre, terms = full
+    b_ref = kkt.rhs(prob)
+    assert np.abs(op.b.cpu().numpy() - b_ref).max() <= 1e-15 * np.abs(b_ref).max()
+    x = np.random.default_rng(7).standard_normal(prob.unknowns)
+    y = op.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    y_ref = kkt.apply_terms(terms, x)
+    err = np.abs(y - y_ref).max() / np.abs(y_ref).max()
+    _say(f"  full-size matvec max rel err {err:.2e}")
+    assert err <= 1e-13
+
+
+def test_fullsize_boxes_bit_exact(full):
+    st, prob, cfg, op, pre, terms = full
+    subs = oras.subdomains(prob, cfg.parts, cfg.overlap)
+    ref = np.array([list(s.own_lo) + list(s.own_hi) + list(s.box_lo) + list(s.box_hi) for s in subs])
+    assert np.array_equal(pre.boxes(), ref)
+    # factor storage is exactly the ILU(0) pattern: sum over boxes of prod(3 l - 2) blocks
+    nblk = sum(int(np.prod([3 * l - 2 for l in s.dims])) for s in subs)
+    assert pre.factor_bytes == nblk * 72
+
+
+def test_fullsize_sampled_subdomains(full):
+    st, prob, cfg, op, pre, terms = full
+    subs = oras.subdomains(prob, cfg.parts, cfg.overlap)
+    # one interior 12^4 box and one corner box
+    cands = [i for i, s in enumerate(subs) if s.dims == (12, 12, 12, 12)]
+    interior = cands[len(cands) // 2]
+    pick = [0, interior]
+    R = oras.RAS(prob, cfg.parts, cfg.overlap, terms=terms, subset=pick)
+    r = np.random.default_rng(8).standard_normal(prob.unknowns)
+    z = pre.apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    for sid in pick:
+        zl = R.solve_sub(sid, r)
+        own = R.own[sid]
+        got = z[R.gidx[sid][own]]
+        err = np.linalg.norm(got - zl[own]) / np.linalg.norm(zl[own])
+        f_err = np.abs(pre.export_factors(sid) - R.ilu[sid].padded()).max() / np.abs(R.ilu[sid].padded()).max()
+        _say(f"  sub {sid} dims {subs[sid].dims}: apply rel err {err:.2e}, factor max rel err {f_err:.2e}")
+        assert err <= 1e-11 and f_err <= 1e-11
+
+
+def test_fullsize_solve_true_residual(full):
+    st, prob, cfg, op, pre, terms = full
+    x, s = st.solve(op, pre, restart=cfg.restart, rtol=cfg.rtol)
+    xh = x.cpu().numpy()
+    b = kkt.rhs(prob)
+    res = np.linalg.norm(b - kkt.apply_terms(terms, xh)) / np.linalg.norm(b)
+    _say(f"  cfg1 solve: {s.iters} its, {s.ms:.0f} ms, gpu res {s.rel_res_true:.2e}, oracle res {res:.2e}")
+    assert s.converged and res <= 1e-6 * (1 + 1e-6)
+    # deterministic: a second solve is bit-identical
+    x2, s2 = st.solve(op, pre, restart=cfg.restart, rtol=cfg.rtol)
+    assert s2.iters == s.iters and torch.equal(x, x2)

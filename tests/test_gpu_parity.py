@@ -1,0 +1,179 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Small cases compare every element; the 32^3 x 64 single-GPU configuration is
+checked on sampled subdomains and through properties that hold at any size.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import kkt, ras as oras, krylov, fem
+from workloads.generate import make_custom, make_problem, DTO, OTD
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def st():
+    import paper_1508_06103_amd as st_mod
+    assert torch.cuda.is_available()
+    return st_mod
+
+
+SMALL = [
+    ("cfg0", None),
+    ("ragged", dict(n=(5, 6, 7), M=9, seed=3, lattice=2)),
+    ("aniso_otd", dict(n=(7, 3, 4), M=6, seed=4, lattice=2, variant=OTD, faces=0b010011)),
+    ("neumann_all", dict(n=(4, 4, 4), M=5, seed=5, lattice=2, faces=0)),
+]
+
+
+def small_problem(name):
+    spec = dict(SMALL)[name]
+    if spec is None:
+        return make_problem("cfg0")[0]
+    spec = dict(spec)
+    n, M, seed = spec.pop("n"), spec.pop("M"), spec.pop("seed")
+    return make_custom(n, M, seed, **spec)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.mark.parametrize("name", [s[0] for s in SMALL])
+def test_rhs_and_matvec(st, name):
+    prob = small_problem(name)
+    _say(f"case {name}: n={prob.n} M={prob.M}")
+    op = st.KKTOperator(prob)
+    b_ref = kkt.rhs(prob)
+    b = op.b.cpu().numpy()
+    assert np.abs(b - b_ref).max() <= 1e-15 * np.abs(b_ref).max()
+    F = kkt.assemble(prob)
+    x = np.random.default_rng(1).standard_normal(F.shape[0])
+    y = op.matvec(_dev(x)).cpu().numpy()
+    y_ref = F @ x
+    err = np.abs(y - y_ref).max() / np.abs(y_ref).max()
+    _say(f"  matvec max rel err {err:.2e}")
+    assert err <= 1e-13
+
+
+@pytest.mark.parametrize("name,parts,delta", [("cfg0", (2, 2, 2, 2), 1), ("ragged", (2, 3, 2, 3), 1),
+                                              ("ragged", (3, 2, 3, 2), 2), ("aniso_otd", (2, 1, 2, 2), 1),
+                                              ("neumann_all", (1, 2, 2, 1), 0)])
+def test_boxes_factors_and_apply(st, name, parts, delta):
+    prob = small_problem(name)
+    _say(f"case {name}: parts={parts} overlap={delta}")
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, parts, delta)
+    terms = kkt.kkt_terms(prob)
+    R = oras.RAS(prob, parts, delta, terms=terms)
+    # partition and overlap maps: bit-exact
+    boxes = pre.boxes()
+    ref = np.array([list(s.own_lo) + list(s.own_hi) + list(s.box_lo) + list(s.box_hi) for s in R.subs])
+    assert np.array_equal(boxes, ref)
+    # factors and ILU(0) pattern
+    for sid in sorted({0, len(R.subs) // 2, len(R.subs) - 1}):
+        got = pre.export_factors(sid)
+        want = R.ilu[sid].padded()
+        mask = R.ilu[sid].pattern_mask()
+        assert np.all(got[~mask] == 0.0)
+        scale = np.abs(want).max(axis=(1, 2, 3), keepdims=True)
+        err = np.abs(got - want) / scale
+        _say(f"  sub {sid}: factor max rel err {err.max():.2e}")
+        assert err.max() <= 1e-11
+    # preconditioner application
+    r = np.random.default_rng(2).standard_normal(prob.unknowns)
+    z = pre.apply(_dev(r)).cpu().numpy()
+    z_ref = R.apply(r)
+    err = np.linalg.norm(z - z_ref) / np.linalg.norm(z_ref)
+    _say(f"  apply rel err {err:.2e}")
+    assert err <= 1e-11
+
+
+def test_apply_f32_factors(st):
+    prob = small_problem("cfg0")
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, (2, 2, 2, 2), 1, precision=st.F32)
+    R = oras.RAS(prob, (2, 2, 2, 2), 1)
+    r = np.random.default_rng(3).standard_normal(prob.unknowns)
+    z = pre.apply(_dev(r)).cpu().numpy()
+    err = np.linalg.norm(z - R.apply(r)) / np.linalg.norm(R.apply(r))
+    _say(f"  f32 apply rel err {err:.2e}")
+    assert err <= 1e-3
+
+
+@pytest.mark.parametrize("name,parts,delta,restart", [("cfg0", (2, 2, 2, 2), 1, 30), ("ragged", (2, 3, 2, 3), 1, 20),
+                                                      ("aniso_otd", (2, 1, 2, 2), 1, 25)])
+def test_solve_parity(st, name, parts, delta, restart):
+    prob = small_problem(name)
+    _say(f"case {name}: solve")
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, parts, delta)
+    x, s = st.solve(op, pre, restart=restart, rtol=1e-6)
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    b = kkt.rhs(prob)
+    R = oras.RAS(prob, parts, delta, terms=terms)
+    xo, so = krylov.gmres(lambda v: F @ v, R.apply, b, restart=restart, rtol=1e-6)
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(b - F @ xg) / np.linalg.norm(b)
+    _say(f"  gpu its {s.iters} oracle its {so.iters} true res {res:.2e}")
+    assert s.converged and res <= 1e-6
+    assert abs(s.iters - so.iters) <= 1
+    if s.iters == so.iters:
+        for c in range(3):
+            e = np.linalg.norm(xg[c::3] - xo[c::3]) / np.linalg.norm(xo[c::3])
+            assert e <= 1e-7, (c, e)
+    # like-for-like: exactly the same number of Arnoldi steps
+    k = so.iters
+    x2, s2 = st.solve(op, pre, restart=restart, rtol=1e-6, fixed_iters=k)
+    xo2, _ = krylov.gmres(lambda v: F @ v, R.apply, b, restart=restart, rtol=1e-6, fixed_iters=k)
+    e = np.linalg.norm(x2.cpu().numpy() - xo2) / np.linalg.norm(xo2)
+    _say(f"  fixed {k} iterations: rel diff {e:.2e}")
+    assert e <= 1e-7
+
+
+def test_solve_recovers_source_cfg0(st):
+    """The KKT solution's source equals the reduced-space minimiser of J_h."""
+    from oracle import reduced
+    prob, cfg = make_problem("cfg0")
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, cfg.parts, cfg.overlap)
+    x, s = st.solve(op, pre, restart=cfg.restart, rtol=1e-10)
+    f_gpu = x.cpu().numpy().reshape(prob.M + 1, prob.N, 3)[:, :, 2]
+    f_cg, _ = reduced.Reduced(prob).cg(tol=1e-13)
+    assert np.linalg.norm(f_gpu - f_cg) <= 1e-7 * np.linalg.norm(f_cg)
+
+
+def test_error_paths(st):
+    prob = small_problem("cfg0")
+    op = st.KKTOperator(prob)
+    with pytest.raises(st.StkktError) as e:
+        st.RAS(op, (20, 1, 1, 1), 1)
+    assert e.value.code == st.EINVAL
+    pre = st.RAS(op, (2, 2, 2, 2), 1)
+    x, s = st.solve(op, pre, restart=5, rtol=1e-6, maxit=3, raise_on_fail=False)
+    assert s.status == st.NOT_CONVERGED and s.iters == 3
+    bad = np.array(prob.data)
+    bad[3, 2] = np.nan
+    with pytest.raises(st.StkktError):
+        op.rhs(bad)
+
+
+def test_handles_released_in_any_order(st):
+    """A preconditioner may be released after its operator (garbage-collected cycles)."""
+    prob = small_problem("cfg0")
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, (2, 2, 2, 2), 1)
+    op.close()
+    pre.close()
+    torch.cuda.synchronize()

@@ -44,6 +44,8 @@ class Problem:
     variant: int = DTO
     name: str = ""
     f_true: Optional[np.ndarray] = None   # float64[M+1, N] when kept (diagnostic)
+    data_clean: Optional[np.ndarray] = None  # noise-free sensor values (for fresh noise draws)
+    noise: float = 0.0
 
     @property
     def nodes(self):
@@ -262,7 +264,15 @@ def _make(name, n, M, seed, *, smooth_coef, nsrc, width, sin_int, starts=None, e
     return Problem(n=n, M=int(M), a_elem=np.ascontiguousarray(a_elem, dtype=np.float64), v=tuple(v),
                    beta1=float(beta), beta2=float(beta), sensor_node=sensor_node,
                    data=np.ascontiguousarray(data), length=tuple(length), T=float(T),
-                   dirichlet_faces=faces, variant=variant, name=name, f_true=f_true)
+                   dirichlet_faces=faces, variant=variant, name=name, f_true=f_true,
+                   data_clean=clean, noise=float(noise))
+
+
+def redraw_noise(prob, seed):
+    """New observations of the same concentrations: fresh multiplicative uniform noise."""
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-1.0, 1.0, size=prob.data_clean.shape)
+    return prob.data_clean * (1.0 + prob.noise * u)
 
 
 def lattice_nodes(n, k):
