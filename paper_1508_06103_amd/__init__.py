@@ -16,7 +16,8 @@ import numpy as np
 import torch  # imported first so that the teardown below runs before torch's own
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libstkkt.so")
+# STKKT_LIB may name another build of the same library (e.g. an instrumented one)
+LIB_PATH = os.environ.get("STKKT_LIB", os.path.join(_HERE, "libstkkt.so"))
 
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, EBREAKDOWN = 0, 1, -1, -2, -3, -4
 DTO, OTD = 0, 1

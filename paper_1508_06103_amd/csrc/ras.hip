@@ -3,14 +3,16 @@
 // decomposition, subdomain matrices taken from F_h on the extended boxes,
 // restricted prolongation of the owned part; Section 4: ILU(0)).
 //
-// Factor storage ("level-major, slot-major SoA"): for every subdomain, level
-// L and stencil slot s (0..80, s = (dx+1) + 3(dy+1) + 9(dz+1) + 27(dt+1);
-// s < 40 are the L blocks, s = 40 holds inv(U_rr), s > 40 the U blocks), the
-// blocks of the rows of level L that have neighbour s inside the box are
-// stored entry-major: value(e, k) at base(L, s) + e * count(L, s) + k, where
-// k is the rank of the row among those rows.  A wavefront of 64 consecutive
-// rows therefore reads every entry of a slot with one coalesced load, and no
-// padding is stored for neighbours outside the box.
+// Factor storage ("chunk-major SoA"): the rows of a subdomain are grouped by
+// wavefront level L = x + 2y + 4z + 8t (every lower neighbour of the 81-point
+// stencil has a smaller level) and, inside a level, in 64-row chunks.  For
+// every (level, chunk, stencil slot s) with s = (dx+1) + 3(dy+1) + 9(dz+1) +
+// 27(dt+1) -- s < 40 the L blocks, s = 40 inv(U_rr), s > 40 the U blocks --
+// the blocks of the chunk's rows that have neighbour s inside the box are
+// stored entry-major: value(e, k) at off9 + e * cnt + k, k being the rank of
+// the row among those rows.  A wavefront of 64 rows reads each entry of a slot
+// with one coalesced load, the five slots it owns for a chunk form one
+// contiguous stretch, and no padding is stored for neighbours outside the box.
 #include <algorithm>
 #include <cstdlib>
 #include <map>
@@ -24,8 +26,26 @@ namespace stkkt {
 
 namespace {
 
-constexpr int kSeg = 256;       // rows per level segment in the apply kernel
 constexpr int kApplyThreads = 512;
+constexpr size_t kRingLdsLimit = 160 * 1024;   // LDS of one gfx950 workgroup
+
+// Read-only tables indexed by wave-uniform values are read through the
+// constant address space, which lets the compiler use scalar loads (waited on
+// with lgkmcnt) instead of vector loads that would drain the in-order vmcnt
+// counter and with it every prefetch in flight.
+template <class V> using cptr = const __attribute__((address_space(4))) V *;
+template <class V> __device__ inline cptr<V> as_const(const V *p) { return (cptr<V>)p; }
+
+// Copy a table entry (a struct of 32-bit words) through scalar loads.
+template <class S> __device__ inline S load_uniform(const S *p) {
+  static_assert(sizeof(S) % 4 == 0, "word-sized struct expected");
+  S out;
+  cptr<int32_t> src = (cptr<int32_t>)p;
+  int32_t *dst = reinterpret_cast<int32_t *>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) dst[i] = src[i];
+  return out;
+}
 
 __host__ __device__ inline void slot_off(int s, int &dx, int &dy, int &dz, int &dt) {
   dx = s % 3 - 1;
@@ -93,26 +113,46 @@ ShapeHost make_shape(const int dims[4]) {
   }
   sh.nchunk = (sh.rmax + 63) / 64;
   const int32_t d32[4] = {lx, ly, lz, lt};
-  sh.blkoff.assign((size_t)sh.nlev * 81 + 1, 0);
-  sh.rankbase.assign((size_t)sh.nlev * sh.nchunk * 81, 0);
+  // chunk-major factor layout: for level L, 64-row chunk c of the level, slot s,
+  // the blocks of the chunk's rows that have neighbour s, entry-major:
+  // element (e, k) at ctab.off9 + e * ctab.cnt + k, k = rank inside the chunk
+  sh.ctab.assign((size_t)sh.nlev * sh.nchunk * 81 * 2, 0);
   int64_t off = 0;
   for (int L = 0; L < sh.nlev; ++L) {
-    const int r0 = sh.lvl_start[L], r1 = sh.lvl_start[L + 1];
-    for (int s = 0; s < 81; ++s) {
-      int dx, dy, dz, dt;
-      slot_off(s, dx, dy, dz, dt);
-      sh.blkoff[(size_t)L * 81 + s] = off;
-      int cnt = 0;
-      for (int q = r0; q < r1; ++q) {
-        if ((q - r0) % 64 == 0) sh.rankbase[((size_t)L * sh.nchunk + (q - r0) / 64) * 81 + s] = cnt;
-        int x, y, z, t;
-        unpack(sh.coords[q], x, y, z, t);
-        if (inside(x + dx, y + dy, z + dz, t + dt, d32)) ++cnt;
+    const int r0 = sh.lvl_start[L], R = sh.lvl_start[L + 1] - r0;
+    for (int c = 0; c * 64 < R; ++c)
+      for (int s = 0; s < 81; ++s) {
+        int dx, dy, dz, dt;
+        slot_off(s, dx, dy, dz, dt);
+        int cnt = 0;
+        for (int q = c * 64; q < std::min(R, c * 64 + 64); ++q) {
+          int x, y, z, t;
+          unpack(sh.coords[r0 + q], x, y, z, t);
+          if (inside(x + dx, y + dy, z + dz, t + dt, d32)) ++cnt;
+        }
+        if (9 * (off + cnt) > INT32_MAX) throw Error(STKKT_EINVAL, "ras_setup: subdomain too large");
+        const size_t i = (((size_t)L * sh.nchunk + c) * 81 + s) * 2;
+        sh.ctab[i] = (int32_t)(9 * off);
+        sh.ctab[i + 1] = cnt;
+        off += cnt;
       }
-      off += cnt;
-    }
   }
-  sh.blkoff[(size_t)sh.nlev * 81] = off;
+  sh.nblocks = off;
+  // tzpref[L][t][z]: rows of level L in earlier (t, z) groups (rows of a level
+  // are ordered by (t, z, y), x being implied by the level)
+  sh.tzpref.assign((size_t)sh.nlev * lt * lz, 0);
+  for (int L = 0; L < sh.nlev; ++L) {
+    int cnt = 0;
+    for (int t = 0; t < lt; ++t)
+      for (int z = 0; z < lz; ++z) {
+        sh.tzpref[((size_t)L * lt + t) * lz + z] = cnt;
+        for (int y = 0; y < ly; ++y) {
+          const int x = L - 8 * t - 4 * z - 2 * y;
+          if (x >= 0 && x < lx) ++cnt;
+        }
+      }
+    if (cnt != sh.lvl_start[L + 1] - sh.lvl_start[L]) throw Error(STKKT_EINVAL, "ras_setup: level table mismatch");
+  }
   return sh;
 }
 
@@ -244,8 +284,7 @@ __global__ void __launch_bounds__(512) compact_kernel(const SubInfo *__restrict_
                                                       const ShapeInfo *__restrict__ shapes,
                                                       const int32_t *__restrict__ lvl_start,
                                                       const uint64_t *__restrict__ coords,
-                                                      const int64_t *__restrict__ blkoff,
-                                                      const int32_t *__restrict__ rankbase, int sub0,
+                                                      const int32_t *__restrict__ ctab, int sub0,
                                                       const double *__restrict__ W, T *__restrict__ F) {
   const SubInfo sd = subs[sub0 + blockIdx.x];
   const ShapeInfo sh = shapes[sd.shape];
@@ -269,10 +308,9 @@ __global__ void __launch_bounds__(512) compact_kernel(const SubInfo *__restrict_
         const bool has = valid && inside(x + dx, y + dy, z + dz, t + dt, sh.dims);
         const unsigned long long mask = __ballot(has);
         if (has) {
-          const int rank = rankbase[sh.rank_off + ((int64_t)L * sh.nchunk + c) * 81 + s] + (int)lanes_below(mask);
-          const int64_t b0 = blkoff[sh.blk_off + (int64_t)L * 81 + s];
-          const int64_t cnt = blkoff[sh.blk_off + (int64_t)L * 81 + s + 1] - b0;
-          T *dst = F + sd.fbase + 9 * b0 + rank;
+          const int32_t *ct = ctab + sh.ct_off + (((int64_t)L * sh.nchunk + c) * 81 + s) * 2;
+          const int64_t cnt = ct[1];
+          T *dst = F + sd.fbase + ct[0] + (int)lanes_below(mask);
           const double *src = Wb + rho * 729 + 9 * s;
           for (int e = 0; e < 9; ++e) dst[e * cnt] = (T)src[e];
         }
@@ -283,127 +321,600 @@ __global__ void __launch_bounds__(512) compact_kernel(const SubInfo *__restrict_
 
 // --------------------------------------------------------------------------
 // apply: z = sum_i (R^0_i)^T U_i^{-1} L_i^{-1} R^delta_i r
+//
 // One workgroup (8 wavefronts) per subdomain runs the forward sweep over the
-// levels, then the backward sweep.  For each level, work items are (chunk of
-// 64 rows, group of 10 slots); partial products go to LDS and are summed in a
-// fixed order, so results are reproducible run to run.
+// levels, then the backward sweep.  A level is cut into phases of up to
+// kRows rows.  Wavefront w owns 5 of the 40 off-diagonal stencil slots of the
+// sweep and walks the 64-row chunks of a phase in "units" of three slots
+// (chunk, slots 0-2) and (chunk, slots 3-4): the loads of the next unit
+// (factor blocks and neighbour values) are issued before the current unit is
+// multiplied, so a wavefront always has a unit of loads in flight.  Partial
+// sums go to LDS; after a barrier each thread finishes one row (y = r - sum,
+// or z = inv(D)(y - sum)) and a second barrier publishes the new values.
+// Everything a phase needs besides the factor stream is requested at the
+// start of the phase, ahead of the factor loads: the coordinates of the next
+// phase (kept in LDS, so address computation never waits on a vector load)
+// and the inputs of the final step (r, or inv(D) and y).
+//
+// Local vectors use a strided (level, t, z, y) layout
+//     row index = L * (lt lz ly) + (t lz + z) ly + y      (x = L - 2y - 4z - 8t)
+// so the neighbour of any row through slot s is at a constant offset
+// (dx + 2dy + 4dz + 8dt)(lt lz ly) + (dt lz + dz) ly + dy, and the 64 rows of
+// a chunk touch nearly contiguous neighbour rows.
 // --------------------------------------------------------------------------
-template <typename T, bool kForward>
-__device__ inline void sweep_level(const SubInfo &sd, const ShapeInfo &sh, int L, int r0, int R, OpDev op,
-                                   const uint64_t *__restrict__ coords, const int64_t *__restrict__ blkoff,
-                                   const int32_t *__restrict__ rankbase, const T *__restrict__ F, T *__restrict__ Y,
-                                   const double *__restrict__ r, double *__restrict__ z, T (*part)[kSeg][3]) {
-  const int lx = sh.dims[0], ly = sh.dims[1], lz = sh.dims[2];
-  const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
-  constexpr int nwaves = kApplyThreads / 64;
-  const int sbase = kForward ? 0 : 41;
-  for (int seg0 = 0; seg0 < R; seg0 += kSeg) {
-    const int segR = min(kSeg, R - seg0);
-    const int nch = (segR + 63) / 64;
-    for (int item = wave; item < nch * 4; item += nwaves) {
-      const int cl = item >> 2, g = item & 3;
-      const int qq = cl * 64 + lane;
-      const int q = seg0 + qq;
-      const int c = q >> 6;
-      const bool valid = qq < segR;
-      int x = 0, y = 0, zc = 0, t = 0;
-      if (valid) unpack(coords[sh.coord_off + r0 + q], x, y, zc, t);
-      const long long rho = x + (long long)lx * (y + (long long)ly * (zc + (long long)lz * t));
-      T a0 = 0, a1 = 0, a2 = 0;
+constexpr int kRows = 256;
+constexpr int kWaves = kApplyThreads / 64;
+constexpr int kSlotsPerWave = 40 / kWaves;   // 5
+constexpr int kUnit = 3;                     // slots per pipeline unit
+
+template <typename T>
+struct SweepArgs {
+  SubInfo sd;
+  ShapeInfo sh;
+  OpDev op;
+  cptr<int32_t> lvls;       // shape-relative level starts
+  const uint64_t *crd;      // shape coords (read per lane)
+  cptr<int32_t> ct;         // shape chunk table: (off9, cnt) per (level, chunk, slot)
+  const T *F;
+  T *Y;
+  int64_t fzero, yzero;
+  int64_t SL;               // lt * lz * ly
+  const double *r;
+  double *z;
+};
+
+// (element offset inside the subdomain, count) of the blocks of (level L, chunk cl, slot s)
+template <typename T>
+__device__ inline void chunk_slot(const SweepArgs<T> &a, int L, int cl, int s, int64_t &off9, int64_t &cnt) {
+  const int64_t i = (((int64_t)L * a.sh.nchunk + cl) * 81 + s) * 2;
+  off9 = a.ct[i];
+  cnt = a.ct[i + 1];
+}
+
+template <typename T>
+__device__ inline int64_t yrow_of(const SweepArgs<T> &a, int x, int y, int zc, int t) {
+  const int L = x + 2 * y + 4 * zc + 8 * t;
+  return (int64_t)L * a.SL + ((int64_t)t * a.sh.dims[2] + zc) * a.sh.dims[1] + y;
+}
+
+template <typename T>
+__device__ inline int64_t global_row(const SweepArgs<T> &a, int x, int y, int zc, int t) {
+  const long long node =
+      (a.sd.org[0] + x) + (long long)a.op.nn[0] * ((a.sd.org[1] + y) + (long long)a.op.nn[1] * (a.sd.org[2] + zc));
+  return 3 * ((long long)(a.sd.org[3] + t) * a.op.N + node);
+}
+
+// Issue the loads of one unit: slots 3h .. 3h+2 of this wavefront's five for
+// the lane's row (coordinates cw) in chunk cl of level L.
+template <typename T, bool kFwd>
+__device__ inline void load_unit(const SweepArgs<T> &a, int L, int cl, bool valid, uint64_t cw, int wave, int h,
+                                 T (&f)[kUnit][9], T (&yv)[kUnit][3]) {
+  int x, y, zc, t;
+  unpack(cw, x, y, zc, t);
+  const int64_t own = yrow_of(a, x, y, zc, t);
 #pragma unroll
-      for (int j = 0; j < 10; ++j) {
-        const int s = sbase + 10 * g + j;
-        int dx, dy, dz, dt;
-        slot_off(s, dx, dy, dz, dt);
-        const bool has = valid && inside(x + dx, y + dy, zc + dz, t + dt, sh.dims);
-        const unsigned long long mask = __ballot(has);
-        if (has) {
-          const int rank = rankbase[sh.rank_off + ((int64_t)L * sh.nchunk + c) * 81 + s] + (int)lanes_below(mask);
-          const int64_t b0 = blkoff[sh.blk_off + (int64_t)L * 81 + s];
-          const int64_t cnt = blkoff[sh.blk_off + (int64_t)L * 81 + s + 1] - b0;
-          const T *f = F + sd.fbase + 9 * b0 + rank;
-          const long long rk = rho + dx + (long long)lx * (dy + (long long)ly * (dz + (long long)lz * dt));
-          const T *yk = Y + sd.sbase + 3 * rk;
-          const T y0 = yk[0], y1 = yk[1], y2 = yk[2];
-          a0 += f[0] * y0 + f[cnt] * y1 + f[2 * cnt] * y2;
-          a1 += f[3 * cnt] * y0 + f[4 * cnt] * y1 + f[5 * cnt] * y2;
-          a2 += f[6 * cnt] * y0 + f[7 * cnt] * y1 + f[8 * cnt] * y2;
-        }
-      }
-      if (valid) {
-        part[g][qq][0] = a0;
-        part[g][qq][1] = a1;
-        part[g][qq][2] = a2;
-      }
-    }
-    __syncthreads();
-    for (int qq = (int)threadIdx.x; qq < segR; qq += kApplyThreads) {
-      const int q = seg0 + qq;
-      int x, y, zc, t;
-      unpack(coords[sh.coord_off + r0 + q], x, y, zc, t);
-      const long long rho = x + (long long)lx * (y + (long long)ly * (zc + (long long)lz * t));
-      T s3[3];
-      for (int cc = 0; cc < 3; ++cc) s3[cc] = (part[0][qq][cc] + part[1][qq][cc]) + (part[2][qq][cc] + part[3][qq][cc]);
-      const long long node = (sd.org[0] + x) + (long long)op.nn[0] * ((sd.org[1] + y) + (long long)op.nn[1] * (sd.org[2] + zc));
-      const long long gi = 3 * ((long long)(sd.org[3] + t) * op.N + node);
-      T *yr = Y + sd.sbase + 3 * rho;
-      if (kForward) {
-        for (int cc = 0; cc < 3; ++cc) yr[cc] = (T)r[gi + cc] - s3[cc];
-      } else {
-        const int64_t b0 = blkoff[sh.blk_off + (int64_t)L * 81 + 40];
-        const T *d = F + sd.fbase + 9 * b0 + q;   // all R rows have slot 40: count = R, rank = q
-        T v[3];
-        for (int cc = 0; cc < 3; ++cc) v[cc] = yr[cc] - s3[cc];
-        T o[3];
-        for (int cc = 0; cc < 3; ++cc)
-          o[cc] = d[(3 * cc) * (int64_t)R] * v[0] + d[(3 * cc + 1) * (int64_t)R] * v[1] + d[(3 * cc + 2) * (int64_t)R] * v[2];
-        for (int cc = 0; cc < 3; ++cc) yr[cc] = o[cc];
-        const bool owned = x >= sd.olo[0] && x < sd.ohi[0] && y >= sd.olo[1] && y < sd.ohi[1] && zc >= sd.olo[2] &&
-                           zc < sd.ohi[2] && t >= sd.olo[3] && t < sd.ohi[3];
-        if (owned)
-          for (int cc = 0; cc < 3; ++cc) z[gi + cc] = (double)o[cc];
-      }
-    }
-    __syncthreads();
+  for (int u = 0; u < kUnit; ++u) {
+    const int j = kUnit * h + u;
+    const bool real = j < kSlotsPerWave;
+    const int s = (kFwd ? 0 : 41) + kSlotsPerWave * wave + (real ? j : 0);
+    int dx, dy, dz, dt;
+    slot_off(s, dx, dy, dz, dt);
+    const bool has = real && valid && inside(x + dx, y + dy, zc + dz, t + dt, a.sh.dims);
+    const unsigned long long mask = __ballot(has);
+    int64_t off9, cnt;
+    chunk_slot(a, L, cl, s, off9, cnt);
+    const int64_t dY = (int64_t)(dx + 2 * dy + 4 * dz + 8 * dt) * a.SL + ((int64_t)dt * a.sh.dims[2] + dz) * a.sh.dims[1] + dy;
+    const int64_t fi = has ? a.sd.fbase + off9 + (int64_t)lanes_below(mask) : a.fzero;
+    const int64_t stride = has ? cnt : 0;
+    const int64_t yi = has ? a.sd.sbase + 3 * (own + dY) : a.yzero;
+    const T *p = a.F + fi;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) f[u][e] = __builtin_nontemporal_load(p + e * stride);
+    const T *q = a.Y + yi;
+    yv[u][0] = q[0];
+    yv[u][1] = q[1];
+    yv[u][2] = q[2];
   }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kApplyThreads) apply_kernel(OpDev op, const SubInfo *__restrict__ subs,
-                                                              const ShapeInfo *__restrict__ shapes,
-                                                              const int32_t *__restrict__ lvl_start,
-                                                              const uint64_t *__restrict__ coords,
-                                                              const int64_t *__restrict__ blkoff,
-                                                              const int32_t *__restrict__ rankbase,
-                                                              const T *__restrict__ F, T *__restrict__ Y,
-                                                              const double *__restrict__ r, double *__restrict__ z) {
-  __shared__ T part[4][kSeg][3];
-  const SubInfo sd = subs[blockIdx.x];
-  const ShapeInfo sh = shapes[sd.shape];
-  for (int L = 0; L < sh.nlev; ++L) {
-    const int r0 = lvl_start[sh.lvl_off + L], r1 = lvl_start[sh.lvl_off + L + 1];
-    sweep_level<T, true>(sd, sh, L, r0, r1 - r0, op, coords, blkoff, rankbase, F, Y, r, z, part);
+__device__ inline void mac_unit(const T (&f)[kUnit][9], const T (&yv)[kUnit][3], T &a0, T &a1, T &a2) {
+#pragma unroll
+  for (int u = 0; u < kUnit; ++u) {
+    a0 += f[u][0] * yv[u][0] + f[u][1] * yv[u][1] + f[u][2] * yv[u][2];
+    a1 += f[u][3] * yv[u][0] + f[u][4] * yv[u][1] + f[u][5] * yv[u][2];
+    a2 += f[u][6] * yv[u][0] + f[u][7] * yv[u][1] + f[u][8] * yv[u][2];
   }
-  for (int L = sh.nlev - 1; L >= 0; --L) {
-    const int r0 = lvl_start[sh.lvl_off + L], r1 = lvl_start[sh.lvl_off + L + 1];
-    sweep_level<T, false>(sd, sh, L, r0, r1 - r0, op, coords, blkoff, rankbase, F, Y, r, z, part);
+}
+
+// Next non-empty level after level counter li of the sweep (-1 if none).
+__device__ inline int next_level(cptr<int32_t> lvls, int nlev, int li, bool fwd) {
+  for (int k = li + 1; k < nlev; ++k) {
+    const int L = fwd ? k : nlev - 1 - k;
+    if (lvls[L + 1] > lvls[L]) return k;
   }
+  return -1;
+}
+
+template <typename T, bool kFwd>
+__device__ inline void sweep(const SweepArgs<T> &a, T (*part)[kRows][3], uint64_t *crdL) {
+  const int lane = (int)__lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tq = (int)threadIdx.x;
+  const int nlev = a.sh.nlev;
+  int li = next_level(a.lvls, nlev, -1, kFwd);
+  if (li < 0) return;
+  // coordinates of the first phase
+  {
+    const int L = kFwd ? li : nlev - 1 - li;
+    const int r0 = a.lvls[L], segR = min(kRows, a.lvls[L + 1] - r0);
+    if (tq < segR) crdL[tq] = a.crd[a.sh.coord_off + r0 + tq];
+    __syncthreads();
+  }
+  int seg = 0;
+  while (li >= 0) {
+    const int L = kFwd ? li : nlev - 1 - li;
+    const int r0 = a.lvls[L];
+    const int R = a.lvls[L + 1] - r0;
+    const int segR = min(kRows, R - seg * kRows);
+    const int nch = (segR + 63) >> 6;
+    // the phase after this one
+    int nli = li, nseg = seg + 1;
+    if (nseg * kRows >= R) {
+      nli = next_level(a.lvls, nlev, li, kFwd);
+      nseg = 0;
+    }
+    int nsegR = 0, nr0 = 0;
+    if (nli >= 0) {
+      const int nL = kFwd ? nli : nlev - 1 - nli;
+      nr0 = a.lvls[nL];
+      nsegR = min(kRows, a.lvls[nL + 1] - nr0 - nseg * kRows);
+    }
+    // requests issued ahead of the factor stream
+    uint64_t cnext = 0;
+    if (tq < nsegR) cnext = a.crd[a.sh.coord_off + nr0 + nseg * kRows + tq];
+    uint64_t fc = 0;
+    T pre[12];
+    int64_t gi = 0, yown = 0;
+    if (tq < segR) {
+      fc = crdL[tq];
+      int x, y, zc, t;
+      unpack(fc, x, y, zc, t);
+      gi = global_row(a, x, y, zc, t);
+      yown = a.sd.sbase + 3 * yrow_of(a, x, y, zc, t);
+      if (kFwd) {
+        pre[0] = (T)a.r[gi];
+        pre[1] = (T)a.r[gi + 1];
+        pre[2] = (T)a.r[gi + 2];
+      } else {
+        const int qrow = seg * kRows + tq;   // slot 40: every row of the chunk, rank = row & 63
+        int64_t off9, cnt;
+        chunk_slot(a, L, qrow >> 6, 40, off9, cnt);
+        const T *d = a.F + a.sd.fbase + off9 + (qrow & 63);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) pre[e] = __builtin_nontemporal_load(d + (int64_t)e * cnt);
+        pre[9] = a.Y[yown];
+        pre[10] = a.Y[yown + 1];
+        pre[11] = a.Y[yown + 2];
+      }
+    }
+    // factor stream: units (chunk c, slots 0-2) and (chunk c, slots 3-4)
+    const int cl0 = (seg * kRows) >> 6;
+    T fA[kUnit][9], yA[kUnit][3], fB[kUnit][9], yB[kUnit][3];
+    load_unit<T, kFwd>(a, L, cl0, lane < segR, crdL[lane], wave, 0, fA, yA);
+    for (int c = 0; c < nch; ++c) {
+      const bool valid = c * 64 + lane < segR;
+      const uint64_t cw = crdL[c * 64 + lane];
+      load_unit<T, kFwd>(a, L, cl0 + c, valid, cw, wave, 1, fB, yB);
+      T a0 = 0, a1 = 0, a2 = 0;
+      mac_unit(fA, yA, a0, a1, a2);
+      if (c + 1 < nch) {
+        const bool valid1 = (c + 1) * 64 + lane < segR;
+        load_unit<T, kFwd>(a, L, cl0 + c + 1, valid1, crdL[(c + 1) * 64 + lane], wave, 0, fA, yA);
+      }
+      mac_unit(fB, yB, a0, a1, a2);
+      if (valid) {
+        part[wave][c * 64 + lane][0] = a0;
+        part[wave][c * 64 + lane][1] = a1;
+        part[wave][c * 64 + lane][2] = a2;
+      }
+    }
+    __syncthreads();
+    if (tq < segR) {
+      T s3[3];
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        T acc = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) acc += part[w][tq][cc];
+        s3[cc] = acc;
+      }
+      T *yr = a.Y + yown;
+      if (kFwd) {
+        for (int cc = 0; cc < 3; ++cc) yr[cc] = pre[cc] - s3[cc];
+      } else {
+        T v[3], o[3];
+        for (int cc = 0; cc < 3; ++cc) v[cc] = pre[9 + cc] - s3[cc];
+        for (int cc = 0; cc < 3; ++cc) o[cc] = pre[3 * cc] * v[0] + pre[3 * cc + 1] * v[1] + pre[3 * cc + 2] * v[2];
+        for (int cc = 0; cc < 3; ++cc) yr[cc] = o[cc];
+        int x, y, zc, t;
+        unpack(fc, x, y, zc, t);
+        const SubInfo &sd = a.sd;
+        const bool owned = x >= sd.olo[0] && x < sd.ohi[0] && y >= sd.olo[1] && y < sd.ohi[1] && zc >= sd.olo[2] &&
+                           zc < sd.ohi[2] && t >= sd.olo[3] && t < sd.ohi[3];
+        if (owned)
+          for (int cc = 0; cc < 3; ++cc) a.z[gi + cc] = (double)o[cc];
+      }
+    }
+    if (tq < nsegR) crdL[tq] = cnext;
+    __syncthreads();
+    li = nli;
+    seg = nseg;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kApplyThreads, 2) apply_kernel(OpDev op, const SubInfo *__restrict__ subs,
+                                                                 const int32_t *__restrict__ order,
+                                                                 const ShapeInfo *__restrict__ shapes,
+                                                                 const int32_t *__restrict__ lvl_start,
+                                                                 const uint64_t *__restrict__ coords,
+                                                                 const int32_t *__restrict__ ctab,
+                                                                 const T *__restrict__ F, T *__restrict__ Y,
+                                                                 int64_t fzero, int64_t yzero,
+                                                                 const double *__restrict__ r,
+                                                                 double *__restrict__ z) {
+  __shared__ T part[kWaves][kRows][3];
+  __shared__ uint64_t crdL[kRows];
+  SweepArgs<T> a;
+  const int sub = as_const(order)[blockIdx.x];
+  a.sd = load_uniform(subs + sub);
+  a.sh = load_uniform(shapes + a.sd.shape);
+  a.op = op;
+  a.lvls = as_const(lvl_start) + a.sh.lvl_off;
+  a.crd = coords;
+  a.ct = as_const(ctab) + a.sh.ct_off;
+  a.F = F;
+  a.Y = Y;
+  a.fzero = fzero;
+  a.yzero = yzero;
+  a.SL = (int64_t)a.sh.dims[3] * a.sh.dims[2] * a.sh.dims[1];
+  a.r = r;
+  a.z = z;
+  sweep<T, true>(a, part, crdL);
+  __syncthreads();
+  sweep<T, false>(a, part, crdL);
+}
+
+// --------------------------------------------------------------------------
+// apply, LDS-ring form (used when the ring fits in LDS).
+//
+// Same work split as above, but the values of the last 16 levels live in an
+// LDS ring (16 is one more than the largest level distance between a row and
+// its stencil neighbours, x + 2y + 4z + 8t changes by at most 15).  A row's
+// place inside its level is (rows of the level in earlier (t, z) groups) +
+// (y - first y of its group); the per-level (t, z) prefix rows sit in a
+// second LDS ring.  Level barriers therefore only synchronise LDS, so the
+// factor loads of the next chunk -- also across phase and level boundaries --
+// stay in flight through them: a wavefront streams its factor blocks
+// continuously, one 64-row chunk ahead of the multiply.  The forward result y
+// is also written to global memory (the backward sweep reads it once per row),
+// and z is written to the output on owned rows.
+// --------------------------------------------------------------------------
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+struct Phase {
+  int li, L, r0, R, seg, segR, nch;
+  bool done;
+};
+
+__device__ inline void phase_at(Phase &p, cptr<int32_t> lvls, int nlev, int li, int seg, bool fwd) {
+  p.li = li;
+  p.done = li < 0;
+  if (p.done) return;
+  p.L = fwd ? li : nlev - 1 - li;
+  p.r0 = lvls[p.L];
+  p.R = lvls[p.L + 1] - p.r0;
+  p.seg = seg;
+  p.segR = min(kRows, p.R - seg * kRows);
+  p.nch = (p.segR + 63) >> 6;
+}
+
+__device__ inline void phase_next(Phase &n, const Phase &p, cptr<int32_t> lvls, int nlev, bool fwd) {
+  if (p.done) {
+    n = p;
+    return;
+  }
+  if ((p.seg + 1) * kRows < p.R) phase_at(n, lvls, nlev, p.li, p.seg + 1, fwd);
+  else phase_at(n, lvls, nlev, next_level(lvls, nlev, p.li, fwd), 0, fwd);
+}
+
+struct Ring {
+  int rmax;   // rows per ring level
+  int ltlz;   // (t, z) groups per level
+};
+
+// Factor loads of all five slots of this wavefront for chunk c of phase p.
+template <typename T, bool kFwd>
+__device__ inline void load_chunk_f(const SweepArgs<T> &a, const Phase &p, int c, uint64_t cw, int wave,
+                                    T (&f)[kSlotsPerWave][9]) {
+  const int lane = (int)__lane_id();
+  int x, y, zc, t;
+  unpack(cw, x, y, zc, t);
+  const bool valid = !p.done && c * 64 + lane < p.segR;
+  const int cl = ((p.seg * kRows) >> 6) + c;
+#pragma unroll
+  for (int j = 0; j < kSlotsPerWave; ++j) {
+    const int s = (kFwd ? 0 : 41) + kSlotsPerWave * wave + j;
+    int dx, dy, dz, dt;
+    slot_off(s, dx, dy, dz, dt);
+    const bool has = valid && inside(x + dx, y + dy, zc + dz, t + dt, a.sh.dims);
+    const unsigned long long mask = __ballot(has);
+    int64_t fi = a.fzero, stride = 0;
+    if (!p.done) {
+      int64_t off9, cnt;
+      chunk_slot(a, p.L, cl, s, off9, cnt);
+      if (has) {
+        fi = a.sd.fbase + off9 + (int64_t)lanes_below(mask);
+        stride = cnt;
+      }
+    }
+    const T *q = a.F + fi;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) f[j][e] = __builtin_nontemporal_load(q + e * stride);
+  }
+}
+
+// Multiply chunk c of phase p: neighbour values from the LDS ring.
+template <typename T, bool kFwd>
+__device__ inline void mac_chunk_ring(const SweepArgs<T> &a, const Phase &p, int c, uint64_t cw, int wave,
+                                      const T (&f)[kSlotsPerWave][9], const T *yring, const int32_t *tzr,
+                                      const Ring &rg, T &a0, T &a1, T &a2) {
+  const int lane = (int)__lane_id();
+  int x, y, zc, t;
+  unpack(cw, x, y, zc, t);
+  const bool valid = c * 64 + lane < p.segR;
+  const int lx = a.sh.dims[0], lz = a.sh.dims[2];
+#pragma unroll
+  for (int j = 0; j < kSlotsPerWave; ++j) {
+    const int s = (kFwd ? 0 : 41) + kSlotsPerWave * wave + j;
+    int dx, dy, dz, dt;
+    slot_off(s, dx, dy, dz, dt);
+    const int nx = x + dx, ny = y + dy, nz = zc + dz, nt = t + dt;
+    const bool has = valid && inside(nx, ny, nz, nt, a.sh.dims);
+    T v0 = 0, v1 = 0, v2 = 0;
+    if (has) {
+      const int nL = nx + 2 * ny + 4 * nz + 8 * nt;
+      const int slot = nL & 15;
+      const int rem = nx + 2 * ny;   // = nL - 8 nt - 4 nz
+      const int ymin = max(0, (rem - lx + 2) >> 1);
+      const int q = tzr[slot * rg.ltlz + nt * lz + nz] + (ny - ymin);
+      const T *v = yring + ((int64_t)slot * rg.rmax + q) * 3;
+      v0 = v[0];
+      v1 = v[1];
+      v2 = v[2];
+    }
+    a0 += f[j][0] * v0 + f[j][1] * v1 + f[j][2] * v2;
+    a1 += f[j][3] * v0 + f[j][4] * v1 + f[j][5] * v2;
+    a2 += f[j][6] * v0 + f[j][7] * v1 + f[j][8] * v2;
+  }
+}
+
+// One chunk step: issue the factor loads of the next chunk, multiply the
+// current one, and close the phase if this was its last chunk.
+template <typename T, bool kFwd>
+__device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int nlev, int wave, Phase &pc, int &cc,
+                                 int &par, Phase &pn, Phase &pnn, const T (&fcur)[kSlotsPerWave][9],
+                                 T (&fnext)[kSlotsPerWave][9], T (*part)[kRows][3], uint64_t *crd2, T *yring,
+                                 int32_t *tzr, const Ring &rg, uint64_t &c2, int &tzrow, T (&pre)[12]) {
+  const int lane = (int)__lane_id();
+  const int tq = (int)threadIdx.x;
+  // requests of the phase, issued when its first chunk is multiplied: coordinates
+  // two phases ahead, the (t, z) prefix row of a new level, final-step inputs
+  if (cc == 0) {
+    if (!pnn.done && tq < pnn.segR) c2 = a.crd[a.sh.coord_off + pnn.r0 + pnn.seg * kRows + tq];
+    if (pc.seg == 0 && tq < rg.ltlz) tzrow = tzp[(int64_t)pc.L * rg.ltlz + tq];
+    if (tq < pc.segR) {
+      const uint64_t fc = crd2[par * kRows + tq];
+      int x, y, zc, t;
+      unpack(fc, x, y, zc, t);
+      if (kFwd) {
+        const int64_t gi = global_row(a, x, y, zc, t);
+        pre[0] = (T)a.r[gi];
+        pre[1] = (T)a.r[gi + 1];
+        pre[2] = (T)a.r[gi + 2];
+      } else {
+        const int qrow = pc.seg * kRows + tq;
+        int64_t off9, cnt;
+        chunk_slot(a, pc.L, qrow >> 6, 40, off9, cnt);
+        const T *d = a.F + a.sd.fbase + off9 + (qrow & 63);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) pre[e] = __builtin_nontemporal_load(d + (int64_t)e * cnt);
+        const int64_t yo = a.sd.sbase + 3 * yrow_of(a, x, y, zc, t);
+        pre[9] = a.Y[yo];
+        pre[10] = a.Y[yo + 1];
+        pre[11] = a.Y[yo + 2];
+      }
+    }
+  }
+  // next chunk: same phase, or the first chunk of the next phase
+  const bool last = cc == pc.nch - 1;
+  {
+    const Phase &pt = last ? pn : pc;
+    const int ct = last ? 0 : cc + 1;
+    const int pt_par = last ? par ^ 1 : par;
+    const uint64_t cw = crd2[pt_par * kRows + ct * 64 + lane];
+    load_chunk_f<T, kFwd>(a, pt, ct, cw, wave, fnext);
+  }
+  // multiply the current chunk
+  {
+    const uint64_t cw = crd2[par * kRows + cc * 64 + lane];
+    T a0 = 0, a1 = 0, a2 = 0;
+    mac_chunk_ring<T, kFwd>(a, pc, cc, cw, wave, fcur, yring, tzr, rg, a0, a1, a2);
+    if (cc * 64 + lane < pc.segR) {
+      part[wave][cc * 64 + lane][0] = a0;
+      part[wave][cc * 64 + lane][1] = a1;
+      part[wave][cc * 64 + lane][2] = a2;
+    }
+  }
+  if (!last) {
+    ++cc;
+    return;
+  }
+  // close the phase
+  lds_barrier();
+  if (tq < pc.segR) {
+    const uint64_t fc = crd2[par * kRows + tq];
+    T s3[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      T acc = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) acc += part[w][tq][k];
+      s3[k] = acc;
+    }
+    T o[3];
+    int x, y, zc, t;
+    unpack(fc, x, y, zc, t);
+    if (kFwd) {
+      for (int k = 0; k < 3; ++k) o[k] = pre[k] - s3[k];
+      T *yg = a.Y + a.sd.sbase + 3 * yrow_of(a, x, y, zc, t);
+      for (int k = 0; k < 3; ++k) yg[k] = o[k];
+    } else {
+      T v[3];
+      for (int k = 0; k < 3; ++k) v[k] = pre[9 + k] - s3[k];
+      for (int k = 0; k < 3; ++k) o[k] = pre[3 * k] * v[0] + pre[3 * k + 1] * v[1] + pre[3 * k + 2] * v[2];
+      const SubInfo &sd = a.sd;
+      const bool owned = x >= sd.olo[0] && x < sd.ohi[0] && y >= sd.olo[1] && y < sd.ohi[1] && zc >= sd.olo[2] &&
+                         zc < sd.ohi[2] && t >= sd.olo[3] && t < sd.ohi[3];
+      if (owned) {
+        const int64_t gi = global_row(a, x, y, zc, t);
+        for (int k = 0; k < 3; ++k) a.z[gi + k] = (double)o[k];
+      }
+    }
+    T *yr = yring + ((int64_t)(pc.L & 15) * rg.rmax + pc.seg * kRows + tq) * 3;
+    for (int k = 0; k < 3; ++k) yr[k] = o[k];
+  }
+  if (pc.seg == 0 && tq < rg.ltlz) tzr[(pc.L & 15) * rg.ltlz + tq] = tzrow;
+  if (!pnn.done && tq < pnn.segR) crd2[par * kRows + tq] = c2;   // phase after next reuses this buffer
+  lds_barrier();
+  // advance
+  pc = pn;
+  pn = pnn;
+  phase_next(pnn, pn, a.lvls, nlev, kFwd);
+  par ^= 1;
+  cc = 0;
+}
+
+template <typename T, bool kFwd>
+__device__ inline void sweep_ring(const SweepArgs<T> &a, cptr<int32_t> tzp, T (*part)[kRows][3], uint64_t *crd2,
+                                  T *yring, int32_t *tzr, const Ring &rg) {
+  const int lane = (int)__lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tq = (int)threadIdx.x;
+  const int nlev = a.sh.nlev;
+  Phase pc, pn, pnn;
+  phase_at(pc, a.lvls, nlev, next_level(a.lvls, nlev, -1, kFwd), 0, kFwd);
+  if (pc.done) return;
+  phase_next(pn, pc, a.lvls, nlev, kFwd);
+  phase_next(pnn, pn, a.lvls, nlev, kFwd);
+  // coordinates of the first two phases
+  if (tq < pc.segR) crd2[tq] = a.crd[a.sh.coord_off + pc.r0 + pc.seg * kRows + tq];
+  if (!pn.done && tq < pn.segR) crd2[kRows + tq] = a.crd[a.sh.coord_off + pn.r0 + pn.seg * kRows + tq];
+  __syncthreads();
+  int par = 0, cc = 0;
+  uint64_t c2 = 0;
+  int tzrow = 0;
+  T pre[12];
+  T fA[kSlotsPerWave][9], fB[kSlotsPerWave][9];
+  load_chunk_f<T, kFwd>(a, pc, 0, crd2[lane], wave, fA);
+  for (;;) {
+    ring_step<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, fA, fB, part, crd2, yring, tzr, rg, c2, tzrow, pre);
+    if (pc.done) break;
+    ring_step<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, fB, fA, part, crd2, yring, tzr, rg, c2, tzrow, pre);
+    if (pc.done) break;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kApplyThreads, 2) apply_ring_kernel(
+    OpDev op, const SubInfo *__restrict__ subs, const int32_t *__restrict__ order,
+    const ShapeInfo *__restrict__ shapes, const int32_t *__restrict__ lvl_start,
+    const uint64_t *__restrict__ coords, const int32_t *__restrict__ ctab, const int32_t *__restrict__ tzpref, const T *__restrict__ F, T *__restrict__ Y, int64_t fzero, int64_t yzero,
+    Ring rg, const double *__restrict__ r, double *__restrict__ z) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T(*part)[kRows][3] = reinterpret_cast<T(*)[kRows][3]>(smem);
+  uint64_t *crd2 = reinterpret_cast<uint64_t *>(smem + sizeof(T) * kWaves * kRows * 3);
+  T *yring = reinterpret_cast<T *>(smem + sizeof(T) * kWaves * kRows * 3 + sizeof(uint64_t) * 2 * kRows);
+  int32_t *tzr = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(yring) +
+                                             sizeof(T) * (size_t)16 * rg.rmax * 3);
+  SweepArgs<T> a;
+  const int sub = as_const(order)[blockIdx.x];
+  a.sd = load_uniform(subs + sub);
+  a.sh = load_uniform(shapes + a.sd.shape);
+  a.op = op;
+  a.lvls = as_const(lvl_start) + a.sh.lvl_off;
+  a.crd = coords;
+  a.ct = as_const(ctab) + a.sh.ct_off;
+  a.F = F;
+  a.Y = Y;
+  a.fzero = fzero;
+  a.yzero = yzero;
+  a.SL = (int64_t)a.sh.dims[3] * a.sh.dims[2] * a.sh.dims[1];
+  a.r = r;
+  a.z = z;
+  const cptr<int32_t> tzp = as_const(tzpref) + a.sh.tz_off;
+  Ring rl = rg;
+  rl.ltlz = a.sh.dims[3] * a.sh.dims[2];
+  sweep_ring<T, true>(a, tzp, part, crd2, yring, tzr, rl);
+  __syncthreads();   // forward results in global memory are read by the backward sweep
+  sweep_ring<T, false>(a, tzp, part, crd2, yring, tzr, rl);
 }
 
 }  // namespace
 
-void ras_apply_device(const ras *R, const double *r, double *z, hipStream_t s) {
-  if (R->params.precision == STKKT_F32) {
-    hipLaunchKernelGGL(apply_kernel<float>, dim3(R->nsub), dim3(kApplyThreads), 0, s, R->d,
-                       R->d_subs.as<SubInfo>(), R->d_shapes.as<ShapeInfo>(), R->d_lvl.as<int32_t>(),
-                       R->d_coords.as<uint64_t>(), R->d_blkoff.as<int64_t>(), R->d_rank.as<int32_t>(),
-                       R->factors.as<float>(), R->scratch.as<float>(), r, z);
+template <typename T>
+static size_t ring_lds_bytes(const ras *R) {
+  return sizeof(T) * kWaves * kRows * 3 + sizeof(uint64_t) * 2 * kRows + sizeof(T) * (size_t)16 * R->ring_rmax * 3 +
+         sizeof(int32_t) * (size_t)16 * R->ring_ltlz;
+}
+
+template <typename T>
+static void launch_apply(const ras *R, const double *r, double *z, hipStream_t s) {
+  const size_t lds = ring_lds_bytes<T>(R);
+  if (lds <= kRingLdsLimit && R->ring_ltlz <= kApplyThreads) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_ring_kernel<T>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRingLdsLimit));
+      attr_set = true;
+    }
+    Ring rg{R->ring_rmax, R->ring_ltlz};
+    hipLaunchKernelGGL((apply_ring_kernel<T>), dim3(R->nsub), dim3(kApplyThreads), lds, s, R->d,
+                       R->d_subs.as<SubInfo>(), R->d_order.as<int32_t>(), R->d_shapes.as<ShapeInfo>(),
+                       R->d_lvl.as<int32_t>(), R->d_coords.as<uint64_t>(), R->d_ctab.as<int32_t>(),
+                       R->d_tz.as<int32_t>(), R->factors.as<T>(), R->scratch.as<T>(),
+                       9 * R->total_blocks, R->scratch_elems, rg, r, z);
   } else {
-    hipLaunchKernelGGL(apply_kernel<double>, dim3(R->nsub), dim3(kApplyThreads), 0, s, R->d,
-                       R->d_subs.as<SubInfo>(), R->d_shapes.as<ShapeInfo>(), R->d_lvl.as<int32_t>(),
-                       R->d_coords.as<uint64_t>(), R->d_blkoff.as<int64_t>(), R->d_rank.as<int32_t>(),
-                       R->factors.as<double>(), R->scratch.as<double>(), r, z);
+    hipLaunchKernelGGL((apply_kernel<T>), dim3(R->nsub), dim3(kApplyThreads), 0, s, R->d, R->d_subs.as<SubInfo>(),
+                       R->d_order.as<int32_t>(), R->d_shapes.as<ShapeInfo>(), R->d_lvl.as<int32_t>(),
+                       R->d_coords.as<uint64_t>(), R->d_ctab.as<int32_t>(), R->factors.as<T>(), R->scratch.as<T>(),
+                       9 * R->total_blocks, R->scratch_elems, r, z);
   }
+}
+
+bool ras_uses_ring(const ras *R) {
+  return (R->params.precision == STKKT_F32 ? ring_lds_bytes<float>(R) : ring_lds_bytes<double>(R)) <= kRingLdsLimit &&
+         R->ring_ltlz <= kApplyThreads;
+}
+
+void ras_apply_device(const ras *R, const double *r, double *z, hipStream_t s) {
+  if (R->params.precision == STKKT_F32) launch_apply<float>(R, r, z, s);
+  else launch_apply<double>(R, r, z, s);
   STKKT_HIP(hipGetLastError());
 }
 
@@ -473,8 +984,8 @@ ras *ras_create(const kkt_op *op, const ras_params_t *rp, hipStream_t s) {
           const ShapeHost &sh = R->shapes[sid];
           si.fbase = fb;
           si.sbase = sb;
-          fb += 9 * sh.blkoff.back();
-          sb += 3LL * sh.vol;
+          fb += 9 * sh.nblocks;
+          sb += 3LL * sh.nlev * sh.dims[3] * sh.dims[2] * sh.dims[1];
           R->subs.push_back(si);
           for (int d = 0; d < 4; ++d) {
             R->boxes.push_back(lo[d]);
@@ -485,12 +996,18 @@ ras *ras_create(const kkt_op *op, const ras_params_t *rp, hipStream_t s) {
         }
   R->total_blocks = fb / 9;
   R->scratch_elems = sb;
+  // launch order: largest boxes first, so that the last workgroups to start are the short ones
+  std::vector<int32_t> order(nsub);
+  for (int i = 0; i < nsub; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return R->shapes[R->subs[a].shape].nblocks > R->shapes[R->subs[b].shape].nblocks;
+  });
   // shape tables
   std::vector<ShapeInfo> shinfo;
   std::vector<int32_t> lvl;
   std::vector<uint64_t> crd;
-  std::vector<int64_t> blk;
-  std::vector<int32_t> rnk;
+  std::vector<int32_t> ctb;
+  std::vector<int32_t> tzp;
   for (auto &sh : R->shapes) {
     ShapeInfo si{};
     for (int d = 0; d < 4; ++d) si.dims[d] = sh.dims[d];
@@ -500,20 +1017,23 @@ ras *ras_create(const kkt_op *op, const ras_params_t *rp, hipStream_t s) {
     si.vol = sh.vol;
     si.lvl_off = (int64_t)lvl.size();
     si.coord_off = (int64_t)crd.size();
-    si.blk_off = (int64_t)blk.size();
-    si.rank_off = (int64_t)rnk.size();
+    si.ct_off = (int64_t)ctb.size();
+    si.tz_off = (int64_t)tzp.size();
+    R->ring_rmax = std::max(R->ring_rmax, sh.rmax);
+    R->ring_ltlz = std::max(R->ring_ltlz, sh.dims[3] * sh.dims[2]);
     lvl.insert(lvl.end(), sh.lvl_start.begin(), sh.lvl_start.end());
     crd.insert(crd.end(), sh.coords.begin(), sh.coords.end());
-    blk.insert(blk.end(), sh.blkoff.begin(), sh.blkoff.end());
-    rnk.insert(rnk.end(), sh.rankbase.begin(), sh.rankbase.end());
+    ctb.insert(ctb.end(), sh.ctab.begin(), sh.ctab.end());
+    tzp.insert(tzp.end(), sh.tzpref.begin(), sh.tzpref.end());
     shinfo.push_back(si);
   }
   const Allocator *al = &R->al;
   upload(al, R->d_shapes, shinfo, s);
   upload(al, R->d_lvl, lvl, s);
   upload(al, R->d_coords, crd, s);
-  upload(al, R->d_blkoff, blk, s);
-  upload(al, R->d_rank, rnk, s);
+  upload(al, R->d_ctab, ctb, s);
+  upload(al, R->d_tz, tzp, s);
+  upload(al, R->d_order, order, s);
   std::vector<int16_t> pstart;
   std::vector<uint8_t> pairs;
   build_pairs(pstart, pairs);
@@ -521,9 +1041,11 @@ ras *ras_create(const kkt_op *op, const ras_params_t *rp, hipStream_t s) {
   upload(al, d_pstart, pstart, s);
   upload(al, d_pairs, pairs, s);
   const size_t esz = rp->precision == STKKT_F32 ? sizeof(float) : sizeof(double);
-  R->factors = DevBuf(al, esz * (size_t)fb);
-  STKKT_REQUIRE(R->factors.ptr != nullptr || fb == 0, "ras_setup: out of memory for factors");
-  R->scratch = DevBuf(al, esz * (size_t)sb);
+  // trailing all-zero sentinels read for neighbours outside a box
+  R->factors = DevBuf(al, esz * ((size_t)fb + 16));
+  R->scratch = DevBuf(al, esz * ((size_t)sb + 4));
+  STKKT_HIP(hipMemsetAsync(static_cast<char *>(R->factors.ptr) + esz * (size_t)fb, 0, esz * 16, s));
+  STKKT_HIP(hipMemsetAsync(static_cast<char *>(R->scratch.ptr) + esz * (size_t)sb, 0, esz * 4, s));
   // working buffer: subdomains factored in batches that fit the budget
   size_t budget = (size_t)64 << 30;
   if (const char *e = getenv("STKKT_SETUP_WORK_GB")) budget = (size_t)(atof(e) * (double)(1ull << 30));
@@ -555,12 +1077,12 @@ ras *ras_create(const kkt_op *op, const ras_params_t *rp, hipStream_t s) {
     if (rp->precision == STKKT_F32) {
       hipLaunchKernelGGL(compact_kernel<float>, dim3(last - first), dim3(512), 0, s, R->d_subs.as<SubInfo>(),
                          R->d_shapes.as<ShapeInfo>(), R->d_lvl.as<int32_t>(), R->d_coords.as<uint64_t>(),
-                         R->d_blkoff.as<int64_t>(), R->d_rank.as<int32_t>(), first, work.as<double>(),
+                         R->d_ctab.as<int32_t>(), first, work.as<double>(),
                          R->factors.as<float>());
     } else {
       hipLaunchKernelGGL(compact_kernel<double>, dim3(last - first), dim3(512), 0, s, R->d_subs.as<SubInfo>(),
                          R->d_shapes.as<ShapeInfo>(), R->d_lvl.as<int32_t>(), R->d_coords.as<uint64_t>(),
-                         R->d_blkoff.as<int64_t>(), R->d_rank.as<int32_t>(), first, work.as<double>(),
+                         R->d_ctab.as<int32_t>(), first, work.as<double>(),
                          R->factors.as<double>());
     }
     STKKT_HIP(hipGetLastError());
@@ -577,7 +1099,7 @@ void ras_export(const ras *R, int sub, double *out) {
   STKKT_REQUIRE(sub >= 0 && sub < R->nsub, "ras_export_factors: bad subdomain");
   const SubInfo &sd = R->subs[sub];
   const ShapeHost &sh = R->shapes[sd.shape];
-  const int64_t nb = sh.blkoff.back();
+  const int64_t nb = sh.nblocks;
   const bool f32 = R->params.precision == STKKT_F32;
   std::vector<double> buf(9 * (size_t)nb);
   if (f32) {
@@ -593,21 +1115,24 @@ void ras_export(const ras *R, int sub, double *out) {
   const int32_t d32[4] = {sh.dims[0], sh.dims[1], sh.dims[2], sh.dims[3]};
   std::fill(out, out + (size_t)sh.vol * 729, 0.0);
   for (int L = 0; L < sh.nlev; ++L) {
-    for (int s = 0; s < 81; ++s) {
-      int dx, dy, dz, dt;
-      slot_off(s, dx, dy, dz, dt);
-      const int64_t b0 = sh.blkoff[(size_t)L * 81 + s], cnt = sh.blkoff[(size_t)L * 81 + s + 1] - b0;
-      int64_t k = 0;
-      for (int q = sh.lvl_start[L]; q < sh.lvl_start[L + 1]; ++q) {
-        int x, y, z, t;
-        unpack(sh.coords[q], x, y, z, t);
-        if (!inside(x + dx, y + dy, z + dz, t + dt, d32)) continue;
-        const int64_t rho = x + (int64_t)lx * (y + (int64_t)ly * (z + (int64_t)lz * t));
-        for (int e = 0; e < 9; ++e) out[rho * 729 + 9 * s + e] = buf[9 * b0 + e * cnt + k];
-        ++k;
+    const int r0 = sh.lvl_start[L], R = sh.lvl_start[L + 1] - r0;
+    for (int c = 0; c * 64 < R; ++c)
+      for (int s = 0; s < 81; ++s) {
+        int dx, dy, dz, dt;
+        slot_off(s, dx, dy, dz, dt);
+        const size_t i = (((size_t)L * sh.nchunk + c) * 81 + s) * 2;
+        const int64_t off9 = sh.ctab[i], cnt = sh.ctab[i + 1];
+        int64_t k = 0;
+        for (int q = c * 64; q < std::min(R, c * 64 + 64); ++q) {
+          int x, y, z, t;
+          unpack(sh.coords[r0 + q], x, y, z, t);
+          if (!inside(x + dx, y + dy, z + dz, t + dt, d32)) continue;
+          const int64_t rho = x + (int64_t)lx * (y + (int64_t)ly * (z + (int64_t)lz * t));
+          for (int e = 0; e < 9; ++e) out[rho * 729 + 9 * s + e] = buf[off9 + e * cnt + k];
+          ++k;
+        }
+        if (k != cnt) throw Error(STKKT_EINVAL, "ras_export_factors: inconsistent layout");
       }
-      if (k != cnt) throw Error(STKKT_EINVAL, "ras_export_factors: inconsistent layout");
-    }
   }
 }
 

@@ -25,8 +25,8 @@ struct ShapeInfo {
   int32_t nlev, nchunk, rmax, vol;
   int64_t lvl_off;     // into lvl_start (nlev + 1 entries, row offsets)
   int64_t coord_off;   // into coords (vol entries, packed 16-bit x|y|z|t)
-  int64_t blk_off;     // into blkoff (nlev*81 + 1 entries, block offsets)
-  int64_t rank_off;    // into rankbase (nlev*nchunk*81 entries)
+  int64_t ct_off;      // into the chunk table (nlev*nchunk*81 (off9, cnt) pairs)
+  int64_t tz_off;      // into tzpref (nlev*lt*lz entries)
 };
 
 struct ShapeHost {
@@ -34,8 +34,9 @@ struct ShapeHost {
   int nlev = 0, nchunk = 0, rmax = 0, vol = 0;
   std::vector<int32_t> lvl_start;
   std::vector<uint64_t> coords;
-  std::vector<int64_t> blkoff;
-  std::vector<int32_t> rankbase;
+  std::vector<int32_t> ctab;   // (off9, cnt) per (level, chunk, slot)
+  int64_t nblocks = 0;
+  std::vector<int32_t> tzpref;
 };
 
 }  // namespace stkkt
@@ -52,11 +53,13 @@ struct ras {
   std::vector<int32_t> boxes;   // nsub x 16
   int64_t total_blocks = 0;
   int64_t scratch_elems = 0;
-  stkkt::DevBuf d_subs, d_shapes, d_lvl, d_coords, d_blkoff, d_rank;
+  int ring_rmax = 0, ring_ltlz = 0;   // LDS ring sizes of the apply kernel
+  stkkt::DevBuf d_subs, d_shapes, d_lvl, d_coords, d_ctab, d_order, d_tz;
   stkkt::DevBuf factors;   // double or float, 9 per block
   stkkt::DevBuf scratch;   // local vectors
 };
 
 namespace stkkt {
 void ras_apply_device(const ras *R, const double *r, double *z, hipStream_t s);
+bool ras_uses_ring(const ras *R);
 }

@@ -33,6 +33,8 @@ SMALL = [
     ("ragged", dict(n=(5, 6, 7), M=9, seed=3, lattice=2)),
     ("aniso_otd", dict(n=(7, 3, 4), M=6, seed=4, lattice=2, variant=OTD, faces=0b010011)),
     ("neumann_all", dict(n=(4, 4, 4), M=5, seed=5, lattice=2, faces=0)),
+    # one long box: (t, z) groups per level exceed the LDS-ring limits of the apply kernel
+    ("tall", dict(n=(2, 2, 40), M=24, seed=6, lattice=1)),
 ]
 
 
@@ -68,7 +70,8 @@ def test_rhs_and_matvec(st, name):
 
 @pytest.mark.parametrize("name,parts,delta", [("cfg0", (2, 2, 2, 2), 1), ("ragged", (2, 3, 2, 3), 1),
                                               ("ragged", (3, 2, 3, 2), 2), ("aniso_otd", (2, 1, 2, 2), 1),
-                                              ("neumann_all", (1, 2, 2, 1), 0)])
+                                              ("neumann_all", (1, 2, 2, 1), 0), ("tall", (1, 1, 1, 1), 0),
+                                              ("tall", (1, 1, 2, 2), 1)])
 def test_boxes_factors_and_apply(st, name, parts, delta):
     prob = small_problem(name)
     _say(f"case {name}: parts={parts} overlap={delta}")
