@@ -409,7 +409,7 @@ __device__ inline void load_unit(const SweepArgs<T> &a, int L, int cl, bool vali
     const int64_t yi = has ? a.sd.sbase + 3 * (own + dY) : a.yzero;
     const T *p = a.F + fi;
 #pragma unroll
-    for (int e = 0; e < 9; ++e) f[u][e] = __builtin_nontemporal_load(p + e * stride);
+    for (int e = 0; e < 9; ++e) f[u][e] = *(p + e * stride);
     const T *q = a.Y + yi;
     yv[u][0] = q[0];
     yv[u][1] = q[1];
@@ -492,7 +492,7 @@ __device__ inline void sweep(const SweepArgs<T> &a, T (*part)[kRows][3], uint64_
         chunk_slot(a, L, qrow >> 6, 40, off9, cnt);
         const T *d = a.F + a.sd.fbase + off9 + (qrow & 63);
 #pragma unroll
-        for (int e = 0; e < 9; ++e) pre[e] = __builtin_nontemporal_load(d + (int64_t)e * cnt);
+        for (int e = 0; e < 9; ++e) pre[e] = *(d + (int64_t)e * cnt);
         pre[9] = a.Y[yown];
         pre[10] = a.Y[yown + 1];
         pre[11] = a.Y[yown + 2];
@@ -665,7 +665,7 @@ __device__ inline void load_chunk_f(const SweepArgs<T> &a, const Phase &p, int c
     }
     const T *q = a.F + fi;
 #pragma unroll
-    for (int e = 0; e < 9; ++e) f[j][e] = __builtin_nontemporal_load(q + e * stride);
+    for (int e = 0; e < 9; ++e) f[j][e] = *(q + e * stride);
   }
 }
 
@@ -733,7 +733,7 @@ __device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int n
         chunk_slot(a, pc.L, qrow >> 6, 40, off9, cnt);
         const T *d = a.F + a.sd.fbase + off9 + (qrow & 63);
 #pragma unroll
-        for (int e = 0; e < 9; ++e) pre[e] = __builtin_nontemporal_load(d + (int64_t)e * cnt);
+        for (int e = 0; e < 9; ++e) pre[e] = *(d + (int64_t)e * cnt);
         const int64_t yo = a.sd.sbase + 3 * yrow_of(a, x, y, zc, t);
         pre[9] = a.Y[yo];
         pre[10] = a.Y[yo + 1];
