@@ -29,6 +29,29 @@ WORKLOADS = {
 }
 
 
+# HBM bytes per ras_apply launch measured with the FETCH_SIZE and WRITE_SIZE
+# counters (one pass each, `bench.py --kernels-only`), each scaled by what the
+# same counter reads for a 1 GiB device-to-device copy (FETCH x 2.000,
+# WRITE x 1.000).  Valid only for the apply-kernel source the counters were
+# taken on: a different source hash reports null.
+COUNTED_TRAFFIC = {
+    ("cfg1", "f64"): {"ras_hip_sha256": "aba38399a4a410e32d2e2fe2b8c0ea9f9567bb70b8be87e2f995e5b16a79e4bf",
+                      "read_bytes": 20006209.4 * 2.0 * 1024, "write_bytes": 366410.7 * 1.0 * 1024},
+}
+
+
+def counted_traffic(config, precision):
+    import hashlib
+    rec = COUNTED_TRAFFIC.get((config, precision))
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, "paper_1508_06103_amd", "csrc", "ras.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["ras_hip_sha256"]:
+            return None
+    return rec["read_bytes"] + rec["write_bytes"]
+
+
 def percentile(v, p):
     import numpy as np
     return float(np.percentile(np.asarray(v), p))
@@ -89,6 +112,44 @@ def cpu_baseline(prob, cfg, iters, sample_subs=2, seed=0):
     }
 
 
+def time_kernels(op, pre, reps):
+    """Average ras_apply and kkt_matvec durations, from events recorded on the
+    stream the library launches on (torch's current stream)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    r = torch.randn(op.n, dtype=torch.float64, device="cuda")
+    z = torch.empty_like(r)
+    pre.apply(r, z, stream=stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        pre.apply(r, z, stream=stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    apply_ms = ev0.elapsed_time(ev1) / reps
+    ev0.record(stream)
+    for _ in range(reps):
+        op.matvec(r, z, stream=stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    return apply_ms, ev0.elapsed_time(ev1) / reps
+
+
+def kernels_only(op, pre, prob, reps):
+    """Kernel timing plus a plain copy of known size (the reference point that
+    converts the FETCH_SIZE / WRITE_SIZE counters to bytes)."""
+    import torch
+    apply_ms, matvec_ms = time_kernels(op, pre, reps)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"ras_apply_ms": apply_ms, "kkt_matvec_ms": matvec_ms,
+                      "ras_apply_algorithmic_bytes": algorithmic_apply_bytes(pre, prob),
+                      "copy_bytes_each_way": src.numel() * 8, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +159,8 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--apply-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="no solves: time ras_apply, kkt_matvec and a plain 1 GiB device copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -127,6 +190,9 @@ def main():
     print(f"[bench] assemble {t_asm*1e3:.1f} ms, ras_setup {t_setup*1e3:.1f} ms, "
           f"factors {pre.factor_bytes/1e9:.2f} GB", file=sys.stderr, flush=True)
 
+    if args.kernels_only:
+        kernels_only(op, pre, prob, args.apply_reps)
+        return
     b = torch.empty(op.n, dtype=torch.float64, device="cuda")
     x = torch.zeros(op.n, dtype=torch.float64, device="cuda")
     flexible = prec == st.F32
@@ -156,25 +222,9 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
 
-    # dominant kernel: the preconditioner application, timed with events on the launch stream
-    r = torch.randn(op.n, dtype=torch.float64, device="cuda")
-    z = torch.empty_like(r)
-    pre.apply(r, z)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.apply_reps):
-        pre.apply(r, z)
-    ev1.record()
-    ev1.synchronize()
-    apply_ms = ev0.elapsed_time(ev1) / args.apply_reps
+    apply_ms, matvec_ms = time_kernels(op, pre, args.apply_reps)
     apply_bytes = algorithmic_apply_bytes(pre, prob)
     achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
-    ev0.record()
-    for _ in range(args.apply_reps):
-        op.matvec(r, z)
-    ev1.record()
-    ev1.synchronize()
-    matvec_ms = ev0.elapsed_time(ev1) / args.apply_reps
 
     value = args.steps / total
     mean_its = float(np.mean(its))
@@ -190,7 +240,8 @@ def main():
         "gmres_iters": mean_its, "setup_ms": {"assemble": 1e3 * t_asm, "ras_setup": 1e3 * t_setup},
         "kernels_ms": {"ras_apply": apply_ms, "kkt_matvec": matvec_ms},
         "roofline": {"kernel": "ras_apply", "bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                     "frac": achieved / 8000.0, "traffic": None, "algorithmic_bytes": apply_bytes},
+                     "frac": achieved / 8000.0, "traffic": counted_traffic(args.config, args.precision),
+                     "algorithmic_bytes": apply_bytes},
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)

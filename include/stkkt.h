@@ -103,14 +103,25 @@ typedef struct {
   int32_t ilu_level;        /* must be 0 */
 } ras_params_t;
 
-/* Two-level preconditioner (Section 3.2): nested coarse mesh with integer
- * coarsening factors (must divide n[] and nt), linear interpolation I_c^h,
- * restriction (I_c^h)^T or injection, coarse KKT rediscretised on the coarse
- * mesh, solved exactly by block LU in time. */
+/* Two-level preconditioner (Section 3.2, two-level paragraph): nested coarse
+ * space-time mesh with integer coarsening factors (must divide n[] and nt),
+ * interpolation I_c^h linear on the coarse mesh (per unknown slot), restriction
+ * I_h^c = (I_c^h)^T or injection, coarse KKT system F_c rediscretised on the
+ * coarse mesh (element coefficient = mean of the fine ones it covers; every
+ * sensor must sit on a coarse node).  F_c^{-1} is applied as in the paper's
+ * experiments (Section 4): restarted GMRES from a zero guess with relative
+ * tolerance `rtol` and at most `maxit` steps, right-preconditioned by the
+ * one-level space-time RAS of the coarse mesh (`p`, `overlap`, ILU(0)). */
+#define STKKT_COARSE_GMRES_RAS 0
 typedef struct {
-  int32_t factor[4];
-  int32_t precision;        /* STKKT_F64 or STKKT_F32 coarse LU */
-  int32_t restrict_kind;    /* STKKT_RESTRICT_TRANSPOSE or _INJECTION */
+  int32_t factor[4];        /* coarsening in x, y, z, t                    */
+  int32_t method;           /* STKKT_COARSE_GMRES_RAS                       */
+  int32_t precision;        /* STKKT_F64 or STKKT_F32 coarse ILU factors    */
+  int32_t restrict_kind;    /* STKKT_RESTRICT_TRANSPOSE or _INJECTION       */
+  int32_t p[4];             /* coarse subdomains in x, y, z, t              */
+  int32_t overlap;          /* coarse overlap (paper: 1)                    */
+  int32_t maxit;            /* coarse GMRES steps (paper: 4)                */
+  double rtol;              /* coarse GMRES relative tolerance (paper: 0.1) */
 } coarse_params_t;
 
 /* Restarted right-preconditioned GMRES / FGMRES (Sections 3.2 and 4). */
@@ -169,10 +180,14 @@ int64_t ras_factor_bytes(const ras_t *ras);
  * U (s > 40); blocks outside the box are zero. */
 int ras_export_factors(const ras_t *ras, int32_t sub, double *host_out);
 
-/* Coarse level: build F_c, its block LU and the transfer operators. */
+/* Coarse level: build F_c on the coarse mesh, its one-level RAS (ILU(0)
+ * factors) and the inner GMRES workspace.  Fails with STKKT_EINVAL when a
+ * factor does not divide the mesh or a sensor is not on a coarse node. */
 int coarse_setup(const kkt_op_t *fine, const coarse_params_t *cp, void *stream, coarse_t **out);
 
-/* y = I_c^h F_c^{-1} I_h^c x (device vectors of the fine size). */
+/* y = I_c^h F_c^{-1} I_h^c x (device vectors of the fine size), F_c^{-1}
+ * being the inner GMRES(maxit) described above (not converging within maxit
+ * steps is the normal case and not an error).  Synchronises `stream`. */
 int coarse_apply(const coarse_t *c, const double *x, double *y, void *stream);
 
 /* Solve F_h x = b.  coarse == NULL selects the one-level preconditioner;

@@ -9,8 +9,11 @@ The coarse operator F_c is the same KKT system rediscretised on the coarse
 mesh (coarse element coefficient = mean of the fine element coefficients it
 contains; sensor matrix S_c = P_x^T S P_x, which is the coarse 0/1 diagonal
 when every sensor sits on a coarse node -- required here).
-F_c^{-1} is applied exactly by a block LU in time: S_0 = D_0,
-S_k = D_k - L_k S_{k-1}^{-1} U_{k-1} with dense partial-pivoting LU of S_k.
+F_c^{-1} is applied either exactly, by a block LU in time (S_0 = D_0,
+S_k = D_k - L_k S_{k-1}^{-1} U_{k-1} with dense partial-pivoting LU of S_k),
+or as in the paper's experiments (Section 4): restarted GMRES from a zero
+guess with a loose tolerance and a few steps, right-preconditioned by the
+one-level space-time RAS of the coarse mesh.
 Multiplicative combination:
     y = I_c^h F_c^{-1} I_h^c x,    M^{-1} x = y + M_one^{-1} (x - F_h y).
 """
@@ -23,6 +26,8 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from . import kkt as kkt_mod
+from . import krylov
+from . import ras as ras_mod
 
 
 def interp_1d(nc: int, f: int) -> sp.csr_matrix:
@@ -107,10 +112,26 @@ class BlockTridiagLU:
         return x.ravel()
 
 
+class CoarseGmresRas:
+    """F_c^{-1} r ~ GMRES(maxit) from zero, rtol, right-preconditioned by coarse RAS."""
+
+    def __init__(self, cprob, Fc, parts, overlap, maxit=4, rtol=0.1):
+        self.Fc = Fc
+        self.R = ras_mod.RAS(cprob, parts, overlap)
+        self.maxit = maxit
+        self.rtol = rtol
+
+    def solve(self, r):
+        x, _ = krylov.gmres(lambda v: self.Fc @ v, self.R.apply, r, restart=self.maxit, rtol=self.rtol,
+                            maxit=self.maxit)
+        return x
+
+
 class TwoLevel:
     """M^{-1} x = y + M_one^{-1}(x - F_h y),  y = P F_c^{-1} R x."""
 
-    def __init__(self, prob, one_level, F_apply, factors, restrict="transpose"):
+    def __init__(self, prob, one_level, F_apply, factors, restrict="transpose", coarse="lu",
+                 coarse_parts=None, coarse_overlap=1, coarse_maxit=4, coarse_rtol=0.1):
         self.P = prolongation(prob, factors)
         if restrict == "transpose":
             self.R = self.P.T.tocsr()
@@ -120,7 +141,13 @@ class TwoLevel:
             raise ValueError(restrict)
         self.cprob = coarse_problem(prob, factors)
         self.Fc = kkt_mod.assemble(self.cprob)
-        self.coarse = BlockTridiagLU(self.Fc, self.cprob.M + 1)
+        if coarse == "lu":
+            self.coarse = BlockTridiagLU(self.Fc, self.cprob.M + 1)
+        elif coarse == "gmres_ras":
+            self.coarse = CoarseGmresRas(self.cprob, self.Fc, coarse_parts, coarse_overlap, coarse_maxit,
+                                         coarse_rtol)
+        else:
+            raise ValueError(coarse)
         self.one = one_level
         self.F = F_apply
 

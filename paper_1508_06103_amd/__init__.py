@@ -23,6 +23,7 @@ OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, EBREAKDOWN = 0, 1, -1, -2, -3, -4
 DTO, OTD = 0, 1
 F64, F32 = 0, 1
 RESTRICT_TRANSPOSE, RESTRICT_INJECTION = 0, 1
+COARSE_GMRES_RAS = 0
 
 
 class StkktError(RuntimeError):
@@ -60,7 +61,9 @@ class _RasParams(ctypes.Structure):
 
 
 class _CoarseParams(ctypes.Structure):
-    _fields_ = [("factor", ctypes.c_int32 * 4), ("precision", ctypes.c_int32), ("restrict_kind", ctypes.c_int32)]
+    _fields_ = [("factor", ctypes.c_int32 * 4), ("method", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("restrict_kind", ctypes.c_int32), ("p", ctypes.c_int32 * 4), ("overlap", ctypes.c_int32),
+                ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double)]
 
 
 class _SolveParams(ctypes.Structure):
@@ -287,15 +290,25 @@ class RAS:
 
 
 class Coarse:
-    """Coarse space-time level of the two-level preconditioner."""
+    """Coarse space-time level of the two-level preconditioner.
 
-    def __init__(self, op: KKTOperator, factor, precision=F64, restrict=RESTRICT_TRANSPOSE, stream=None):
+    factor: coarsening in (x, y, z, t); parts/overlap: the coarse mesh's RAS;
+    F_c^{-1} is `maxit` steps of GMRES (relative tolerance `rtol`) from zero.
+    """
+
+    def __init__(self, op: KKTOperator, factor, parts, overlap=1, maxit=4, rtol=0.1, precision=F64,
+                 restrict=RESTRICT_TRANSPOSE, stream=None):
         self.op = op
         self.alloc = op.alloc
         cp = _CoarseParams()
         cp.factor = (ctypes.c_int32 * 4)(*factor)
+        cp.method = COARSE_GMRES_RAS
         cp.precision = int(precision)
         cp.restrict_kind = int(restrict)
+        cp.p = (ctypes.c_int32 * 4)(*parts)
+        cp.overlap = int(overlap)
+        cp.maxit = int(maxit)
+        cp.rtol = float(rtol)
         h = ctypes.c_void_p()
         _check(_lib.coarse_setup(op.handle, ctypes.byref(cp), _stream(stream), ctypes.byref(h)))
         self.handle = h

@@ -10,10 +10,7 @@
 
 namespace stkkt {
 
-ras *ras_create(const kkt_op *op, const ras_params_t *rp, hipStream_t s);
 void ras_export(const ras *R, int sub, double *out);
-int gmres_solve(const kkt_op *op, const ras *R, const coarse *C, const solve_params_t &sp, const double *b,
-                double *x, hipStream_t s, kkt_stats_t *st);
 
 namespace {
 thread_local std::string g_last_error;
@@ -60,7 +57,7 @@ template <class F> static int guarded(F &&f) {
   }
 }
 
-static kkt_op *op_create(const kkt_problem_t *p, const kkt_alloc_t *al, hipStream_t s) {
+kkt_op *op_create(const kkt_problem_t *p, const kkt_alloc_t *al, hipStream_t s) {
   STKKT_REQUIRE(p != nullptr, "kkt_assemble: problem is NULL");
   for (int d = 0; d < 3; ++d) {
     STKKT_REQUIRE(p->n[d] >= 1 && p->n[d] < 65535, "kkt_assemble: n[d] must be in [1, 65534]");
@@ -226,6 +223,7 @@ int kkt_solve(const kkt_op_t *op, const ras_t *R, const coarse_t *C, const solve
   return guarded([&] {
     STKKT_REQUIRE(op && R && sp && b && x, "kkt_solve: NULL argument");
     STKKT_REQUIRE(R->op == op, "kkt_solve: preconditioner built for another operator");
+    STKKT_REQUIRE(!C || coarse_built_for(C, op), "kkt_solve: coarse level built for another operator");
     STKKT_REQUIRE(sp->restart >= 1 && sp->restart <= 1000, "kkt_solve: restart must be in [1, 1000]");
     STKKT_REQUIRE(sp->maxit >= 1 || sp->fixed_iters > 0, "kkt_solve: maxit must be >= 1");
     STKKT_REQUIRE(sp->rtol > 0 && sp->rtol < 1, "kkt_solve: rtol must be in (0, 1)");

@@ -1,12 +1,43 @@
 // Two-level space-time preconditioner: coarse operator and transfers.
 #pragma once
 
+#include <memory>
+
 #include "common.hpp"
 
 struct coarse;
+struct ras;
 
 namespace stkkt {
+
+struct PinnedHost {
+  double *p = nullptr;
+  explicit PinnedHost(size_t n);
+  ~PinnedHost();
+  PinnedHost(const PinnedHost &) = delete;
+  PinnedHost &operator=(const PinnedHost &) = delete;
+};
+
+// Device workspace of one GMRES/FGMRES run: the Krylov basis V (m+1 vectors),
+// the preconditioned basis Z (FGMRES, m vectors), five work vectors, two more
+// for the two-level combination, reduction partials and the Hessenberg
+// column; plus a pinned host mirror of the column.
+struct GmresWork {
+  long long n;
+  int m;
+  bool flex, coarse;
+  int G, hlen;
+  DevBuf V, Z, rb, wb, tb, ub, yb, t2, partial, hdev;
+  PinnedHost hh;
+  GmresWork(const Allocator *al, long long n, int m, bool flex, bool two_level);
+  bool fits(long long n, int m, bool flex, bool two_level) const;
+};
+
 void coarse_apply_device(const coarse *C, const double *x, double *y, hipStream_t s);
 coarse *coarse_create(const kkt_op *fine, const coarse_params_t *cp, hipStream_t s);
 void coarse_free(coarse *c);
+bool coarse_built_for(const coarse *c, const kkt_op *op);
+ras *ras_create(const kkt_op *op, const ras_params_t *rp, hipStream_t s);
+int gmres_solve(const kkt_op *op, const ras *R, const coarse *C, const solve_params_t &sp, const double *b,
+                double *x, hipStream_t s, kkt_stats_t *st, GmresWork *work = nullptr);
 }  // namespace stkkt

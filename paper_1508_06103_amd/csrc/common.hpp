@@ -101,6 +101,7 @@ inline int blocks_for(long long n, int threads, int cap = 1 << 20) {
   if (b < 1) b = 1;
   return static_cast<int>(b);
 }
+kkt_op *op_create(const kkt_problem_t *p, const kkt_alloc_t *al, hipStream_t s);
 void rhs_device(const kkt_op *op, const double *data_host, hipStream_t s, double *b);
 void fill_zero(double *p, long long n, hipStream_t s);
 void stiff_table(const OpDev &d, double *tab, hipStream_t s);

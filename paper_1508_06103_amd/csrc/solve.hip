@@ -14,20 +14,26 @@
 
 namespace stkkt {
 
-namespace {
+PinnedHost::PinnedHost(size_t n) {
+  if (hipHostMalloc((void **)&p, n * sizeof(double), hipHostMallocDefault) != hipSuccess) p = nullptr;
+  if (!p) throw Error(STKKT_ENOMEM, "kkt_solve: pinned host allocation failed");
+}
 
-struct PinnedHost {
-  double *p = nullptr;
-  explicit PinnedHost(size_t n) {
-    if (hipHostMalloc((void **)&p, n * sizeof(double), hipHostMallocDefault) != hipSuccess) p = nullptr;
-    if (!p) throw Error(STKKT_ENOMEM, "kkt_solve: pinned host allocation failed");
-  }
-  ~PinnedHost() {
-    if (p) (void)hipHostFree(p);
-  }
-};
+PinnedHost::~PinnedHost() {
+  if (p) (void)hipHostFree(p);
+}
 
-}  // namespace
+GmresWork::GmresWork(const Allocator *al, long long n_, int m_, bool flex_, bool two_level)
+    : n(n_), m(m_), flex(flex_), coarse(two_level), G(reduction_blocks(n_)), hlen(2 * (m_ + 1) + 2),
+      V(al, sizeof(double) * (size_t)(m_ + 1) * n_), Z(al, flex_ ? sizeof(double) * (size_t)m_ * n_ : 0),
+      rb(al, sizeof(double) * n_), wb(al, sizeof(double) * n_), tb(al, sizeof(double) * n_),
+      ub(al, sizeof(double) * n_), yb(al, two_level ? sizeof(double) * n_ : 0),
+      t2(al, two_level ? sizeof(double) * n_ : 0), partial(al, sizeof(double) * (size_t)(m_ + 1) * G),
+      hdev(al, sizeof(double) * (size_t)(hlen + m_ + 1)), hh((size_t)(hlen + m_ + 1)) {}
+
+bool GmresWork::fits(long long n_, int m_, bool flex_, bool two_level) const {
+  return n == n_ && m >= m_ && (flex || !flex_) && (coarse || !two_level);
+}
 
 void precond_apply(const kkt_op *op, const ras *R, const coarse *C, const double *v, double *z, double *y,
                    double *t, hipStream_t s) {
@@ -45,25 +51,21 @@ void precond_apply(const kkt_op *op, const ras *R, const coarse *C, const double
 }
 
 int gmres_solve(const kkt_op *op, const ras *R, const coarse *C, const solve_params_t &sp, const double *b,
-                double *x, hipStream_t s, kkt_stats_t *st) {
+                double *x, hipStream_t s, kkt_stats_t *st, GmresWork *work) {
   const auto t0 = std::chrono::steady_clock::now();
   const long long n = 3 * op->d.V;
   const int m = sp.restart;
   const bool flex = sp.flexible != 0;
-  const Allocator *al = &op->al;
-  DevBuf V(al, sizeof(double) * (size_t)(m + 1) * n);
-  DevBuf Z(al, flex ? sizeof(double) * (size_t)m * n : 0);
-  DevBuf rb(al, sizeof(double) * n), wb(al, sizeof(double) * n), tb(al, sizeof(double) * n),
-      ub(al, sizeof(double) * n);
-  DevBuf yb(al, C ? sizeof(double) * n : 0), t2(al, C ? sizeof(double) * n : 0);
-  const int G = reduction_blocks(n);
-  DevBuf partial(al, sizeof(double) * (size_t)(m + 1) * G);
+  std::unique_ptr<GmresWork> own;
+  if (!work || !work->fits(n, m, flex, C != nullptr)) {
+    own = std::make_unique<GmresWork>(&op->al, n, m, flex, C != nullptr);
+    work = own.get();
+  }
+  GmresWork &W = *work;
+  DevBuf &V = W.V, &Z = W.Z, &rb = W.rb, &wb = W.wb, &tb = W.tb, &ub = W.ub, &yb = W.yb, &t2 = W.t2,
+         &partial = W.partial, &hdev = W.hdev;
+  PinnedHost &hh = W.hh;
   const int hlen = 2 * (m + 1) + 2;
-  DevBuf hdev(al, sizeof(double) * (size_t)hlen + sizeof(double) * (size_t)(m + 1));
-  if ((!V.ptr) || (flex && !Z.ptr) || !rb.ptr || !wb.ptr || !tb.ptr || !ub.ptr || !partial.ptr || !hdev.ptr ||
-      (C && (!yb.ptr || !t2.ptr)))
-    throw Error(STKKT_ENOMEM, "kkt_solve: workspace allocation failed");
-  PinnedHost hh(hlen + m + 1);
   double *Vd = V.as<double>(), *Zd = Z.as<double>(), *r = rb.as<double>(), *w = wb.as<double>(),
          *t = tb.as<double>(), *u = ub.as<double>(), *hd = hdev.as<double>();
   double *ydev = hd + hlen;

@@ -1,0 +1,143 @@
+"""GPU parity of the two-level space-time preconditioner against the oracle.
+
+The coarse correction y = I_c^h F_c^{-1} I_h^c x (F_c^{-1} = GMRES(maxit) from
+zero, right-preconditioned by the coarse mesh's RAS) is compared element by
+element; the two-level FGMRES solve is compared by iteration count and, at a
+fixed number of Arnoldi steps, by its iterate.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import kkt, krylov, ras as oras, twolevel
+from workloads.generate import make_custom, make_problem, OTD
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def st():
+    import paper_1508_06103_amd as st_mod
+    assert torch.cuda.is_available()
+    return st_mod
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _grid_sensors(n, fac, picks, faces=0b000011):
+    """Sensor node ids on coarse nodes: picks = list of (I, J, K) coarse indices."""
+    nn = (n[0] + 1, n[1] + 1)
+    return np.array([I * fac[0] + nn[0] * (J * fac[1] + nn[1] * K * fac[2]) for I, J, K in picks], dtype=np.int32)
+
+
+def case(name):
+    if name == "cfg0":
+        return make_problem("cfg0")[0], (2, 2, 2, 2), (2, 2, 2, 2)
+    if name == "aniso":
+        n, fac = (6, 6, 4), (3, 2, 2, 3)
+        sens = _grid_sensors(n, fac, [(1, 0, 0), (1, 1, 1), (1, 2, 2), (1, 3, 1), (1, 1, 2)])
+        return make_custom(n, 6, 11, sensors=sens), fac, (1, 2, 1, 2)
+    if name == "otd_neumann":
+        n, fac = (4, 6, 6), (2, 3, 2, 2)
+        sens = _grid_sensors(n, fac, [(1, 1, 1), (0, 1, 2), (2, 0, 1), (1, 2, 3)])
+        return make_custom(n, 8, 12, sensors=sens, variant=OTD, faces=0), fac, (2, 1, 2, 2)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name,restrict,rtol", [("cfg0", "transpose", 1e-12), ("cfg0", "transpose", 0.1),
+                                                ("cfg0", "injection", 1e-12), ("aniso", "transpose", 1e-12),
+                                                ("otd_neumann", "transpose", 0.1)])
+def test_coarse_correction(st, name, restrict, rtol):
+    prob, fac, cparts = case(name)
+    _say(f"case {name}: factor {fac} coarse parts {cparts} restrict {restrict} rtol {rtol}")
+    op = st.KKTOperator(prob)
+    kind = st.RESTRICT_TRANSPOSE if restrict == "transpose" else st.RESTRICT_INJECTION
+    C = st.Coarse(op, fac, cparts, overlap=1, maxit=4, rtol=rtol, restrict=kind)
+    F = kkt.assemble(prob)
+    tl = twolevel.TwoLevel(prob, None, None, fac, restrict=restrict, coarse="gmres_ras", coarse_parts=cparts,
+                           coarse_overlap=1, coarse_maxit=4, coarse_rtol=rtol)
+    for seed in (1, 2):
+        x = np.random.default_rng(seed).standard_normal(F.shape[0])
+        y = C.apply(_dev(x)).cpu().numpy()
+        y_ref = tl.coarse_correction(x)
+        err = np.linalg.norm(y - y_ref) / np.linalg.norm(y_ref)
+        _say(f"  seed {seed}: coarse correction rel err {err:.2e}")
+        assert err <= 1e-10
+
+
+@pytest.mark.parametrize("name,restart", [("cfg0", 30), ("aniso", 20)])
+def test_two_level_fgmres_parity(st, name, restart):
+    prob, fac, cparts = case(name)
+    parts = {"cfg0": (2, 2, 2, 2), "aniso": (2, 2, 1, 2)}[name]
+    _say(f"case {name}: two-level FGMRES({restart}), fine parts {parts}")
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, parts, 1)
+    C = st.Coarse(op, fac, cparts, overlap=1, maxit=4, rtol=0.1)
+    x, s = st.solve(op, pre, coarse=C, restart=restart, rtol=1e-6, flexible=True)
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    b = kkt.rhs(prob)
+    A = lambda v: F @ v
+    R = oras.RAS(prob, parts, 1, terms=terms)
+    tl = twolevel.TwoLevel(prob, R.apply, A, fac, coarse="gmres_ras", coarse_parts=cparts, coarse_overlap=1,
+                           coarse_maxit=4, coarse_rtol=0.1)
+    xo, so = krylov.gmres(A, tl, b, restart=restart, rtol=1e-6, flexible=True)
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(b - F @ xg) / np.linalg.norm(b)
+    _say(f"  gpu its {s.iters} oracle its {so.iters} true res {res:.2e}")
+    assert s.converged and res <= 1e-6
+    assert abs(s.iters - so.iters) <= 1
+    k = so.iters
+    x2, _ = st.solve(op, pre, coarse=C, restart=restart, rtol=1e-6, flexible=True, fixed_iters=k)
+    xo2, _ = krylov.gmres(A, tl, b, restart=restart, rtol=1e-6, flexible=True, fixed_iters=k)
+    e = np.linalg.norm(x2.cpu().numpy() - xo2) / np.linalg.norm(xo2)
+    _say(f"  fixed {k} iterations: rel diff {e:.2e}")
+    assert e <= 1e-7
+
+
+def test_two_level_cuts_iterations(st):
+    """Space-time coarse correction reduces the FGMRES count of the one-level method."""
+    nn = 13
+    idx = [3, 6, 9]
+    sens = np.array([i + nn * (j + nn * k) for k in idx for j in idx for i in idx], dtype=np.int32)
+    prob = make_custom((12, 12, 12), 16, 4, sensors=sens)
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, (3, 3, 3, 4), 1)
+    _, s1 = st.solve(op, pre, restart=50, rtol=1e-6)
+    C = st.Coarse(op, (3, 3, 3, 4), (2, 2, 2, 2), overlap=1, maxit=4, rtol=0.1)
+    x, s2 = st.solve(op, pre, coarse=C, restart=50, rtol=1e-6, flexible=True)
+    _say(f"  one-level {s1.iters} its, two-level {s2.iters} its")
+    assert s1.converged and s2.converged and s2.iters < s1.iters
+    F = kkt.assemble(prob)
+    b = kkt.rhs(prob)
+    assert np.linalg.norm(b - F @ x.cpu().numpy()) <= 1e-6 * np.linalg.norm(b)
+
+
+def test_coarse_errors(st):
+    prob, fac, cparts = case("cfg0")
+    op = st.KKTOperator(prob)
+    with pytest.raises(st.StkktError) as e:
+        st.Coarse(op, (3, 2, 2, 2), cparts)          # 3 does not divide 8
+    assert e.value.code == st.EINVAL
+    n = (8, 8, 8)
+    odd = make_custom(n, 8, 5, sensors=np.array([3 + 9 * (2 + 9 * 2)], dtype=np.int32))
+    op_odd = st.KKTOperator(odd)
+    with pytest.raises(st.StkktError):
+        st.Coarse(op_odd, (2, 2, 2, 2), cparts)      # sensor at x = 3 is not a coarse node
+    with pytest.raises(st.StkktError):
+        st.Coarse(op, fac, cparts, maxit=0)
+    C = st.Coarse(op, fac, cparts)
+    other = st.KKTOperator(prob)
+    pre_other = st.RAS(other, (2, 2, 2, 2), 1)
+    with pytest.raises(st.StkktError):
+        st.solve(other, pre_other, coarse=C, flexible=True)

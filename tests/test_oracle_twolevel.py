@@ -84,3 +84,22 @@ def test_two_level_fewer_iterations_than_one_level():
     x2, st2 = krylov.gmres(A, tl, b, restart=50, rtol=1e-6, flexible=True)
     assert st1.converged and st2.converged
     assert st2.iters < st1.iters
+
+
+def test_two_level_gmres_ras_coarse_solver():
+    """The paper's coarse solver (GMRES(4), rtol 0.1, coarse RAS) still cuts iterations."""
+    nn = 13
+    idx = [3, 6, 9]
+    sens = np.array([i + nn * (j + nn * k) for k in idx for j in idx for i in idx], dtype=np.int32)
+    prob = make_custom((12, 12, 12), 16, 4, sensors=sens)
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    b = kkt.rhs(prob)
+    A = lambda v: F @ v
+    R = ras.RAS(prob, (3, 3, 3, 4), 1, terms=terms)
+    _, st1 = krylov.gmres(A, R.apply, b, restart=50, rtol=1e-6)
+    tl = twolevel.TwoLevel(prob, R.apply, A, (3, 3, 3, 4), coarse="gmres_ras", coarse_parts=(2, 2, 2, 2),
+                           coarse_overlap=1, coarse_maxit=4, coarse_rtol=0.1)
+    x, st2 = krylov.gmres(A, tl, b, restart=50, rtol=1e-6, flexible=True)
+    assert st2.converged and st2.iters < st1.iters
+    assert np.linalg.norm(b - F @ x) <= 1e-6 * np.linalg.norm(b)
