@@ -117,6 +117,7 @@ kkt_op *op_create(const kkt_problem_t *p, const kkt_alloc_t *al, hipStream_t s) 
   d.a_elem = op->a_elem.as<double>();
   d.sensor = op->sensor.as<double>();
   stiff_table(d, op->atab.as<double>(), s);
+  op->mv = choose_matvec_tile(d);
   STKKT_HIP(hipStreamSynchronize(s));
   return op.release();
 }
@@ -152,7 +153,7 @@ int kkt_matvec(const kkt_op_t *op, const double *x, double *y, void *stream) {
   return guarded([&] {
     STKKT_REQUIRE(op && x && y, "kkt_matvec: NULL argument");
     STKKT_REQUIRE(x != y, "kkt_matvec: x and y must not alias");
-    matvec_device(op->d, op->atab.as<double>(), x, y, as_stream(stream));
+    matvec_device(op, x, y, as_stream(stream));
     return STKKT_OK;
   });
 }

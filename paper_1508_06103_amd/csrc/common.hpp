@@ -82,11 +82,19 @@ struct OpDev {
   const double *sensor;   // device [N], 1 at sensor nodes
 };
 
+// Launch shape of the matvec: spatial tiles of t[0] x t[1] x t[2] nodes
+// (nt[] tiles per axis) marched over time chunks of clen levels.
+struct MvTile {
+  int t[3], nt[3];
+  int ntiles, halo, clen, nchunks;
+};
+
 }  // namespace stkkt
 
 struct kkt_op {
   stkkt::Allocator al;
   stkkt::OpDev d{};
+  stkkt::MvTile mv{};
   stkkt::DevBuf a_elem, sensor, atab;   // atab: [N][27] diffusion stiffness rows
   std::vector<int32_t> sensor_node;   // host copy
   double T = 1.0, len[3] = {1, 1, 1};
@@ -105,5 +113,6 @@ kkt_op *op_create(const kkt_problem_t *p, const kkt_alloc_t *al, hipStream_t s);
 void rhs_device(const kkt_op *op, const double *data_host, hipStream_t s, double *b);
 void fill_zero(double *p, long long n, hipStream_t s);
 void stiff_table(const OpDev &d, double *tab, hipStream_t s);
-void matvec_device(const OpDev &d, const double *Atab, const double *x, double *y, hipStream_t s);
+MvTile choose_matvec_tile(const OpDev &d);
+void matvec_device(const kkt_op *op, const double *x, double *y, hipStream_t s);
 }  // namespace stkkt

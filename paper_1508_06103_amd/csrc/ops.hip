@@ -1,4 +1,7 @@
 // Operator assembly, right-hand side and the matrix-free space-time matvec.
+#include <algorithm>
+#include <climits>
+
 #include "common.hpp"
 #include "stencil.hpp"
 
@@ -74,100 +77,326 @@ void stiff_table(const OpDev &d, double *tab, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------------
-// y = F_h x.  One thread per space-time node (n, j); the 27 spatial
-// neighbours at levels n-1, n, n+1 are read through the caches.  Rows follow
-// the block formula of kkt_block_c() with the time couplings fused:
-//   C row (n >= 1, interior j): sum_i Pi[(B + tau/2 (A+N)) C_i^n + (-B + tau/2 (A+N)) C_i^{n-1}]
-//                               - tau/2 B (f_i^{n-1} + f_i^n)
-//   G row (interior j), DTO: sum_i Pi[[n>=1](B + tau/2(A+N^T)) G_i^n + [n<M](-B + tau/2 (A+N^T)) G_i^{n+1}]
-//                            + [n=0] G_j^0 + w_n S_j C_j^n
-//                       OTD (n < M): sum_i Pi[(B + tau/2(A+N^T)) G_i^n + (-B + tau/2(A+N^T)) G_i^{n+1}]
-//                            + tau/2 S_j (C_j^n + C_j^{n+1});  n = M: G_j^M
-//   f row: sum_i beta1 B (St f_i)^n + beta2 K (Tt f_i)^n
-//          - DTO: tau/2 B Pi ([n>=1] G_i^n + [n<M] G_i^{n+1});  OTD: B Pi (Tt G_i)^n
-//   Dirichlet rows of C and G, and the C row of level 0, are identity rows.
+// y = F_h x, matrix-free.  Rows follow the block formula of kkt_block_c()
+// regrouped by spatial operator.  With P_i = 0 on Dirichlet nodes and 1
+// elsewhere, and per node i the combined fields
+//   U1 = P (c^n - c^{n-1}) - tau/2 (f^{n-1} + f^n)       S1 = P (c^n + c^{n-1})
+//   U2 = P (m g^n - p g^{n+1})                          S2 = P (m g^n + p g^{n+1})
+//   U3 = beta1 (St f)^n - { DTO: tau/2 S2 ; OTD: P (Tt g)^n }   T3 = beta2 (Tt f)^n
+// (m = [n >= 1] for DTO and 1 for OTD, p = [n < M]; (St f)^n, (Tt f)^n the
+// time stiffness / mass rows of level n), the rows of an interior node j are
+//   C (n >= 1):  sum_i B_ji U1_i + tau/2 (A + N)_ji S1_i
+//   G:           sum_i B_ji U2_i + tau/2 (A + N^T)_ji S2_i
+//                + DTO: [n = 0] g_j^0 + w_n S_j c_j^n ; OTD (n < M): tau/2 S_j (c_j^n + c_j^{n+1})
+//   f:           sum_i B_ji U3_i + K_ji T3_i
+// and Dirichlet C/G rows, the C row of level 0 and the OTD G row of level M
+// are identity rows.
+//
+// One workgroup owns a TX x TY x TZ tile of spatial nodes over a chunk of
+// consecutive time levels and marches through them: every thread keeps the
+// raw (c, g, f) of up to KH halo nodes for levels n-1 and n in registers,
+// loads level n+1 once, writes the six combined fields of its halo nodes to
+// LDS, and after a barrier evaluates the 27-point sums of its own node from
+// LDS.  The spatial 1-D factors of B, K and N are rebuilt from the node's
+// position (end-node rules); the variable-coefficient diffusion A comes from
+// the per-node table, read once per chunk into registers.
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) matvec_kernel(OpDev op, const double *__restrict__ Atab,
-                                                     const double *__restrict__ x, double *__restrict__ y) {
-  const long long V = op.V;
+namespace {
+
+constexpr int kMvThreads = 256;
+
+// Mesh and time constants of the matvec, formed on the host so that the
+// kernel never evaluates a product of uniform values in vector registers.
+struct MvConst {
+  double h6[3], hinv[3];   // h/6 and 1/h per axis (off-centre mass, -stiffness)
+  double v[3];
+  double cyz[2][2][4];     // corner rows (dy, dz = +-1): myz, kyz, nyz, v0 myz
+  double ht, inv_tau, tau6, tau3, beta1, beta2;
+};
+
+MvConst make_mv_const(const OpDev &d) {
+  MvConst c{};
+  for (int a = 0; a < 3; ++a) {
+    c.h6[a] = d.h[a] / 6.0;
+    c.hinv[a] = 1.0 / d.h[a];
+    c.v[a] = d.v[a];
+  }
+  for (int sy = 0; sy < 2; ++sy)
+    for (int sz = 0; sz < 2; ++sz) {
+      const double dy = sy ? 1.0 : -1.0, dz = sz ? 1.0 : -1.0;
+      const double my = c.h6[1], mz = c.h6[2], ky = -c.hinv[1], kz = -c.hinv[2];
+      c.cyz[sy][sz][0] = my * mz;
+      c.cyz[sy][sz][1] = ky * mz + my * kz;
+      c.cyz[sy][sz][2] = d.v[1] * 0.5 * dy * mz + d.v[2] * my * 0.5 * dz;
+      c.cyz[sy][sz][3] = d.v[0] * my * mz;
+    }
+  c.ht = 0.5 * d.tau;
+  c.inv_tau = 1.0 / d.tau;
+  c.tau6 = d.tau / 6.0;
+  c.tau3 = d.tau / 3.0;
+  c.beta1 = d.beta1;
+  c.beta2 = d.beta2;
+  return c;
+}
+
+struct Centre {
+  double m, k, c;   // centre mass, stiffness and convection entries of the node on one axis
+};
+
+__device__ inline Centre axis_centre(const MvConst &mc, int a, int i, int nn) {
+  const bool end = (i == 0) || (i == nn - 1);
+  Centre r;
+  r.m = end ? 2.0 * mc.h6[a] : 4.0 * mc.h6[a];
+  r.k = end ? mc.hinv[a] : 2.0 * mc.hinv[a];
+  r.c = (i == 0) ? -0.5 : ((i == nn - 1) ? 0.5 : 0.0);
+  return r;
+}
+
+template <int KH>
+__global__ void __launch_bounds__(kMvThreads) matvec_tile_kernel(OpDev op, MvTile tl, MvConst mc,
+                                                                 const double *__restrict__ Atab,
+                                                                 const double *__restrict__ x,
+                                                                 double *__restrict__ y) {
+  // per halo node: {U1, S1}, {U2, S2}, {U3, T3} side by side (48 B)
+  extern __shared__ double2 mv_lds[];
+  // consecutive work items on the same XCD (blocks are dealt to the 8 XCDs round robin)
+  const int G = gridDim.x, b = blockIdx.x;
+  const int q = G >> 3, r = G & 7, xcd = b & 7;
+  const int w = xcd * q + min(xcd, r) + (b >> 3);
+  const int tile = w % tl.ntiles, chunk = w / tl.ntiles;
   const int M = op.M;
-  const double tau = op.tau, ht = 0.5 * tau;
+  const int n0 = chunk * tl.clen, n1 = min(n0 + tl.clen, M + 1);
+  const int tix = tile % tl.nt[0], tiy = (tile / tl.nt[0]) % tl.nt[1], tiz = tile / (tl.nt[0] * tl.nt[1]);
+  const int ox = tix * tl.t[0], oy = tiy * tl.t[1], oz = tiz * tl.t[2];
+  const int hx = tl.t[0] + 2, hy = tl.t[1] + 2;
+  const int nn0 = op.nn[0], nn1 = op.nn[1], nn2 = op.nn[2];
+  const long long N = op.N;
+  const double ht = mc.ht;
   const bool dto = op.variant == STKKT_DTO;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < V;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const int n = (int)(idx / op.N);
-    const long long j = idx - (long long)n * op.N;
-    const int jx = (int)(j % op.nn[0]);
-    const int jy = (int)((j / op.nn[0]) % op.nn[1]);
-    const int jz = (int)(j / ((long long)op.nn[0] * op.nn[1]));
-    const bool Pj = !on_dirichlet(op, jx, jy, jz);
-    const bool has_m = n >= 1, has_p = n <= M - 1;
-    const double stm = has_m ? tstiff(tau, n, -1, M) : 0.0, st0 = tstiff(tau, n, 0, M),
-                 stp = has_p ? tstiff(tau, n, 1, M) : 0.0;
-    const double ttm = has_m ? tmass(tau, n, -1, M) : 0.0, tt0 = tmass(tau, n, 0, M),
-                 ttp = has_p ? tmass(tau, n, 1, M) : 0.0;
-    double accC = 0.0, accG = 0.0, accF = 0.0;
-    for (int k = 0; k < 27; ++k) {
-      const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
-      const int ix = jx + dx, iy = jy + dy, iz = jz + dz;
-      if (ix < 0 || ix >= op.nn[0] || iy < 0 || iy >= op.nn[1] || iz < 0 || iz >= op.nn[2]) continue;
-      const double mx = mass1(op.h[0], jx, dx, op.nn[0]);
-      const double my = mass1(op.h[1], jy, dy, op.nn[1]);
-      const double mz = mass1(op.h[2], jz, dz, op.nn[2]);
-      const double B = mx * my * mz;
-      const double K = stiff1(op.h[0], jx, dx, op.nn[0]) * my * mz + mx * stiff1(op.h[1], jy, dy, op.nn[1]) * mz +
-                       mx * my * stiff1(op.h[2], jz, dz, op.nn[2]);
-      const double Nv = op.v[0] * conv1(jx, dx, op.nn[0]) * my * mz + op.v[1] * mx * conv1(jy, dy, op.nn[1]) * mz +
-                        op.v[2] * mx * my * conv1(jz, dz, op.nn[2]);
-      const double Nt = op.v[0] * conv1(ix, -dx, op.nn[0]) * my * mz + op.v[1] * mx * conv1(iy, -dy, op.nn[1]) * mz +
-                        op.v[2] * mx * my * conv1(iz, -dz, op.nn[2]);
-      const double A = Atab[27 * j + k];
-      const double Pi = on_dirichlet(op, ix, iy, iz) ? 0.0 : 1.0;
-      const long long i = ix + (long long)op.nn[0] * (iy + (long long)op.nn[1] * iz);
-      const double *x0 = x + 3 * ((long long)n * op.N + i);
-      const double c0 = x0[0], g0 = x0[1], f0 = x0[2];
-      double cm = 0.0, fm = 0.0, gp = 0.0, fp = 0.0, gm = 0.0;
-      if (has_m) {
-        const double *xm = x0 - 3LL * op.N;
-        cm = xm[0];
-        gm = xm[1];
-        fm = xm[2];
+
+  // own node
+  const int t = threadIdx.x;
+  const int lx = t % tl.t[0], ly = (t / tl.t[0]) % tl.t[1], lz = t / (tl.t[0] * tl.t[1]);
+  const int jx = ox + lx, jy = oy + ly, jz = oz + lz;
+  const bool own = t < tl.t[0] * tl.t[1] * tl.t[2] && jx < nn0 && jy < nn1 && jz < nn2;
+  const long long j = own ? jx + (long long)nn0 * (jy + (long long)nn1 * jz) : 0;
+  double A[27];
+#pragma unroll
+  for (int k = 0; k < 27; ++k) A[k] = own ? Atab[27 * j + k] : 0.0;
+  Centre cx = axis_centre(mc, 0, jx, nn0), cy = axis_centre(mc, 1, jy, nn1), cz = axis_centre(mc, 2, jz, nn2);
+  const bool Pj = own && !on_dirichlet(op, jx, jy, jz);
+  const double sens = own ? op.sensor[j] : 0.0;
+  const int hc = (lx + 1) + hx * ((ly + 1) + hy * (lz + 1));
+
+  // halo nodes loaded by this thread
+  long long hoff[KH];
+  double hP[KH];
+  bool hin[KH], hact[KH];
+#pragma unroll
+  for (int s = 0; s < KH; ++s) {
+    const int h = t + kMvThreads * s;
+    hact[s] = h < tl.halo;
+    hin[s] = false;
+    hoff[s] = 0;
+    hP[s] = 0.0;
+    if (hact[s]) {
+      const int axh = h % hx, ayh = (h / hx) % hy, azh = h / (hx * hy);
+      const int gx = ox + axh - 1, gy = oy + ayh - 1, gz = oz + azh - 1;
+      if (gx >= 0 && gx < nn0 && gy >= 0 && gy < nn1 && gz >= 0 && gz < nn2) {
+        hin[s] = true;
+        hoff[s] = 3 * (gx + (long long)nn0 * (gy + (long long)nn1 * gz));
+        hP[s] = on_dirichlet(op, gx, gy, gz) ? 0.0 : 1.0;
       }
-      if (has_p) {
-        const double *xp = x0 + 3LL * op.N;
-        gp = xp[1];
-        fp = xp[2];
+    }
+  }
+  double cm[KH], c0[KH], gm[KH], g0[KH], fm[KH], f0[KH];
+#pragma unroll
+  for (int s = 0; s < KH; ++s) {
+    cm[s] = gm[s] = fm[s] = c0[s] = g0[s] = f0[s] = 0.0;
+    if (hin[s] && n0 >= 1) {
+      const double *p = x + 3LL * (n0 - 1) * N + hoff[s];
+      cm[s] = p[0];
+      gm[s] = p[1];
+      fm[s] = p[2];
+    }
+    if (hin[s]) {
+      const double *p = x + 3LL * n0 * N + hoff[s];
+      c0[s] = p[0];
+      g0[s] = p[1];
+      f0[s] = p[2];
+    }
+  }
+
+  for (int n = n0; n < n1; ++n) {
+    const bool hm = n >= 1, hp = n < M;
+    const bool tend = (n == 0) || (n == M);
+    // rows of the time stiffness St and mass Tt at level n
+    const double stm = hm ? -mc.inv_tau : 0.0, st0 = tend ? mc.inv_tau : 2.0 * mc.inv_tau,
+                 stp = hp ? -mc.inv_tau : 0.0;
+    const double ttm = hm ? mc.tau6 : 0.0, tt0 = tend ? mc.tau3 : 2.0 * mc.tau3, ttp = hp ? mc.tau6 : 0.0;
+    const bool mflag = !dto || hm;
+#pragma unroll
+    for (int s = 0; s < KH; ++s) {
+      double cp = 0.0, gp = 0.0, fp = 0.0;
+      if (hin[s] && hp) {
+        const double *p = x + 3LL * (n + 1) * N + hoff[s];
+        cp = p[0];
+        gp = p[1];
+        fp = p[2];
       }
-      const double AN = A + Nv, ANt = A + Nt;
-      if (has_m) accC += Pi * ((B + ht * AN) * c0 + (-B + ht * AN) * cm) - ht * B * (fm + f0);
-      if (dto) {
-        accG += Pi * ((has_m ? (B + ht * ANt) * g0 : 0.0) + (has_p ? (-B + ht * ANt) * gp : 0.0));
-        accF -= ht * B * Pi * ((has_m ? g0 : 0.0) + (has_p ? gp : 0.0));
+      if (hact[s]) {
+        const int h = t + kMvThreads * s;
+        const double P = hP[s];
+        const double gn = mflag ? g0[s] : 0.0;
+        const double S2 = P * (gn + gp);
+        const double stf = stm * fm[s] + st0 * f0[s] + stp * fp;
+        const double ttf = ttm * fm[s] + tt0 * f0[s] + ttp * fp;
+        const double U3 = mc.beta1 * stf - (dto ? ht * S2 : P * (ttm * gm[s] + tt0 * g0[s] + ttp * gp));
+        mv_lds[3 * h] = make_double2(P * (c0[s] - cm[s]) - ht * (fm[s] + f0[s]), P * (c0[s] + cm[s]));
+        mv_lds[3 * h + 1] = make_double2(P * (gn - gp), S2);
+        mv_lds[3 * h + 2] = make_double2(U3, mc.beta2 * ttf);
+      }
+      cm[s] = c0[s];
+      c0[s] = cp;
+      gm[s] = g0[s];
+      g0[s] = gp;
+      fm[s] = f0[s];
+      f0[s] = fp;
+    }
+    __syncthreads();
+    // rebuild the node's stencil weights every level instead of keeping them live
+    asm volatile("" : "+v"(cx.m), "+v"(cx.k), "+v"(cx.c), "+v"(cy.m), "+v"(cy.k), "+v"(cy.c));
+    asm volatile("" : "+v"(cz.m), "+v"(cz.k), "+v"(cz.c));
+    if (own) {
+      // Sum factorisation: B, K and N are tensor products of 1-D factors, so
+      // each row of three x-neighbours is first contracted with the x factors
+      // (off-centre entries are the same for every node, the centre ones are
+      // the node's), then weighted by the (y, z) factors of the row.  The
+      // variable diffusion A is applied point by point.
+      double aC = 0.0, sC = 0.0, aG = 0.0, sG = 0.0, aF = 0.0;
+#pragma unroll
+      for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+          double myz, kyz, nyz, vmyz;
+          if (dy != 0 && dz != 0) {
+            const double *c4 = mc.cyz[dy > 0][dz > 0];
+            myz = c4[0];
+            kyz = c4[1];
+            nyz = c4[2];
+            vmyz = c4[3];
+          } else if (dy == 0 && dz != 0) {
+            myz = cy.m * mc.h6[2];
+            kyz = cy.k * mc.h6[2] - cy.m * mc.hinv[2];
+            nyz = mc.v[1] * mc.h6[2] * cy.c + (0.5 * dz) * mc.v[2] * cy.m;
+            vmyz = mc.v[0] * myz;
+          } else if (dy != 0 && dz == 0) {
+            myz = mc.h6[1] * cz.m;
+            kyz = -mc.hinv[1] * cz.m + mc.h6[1] * cz.k;
+            nyz = (0.5 * dy) * mc.v[1] * cz.m + mc.v[2] * mc.h6[1] * cz.c;
+            vmyz = mc.v[0] * myz;
+          } else {
+            myz = cy.m * cz.m;
+            kyz = cy.k * cz.m + cy.m * cz.k;
+            nyz = mc.v[1] * cy.c * cz.m + mc.v[2] * cy.m * cz.c;
+            vmyz = mc.v[0] * myz;
+          }
+          // N^T differs from N only in the sign of the off-centre convection entries
+          double ntyz;
+          if (dy != 0 && dz != 0) ntyz = -nyz;
+          else if (dy == 0 && dz != 0) ntyz = mc.v[1] * mc.h6[2] * cy.c - (0.5 * dz) * mc.v[2] * cy.m;
+          else if (dy != 0 && dz == 0) ntyz = -(0.5 * dy) * mc.v[1] * cz.m + mc.v[2] * mc.h6[1] * cz.c;
+          else ntyz = nyz;
+          const double2 *row = mv_lds + 3 * (hc + hx * (dy + hy * dz));
+          const double2 w1 = row[-3], w2 = row[-2], w3 = row[-1];   // x - 1
+          const double2 c1 = row[0], c2 = row[1], c3 = row[2];      // x
+          const double2 e1 = row[3], e2 = row[4], e3 = row[5];      // x + 1
+          const int k0 = 3 * (dy + 1) + 9 * (dz + 1);
+          const double mU1 = mc.h6[0] * (w1.x + e1.x) + cx.m * c1.x;
+          const double mU2 = mc.h6[0] * (w2.x + e2.x) + cx.m * c2.x;
+          const double mU3 = mc.h6[0] * (w3.x + e3.x) + cx.m * c3.x;
+          const double mT = mc.h6[0] * (w3.y + e3.y) + cx.m * c3.y;
+          const double kT = cx.k * c3.y - mc.hinv[0] * (w3.y + e3.y);
+          const double mS1 = mc.h6[0] * (w1.y + e1.y) + cx.m * c1.y;
+          const double cS1 = 0.5 * (e1.y - w1.y) + cx.c * c1.y;
+          const double aS1 = A[k0] * w1.y + A[k0 + 1] * c1.y + A[k0 + 2] * e1.y;
+          const double mS2 = mc.h6[0] * (w2.y + e2.y) + cx.m * c2.y;
+          const double cS2 = 0.5 * (w2.y - e2.y) + cx.c * c2.y;
+          const double aS2 = A[k0] * w2.y + A[k0 + 1] * c2.y + A[k0 + 2] * e2.y;
+          aC += myz * mU1;
+          aG += myz * mU2;
+          aF += myz * (mU3 + kT) + kyz * mT;
+          sC += aS1 + vmyz * cS1 + nyz * mS1;
+          sG += aS2 + vmyz * cS2 + ntyz * mS2;
+        }
+      }
+      const long long idx = (long long)n * N + j;
+      const double *xs = x + 3 * idx;
+      double *ys = y + 3 * idx;
+      const double cj = xs[0], gj = xs[1];
+      ys[0] = (n == 0 || !Pj) ? cj : aC + ht * sC;
+      double g;
+      if (!Pj) {
+        g = gj;
+      } else if (dto) {
+        const double wn = tend ? ht : 2.0 * ht;   // trapezoid weight of level n
+        g = aG + ht * sG + (n == 0 ? gj : 0.0) + wn * sens * cj;
       } else {
-        if (has_p) accG += Pi * ((B + ht * ANt) * g0 + (-B + ht * ANt) * gp);
-        accF -= B * Pi * (ttm * gm + tt0 * g0 + ttp * gp);
+        g = hp ? aG + ht * sG + ht * sens * (cj + xs[3 * N]) : gj;
       }
-      accF += op.beta1 * B * (stm * fm + st0 * f0 + stp * fp) + op.beta2 * K * (ttm * fm + tt0 * f0 + ttp * fp);
+      ys[1] = g;
+      ys[2] = aF;
     }
-    const double *xs = x + 3 * idx;
-    double *ys = y + 3 * idx;
-    const double sens = op.sensor[j];
-    ys[0] = (n == 0 || !Pj) ? xs[0] : accC;
-    double g;
-    if (!Pj) {
-      g = xs[1];
-    } else if (dto) {
-      g = accG + (n == 0 ? xs[1] : 0.0) + wtrap(tau, n, M) * sens * xs[0];
-    } else {
-      g = (n < M) ? accG + ht * sens * (xs[0] + xs[3 * (long long)op.N]) : xs[1];
-    }
-    ys[1] = g;
-    ys[2] = accF;
+    __syncthreads();
   }
 }
 
-void matvec_device(const OpDev &d, const double *Atab, const double *x, double *y, hipStream_t s) {
-  hipLaunchKernelGGL(matvec_kernel, dim3(blocks_for(d.V, 256, 1 << 16)), dim3(256), 0, s, d, Atab, x, y);
+}  // namespace
+
+MvTile choose_matvec_tile(const OpDev &d) {
+  MvTile best{};
+  double best_cost = 1e300;
+  const int cap = kMvThreads;
+  for (int tx = 1; tx <= std::min(d.nn[0], cap); ++tx)
+    for (int ty = 1; ty <= std::min(d.nn[1], cap / tx); ++ty)
+      for (int tz = 1; tz <= std::min(d.nn[2], cap / (tx * ty)); ++tz) {
+        const int halo = (tx + 2) * (ty + 2) * (tz + 2);
+        if (halo > 3 * kMvThreads) continue;
+        const long long ntiles = (long long)((d.nn[0] + tx - 1) / tx) * ((d.nn[1] + ty - 1) / ty) *
+                                 ((d.nn[2] + tz - 1) / tz);
+        const double cost = (double)ntiles * (halo + kMvThreads);
+        if (cost < best_cost) {
+          best_cost = cost;
+          best.t[0] = tx;
+          best.t[1] = ty;
+          best.t[2] = tz;
+        }
+      }
+  for (int a = 0; a < 3; ++a) best.nt[a] = (d.nn[a] + best.t[a] - 1) / best.t[a];
+  best.ntiles = best.nt[0] * best.nt[1] * best.nt[2];
+  best.halo = (best.t[0] + 2) * (best.t[1] + 2) * (best.t[2] + 2);
+  const int levels = d.M + 1;
+  int chunks = std::max(1, std::min(levels, (1024 + best.ntiles - 1) / best.ntiles));
+  best.clen = (levels + chunks - 1) / chunks;
+  best.nchunks = (levels + best.clen - 1) / best.clen;
+  return best;
+}
+
+void matvec_device(const kkt_op *op, const double *x, double *y, hipStream_t s) {
+  const OpDev &d = op->d;
+  const MvTile &tl = op->mv;
+  const long long grid = (long long)tl.ntiles * tl.nchunks;
+  if (grid > INT32_MAX) throw Error(STKKT_EINVAL, "kkt_matvec: mesh too large");
+  const size_t lds = sizeof(double2) * 3 * (size_t)tl.halo;   // 48 B per halo node
+  const int kh = (tl.halo + kMvThreads - 1) / kMvThreads;
+  const double *atab = op->atab.as<double>();
+  const MvConst mc = make_mv_const(d);
+  if (kh == 1)
+    hipLaunchKernelGGL(matvec_tile_kernel<1>, dim3((unsigned)grid), dim3(kMvThreads), lds, s, d, tl, mc, atab, x, y);
+  else if (kh == 2)
+    hipLaunchKernelGGL(matvec_tile_kernel<2>, dim3((unsigned)grid), dim3(kMvThreads), lds, s, d, tl, mc, atab, x, y);
+  else
+    hipLaunchKernelGGL(matvec_tile_kernel<3>, dim3((unsigned)grid), dim3(kMvThreads), lds, s, d, tl, mc, atab, x, y);
   STKKT_HIP(hipGetLastError());
 }
 

@@ -44,7 +44,7 @@ void precond_apply(const kkt_op *op, const ras *R, const coarse *C, const double
   }
   // y = I_c^h F_c^{-1} I_h^c v;  z = y + M_one^{-1} (v - F_h y)
   coarse_apply_device(C, v, y, s);
-  matvec_device(op->d, op->atab.as<double>(), y, t, s);
+  matvec_device(op, y, t, s);
   axpby(t, 1.0, v, -1.0, t, n, s);
   ras_apply_device(R, t, z, s);
   axpby(z, 1.0, z, 1.0, y, n, s);
@@ -94,7 +94,7 @@ int gmres_solve(const kkt_op *op, const ras *R, const coarse *C, const solve_par
   }
   const double target = sp.rtol * bnorm;
   const int limit = sp.fixed_iters > 0 ? sp.fixed_iters : sp.maxit;
-  matvec_device(op->d, op->atab.as<double>(), x, t, s);
+  matvec_device(op, x, t, s);
   axpby(r, 1.0, b, -1.0, t, n, s);
   double beta = std::sqrt(dot(r, r));
   stats.rel_res_true = beta / bnorm;
@@ -123,7 +123,7 @@ int gmres_solve(const kkt_op *op, const ras *R, const coarse *C, const solve_par
       const double *vj = Vd + (long long)j * n;
       double *zj = flex ? Zd + (long long)j * n : u;
       precond(vj, zj);
-      matvec_device(op->d, op->atab.as<double>(), zj, w, s);
+      matvec_device(op, zj, w, s);
       multidot(Vd, n, j + 1, w, n, partial.as<double>(), hd, s);
       gs_update(w, Vd, n, j + 1, hd, n, s);
       multidot(Vd, n, j + 1, w, n, partial.as<double>(), hd + (m + 1), s);
@@ -183,7 +183,7 @@ int gmres_solve(const kkt_op *op, const ras *R, const coarse *C, const solve_par
       precond(u, t);
       axpby(x, 1.0, x, 1.0, t, n, s);
     }
-    matvec_device(op->d, op->atab.as<double>(), x, t, s);
+    matvec_device(op, x, t, s);
     axpby(r, 1.0, b, -1.0, t, n, s);
     beta = std::sqrt(dot(r, r));
     stats.rel_res_est = std::fabs(g[k]) / bnorm;
