@@ -22,6 +22,5 @@ decomposition methods for unsteady inverse problems", arXiv:1508.06103):
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The GPU product path never does.
-Where the paper is silent or garbled the readings used here are listed in
-the design doc of the repository.
+Where the paper is silent or garbled, each module states the reading it takes.
 """

@@ -26,5 +26,5 @@ def cached_problem(name, **kw):
 
 
 @pytest.fixture(scope="session")
-def cfg0():
-    return cached_problem("cfg0")
+def cube8x16():
+    return cached_problem("cube8x16")

@@ -24,8 +24,8 @@ def _say(msg):
 @pytest.fixture(scope="module")
 def full():
     import paper_1508_06103_amd as st
-    prob, cfg = make_problem("cfg1")
-    _say(f"cfg1: {prob.unknowns} unknowns; setting up on the GPU")
+    prob, cfg = make_problem("cube32x64")
+    _say(f"cube32x64: {prob.unknowns} unknowns; setting up on the GPU")
     op = st.KKTOperator(prob)
     pre = st.RAS(op, cfg.parts, cfg.overlap)
     torch.cuda.synchronize()
@@ -81,7 +81,7 @@ def test_fullsize_solve_true_residual(full):
     xh = x.cpu().numpy()
     b = kkt.rhs(prob)
     res = np.linalg.norm(b - kkt.apply_terms(terms, xh)) / np.linalg.norm(b)
-    _say(f"  cfg1 solve: {s.iters} its, {s.ms:.0f} ms, gpu res {s.rel_res_true:.2e}, oracle res {res:.2e}")
+    _say(f"  cube32x64 solve: {s.iters} its, {s.ms:.0f} ms, gpu res {s.rel_res_true:.2e}, oracle res {res:.2e}")
     assert s.converged and res <= 1e-6 * (1 + 1e-6)
     # deterministic: a second solve is bit-identical
     x2, s2 = st.solve(op, pre, restart=cfg.restart, rtol=cfg.rtol)

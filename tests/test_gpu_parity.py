@@ -29,7 +29,7 @@ def st():
 
 
 SMALL = [
-    ("cfg0", None),
+    ("cube8x16", None),
     ("ragged", dict(n=(5, 6, 7), M=9, seed=3, lattice=2)),
     ("aniso_otd", dict(n=(7, 3, 4), M=6, seed=4, lattice=2, variant=OTD, faces=0b010011)),
     ("neumann_all", dict(n=(4, 4, 4), M=5, seed=5, lattice=2, faces=0)),
@@ -41,7 +41,7 @@ SMALL = [
 def small_problem(name):
     spec = dict(SMALL)[name]
     if spec is None:
-        return make_problem("cfg0")[0]
+        return make_problem("cube8x16")[0]
     spec = dict(spec)
     n, M, seed = spec.pop("n"), spec.pop("M"), spec.pop("seed")
     return make_custom(n, M, seed, **spec)
@@ -68,7 +68,7 @@ def test_rhs_and_matvec(st, name):
     assert err <= 1e-13
 
 
-@pytest.mark.parametrize("name,parts,delta", [("cfg0", (2, 2, 2, 2), 1), ("ragged", (2, 3, 2, 3), 1),
+@pytest.mark.parametrize("name,parts,delta", [("cube8x16", (2, 2, 2, 2), 1), ("ragged", (2, 3, 2, 3), 1),
                                               ("ragged", (3, 2, 3, 2), 2), ("aniso_otd", (2, 1, 2, 2), 1),
                                               ("neumann_all", (1, 2, 2, 1), 0), ("tall", (1, 1, 1, 1), 0),
                                               ("tall", (1, 1, 2, 2), 1)])
@@ -103,7 +103,7 @@ def test_boxes_factors_and_apply(st, name, parts, delta):
 
 
 def test_apply_f32_factors(st):
-    prob = small_problem("cfg0")
+    prob = small_problem("cube8x16")
     op = st.KKTOperator(prob)
     pre = st.RAS(op, (2, 2, 2, 2), 1, precision=st.F32)
     R = oras.RAS(prob, (2, 2, 2, 2), 1)
@@ -114,7 +114,7 @@ def test_apply_f32_factors(st):
     assert err <= 1e-3
 
 
-@pytest.mark.parametrize("name,parts,delta,restart", [("cfg0", (2, 2, 2, 2), 1, 30), ("ragged", (2, 3, 2, 3), 1, 20),
+@pytest.mark.parametrize("name,parts,delta,restart", [("cube8x16", (2, 2, 2, 2), 1, 30), ("ragged", (2, 3, 2, 3), 1, 20),
                                                       ("aniso_otd", (2, 1, 2, 2), 1, 25)])
 def test_solve_parity(st, name, parts, delta, restart):
     prob = small_problem(name)
@@ -145,10 +145,10 @@ def test_solve_parity(st, name, parts, delta, restart):
     assert e <= 1e-7
 
 
-def test_solve_recovers_source_cfg0(st):
+def test_solve_recovers_source_cube8x16(st):
     """The KKT solution's source equals the reduced-space minimiser of J_h."""
     from oracle import reduced
-    prob, cfg = make_problem("cfg0")
+    prob, cfg = make_problem("cube8x16")
     op = st.KKTOperator(prob)
     pre = st.RAS(op, cfg.parts, cfg.overlap)
     x, s = st.solve(op, pre, restart=cfg.restart, rtol=1e-10)
@@ -158,7 +158,7 @@ def test_solve_recovers_source_cfg0(st):
 
 
 def test_error_paths(st):
-    prob = small_problem("cfg0")
+    prob = small_problem("cube8x16")
     op = st.KKTOperator(prob)
     with pytest.raises(st.StkktError) as e:
         st.RAS(op, (20, 1, 1, 1), 1)
@@ -174,7 +174,7 @@ def test_error_paths(st):
 
 def test_handles_released_in_any_order(st):
     """A preconditioner may be released after its operator (garbage-collected cycles)."""
-    prob = small_problem("cfg0")
+    prob = small_problem("cube8x16")
     op = st.KKTOperator(prob)
     pre = st.RAS(op, (2, 2, 2, 2), 1)
     op.close()

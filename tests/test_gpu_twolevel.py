@@ -41,8 +41,8 @@ def _grid_sensors(n, fac, picks, faces=0b000011):
 
 
 def case(name):
-    if name == "cfg0":
-        return make_problem("cfg0")[0], (2, 2, 2, 2), (2, 2, 2, 2)
+    if name == "cube8x16":
+        return make_problem("cube8x16")[0], (2, 2, 2, 2), (2, 2, 2, 2)
     if name == "aniso":
         n, fac = (6, 6, 4), (3, 2, 2, 3)
         sens = _grid_sensors(n, fac, [(1, 0, 0), (1, 1, 1), (1, 2, 2), (1, 3, 1), (1, 1, 2)])
@@ -54,8 +54,8 @@ def case(name):
     raise KeyError(name)
 
 
-@pytest.mark.parametrize("name,restrict,rtol", [("cfg0", "transpose", 1e-12), ("cfg0", "transpose", 0.1),
-                                                ("cfg0", "injection", 1e-12), ("aniso", "transpose", 1e-12),
+@pytest.mark.parametrize("name,restrict,rtol", [("cube8x16", "transpose", 1e-12), ("cube8x16", "transpose", 0.1),
+                                                ("cube8x16", "injection", 1e-12), ("aniso", "transpose", 1e-12),
                                                 ("otd_neumann", "transpose", 0.1)])
 def test_coarse_correction(st, name, restrict, rtol):
     prob, fac, cparts = case(name)
@@ -75,10 +75,10 @@ def test_coarse_correction(st, name, restrict, rtol):
         assert err <= 1e-10
 
 
-@pytest.mark.parametrize("name,restart", [("cfg0", 30), ("aniso", 20)])
+@pytest.mark.parametrize("name,restart", [("cube8x16", 30), ("aniso", 20)])
 def test_two_level_fgmres_parity(st, name, restart):
     prob, fac, cparts = case(name)
-    parts = {"cfg0": (2, 2, 2, 2), "aniso": (2, 2, 1, 2)}[name]
+    parts = {"cube8x16": (2, 2, 2, 2), "aniso": (2, 2, 1, 2)}[name]
     _say(f"case {name}: two-level FGMRES({restart}), fine parts {parts}")
     op = st.KKTOperator(prob)
     pre = st.RAS(op, parts, 1)
@@ -124,7 +124,7 @@ def test_two_level_cuts_iterations(st):
 
 
 def test_coarse_errors(st):
-    prob, fac, cparts = case("cfg0")
+    prob, fac, cparts = case("cube8x16")
     op = st.KKTOperator(prob)
     with pytest.raises(st.StkktError) as e:
         st.Coarse(op, (3, 2, 2, 2), cparts)          # 3 does not divide 8

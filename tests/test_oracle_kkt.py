@@ -36,8 +36,8 @@ def test_dto_lagrangian_hessian_symmetric(shape):
     assert abs(H - H.T).max() <= 1e-15 * abs(F).max()
 
 
-def test_dto_hessian_symmetric_cfg0(cfg0):
-    prob, _ = cfg0
+def test_dto_hessian_symmetric_cube8x16(cube8x16):
+    prob, _ = cube8x16
     F = kkt.assemble(prob)
     H = F[slot_swap_perm(F.shape[0])]
     assert abs(H - H.T).max() <= 1e-15 * abs(F).max()
@@ -71,8 +71,8 @@ def test_dto_matches_reduced_cg(shape):
     assert np.linalg.norm(f_kkt - f_cg) <= 1e-8 * np.linalg.norm(f_cg)
 
 
-def test_dto_matches_reduced_cg_cfg0(cfg0):
-    prob, s = cfg0
+def test_dto_matches_reduced_cg_cube8x16(cube8x16):
+    prob, s = cube8x16
     terms = kkt.kkt_terms(prob)
     F = kkt.assemble(prob, terms=terms)
     b = kkt.rhs(prob)

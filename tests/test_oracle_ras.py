@@ -13,7 +13,7 @@ def test_split_closed_form():
     assert ras.split(9, 2) == [0, 5, 9]
 
 
-def test_cfg1_boxes():
+def test_cube32x64_boxes():
     """32^3 x 64 with 4x4x4x8 parts and overlap 2: boxes of at most 12^4 nodes."""
     class P:  # only sizes matter
         nodes = (33, 33, 33)
@@ -36,7 +36,7 @@ def test_block_pattern_count_and_order():
             row = indices[indptr[i]:indptr[i + 1]]
             assert np.all(np.diff(row) > 0)
             assert np.all(np.diff(slots[indptr[i]:indptr[i + 1]]) > 0)
-    # whole cfg0 space-time box (9^3 nodes, 17 levels)
+    # whole cube8x16 space-time box (9^3 nodes, 17 levels)
     indptr, _, _ = ras.block_pattern((9, 9, 9, 17))
     assert indptr[-1] == 25 ** 3 * 49 == 765_625
 

@@ -285,14 +285,14 @@ def lattice_nodes(n, k):
 
 CONFIGS = {
     # tiny plain FP64 configuration (about 37k unknowns)
-    "cfg0": dict(n=8, M=16, seed=0, smooth_coef=False, nsrc=1, width=0.1, sin_int=False,
+    "cube8x16": dict(n=8, M=16, seed=0, smooth_coef=False, nsrc=1, width=0.1, sin_int=False,
                  starts=[[0.25, 0.25, 0.25]], ends=[[0.75, 0.75, 0.75]], lattice=3,
                  solver=SolverConfig(parts=(2, 2, 2, 2), overlap=1, restart=30)),
     # single-GPU FP64 configuration (7.0M unknowns)
-    "cfg1": dict(n=32, M=64, seed=1, smooth_coef=True, nsrc=2, width=0.08, sin_int=True, lattice=4,
+    "cube32x64": dict(n=32, M=64, seed=1, smooth_coef=True, nsrc=2, width=0.08, sin_int=True, lattice=4,
                  solver=SolverConfig(parts=(4, 4, 4, 8), overlap=2, restart=50)),
     # two-level mixed precision configuration (34M unknowns), coarse 12^3 x 24
-    "cfg2": dict(n=48, M=96, seed=2, smooth_coef=True, nsrc=2, width=0.08, sin_int=True, lattice=5,
+    "cube48x96": dict(n=48, M=96, seed=2, smooth_coef=True, nsrc=2, width=0.08, sin_int=True, lattice=5,
                  solver=SolverConfig(parts=(4, 4, 4, 8), overlap=1, restart=50, flexible=True,
                                      coarse_factor=(4, 4, 4, 4))),
 }
@@ -303,7 +303,7 @@ def config(name):
     return c
 
 
-def make_problem(name="cfg0", *, seed=None, n=None, M=None, keep_f=False, variant=DTO, **over):
+def make_problem(name="cube8x16", *, seed=None, n=None, M=None, keep_f=False, variant=DTO, **over):
     """Build the seeded Problem of a named configuration (optionally resized)."""
     c = dict(CONFIGS[name])
     c.update(over)
