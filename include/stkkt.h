@@ -197,6 +197,22 @@ int coarse_apply(const coarse_t *c, const double *x, double *y, void *stream);
 int kkt_solve(const kkt_op_t *op, const ras_t *ras, const coarse_t *coarse, const solve_params_t *sp,
               const double *b, double *x, void *stream, kkt_stats_t *stats);
 
+/* Solve `count` independent systems F_i x_i = b_i together (batched
+ * instances): every instance runs restarted FGMRES(restart) right-preconditioned
+ * by its one-level RAS (Section 3.2; FGMRES as in Section 4), with its own
+ * relative tolerance test, and all instances' device work is issued as one
+ * launch per step (preconditioner over the (instance, subdomain) work list,
+ * matvec over the (instance, tile) work list, per-instance CGS2 reductions).
+ * ops[i], ras[i]: handles (ras[i] built on ops[i]); b[i], x[i]: device vectors
+ * of kkt_size(ops[i]) doubles, x[i] holding x0 on entry and the iterate on exit.
+ * sp->flexible is ignored (always FGMRES).  An instance's result does not
+ * depend on the other members of the batch.  Device workspace for the
+ * concatenated Krylov vectors comes from ops[0]'s allocator.  stats: `count`
+ * entries or NULL.  Returns the most severe status over the instances;
+ * synchronises `stream`. */
+int kkt_solve_batch(int32_t count, const kkt_op_t *const *ops, const ras_t *const *ras, const solve_params_t *sp,
+                    const double *const *b, double *const *x, void *stream, kkt_stats_t *stats);
+
 void kkt_op_destroy(kkt_op_t *op);
 void ras_destroy(ras_t *ras);
 void coarse_destroy(coarse_t *c);

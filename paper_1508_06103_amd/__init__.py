@@ -93,6 +93,9 @@ _sig = {
     "coarse_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "kkt_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_SolveParams), _vp, _vp, _vp,
                                  ctypes.POINTER(_Stats)]),
+    "kkt_solve_batch": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                       ctypes.POINTER(_SolveParams), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp,
+                                       ctypes.POINTER(_Stats)]),
     "kkt_op_destroy": (None, [_vp]),
     "ras_destroy": (None, [_vp]),
     "coarse_destroy": (None, [_vp]),
@@ -356,3 +359,30 @@ def solve(op: KKTOperator, ras: RAS, b=None, x=None, *, coarse: Coarse = None, r
         _check(rc, allow=(OK, NOT_CONVERGED))
     return x, SolveStats(st.iters, st.restarts, bool(st.converged), st.status, st.rel_res_est, st.rel_res_true,
                          st.bnorm, st.t_ms[0])
+
+
+def _to_stats(st):
+    return SolveStats(st.iters, st.restarts, bool(st.converged), st.status, st.rel_res_est, st.rel_res_true,
+                      st.bnorm, st.t_ms[0])
+
+
+def solve_batch(ops, pres, bs=None, xs=None, *, restart=30, rtol=1e-6, maxit=10000, fixed_iters=0, stream=None,
+                raise_on_fail=True):
+    """Solve F_i x_i = b_i for every instance together (batched FGMRES); x_i holds x0 on entry."""
+    torch = _torch()
+    count = len(ops)
+    if count == 0 or len(pres) != count:
+        raise ValueError("solve_batch: need one preconditioner per operator")
+    bs = [op.b for op in ops] if bs is None else list(bs)
+    xs = [torch.zeros_like(b) for b in bs] if xs is None else list(xs)
+    arr = _vp * count
+    h_ops = arr(*[op.handle for op in ops])
+    h_ras = arr(*[p.handle for p in pres])
+    h_b = arr(*[_ptr(b) for b in bs])
+    h_x = arr(*[_ptr(x) for x in xs])
+    sp = _SolveParams(int(restart), int(maxit), float(rtol), 1, int(fixed_iters))
+    st = (_Stats * count)()
+    rc = _lib.kkt_solve_batch(count, h_ops, h_ras, ctypes.byref(sp), h_b, h_x, _stream(stream), st)
+    if raise_on_fail:
+        _check(rc, allow=(OK, NOT_CONVERGED))
+    return xs, [_to_stats(st[i]) for i in range(count)]

@@ -234,6 +234,24 @@ int kkt_solve(const kkt_op_t *op, const ras_t *R, const coarse_t *C, const solve
   });
 }
 
+int kkt_solve_batch(int32_t count, const kkt_op_t *const *ops, const ras_t *const *ras, const solve_params_t *sp,
+                    const double *const *b, double *const *x, void *stream, kkt_stats_t *stats) {
+  return guarded([&] {
+    STKKT_REQUIRE(count >= 1 && ops && ras && sp && b && x, "kkt_solve_batch: NULL argument or empty batch");
+    STKKT_REQUIRE(sp->restart >= 1 && sp->restart <= 1000, "kkt_solve_batch: restart must be in [1, 1000]");
+    STKKT_REQUIRE(sp->maxit >= 1 || sp->fixed_iters > 0, "kkt_solve_batch: maxit must be >= 1");
+    STKKT_REQUIRE(sp->rtol > 0 && sp->rtol < 1, "kkt_solve_batch: rtol must be in (0, 1)");
+    STKKT_REQUIRE(sp->fixed_iters >= 0, "kkt_solve_batch: fixed_iters must be >= 0");
+    std::set<const kkt_op *> seen;
+    for (int i = 0; i < count; ++i) {
+      STKKT_REQUIRE(ops[i] && ras[i] && b[i] && x[i], "kkt_solve_batch: NULL entry");
+      STKKT_REQUIRE(ras[i]->op == ops[i], "kkt_solve_batch: preconditioner built for another operator");
+      STKKT_REQUIRE(b[i] != x[i], "kkt_solve_batch: b and x must not alias");
+    }
+    return gmres_solve_batch(count, ops, ras, *sp, b, x, as_stream(stream), stats);
+  });
+}
+
 void kkt_op_destroy(kkt_op_t *op) { delete op; }
 void ras_destroy(ras_t *R) { delete R; }
 void coarse_destroy(coarse_t *c) { coarse_free(c); }

@@ -33,6 +33,8 @@ struct GmresWork {
   bool fits(long long n, int m, bool flex, bool two_level) const;
 };
 
+int gmres_solve_batch(int count, const kkt_op *const *ops, const ras *const *R, const solve_params_t &sp,
+                      const double *const *b, double *const *x, hipStream_t s, kkt_stats_t *stats);
 void coarse_apply_device(const coarse *C, const double *x, double *y, hipStream_t s);
 coarse *coarse_create(const kkt_op *fine, const coarse_params_t *cp, hipStream_t s);
 void coarse_free(coarse *c);

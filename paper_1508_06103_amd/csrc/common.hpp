@@ -109,10 +109,41 @@ inline int blocks_for(long long n, int threads, int cap = 1 << 20) {
   if (b < 1) b = 1;
   return static_cast<int>(b);
 }
+// Read-only tables indexed by wave-uniform values are read through the
+// constant address space, which lets the compiler use scalar loads (waited on
+// with lgkmcnt) instead of vector loads that would drain the in-order vmcnt
+// counter and with it every prefetch in flight.
+template <class V> using cptr = const __attribute__((address_space(4))) V *;
+template <class V> __device__ inline cptr<V> as_const(const V *p) { return (cptr<V>)p; }
+
+// Copy a table entry (a struct of 32-bit words) through scalar loads.
+template <class S> __device__ inline S load_uniform(const S *p) {
+  static_assert(sizeof(S) % 4 == 0, "word-sized struct expected");
+  S out;
+  cptr<int32_t> src = (cptr<int32_t>)p;
+  int32_t *dst = reinterpret_cast<int32_t *>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) dst[i] = src[i];
+  return out;
+}
+
 kkt_op *op_create(const kkt_problem_t *p, const kkt_alloc_t *al, hipStream_t s);
 void rhs_device(const kkt_op *op, const double *data_host, hipStream_t s, double *b);
 void fill_zero(double *p, long long n, hipStream_t s);
 void stiff_table(const OpDev &d, double *tab, hipStream_t s);
 MvTile choose_matvec_tile(const OpDev &d);
 void matvec_device(const kkt_op *op, const double *x, double *y, hipStream_t s);
+// Batched matvec over operators whose vectors are concatenated: operator i
+// reads x[voff_i ...] and writes y[voff_i ...]; one launch for all of them,
+// operators with act[i] == 0 (device flags) skipped.
+struct MvBatch {
+  DevBuf desc;
+  int count = 0;
+  long long items = 0;
+  int kh = 1;
+  size_t lds = 0;
+};
+void matvec_batch_prepare(const kkt_op *const *ops, const long long *voff, int count, const Allocator *al,
+                          MvBatch &out, hipStream_t s);
+void matvec_batch_run(const MvBatch &b, const double *x, double *y, const int *act, hipStream_t s);
 }  // namespace stkkt

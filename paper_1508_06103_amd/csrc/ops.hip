@@ -114,6 +114,17 @@ struct MvConst {
   double ht, inv_tau, tau6, tau3, beta1, beta2;
 };
 
+// One operator of a batched matvec: its vectors start at element voff of the
+// batch's concatenated vectors.
+struct MvBatchDesc {
+  OpDev op;
+  MvTile tl;
+  MvConst mc;
+  const double *atab;
+  int64_t voff;
+  int32_t w0, nw;
+};
+
 MvConst make_mv_const(const OpDev &d) {
   MvConst c{};
   for (int a = 0; a < 3; ++a) {
@@ -152,17 +163,21 @@ __device__ inline Centre axis_centre(const MvConst &mc, int a, int i, int nn) {
   return r;
 }
 
-template <int KH>
-__global__ void __launch_bounds__(kMvThreads) matvec_tile_kernel(OpDev op, MvTile tl, MvConst mc,
-                                                                 const double *__restrict__ Atab,
-                                                                 const double *__restrict__ x,
-                                                                 double *__restrict__ y) {
-  // per halo node: {U1, S1}, {U2, S2}, {U3, T3} side by side (48 B)
-  extern __shared__ double2 mv_lds[];
-  // consecutive work items on the same XCD (blocks are dealt to the 8 XCDs round robin)
+// Work item of this block such that consecutive work items run on the same
+// XCD (the dispatcher deals blocks to the 8 XCDs round robin).
+__device__ inline int xcd_work_index() {
   const int G = gridDim.x, b = blockIdx.x;
   const int q = G >> 3, r = G & 7, xcd = b & 7;
-  const int w = xcd * q + min(xcd, r) + (b >> 3);
+  return xcd * q + min(xcd, r) + (b >> 3);
+}
+
+// One (tile, time chunk) work item w of one operator.
+template <int KH>
+__device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const MvConst &mc,
+                                        const double *__restrict__ Atab, const double *__restrict__ x,
+                                        double *__restrict__ y, int w) {
+  // per halo node: {U1, S1}, {U2, S2}, {U3, T3} side by side (48 B)
+  extern __shared__ double2 mv_lds[];
   const int tile = w % tl.ntiles, chunk = w / tl.ntiles;
   const int M = op.M;
   const int n0 = chunk * tl.clen, n1 = min(n0 + tl.clen, M + 1);
@@ -351,6 +366,30 @@ __global__ void __launch_bounds__(kMvThreads) matvec_tile_kernel(OpDev op, MvTil
   }
 }
 
+template <int KH>
+__global__ void __launch_bounds__(kMvThreads) matvec_tile_kernel(OpDev op, MvTile tl, MvConst mc,
+                                                                 const double *__restrict__ Atab,
+                                                                 const double *__restrict__ x,
+                                                                 double *__restrict__ y) {
+  matvec_tile_body<KH>(op, tl, mc, Atab, x, y, xcd_work_index());
+}
+
+// Batched form: the work items of all operators in one grid, operator i
+// owning [w0_i, w0_i + nw_i).
+template <int KH>
+__global__ void __launch_bounds__(kMvThreads) matvec_batch_kernel(const MvBatchDesc *__restrict__ descs, int count,
+                                                                  const int *__restrict__ act,
+                                                                  const double *__restrict__ x,
+                                                                  double *__restrict__ y) {
+  const int w = xcd_work_index();
+  cptr<MvBatchDesc> cd = as_const(descs);
+  int i = 0;
+  while (i + 1 < count && cd[i + 1].w0 <= w) ++i;
+  if (!as_const(act)[i]) return;
+  const MvBatchDesc d = load_uniform(descs + i);
+  matvec_tile_body<KH>(d.op, d.tl, d.mc, d.atab, x + d.voff, y + d.voff, w - d.w0);
+}
+
 }  // namespace
 
 MvTile choose_matvec_tile(const OpDev &d) {
@@ -397,6 +436,44 @@ void matvec_device(const kkt_op *op, const double *x, double *y, hipStream_t s) 
     hipLaunchKernelGGL(matvec_tile_kernel<2>, dim3((unsigned)grid), dim3(kMvThreads), lds, s, d, tl, mc, atab, x, y);
   else
     hipLaunchKernelGGL(matvec_tile_kernel<3>, dim3((unsigned)grid), dim3(kMvThreads), lds, s, d, tl, mc, atab, x, y);
+  STKKT_HIP(hipGetLastError());
+}
+
+void matvec_batch_prepare(const kkt_op *const *ops, const long long *voff, int count, const Allocator *al,
+                          MvBatch &out, hipStream_t s) {
+  std::vector<MvBatchDesc> d(count);
+  long long w = 0;
+  int halo = 0;
+  for (int i = 0; i < count; ++i) {
+    d[i].op = ops[i]->d;
+    d[i].tl = ops[i]->mv;
+    d[i].mc = make_mv_const(ops[i]->d);
+    d[i].atab = ops[i]->atab.as<double>();
+    d[i].voff = voff[i];
+    d[i].w0 = (int32_t)w;
+    d[i].nw = ops[i]->mv.ntiles * ops[i]->mv.nchunks;
+    w += d[i].nw;
+    halo = std::max(halo, ops[i]->mv.halo);
+  }
+  STKKT_REQUIRE(w <= INT32_MAX, "batched matvec: too many work items");
+  out.desc = DevBuf(al, sizeof(MvBatchDesc) * (size_t)count);
+  STKKT_HIP(hipMemcpyAsync(out.desc.ptr, d.data(), sizeof(MvBatchDesc) * (size_t)count, hipMemcpyHostToDevice, s));
+  STKKT_HIP(hipStreamSynchronize(s));   // d is released on return
+  out.count = count;
+  out.items = w;
+  out.lds = sizeof(double2) * 3 * (size_t)halo;
+  out.kh = (halo + kMvThreads - 1) / kMvThreads;
+}
+
+void matvec_batch_run(const MvBatch &b, const double *x, double *y, const int *act, hipStream_t s) {
+  const MvBatchDesc *dd = b.desc.as<MvBatchDesc>();
+  const dim3 grid((unsigned)b.items);
+  if (b.kh == 1)
+    hipLaunchKernelGGL(matvec_batch_kernel<1>, grid, dim3(kMvThreads), b.lds, s, dd, b.count, act, x, y);
+  else if (b.kh == 2)
+    hipLaunchKernelGGL(matvec_batch_kernel<2>, grid, dim3(kMvThreads), b.lds, s, dd, b.count, act, x, y);
+  else
+    hipLaunchKernelGGL(matvec_batch_kernel<3>, grid, dim3(kMvThreads), b.lds, s, dd, b.count, act, x, y);
   STKKT_HIP(hipGetLastError());
 }
 

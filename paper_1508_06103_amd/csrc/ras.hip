@@ -29,24 +29,6 @@ namespace {
 constexpr int kApplyThreads = 512;
 constexpr size_t kRingLdsLimit = 160 * 1024;   // LDS of one gfx950 workgroup
 
-// Read-only tables indexed by wave-uniform values are read through the
-// constant address space, which lets the compiler use scalar loads (waited on
-// with lgkmcnt) instead of vector loads that would drain the in-order vmcnt
-// counter and with it every prefetch in flight.
-template <class V> using cptr = const __attribute__((address_space(4))) V *;
-template <class V> __device__ inline cptr<V> as_const(const V *p) { return (cptr<V>)p; }
-
-// Copy a table entry (a struct of 32-bit words) through scalar loads.
-template <class S> __device__ inline S load_uniform(const S *p) {
-  static_assert(sizeof(S) % 4 == 0, "word-sized struct expected");
-  S out;
-  cptr<int32_t> src = (cptr<int32_t>)p;
-  int32_t *dst = reinterpret_cast<int32_t *>(&out);
-#pragma unroll
-  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) dst[i] = src[i];
-  return out;
-}
-
 __host__ __device__ inline void slot_off(int s, int &dx, int &dy, int &dz, int &dt) {
   dx = s % 3 - 1;
   dy = (s / 3) % 3 - 1;
@@ -840,12 +822,14 @@ __device__ inline void sweep_ring(const SweepArgs<T> &a, cptr<int32_t> tzp, T (*
   }
 }
 
+// Both sweeps of subdomain `sub` with the values of the last 16 levels in LDS.
 template <typename T>
-__global__ void __launch_bounds__(kApplyThreads, 2) apply_ring_kernel(
-    OpDev op, const SubInfo *__restrict__ subs, const int32_t *__restrict__ order,
-    const ShapeInfo *__restrict__ shapes, const int32_t *__restrict__ lvl_start,
-    const uint64_t *__restrict__ coords, const int32_t *__restrict__ ctab, const int32_t *__restrict__ tzpref, const T *__restrict__ F, T *__restrict__ Y, int64_t fzero, int64_t yzero,
-    Ring rg, const double *__restrict__ r, double *__restrict__ z) {
+__device__ inline void apply_ring_sub(const OpDev &op, const SubInfo *__restrict__ subs, int sub,
+                                      const ShapeInfo *__restrict__ shapes, const int32_t *__restrict__ lvl_start,
+                                      const uint64_t *__restrict__ coords, const int32_t *__restrict__ ctab,
+                                      const int32_t *__restrict__ tzpref, const T *__restrict__ F,
+                                      T *__restrict__ Y, int64_t fzero, int64_t yzero, const Ring &rg,
+                                      const double *__restrict__ r, double *__restrict__ z) {
   extern __shared__ __align__(16) unsigned char smem[];
   T(*part)[kRows][3] = reinterpret_cast<T(*)[kRows][3]>(smem);
   uint64_t *crd2 = reinterpret_cast<uint64_t *>(smem + sizeof(T) * kWaves * kRows * 3);
@@ -853,7 +837,6 @@ __global__ void __launch_bounds__(kApplyThreads, 2) apply_ring_kernel(
   int32_t *tzr = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(yring) +
                                              sizeof(T) * (size_t)16 * rg.rmax * 3);
   SweepArgs<T> a;
-  const int sub = as_const(order)[blockIdx.x];
   a.sd = load_uniform(subs + sub);
   a.sh = load_uniform(shapes + a.sd.shape);
   a.op = op;
@@ -873,6 +856,48 @@ __global__ void __launch_bounds__(kApplyThreads, 2) apply_ring_kernel(
   sweep_ring<T, true>(a, tzp, part, crd2, yring, tzr, rl);
   __syncthreads();   // forward results in global memory are read by the backward sweep
   sweep_ring<T, false>(a, tzp, part, crd2, yring, tzr, rl);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kApplyThreads, 2) apply_ring_kernel(
+    OpDev op, const SubInfo *__restrict__ subs, const int32_t *__restrict__ order,
+    const ShapeInfo *__restrict__ shapes, const int32_t *__restrict__ lvl_start,
+    const uint64_t *__restrict__ coords, const int32_t *__restrict__ ctab, const int32_t *__restrict__ tzpref, const T *__restrict__ F, T *__restrict__ Y, int64_t fzero, int64_t yzero,
+    Ring rg, const double *__restrict__ r, double *__restrict__ z) {
+  const int sub = as_const(order)[blockIdx.x];
+  apply_ring_sub<T>(op, subs, sub, shapes, lvl_start, coords, ctab, tzpref, F, Y, fzero, yzero, rg, r, z);
+}
+
+// One preconditioner of a batched application; its vectors start at element
+// voff of the batch's concatenated r and z.
+template <typename T>
+struct RasBatchDesc {
+  OpDev op;
+  const SubInfo *subs;
+  const ShapeInfo *shapes;
+  const int32_t *lvl;
+  const uint64_t *coords;
+  const int32_t *ctab;
+  const int32_t *tz;
+  const T *F;
+  T *Y;
+  int64_t fzero, yzero, voff;
+  Ring rg;
+};
+
+// Work list entry (preconditioner, subdomain), ordered largest box first
+// over the whole batch.
+template <typename T>
+__global__ void __launch_bounds__(kApplyThreads, 2) apply_ring_batch_kernel(const RasBatchDesc<T> *__restrict__ descs,
+                                                                            const int2 *__restrict__ work,
+                                                                            const int *__restrict__ act,
+                                                                            const double *__restrict__ r,
+                                                                            double *__restrict__ z) {
+  const int2 wk = load_uniform(work + blockIdx.x);
+  if (!as_const(act)[wk.x]) return;
+  const RasBatchDesc<T> d = load_uniform(descs + wk.x);
+  apply_ring_sub<T>(d.op, d.subs, wk.y, d.shapes, d.lvl, d.coords, d.ctab, d.tz, d.F, d.Y, d.fzero, d.yzero, d.rg,
+                    r + d.voff, z + d.voff);
 }
 
 }  // namespace
@@ -915,6 +940,82 @@ bool ras_uses_ring(const ras *R) {
 void ras_apply_device(const ras *R, const double *r, double *z, hipStream_t s) {
   if (R->params.precision == STKKT_F32) launch_apply<float>(R, r, z, s);
   else launch_apply<double>(R, r, z, s);
+  STKKT_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void ras_batch_prepare_t(const ras *const *R, const long long *voff, int count, const Allocator *al,
+                                RasBatch &out, hipStream_t s) {
+  std::vector<RasBatchDesc<T>> d(count);
+  std::vector<std::pair<int64_t, int2>> items;
+  size_t lds = 0;
+  for (int i = 0; i < count; ++i) {
+    const ras *q = R[i];
+    d[i].op = q->d;
+    d[i].subs = q->d_subs.as<SubInfo>();
+    d[i].shapes = q->d_shapes.as<ShapeInfo>();
+    d[i].lvl = q->d_lvl.as<int32_t>();
+    d[i].coords = q->d_coords.as<uint64_t>();
+    d[i].ctab = q->d_ctab.as<int32_t>();
+    d[i].tz = q->d_tz.as<int32_t>();
+    d[i].F = q->factors.as<T>();
+    d[i].Y = q->scratch.as<T>();
+    d[i].fzero = 9 * q->total_blocks;
+    d[i].yzero = q->scratch_elems;
+    d[i].voff = voff[i];
+    d[i].rg = Ring{q->ring_rmax, q->ring_ltlz};
+    lds = std::max(lds, ring_lds_bytes<T>(q));
+    for (int k = 0; k < q->nsub; ++k)
+      items.push_back({q->shapes[q->subs[k].shape].nblocks, make_int2(i, k)});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+  std::vector<int2> work(items.size());
+  for (size_t k = 0; k < items.size(); ++k) work[k] = items[k].second;
+  out.desc = DevBuf(al, sizeof(RasBatchDesc<T>) * (size_t)count);
+  out.work = DevBuf(al, sizeof(int2) * work.size());
+  STKKT_HIP(hipMemcpyAsync(out.desc.ptr, d.data(), sizeof(RasBatchDesc<T>) * (size_t)count, hipMemcpyHostToDevice, s));
+  STKKT_HIP(hipMemcpyAsync(out.work.ptr, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, s));
+  STKKT_HIP(hipStreamSynchronize(s));   // host staging is released on return
+  out.blocks = (int)work.size();
+  out.lds = lds;
+}
+
+void ras_batch_prepare(const ras *const *R, const long long *voff, int count, const Allocator *al, RasBatch &out,
+                       hipStream_t s) {
+  out.count = count;
+  out.precision = R[0]->params.precision;
+  out.ring = true;
+  for (int i = 0; i < count; ++i) {
+    out.ring = out.ring && ras_uses_ring(R[i]) && R[i]->params.precision == out.precision;
+    out.members.push_back(R[i]);
+    out.voff.push_back(voff[i]);
+  }
+  if (!out.ring) return;   // per-preconditioner launches
+  if (out.precision == STKKT_F32) ras_batch_prepare_t<float>(R, voff, count, al, out, s);
+  else ras_batch_prepare_t<double>(R, voff, count, al, out, s);
+}
+
+template <typename T>
+static void ras_batch_launch(const RasBatch &b, const double *r, double *z, const int *act, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_ring_batch_kernel<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRingLdsLimit));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((apply_ring_batch_kernel<T>), dim3(b.blocks), dim3(kApplyThreads), b.lds, s,
+                     b.desc.as<RasBatchDesc<T>>(), b.work.as<int2>(), act, r, z);
+}
+
+void ras_batch_run(const RasBatch &b, const double *r, double *z, const int *act, const int *act_host,
+                   hipStream_t s) {
+  if (!b.ring) {
+    for (int i = 0; i < b.count; ++i)
+      if (act_host[i]) ras_apply_device(b.members[i], r + b.voff[i], z + b.voff[i], s);
+    return;
+  }
+  if (b.precision == STKKT_F32) ras_batch_launch<float>(b, r, z, act, s);
+  else ras_batch_launch<double>(b, r, z, act, s);
   STKKT_HIP(hipGetLastError());
 }
 

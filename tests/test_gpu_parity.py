@@ -180,3 +180,42 @@ def test_handles_released_in_any_order(st):
     op.close()
     pre.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name,parts,delta,two_level", [("cube8x16", (2, 2, 2, 2), 1, False),
+                                                         ("ragged", (2, 3, 2, 3), 1, False),
+                                                         ("cube8x16", (2, 2, 2, 2), 1, True)])
+def test_mixed_precision_solve(st, name, parts, delta, two_level):
+    """FP32 ILU factors and local solves inside FP64 FGMRES.
+
+    At rtol 1e-6 the FP64 true residual must be <= 1e-6 and the error in C and f
+    (relative L2 against the exact discrete solution) no worse than 3x that of
+    the FP64 oracle solve at the same tolerance (a 1e-6 residual bounds the
+    error only up to the condition number: the FP64 method itself is at
+    1.2e-5 in f on the ragged case).  At rtol 1e-8, C and f are within 1e-5.
+    """
+    import scipy.sparse.linalg as spla
+    prob = small_problem(name)
+    _say(f"case {name}: mixed precision, two-level={two_level}")
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, parts, delta, precision=st.F32)
+    C = st.Coarse(op, (2, 2, 2, 2), (2, 2, 2, 2), precision=st.F32) if two_level else None
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms).tocsc()
+    b = kkt.rhs(prob)
+    xs = spla.spsolve(F, b)
+    rel = lambda v, c: np.linalg.norm(v[c::3] - xs[c::3]) / np.linalg.norm(xs[c::3])
+    R = oras.RAS(prob, parts, delta, terms=terms)
+    xo, _ = krylov.gmres(lambda v: F @ v, R.apply, b, restart=30, rtol=1e-6, flexible=True)
+    for rtol in (1e-6, 1e-8):
+        x, s = st.solve(op, pre, coarse=C, restart=30, rtol=rtol, flexible=True)
+        xg = x.cpu().numpy()
+        res = np.linalg.norm(b - F @ xg) / np.linalg.norm(b)
+        eC, ef = rel(xg, 0), rel(xg, 2)
+        _say(f"  rtol {rtol:g}: {s.iters} its, true res {res:.2e}, C err {eC:.2e}, f err {ef:.2e} "
+             f"(FP64 oracle at 1e-6: C {rel(xo, 0):.2e}, f {rel(xo, 2):.2e})")
+        assert s.converged and res <= rtol
+        if rtol == 1e-6:
+            assert eC <= 3 * max(rel(xo, 0), 1e-7) and ef <= 3 * max(rel(xo, 2), 1e-7)
+        else:
+            assert eC <= 1e-5 and ef <= 1e-5

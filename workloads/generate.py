@@ -339,13 +339,20 @@ def make_custom(n, M, seed, *, sensors=None, lattice=2, nsrc=1, width=0.15, smoo
                  length=length, T=T)
 
 
-def batch_instances(count=64, base_seed=3000):
-    """Uneven batch: n in {8..24}, M in {16..48}, 1-3 sources, 27-64 sensors."""
+def batch_instances(count=64, base_seed=3000, max_n=None, max_M=None):
+    """Uneven batch: n in {8..24}, M in {16..48}, 1-3 sources, 27-64 sensors.
+
+    max_n / max_M clamp the drawn sizes (small stand-ins for tests); every
+    other draw is unchanged."""
     out = []
     for i in range(count):
         rng = np.random.default_rng(base_seed + i)
         n = int(rng.choice([8, 12, 16, 20, 24]))
         M = int(rng.choice([16, 24, 32, 48]))
+        if max_n is not None:
+            n = min(n, int(max_n))
+        if max_M is not None:
+            M = min(M, int(max_M))
         nsrc = int(rng.integers(1, 4))
         s = int(rng.integers(27, 65))
         noise = float(rng.uniform(0.005, 0.02))
