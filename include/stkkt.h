@@ -213,6 +213,46 @@ int kkt_solve(const kkt_op_t *op, const ras_t *ras, const coarse_t *coarse, cons
 int kkt_solve_batch(int32_t count, const kkt_op_t *const *ops, const ras_t *const *ras, const solve_params_t *sp,
                     const double *const *b, double *const *x, void *stream, kkt_stats_t *stats);
 
+/* Request server (served stream).  Requests -- an operator with its
+ * preconditioner (and optionally a coarse level for the two-level method),
+ * plus new sensor data -- are queued by kkt_server_submit and, at each
+ * kkt_server_step, admitted first come first served while slots and device
+ * memory allow; every admitted request then advances by one FGMRES(restart)
+ * cycle together with the others (batched launches as in kkt_solve_batch), and
+ * finished requests are retired, their solution copied to the caller's x_out.
+ * Requests arriving while others run join at the next step (continuous
+ * batching).  F_h does not depend on the data: a request only forms b, and
+ * the factors of its operator stay on the device (the caller keeps handles
+ * alive until every request on them has finished).  A request's result does
+ * not depend on which other requests shared its steps. */
+typedef struct kkt_server kkt_server_t;
+typedef struct {
+  int32_t restart;          /* FGMRES cycle length                          */
+  int32_t maxit;            /* Arnoldi steps allowed per request            */
+  double rtol;              /* ||b - F x|| <= rtol ||b|| per request         */
+  int64_t device_bytes;     /* device memory for request state (half for the
+                               Krylov vectors, half for per-request buffers) */
+  int32_t max_active;       /* most requests advanced together              */
+} server_params_t;
+
+int kkt_server_create(const server_params_t *p, const kkt_alloc_t *al, void *stream, kkt_server_t **out);
+
+/* Queue a request.  data_host: [nt+1][n_sensors] (copied); x_out: device
+ * buffer of kkt_size(op) doubles receiving the solution (x0 = 0).  coarse may
+ * be NULL.  EINVAL if the request can never fit the server. */
+int kkt_server_submit(kkt_server_t *srv, const kkt_op_t *op, const ras_t *ras, const coarse_t *coarse,
+                      const double *data_host, double *x_out, int64_t *ticket);
+
+/* Admit, run one cycle, retire.  Reports the requests running and waiting. */
+int kkt_server_step(kkt_server_t *srv, int32_t *n_running, int32_t *n_pending);
+
+/* 1 and the request's stats when it has finished (then the ticket is
+ * forgotten), 0 while it waits or runs.  stats.t_ms[0] = submit-to-result
+ * latency, t_ms[1] = time waiting for admission. */
+int kkt_server_poll(kkt_server_t *srv, int64_t ticket, kkt_stats_t *stats);
+
+void kkt_server_destroy(kkt_server_t *srv);
+
 void kkt_op_destroy(kkt_op_t *op);
 void ras_destroy(ras_t *ras);
 void coarse_destroy(coarse_t *c);

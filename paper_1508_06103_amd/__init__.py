@@ -71,6 +71,11 @@ class _SolveParams(ctypes.Structure):
                 ("flexible", ctypes.c_int32), ("fixed_iters", ctypes.c_int32)]
 
 
+class _ServerParams(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64), ("max_active", ctypes.c_int32)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("rel_res_est", ctypes.c_double), ("rel_res_true", ctypes.c_double),
@@ -96,6 +101,12 @@ _sig = {
     "kkt_solve_batch": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                        ctypes.POINTER(_SolveParams), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp,
                                        ctypes.POINTER(_Stats)]),
+    "kkt_server_create": (ctypes.c_int, [ctypes.POINTER(_ServerParams), ctypes.POINTER(_Alloc), _vp,
+                                         ctypes.POINTER(_vp)]),
+    "kkt_server_submit": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_dp, _vp, ctypes.POINTER(ctypes.c_int64)]),
+    "kkt_server_step": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "kkt_server_poll": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.POINTER(_Stats)]),
+    "kkt_server_destroy": (None, [_vp]),
     "kkt_op_destroy": (None, [_vp]),
     "ras_destroy": (None, [_vp]),
     "coarse_destroy": (None, [_vp]),
@@ -386,3 +397,61 @@ def solve_batch(ops, pres, bs=None, xs=None, *, restart=30, rtol=1e-6, maxit=100
     if raise_on_fail:
         _check(rc, allow=(OK, NOT_CONVERGED))
     return xs, [_to_stats(st[i]) for i in range(count)]
+
+
+class Server:
+    """Request server: continuous batching of source-identification solves.
+
+    submit() queues a request (operator, preconditioner, optional coarse
+    level, new sensor data); step() admits what fits, advances every running
+    request by one FGMRES cycle and retires the finished ones; poll() returns
+    (x, stats) once a request is done.  stats.ms is the submit-to-result
+    latency.
+    """
+
+    def __init__(self, restart=50, maxit=10000, rtol=1e-6, device_bytes=8 << 30, max_active=64, stream=None,
+                 allocator=None):
+        self.alloc = allocator if allocator is not None else TorchAllocator()
+        self.stream = stream
+        p = _ServerParams(int(restart), int(maxit), float(rtol), int(device_bytes), int(max_active))
+        h = ctypes.c_void_p()
+        _check(_lib.kkt_server_create(ctypes.byref(p), ctypes.byref(self.alloc.struct), _stream(stream),
+                                      ctypes.byref(h)))
+        self.handle = h
+        _track(self)
+        self._out = {}
+        self._keep = {}
+
+    def submit(self, op, pre, data, coarse=None):
+        torch = _torch()
+        d = np.ascontiguousarray(data, dtype=np.float64)
+        x = torch.empty(op.n, dtype=torch.float64, device=self.alloc.device)
+        t = ctypes.c_int64()
+        _check(_lib.kkt_server_submit(self.handle, op.handle, pre.handle, coarse.handle if coarse is not None else None,
+                                      d.ctypes.data_as(_c_dp), _ptr(x), ctypes.byref(t)))
+        self._out[t.value] = x
+        self._keep[t.value] = (op, pre, coarse)   # handles must outlive the request
+        return t.value
+
+    def step(self):
+        r, q = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.kkt_server_step(self.handle, ctypes.byref(r), ctypes.byref(q)))
+        return r.value, q.value
+
+    def poll(self, ticket):
+        st = _Stats()
+        rc = _lib.kkt_server_poll(self.handle, int(ticket), ctypes.byref(st))
+        _check(rc, allow=(0, 1))
+        if rc == 0:
+            return None
+        self._keep.pop(ticket, None)
+        return self._out.pop(ticket), _to_stats(st)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.kkt_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if not _finalizing:
+            self.close()

@@ -22,8 +22,8 @@
 #include <cmath>
 #include <memory>
 
-#include "coarse.hpp"
-#include "ras.hpp"
+#include "batch.hpp"
+#include "krylov.hpp"
 
 namespace stkkt {
 
@@ -151,269 +151,442 @@ __global__ void __launch_bounds__(kBT) bcombine_kernel(double *__restrict__ x, c
   }
 }
 
-struct PinnedBuf {
-  void *p = nullptr;
-  explicit PinnedBuf(size_t bytes) {
-    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) p = nullptr;
-    if (!p) throw Error(STKKT_ENOMEM, "kkt_solve_batch: pinned host allocation failed");
-  }
-  ~PinnedBuf() {
-    if (p) (void)hipHostFree(p);
-  }
-  template <class T> T *as() const { return static_cast<T *>(p); }
-};
 
 }  // namespace
 
+
+PinnedBlock::PinnedBlock(size_t bytes) {
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) p = nullptr;
+  if (!p) throw Error(STKKT_ENOMEM, "batch: pinned host allocation failed");
+}
+
+PinnedBlock::~PinnedBlock() {
+  if (p) (void)hipHostFree(p);
+}
+
+BatchEngine::BatchEngine(const Allocator *al, const solve_params_t &sp, long long capacity, int slots,
+                         hipStream_t s)
+    : al_(al), sp_(sp), s_(s), cap_((capacity + 255) / 256 * 256), m_(sp.restart), hs_(2 * (sp.restart + 1) + 2),
+      slots_(slots) {
+  STKKT_REQUIRE(slots >= 1 && cap_ >= 256, "batch: empty engine");
+  const size_t m = (size_t)m_, N = (size_t)cap_;
+  V_ = DevBuf(al, sizeof(double) * (m + 1) * N);
+  Z_ = DevBuf(al, sizeof(double) * m * N);
+  B_ = DevBuf(al, sizeof(double) * N);
+  X_ = DevBuf(al, sizeof(double) * N);
+  R_ = DevBuf(al, sizeof(double) * N);
+  W_ = DevBuf(al, sizeof(double) * N);
+  T_ = DevBuf(al, sizeof(double) * N);
+  const long long max_chunks = cap_ / kChunk + slots;
+  partial_ = DevBuf(al, sizeof(double) * (m + 1) * (size_t)max_chunks);
+  hdev_ = DevBuf(al, sizeof(double) * (size_t)slots * hs_);
+  ydev_ = DevBuf(al, sizeof(double) * (size_t)slots * m);
+  chunks_ = DevBuf(al, sizeof(Chunk) * (size_t)max_chunks);
+  cfirst_ = DevBuf(al, sizeof(int) * (size_t)(slots + 1));
+  kcnt_ = DevBuf(al, sizeof(int) * (size_t)slots);
+  act_a_ = DevBuf(al, sizeof(int) * (size_t)slots);
+  act_b_ = DevBuf(al, sizeof(int) * (size_t)slots);
+  act_c_ = DevBuf(al, sizeof(int) * (size_t)slots);
+  hh_ = std::make_unique<PinnedBlock>(sizeof(double) * (size_t)slots * hs_);
+  hy_ = std::make_unique<PinnedBlock>(sizeof(double) * (size_t)slots * m);
+  hflags_ = std::make_unique<PinnedBlock>(sizeof(int) * 4 * (size_t)slots);
+  fill_zero(V_.as<double>(), (long long)((m + 1) * N), s);
+  fill_zero(Z_.as<double>(), (long long)(m * N), s);
+  fill_zero(B_.as<double>(), cap_, s);
+  fill_zero(X_.as<double>(), cap_, s);
+  fill_zero(R_.as<double>(), cap_, s);
+  fill_zero(W_.as<double>(), cap_, s);
+  fill_zero(T_.as<double>(), cap_, s);
+  free_[0] = cap_;
+}
+
+long long BatchEngine::free_elems() const {
+  long long f = 0;
+  for (auto &kv : free_) f += kv.second;
+  return f;
+}
+
+size_t BatchEngine::member_bytes(const kkt_op *op, const ras *R, const coarse *C) {
+  size_t b = ras_local_bytes(R);
+  if (C) b += 2 * sizeof(double) * 3 * (size_t)op->d.V;
+  return b;
+}
+
+int BatchEngine::admit(const kkt_op *op, const ras *R, const coarse *C) {
+  STKKT_REQUIRE(op && R && R->op == op, "batch: preconditioner built for another operator");
+  STKKT_REQUIRE(!C || coarse_built_for(C, op), "batch: coarse level built for another operator");
+  int slot = -1;
+  for (int i = 0; i < (int)slots_.size(); ++i)
+    if (!slots_[i].used) {
+      slot = i;
+      break;
+    }
+  if (slot < 0) return -1;
+  const long long n = 3 * op->d.V, need = (n + 255) / 256 * 256;
+  auto it = free_.begin();
+  for (; it != free_.end(); ++it)
+    if (it->second >= need) break;
+  if (it == free_.end()) return -1;
+  const long long off = it->first, len = it->second;
+  free_.erase(it);
+  if (len > need) free_[off + need] = len - need;
+  Slot &sl = slots_[slot];
+  sl = Slot{};
+  sl.used = true;
+  sl.op = op;
+  sl.R = R;
+  sl.C = C;
+  sl.voff = off;
+  sl.n = n;
+  sl.local = DevBuf(al_, ras_local_bytes(R));
+  STKKT_HIP(hipMemsetAsync(sl.local.ptr, 0, sl.local.bytes, s_));
+  if (C) {
+    sl.y2 = DevBuf(al_, sizeof(double) * n);
+    sl.t2 = DevBuf(al_, sizeof(double) * n);
+  }
+  sl.Hm.assign((size_t)(m_ + 1) * m_, 0.0);
+  sl.g.assign(m_ + 1, 0.0);
+  sl.cs.assign(m_, 0.0);
+  sl.sn.assign(m_, 0.0);
+  sl.t0 = std::chrono::steady_clock::now();
+  ++nused_;
+  dirty_ = true;
+  return slot;
+}
+
+void BatchEngine::release(int slot) {
+  Slot &sl = slots_[slot];
+  if (!sl.used) return;
+  STKKT_HIP(hipStreamSynchronize(s_));   // nothing in flight may still use the slot's buffers
+  const long long need = (sl.n + 255) / 256 * 256;
+  long long off = sl.voff, len = need;
+  // coalesce with the neighbouring free ranges
+  auto nx = free_.lower_bound(off);
+  if (nx != free_.end() && nx->first == off + len) {
+    len += nx->second;
+    free_.erase(nx);
+  }
+  auto pv = free_.lower_bound(off);
+  if (pv != free_.begin()) {
+    --pv;
+    if (pv->first + pv->second == off) {
+      off = pv->first;
+      len += pv->second;
+      free_.erase(pv);
+    }
+  }
+  free_[off] = len;
+  sl = Slot{};
+  --nused_;
+  dirty_ = true;
+}
+
+void BatchEngine::rebuild() {
+  const int S = (int)slots_.size();
+  std::vector<Chunk> ch;
+  std::vector<int> cf(S + 1);
+  std::vector<const kkt_op *> ops(S, nullptr);
+  std::vector<const ras *> rs(S, nullptr);
+  std::vector<void *> loc(S, nullptr);
+  std::vector<long long> voff(S, 0);
+  for (int i = 0; i < S; ++i) {
+    cf[i] = (int)ch.size();
+    const Slot &sl = slots_[i];
+    if (!sl.used) continue;
+    for (long long lo = 0; lo < sl.n; lo += kChunk)
+      ch.push_back(Chunk{i, 0, sl.voff + lo, sl.voff + std::min(sl.n, lo + kChunk)});
+    ops[i] = sl.op;
+    rs[i] = sl.R;
+    loc[i] = sl.local.ptr;
+    voff[i] = sl.voff;
+  }
+  cf[S] = (int)ch.size();
+  nch_ = (int)ch.size();
+  if (nch_) STKKT_HIP(hipMemcpyAsync(chunks_.ptr, ch.data(), sizeof(Chunk) * ch.size(), hipMemcpyHostToDevice, s_));
+  STKKT_HIP(hipMemcpyAsync(cfirst_.ptr, cf.data(), sizeof(int) * cf.size(), hipMemcpyHostToDevice, s_));
+  matvec_batch_prepare(ops.data(), voff.data(), S, al_, mv_, s_);   // synchronises: ch, cf may go
+  ras_batch_prepare(rs.data(), voff.data(), loc.data(), S, al_, rb_, s_);
+  dirty_ = false;
+}
+
+void BatchEngine::upload(int *host, DevBuf &dev) {
+  STKKT_HIP(hipMemcpyAsync(dev.ptr, host, sizeof(int) * slots_.size(), hipMemcpyHostToDevice, s_));
+}
+
+void BatchEngine::bdot(const double *V, long long ldv, int k, const double *w, const int *act, double *out) {
+  if (nch_ == 0) return;
+  hipLaunchKernelGGL(bmultidot_kernel, dim3(nch_), dim3(kBT), 0, s_, V, ldv, k, w, chunks_.as<Chunk>(), nch_, act,
+                     partial_.as<double>());
+  hipLaunchKernelGGL(breduce_kernel, dim3((unsigned)slots_.size(), k), dim3(kBT), 0, s_, partial_.as<double>(), nch_,
+                     cfirst_.as<int>(), act, hs_, out);
+  STKKT_HIP(hipGetLastError());
+}
+
+void BatchEngine::fetch() {
+  STKKT_HIP(hipMemcpyAsync(hh_->p, hdev_.ptr, sizeof(double) * slots_.size() * hs_, hipMemcpyDeviceToHost, s_));
+  STKKT_HIP(hipStreamSynchronize(s_));
+}
+
+// z_j = M^{-1} v_j for the members flagged in act: one-level members through
+// the batched RAS launch, two-level members one by one.
+void BatchEngine::precondition(int j, const int *act_dev) {
+  const long long N = cap_;
+  const double *v = V_.as<double>() + (long long)j * N;
+  double *z = Z_.as<double>() + (long long)j * N;
+  int *hf = hflags_->as<int>();
+  const int S = (int)slots_.size();
+  int *h_ras = hf + 3 * S;
+  bool any_two = false;
+  for (int i = 0; i < S; ++i) {
+    h_ras[i] = hf[i] && slots_[i].C == nullptr;
+    any_two = any_two || (hf[i] && slots_[i].C != nullptr);
+  }
+  if (!any_two) {
+    ras_batch_run(rb_, v, z, act_dev, hf, s_);
+    return;
+  }
+  upload(h_ras, act_c_);
+  ras_batch_run(rb_, v, z, act_c_.as<int>(), h_ras, s_);
+  for (int i = 0; i < S; ++i) {
+    const Slot &sl = slots_[i];
+    if (!hf[i] || !sl.C) continue;
+    const double *vi = v + sl.voff;
+    double *zi = z + sl.voff, *y = sl.y2.as<double>(), *t = sl.t2.as<double>();
+    // z = y + M_one^{-1} (v - F y),  y = I_c^h F_c^{-1} I_h^c v
+    coarse_apply_device(sl.C, vi, y, s_);
+    matvec_device(sl.op, y, t, s_);
+    axpby(t, 1.0, vi, -1.0, t, sl.n, s_);
+    ras_apply_device(sl.R, t, zi, s_, sl.local.ptr);
+    axpby(zi, 1.0, zi, 1.0, y, sl.n, s_);
+  }
+}
+
+void BatchEngine::cycle(std::vector<int> &finished) {
+  if (dirty_) rebuild();
+  const int S = (int)slots_.size(), m = m_, hs = hs_;
+  const long long N = cap_;
+  int *hf = hflags_->as<int>();
+  int *h_step = hf, *h_cyc = hf + S, *h_k = hf + 2 * S;
+  const double *H = hh_->as<double>();
+  double *hd = hdev_.as<double>(), *Vd = V_.as<double>(), *Zd = Z_.as<double>(), *Bd = B_.as<double>(),
+         *Xd = X_.as<double>(), *Rd = R_.as<double>(), *Wd = W_.as<double>(), *Td = T_.as<double>();
+  const Chunk *chd = chunks_.as<Chunk>();
+  const int limit = sp_.fixed_iters > 0 ? sp_.fixed_iters : sp_.maxit;
+  auto finish = [&](int i) {
+    Slot &sl = slots_[i];
+    sl.state = 2;
+    int status = STKKT_OK;
+    if (sl.breakdown) status = STKKT_EBREAKDOWN;
+    else if (!sl.st.converged && sp_.fixed_iters == 0) status = STKKT_NOT_CONVERGED;
+    sl.st.status = status;
+    sl.st.t_ms[0] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - sl.t0).count();
+    finished.push_back(i);
+  };
+
+  // newly admitted members: ||b||, r = b - F x0, ||r||
+  int nnew = 0;
+  for (int i = 0; i < S; ++i) {
+    h_cyc[i] = slots_[i].used && slots_[i].state == 0;
+    nnew += h_cyc[i];
+  }
+  if (nnew) {
+    upload(h_cyc, act_b_);
+    const int *act = act_b_.as<int>();
+    bdot(Bd, 0, 1, Bd, act, hd);
+    fetch();
+    for (int i = 0; i < S; ++i) {
+      if (!h_cyc[i]) continue;
+      Slot &sl = slots_[i];
+      sl.bnorm = std::sqrt(H[(size_t)i * hs]);
+      sl.st.bnorm = sl.bnorm;
+      sl.target = sp_.rtol * sl.bnorm;
+    }
+    matvec_batch_run(mv_, Xd, Td, act, s_);
+    hipLaunchKernelGGL(bsub_kernel, dim3(nch_), dim3(kBT), 0, s_, Rd, Bd, Td, chd, act);
+    bdot(Rd, 0, 1, Rd, act, hd);
+    fetch();
+    for (int i = 0; i < S; ++i) {
+      if (!h_cyc[i]) continue;
+      Slot &sl = slots_[i];
+      sl.beta = std::sqrt(H[(size_t)i * hs]);
+      sl.st.rel_res_true = sl.st.rel_res_est = sl.bnorm > 0 ? sl.beta / sl.bnorm : 0.0;
+      sl.state = 1;
+      if (!std::isfinite(sl.bnorm) || !std::isfinite(sl.beta)) {
+        sl.breakdown = true;
+        finish(i);
+      } else if (sl.bnorm == 0.0 || sl.beta == 0.0 || (sp_.fixed_iters == 0 && sl.beta <= sl.target)) {
+        sl.st.converged = 1;
+        finish(i);
+      }
+    }
+  }
+  // one cycle of every running member
+  int ncyc = 0;
+  for (int i = 0; i < S; ++i) {
+    Slot &sl = slots_[i];
+    h_cyc[i] = sl.used && sl.state == 1;
+    h_step[i] = h_cyc[i];
+    ncyc += h_cyc[i];
+    if (h_cyc[i]) {
+      sl.kdone = 0;
+      std::fill(sl.g.begin(), sl.g.end(), 0.0);
+      sl.g[0] = sl.beta;
+    }
+  }
+  if (ncyc == 0) return;
+  upload(h_cyc, act_b_);
+  upload(h_step, act_a_);
+  // v_0 = r / beta: |r|^2 of every running member is in hd (last residual)
+  hipLaunchKernelGGL(bnormalize_kernel, dim3(nch_), dim3(kBT), 0, s_, Vd, Rd, hd, hs, chd, act_a_.as<int>());
+  STKKT_HIP(hipGetLastError());
+  int nstep = ncyc;
+  std::vector<double> col(m + 1);
+  for (int j = 0; j < m && nstep > 0; ++j) {
+    const int *act = act_a_.as<int>();
+    double *zj = Zd + (long long)j * N;
+    precondition(j, act);
+    matvec_batch_run(mv_, zj, Wd, act, s_);
+    bdot(Vd, N, j + 1, Wd, act, hd);
+    hipLaunchKernelGGL(bupdate_kernel, dim3(nch_), dim3(kBT), 0, s_, Wd, Vd, N, j + 1, hd, hs, chd, act);
+    bdot(Vd, N, j + 1, Wd, act, hd + (m + 1));
+    hipLaunchKernelGGL(bupdate_kernel, dim3(nch_), dim3(kBT), 0, s_, Wd, Vd, N, j + 1, hd + (m + 1), hs, chd, act);
+    bdot(Wd, 0, 1, Wd, act, hd + 2 * (m + 1));
+    fetch();
+    bool changed = false;
+    for (int i = 0; i < S; ++i) {
+      if (!h_step[i]) continue;
+      Slot &sl = slots_[i];
+      const double *hi = H + (size_t)i * hs;
+      const double hn = std::sqrt(hi[2 * (m + 1)]);
+      std::fill(col.begin(), col.end(), 0.0);
+      for (int q = 0; q <= j; ++q) col[q] = hi[q] + hi[(m + 1) + q];
+      col[j + 1] = hn;
+      for (int q = 0; q < j; ++q) {
+        const double tmp = sl.cs[q] * col[q] + sl.sn[q] * col[q + 1];
+        col[q + 1] = -sl.sn[q] * col[q] + sl.cs[q] * col[q + 1];
+        col[q] = tmp;
+      }
+      const double d = std::hypot(col[j], col[j + 1]);
+      double c = 1.0, sg = 0.0;
+      if (d != 0.0) {
+        c = col[j] / d;
+        sg = col[j + 1] / d;
+      }
+      sl.cs[j] = c;
+      sl.sn[j] = sg;
+      col[j] = d;
+      col[j + 1] = 0.0;
+      for (int q = 0; q <= m; ++q) sl.Hm[(size_t)q * m + j] = col[q];
+      sl.g[j + 1] = -sg * sl.g[j];
+      sl.g[j] = c * sl.g[j];
+      sl.st.iters += 1;
+      sl.kdone = j + 1;
+      const double est = std::fabs(sl.g[j + 1]);
+      bool leave = sl.st.iters >= limit || hn == 0.0 || j + 1 == m;
+      if (!std::isfinite(est) || !std::isfinite(hn)) {
+        leave = true;
+        sl.breakdown = true;
+      }
+      if (sp_.fixed_iters == 0 && est <= sl.target) leave = true;
+      if (leave) {
+        h_step[i] = 0;
+        changed = true;
+        --nstep;
+      }
+    }
+    if (changed) upload(h_step, act_a_);
+    if (nstep > 0) {
+      hipLaunchKernelGGL(bnormalize_kernel, dim3(nch_), dim3(kBT), 0, s_, Vd + (long long)(j + 1) * N, Wd,
+                         hd + 2 * (m + 1), hs, chd, act_a_.as<int>());
+      STKKT_HIP(hipGetLastError());
+    }
+  }
+  // end of cycle: x += Z y, true residual
+  double *Y = hy_->as<double>();
+  for (int i = 0; i < S; ++i) {
+    h_k[i] = 0;
+    if (!h_cyc[i]) continue;
+    Slot &sl = slots_[i];
+    if (sl.breakdown) {
+      h_cyc[i] = 0;
+      finish(i);
+      continue;
+    }
+    const int k = sl.kdone;
+    for (int q = k - 1; q >= 0; --q) {
+      double acc = sl.g[q];
+      for (int l = q + 1; l < k; ++l) acc -= sl.Hm[(size_t)q * m + l] * Y[(size_t)i * m + l];
+      Y[(size_t)i * m + q] = acc / sl.Hm[(size_t)q * m + q];
+    }
+    h_k[i] = k;
+    sl.st.rel_res_est = std::fabs(sl.g[k]) / sl.bnorm;
+  }
+  upload(h_cyc, act_b_);
+  STKKT_HIP(hipMemcpyAsync(kcnt_.ptr, h_k, sizeof(int) * S, hipMemcpyHostToDevice, s_));
+  STKKT_HIP(hipMemcpyAsync(ydev_.ptr, Y, sizeof(double) * (size_t)S * m, hipMemcpyHostToDevice, s_));
+  const int *actb = act_b_.as<int>();
+  hipLaunchKernelGGL(bcombine_kernel, dim3(nch_), dim3(kBT), 0, s_, Xd, Zd, N, ydev_.as<double>(), m,
+                     kcnt_.as<int>(), chd, actb);
+  STKKT_HIP(hipGetLastError());
+  matvec_batch_run(mv_, Xd, Td, actb, s_);
+  hipLaunchKernelGGL(bsub_kernel, dim3(nch_), dim3(kBT), 0, s_, Rd, Bd, Td, chd, actb);
+  bdot(Rd, 0, 1, Rd, actb, hd);
+  fetch();
+  for (int i = 0; i < S; ++i) {
+    if (!h_cyc[i]) continue;
+    Slot &sl = slots_[i];
+    sl.beta = std::sqrt(H[(size_t)i * hs]);
+    sl.st.rel_res_true = sl.beta / sl.bnorm;
+    const bool ok = sl.beta <= sl.target;
+    if (!std::isfinite(sl.beta)) {
+      sl.breakdown = true;
+      finish(i);
+    } else if (sp_.fixed_iters > 0) {
+      sl.st.converged = ok ? 1 : 0;
+      if (sl.st.iters >= sp_.fixed_iters) finish(i);
+      else sl.st.restarts += 1;
+    } else if (ok) {
+      sl.st.converged = 1;
+      finish(i);
+    } else if (sl.st.iters >= limit) {
+      finish(i);
+    } else {
+      sl.st.restarts += 1;
+    }
+  }
+}
+
 int gmres_solve_batch(int count, const kkt_op *const *ops, const ras *const *R, const solve_params_t &sp,
                       const double *const *b, double *const *x, hipStream_t s, kkt_stats_t *stats) {
-  const auto t0 = std::chrono::steady_clock::now();
-  const int m = sp.restart;
-  const Allocator *al = &ops[0]->al;
-  // layout of the concatenated vectors and the reduction chunks
-  std::vector<long long> voff(count), nloc(count);
-  std::vector<Chunk> chunks;
-  std::vector<int> cfirst(count + 1);
-  long long Ntot = 0;
+  long long cap = 0;
+  for (int i = 0; i < count; ++i) cap += (3 * ops[i]->d.V + 255) / 256 * 256;
+  BatchEngine eng(&ops[0]->al, sp, cap, count, s);
+  std::vector<int> slot(count), member(count);
   for (int i = 0; i < count; ++i) {
-    nloc[i] = 3 * ops[i]->d.V;
-    voff[i] = Ntot;
-    cfirst[i] = (int)chunks.size();
-    for (long long lo = 0; lo < nloc[i]; lo += kChunk)
-      chunks.push_back(Chunk{i, 0, Ntot + lo, Ntot + std::min(nloc[i], lo + kChunk)});
-    Ntot += (nloc[i] + 255) / 256 * 256;
+    slot[i] = eng.admit(ops[i], R[i], nullptr);
+    STKKT_REQUIRE(slot[i] >= 0, "kkt_solve_batch: internal capacity error");
+    member[slot[i]] = i;
+    const long long n = eng.size_of(slot[i]);
+    STKKT_HIP(hipMemcpyAsync(eng.b_of(slot[i]), b[i], sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    STKKT_HIP(hipMemcpyAsync(eng.x_of(slot[i]), x[i], sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   }
-  cfirst[count] = (int)chunks.size();
-  const int nch = (int)chunks.size();
-  const int hs = 2 * (m + 1) + 2;   // per instance: h1[m+1], h2[m+1], |w|^2, spare
-  DevBuf V(al, sizeof(double) * (size_t)(m + 1) * Ntot), Z(al, sizeof(double) * (size_t)m * Ntot);
-  DevBuf Bv(al, sizeof(double) * Ntot), X(al, sizeof(double) * Ntot), Rv(al, sizeof(double) * Ntot),
-      Wv(al, sizeof(double) * Ntot), Tv(al, sizeof(double) * Ntot);
-  DevBuf partial(al, sizeof(double) * (size_t)(m + 1) * nch);
-  DevBuf hdev(al, sizeof(double) * (size_t)count * hs), ydev(al, sizeof(double) * (size_t)count * m);
-  DevBuf d_chunks(al, sizeof(Chunk) * (size_t)nch), d_cfirst(al, sizeof(int) * (count + 1));
-  DevBuf act_step(al, sizeof(int) * count), act_cyc(al, sizeof(int) * count), d_kcnt(al, sizeof(int) * count);
-  PinnedBuf hh(sizeof(double) * (size_t)count * hs), hy(sizeof(double) * (size_t)count * m),
-      hflags(sizeof(int) * 3 * (size_t)count);
-  STKKT_HIP(hipMemcpyAsync(d_chunks.ptr, chunks.data(), sizeof(Chunk) * nch, hipMemcpyHostToDevice, s));
-  STKKT_HIP(hipMemcpyAsync(d_cfirst.ptr, cfirst.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice, s));
-  fill_zero(V.as<double>(), (long long)(m + 1) * Ntot, s);
-  fill_zero(Z.as<double>(), (long long)m * Ntot, s);
-  fill_zero(Bv.as<double>(), Ntot, s);
-  fill_zero(X.as<double>(), Ntot, s);
-  fill_zero(Rv.as<double>(), Ntot, s);
-  fill_zero(Wv.as<double>(), Ntot, s);
-  fill_zero(Tv.as<double>(), Ntot, s);
-  for (int i = 0; i < count; ++i) {
-    STKKT_HIP(hipMemcpyAsync(Bv.as<double>() + voff[i], b[i], sizeof(double) * nloc[i], hipMemcpyDeviceToDevice, s));
-    STKKT_HIP(hipMemcpyAsync(X.as<double>() + voff[i], x[i], sizeof(double) * nloc[i], hipMemcpyDeviceToDevice, s));
-  }
-  MvBatch mv;
-  matvec_batch_prepare(ops, voff.data(), count, al, mv, s);
-  RasBatch rb;
-  ras_batch_prepare(R, voff.data(), count, al, rb, s);
-
-  double *Vd = V.as<double>(), *Zd = Z.as<double>(), *Bd = Bv.as<double>(), *Xd = X.as<double>(),
-         *Rd = Rv.as<double>(), *Wd = Wv.as<double>(), *Td = Tv.as<double>(), *hd = hdev.as<double>();
-  const Chunk *chd = d_chunks.as<Chunk>();
-  const int *cfd = d_cfirst.as<int>();
-  int *hf = hflags.as<int>();
-  int *h_step = hf, *h_cyc = hf + count, *h_k = hf + 2 * count;
-  auto upload_flags = [&](int *host, DevBuf &dev) {
-    STKKT_HIP(hipMemcpyAsync(dev.ptr, host, sizeof(int) * count, hipMemcpyHostToDevice, s));
-  };
-  // per-instance reductions: out[i * ostride + g] = V_g . w over instance i, g < k
-  auto bdot = [&](const double *Vb, long long ldv, int k, const double *w, const int *act, int ostride, double *out) {
-    hipLaunchKernelGGL(bmultidot_kernel, dim3(nch), dim3(kBT), 0, s, Vb, ldv, k, w, chd, nch, act,
-                       partial.as<double>());
-    hipLaunchKernelGGL(breduce_kernel, dim3(count, k), dim3(kBT), 0, s, partial.as<double>(), nch, cfd, act, ostride,
-                       out);
-    STKKT_HIP(hipGetLastError());
-  };
-  auto fetch = [&](int n_doubles) {
-    STKKT_HIP(hipMemcpyAsync(hh.p, hd, sizeof(double) * (size_t)n_doubles, hipMemcpyDeviceToHost, s));
-    STKKT_HIP(hipStreamSynchronize(s));
-  };
-  const double *H = hh.as<double>();
-
-  std::vector<kkt_stats_t> st(count);
-  std::vector<double> bnorm(count), target(count), beta(count);
-  std::vector<int> state(count, 0);   // 0 running, 1 converged, 2 stopped (maxit), 3 breakdown
-  const int limit = sp.fixed_iters > 0 ? sp.fixed_iters : sp.maxit;
-  for (int i = 0; i < count; ++i) h_cyc[i] = 1;
-  upload_flags(h_cyc, act_cyc);
-  // ||b|| and the initial residual
-  bdot(Bd, 0, 1, Bd, act_cyc.as<int>(), hs, hd);
-  fetch(count * hs);
-  for (int i = 0; i < count; ++i) {
-    bnorm[i] = std::sqrt(H[(size_t)i * hs]);
-    st[i].bnorm = bnorm[i];
-    target[i] = sp.rtol * bnorm[i];
-    if (!std::isfinite(bnorm[i])) throw Error(STKKT_EINVAL, "kkt_solve_batch: non-finite right-hand side");
-  }
-  matvec_batch_run(mv, Xd, Td, act_cyc.as<int>(), s);
-  hipLaunchKernelGGL(bsub_kernel, dim3(nch), dim3(kBT), 0, s, Rd, Bd, Td, chd, act_cyc.as<int>());
-  bdot(Rd, 0, 1, Rd, act_cyc.as<int>(), hs, hd);
-  fetch(count * hs);
-  for (int i = 0; i < count; ++i) {
-    beta[i] = std::sqrt(H[(size_t)i * hs]);
-    st[i].rel_res_true = st[i].rel_res_est = bnorm[i] > 0 ? beta[i] / bnorm[i] : 0.0;
-    if (bnorm[i] == 0.0 || (sp.fixed_iters == 0 && beta[i] <= target[i]) || beta[i] == 0.0) {
-      state[i] = 1;
-      st[i].converged = 1;
+  std::vector<int> done;
+  int worst = STKKT_OK, left = count;
+  while (left > 0) {
+    done.clear();
+    eng.cycle(done);
+    for (int sl : done) {
+      const int i = member[sl];
+      STKKT_HIP(hipMemcpyAsync(x[i], eng.x_of(sl), sizeof(double) * eng.size_of(sl), hipMemcpyDeviceToDevice, s));
+      const kkt_stats_t &st = eng.stats(sl);
+      if (stats) stats[i] = st;
+      if (st.status < 0) worst = st.status;
+      else if (worst == STKKT_OK) worst = st.status;
+      eng.release(sl);   // synchronises the stream first
+      --left;
     }
   }
-  std::vector<std::vector<double>> Hm(count), g(count), cs(count), sn(count);
-  for (int i = 0; i < count; ++i) {
-    Hm[i].assign((size_t)(m + 1) * m, 0.0);
-    g[i].assign(m + 1, 0.0);
-    cs[i].assign(m, 0.0);
-    sn[i].assign(m, 0.0);
-  }
-  std::vector<int> kdone(count);
-  for (;;) {
-    int ncyc = 0;
-    for (int i = 0; i < count; ++i) {
-      h_cyc[i] = state[i] == 0 ? 1 : 0;
-      h_step[i] = h_cyc[i];
-      ncyc += h_cyc[i];
-      kdone[i] = 0;
-      std::fill(g[i].begin(), g[i].end(), 0.0);
-      g[i][0] = beta[i];
-    }
-    if (ncyc == 0) break;
-    upload_flags(h_cyc, act_cyc);
-    upload_flags(h_step, act_step);
-    // v_0 = r / beta (the squared norm is still in hd from the last residual)
-    hipLaunchKernelGGL(bnormalize_kernel, dim3(nch), dim3(kBT), 0, s, Vd, Rd, hd, hs, chd, act_step.as<int>());
-    STKKT_HIP(hipGetLastError());
-    int nstep = ncyc;
-    for (int j = 0; j < m && nstep > 0; ++j) {
-      const int *act = act_step.as<int>();
-      double *zj = Zd + (long long)j * Ntot;
-      ras_batch_run(rb, Vd + (long long)j * Ntot, zj, act, h_step, s);
-      matvec_batch_run(mv, zj, Wd, act, s);
-      bdot(Vd, Ntot, j + 1, Wd, act, hs, hd);
-      hipLaunchKernelGGL(bupdate_kernel, dim3(nch), dim3(kBT), 0, s, Wd, Vd, Ntot, j + 1, hd, hs, chd, act);
-      bdot(Vd, Ntot, j + 1, Wd, act, hs, hd + (m + 1));
-      hipLaunchKernelGGL(bupdate_kernel, dim3(nch), dim3(kBT), 0, s, Wd, Vd, Ntot, j + 1, hd + (m + 1), hs, chd,
-                         act);
-      bdot(Wd, 0, 1, Wd, act, hs, hd + 2 * (m + 1));
-      fetch(count * hs);
-      bool changed = false;
-      for (int i = 0; i < count; ++i) {
-        if (!h_step[i]) continue;
-        const double *hi = H + (size_t)i * hs;
-        const double hn = std::sqrt(hi[2 * (m + 1)]);
-        std::vector<double> col(m + 1, 0.0);
-        for (int q = 0; q <= j; ++q) col[q] = hi[q] + hi[(m + 1) + q];
-        col[j + 1] = hn;
-        for (int q = 0; q < j; ++q) {
-          const double tmp = cs[i][q] * col[q] + sn[i][q] * col[q + 1];
-          col[q + 1] = -sn[i][q] * col[q] + cs[i][q] * col[q + 1];
-          col[q] = tmp;
-        }
-        const double d = std::hypot(col[j], col[j + 1]);
-        double c = 1.0, sg = 0.0;
-        if (d != 0.0) {
-          c = col[j] / d;
-          sg = col[j + 1] / d;
-        }
-        cs[i][j] = c;
-        sn[i][j] = sg;
-        col[j] = d;
-        col[j + 1] = 0.0;
-        for (int q = 0; q <= m; ++q) Hm[i][(size_t)q * m + j] = col[q];
-        g[i][j + 1] = -sg * g[i][j];
-        g[i][j] = c * g[i][j];
-        st[i].iters += 1;
-        kdone[i] = j + 1;
-        const double est = std::fabs(g[i][j + 1]);
-        bool leave = st[i].iters >= limit || hn == 0.0 || j + 1 == m;
-        if (!std::isfinite(est) || !std::isfinite(hn)) {
-          leave = true;
-          state[i] = 3;
-        }
-        if (sp.fixed_iters == 0 && est <= target[i]) leave = true;
-        if (leave) {
-          h_step[i] = 0;
-          changed = true;
-          --nstep;
-        }
-      }
-      if (changed) upload_flags(h_step, act_step);
-      if (nstep > 0) {
-        // v_{j+1} = w / |w| for the instances still in the cycle
-        hipLaunchKernelGGL(bnormalize_kernel, dim3(nch), dim3(kBT), 0, s, Vd + (long long)(j + 1) * Ntot, Wd,
-                           hd + 2 * (m + 1), hs, chd, act_step.as<int>());
-        STKKT_HIP(hipGetLastError());
-      }
-    }
-    // end of cycle: x += Z y for every instance that took part
-    double *Y = hy.as<double>();
-    for (int i = 0; i < count; ++i) {
-      h_k[i] = 0;
-      if (!h_cyc[i] || state[i] == 3) {
-        h_cyc[i] = state[i] == 3 ? 0 : h_cyc[i];
-        continue;
-      }
-      const int k = kdone[i];
-      std::vector<double> y(k);
-      for (int q = k - 1; q >= 0; --q) {
-        double acc = g[i][q];
-        for (int l = q + 1; l < k; ++l) acc -= Hm[i][(size_t)q * m + l] * y[l];
-        y[q] = acc / Hm[i][(size_t)q * m + q];
-      }
-      for (int q = 0; q < k; ++q) Y[(size_t)i * m + q] = y[q];
-      h_k[i] = k;
-      st[i].rel_res_est = std::fabs(g[i][k]) / bnorm[i];
-    }
-    upload_flags(h_cyc, act_cyc);
-    STKKT_HIP(hipMemcpyAsync(d_kcnt.ptr, h_k, sizeof(int) * count, hipMemcpyHostToDevice, s));
-    STKKT_HIP(hipMemcpyAsync(ydev.ptr, Y, sizeof(double) * (size_t)count * m, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(bcombine_kernel, dim3(nch), dim3(kBT), 0, s, Xd, Zd, Ntot, ydev.as<double>(), m,
-                       d_kcnt.as<int>(), chd, act_cyc.as<int>());
-    STKKT_HIP(hipGetLastError());
-    matvec_batch_run(mv, Xd, Td, act_cyc.as<int>(), s);
-    hipLaunchKernelGGL(bsub_kernel, dim3(nch), dim3(kBT), 0, s, Rd, Bd, Td, chd, act_cyc.as<int>());
-    bdot(Rd, 0, 1, Rd, act_cyc.as<int>(), hs, hd);
-    fetch(count * hs);
-    for (int i = 0; i < count; ++i) {
-      if (!h_cyc[i]) continue;
-      beta[i] = std::sqrt(H[(size_t)i * hs]);
-      st[i].rel_res_true = beta[i] / bnorm[i];
-      const bool ok = beta[i] <= target[i];
-      if (!std::isfinite(beta[i])) {
-        state[i] = 3;
-      } else if (sp.fixed_iters > 0) {
-        st[i].converged = ok ? 1 : 0;
-        if (st[i].iters >= sp.fixed_iters) state[i] = 2;
-        else st[i].restarts += 1;
-      } else if (ok) {
-        st[i].converged = 1;
-        state[i] = 1;
-      } else if (st[i].iters >= limit) {
-        state[i] = 2;
-      } else {
-        st[i].restarts += 1;
-      }
-    }
-  }
-  for (int i = 0; i < count; ++i)
-    STKKT_HIP(hipMemcpyAsync(x[i], Xd + voff[i], sizeof(double) * nloc[i], hipMemcpyDeviceToDevice, s));
   STKKT_HIP(hipStreamSynchronize(s));
-  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  int worst = STKKT_OK;
-  for (int i = 0; i < count; ++i) {
-    int status = STKKT_OK;
-    if (state[i] == 3) status = STKKT_EBREAKDOWN;
-    else if (!st[i].converged && sp.fixed_iters == 0) status = STKKT_NOT_CONVERGED;
-    st[i].status = status;
-    st[i].t_ms[0] = ms;
-    if (status < 0) worst = status;
-    else if (worst == STKKT_OK) worst = status;
-    if (stats) stats[i] = st[i];
-  }
   return worst;
 }
 

@@ -252,6 +252,41 @@ int kkt_solve_batch(int32_t count, const kkt_op_t *const *ops, const ras_t *cons
   });
 }
 
+int kkt_server_create(const server_params_t *p, const kkt_alloc_t *al, void *stream, kkt_server_t **out) {
+  return guarded([&] {
+    STKKT_REQUIRE(out != nullptr, "kkt_server_create: out is NULL");
+    *out = nullptr;
+    *out = server_create(p, al, as_stream(stream));
+    return STKKT_OK;
+  });
+}
+
+int kkt_server_submit(kkt_server_t *srv, const kkt_op_t *op, const ras_t *ras, const coarse_t *coarse,
+                      const double *data_host, double *x_out, int64_t *ticket) {
+  return guarded([&] {
+    STKKT_REQUIRE(srv && ticket, "kkt_server_submit: NULL argument");
+    *ticket = server_submit(srv, op, ras, coarse, data_host, x_out);
+    return STKKT_OK;
+  });
+}
+
+int kkt_server_step(kkt_server_t *srv, int32_t *n_running, int32_t *n_pending) {
+  return guarded([&] {
+    STKKT_REQUIRE(srv != nullptr, "kkt_server_step: NULL server");
+    server_step(srv, n_running, n_pending);
+    return STKKT_OK;
+  });
+}
+
+int kkt_server_poll(kkt_server_t *srv, int64_t ticket, kkt_stats_t *stats) {
+  return guarded([&] {
+    STKKT_REQUIRE(srv != nullptr, "kkt_server_poll: NULL server");
+    return server_poll(srv, ticket, stats);
+  });
+}
+
+void kkt_server_destroy(kkt_server_t *srv) { server_free(srv); }
+
 void kkt_op_destroy(kkt_op_t *op) { delete op; }
 void ras_destroy(ras_t *R) { delete R; }
 void coarse_destroy(coarse_t *c) { coarse_free(c); }

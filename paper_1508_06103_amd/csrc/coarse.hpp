@@ -35,6 +35,12 @@ struct GmresWork {
 
 int gmres_solve_batch(int count, const kkt_op *const *ops, const ras *const *R, const solve_params_t &sp,
                       const double *const *b, double *const *x, hipStream_t s, kkt_stats_t *stats);
+struct kkt_server *server_create(const server_params_t *p, const kkt_alloc_t *al, hipStream_t s);
+int64_t server_submit(struct kkt_server *srv, const kkt_op *op, const ras *R, const coarse *C, const double *data,
+                      double *x_out);
+void server_step(struct kkt_server *srv, int32_t *n_running, int32_t *n_pending);
+int server_poll(struct kkt_server *srv, int64_t ticket, kkt_stats_t *st);
+void server_free(struct kkt_server *srv);
 void coarse_apply_device(const coarse *C, const double *x, double *y, hipStream_t s);
 coarse *coarse_create(const kkt_op *fine, const coarse_params_t *cp, hipStream_t s);
 void coarse_free(coarse *c);

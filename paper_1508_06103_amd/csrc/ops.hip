@@ -445,12 +445,14 @@ void matvec_batch_prepare(const kkt_op *const *ops, const long long *voff, int c
   long long w = 0;
   int halo = 0;
   for (int i = 0; i < count; ++i) {
+    d[i] = MvBatchDesc{};
+    d[i].w0 = (int32_t)w;
+    if (!ops[i]) continue;   // empty slot: no work items
     d[i].op = ops[i]->d;
     d[i].tl = ops[i]->mv;
     d[i].mc = make_mv_const(ops[i]->d);
     d[i].atab = ops[i]->atab.as<double>();
     d[i].voff = voff[i];
-    d[i].w0 = (int32_t)w;
     d[i].nw = ops[i]->mv.ntiles * ops[i]->mv.nchunks;
     w += d[i].nw;
     halo = std::max(halo, ops[i]->mv.halo);
@@ -458,6 +460,7 @@ void matvec_batch_prepare(const kkt_op *const *ops, const long long *voff, int c
   STKKT_REQUIRE(w <= INT32_MAX, "batched matvec: too many work items");
   out.desc = DevBuf(al, sizeof(MvBatchDesc) * (size_t)count);
   STKKT_HIP(hipMemcpyAsync(out.desc.ptr, d.data(), sizeof(MvBatchDesc) * (size_t)count, hipMemcpyHostToDevice, s));
+  halo = std::max(halo, 27);
   STKKT_HIP(hipStreamSynchronize(s));   // d is released on return
   out.count = count;
   out.items = w;
@@ -466,6 +469,7 @@ void matvec_batch_prepare(const kkt_op *const *ops, const long long *voff, int c
 }
 
 void matvec_batch_run(const MvBatch &b, const double *x, double *y, const int *act, hipStream_t s) {
+  if (b.items == 0) return;
   const MvBatchDesc *dd = b.desc.as<MvBatchDesc>();
   const dim3 grid((unsigned)b.items);
   if (b.kh == 1)

@@ -909,7 +909,7 @@ static size_t ring_lds_bytes(const ras *R) {
 }
 
 template <typename T>
-static void launch_apply(const ras *R, const double *r, double *z, hipStream_t s) {
+static void launch_apply(const ras *R, const double *r, double *z, T *Y, hipStream_t s) {
   const size_t lds = ring_lds_bytes<T>(R);
   if (lds <= kRingLdsLimit && R->ring_ltlz <= kApplyThreads) {
     static bool attr_set = false;
@@ -922,14 +922,19 @@ static void launch_apply(const ras *R, const double *r, double *z, hipStream_t s
     hipLaunchKernelGGL((apply_ring_kernel<T>), dim3(R->nsub), dim3(kApplyThreads), lds, s, R->d,
                        R->d_subs.as<SubInfo>(), R->d_order.as<int32_t>(), R->d_shapes.as<ShapeInfo>(),
                        R->d_lvl.as<int32_t>(), R->d_coords.as<uint64_t>(), R->d_ctab.as<int32_t>(),
-                       R->d_tz.as<int32_t>(), R->factors.as<T>(), R->scratch.as<T>(),
+                       R->d_tz.as<int32_t>(), R->factors.as<T>(), Y,
                        9 * R->total_blocks, R->scratch_elems, rg, r, z);
   } else {
     hipLaunchKernelGGL((apply_kernel<T>), dim3(R->nsub), dim3(kApplyThreads), 0, s, R->d, R->d_subs.as<SubInfo>(),
                        R->d_order.as<int32_t>(), R->d_shapes.as<ShapeInfo>(), R->d_lvl.as<int32_t>(),
-                       R->d_coords.as<uint64_t>(), R->d_ctab.as<int32_t>(), R->factors.as<T>(), R->scratch.as<T>(),
+                       R->d_coords.as<uint64_t>(), R->d_ctab.as<int32_t>(), R->factors.as<T>(), Y,
                        9 * R->total_blocks, R->scratch_elems, r, z);
   }
+}
+
+size_t ras_local_bytes(const ras *R) {
+  const size_t esz = R->params.precision == STKKT_F32 ? sizeof(float) : sizeof(double);
+  return esz * ((size_t)R->scratch_elems + 4);
 }
 
 bool ras_uses_ring(const ras *R) {
@@ -937,20 +942,24 @@ bool ras_uses_ring(const ras *R) {
          R->ring_ltlz <= kApplyThreads;
 }
 
-void ras_apply_device(const ras *R, const double *r, double *z, hipStream_t s) {
-  if (R->params.precision == STKKT_F32) launch_apply<float>(R, r, z, s);
-  else launch_apply<double>(R, r, z, s);
+void ras_apply_device(const ras *R, const double *r, double *z, hipStream_t s, void *local) {
+  if (R->params.precision == STKKT_F32)
+    launch_apply<float>(R, r, z, local ? static_cast<float *>(local) : R->scratch.as<float>(), s);
+  else
+    launch_apply<double>(R, r, z, local ? static_cast<double *>(local) : R->scratch.as<double>(), s);
   STKKT_HIP(hipGetLastError());
 }
 
 template <typename T>
-static void ras_batch_prepare_t(const ras *const *R, const long long *voff, int count, const Allocator *al,
-                                RasBatch &out, hipStream_t s) {
+static void ras_batch_prepare_t(const ras *const *R, const long long *voff, void *const *local, int count,
+                                const Allocator *al, RasBatch &out, hipStream_t s) {
   std::vector<RasBatchDesc<T>> d(count);
   std::vector<std::pair<int64_t, int2>> items;
   size_t lds = 0;
   for (int i = 0; i < count; ++i) {
     const ras *q = R[i];
+    d[i] = RasBatchDesc<T>{};
+    if (!q) continue;   // empty slot
     d[i].op = q->d;
     d[i].subs = q->d_subs.as<SubInfo>();
     d[i].shapes = q->d_shapes.as<ShapeInfo>();
@@ -959,7 +968,7 @@ static void ras_batch_prepare_t(const ras *const *R, const long long *voff, int 
     d[i].ctab = q->d_ctab.as<int32_t>();
     d[i].tz = q->d_tz.as<int32_t>();
     d[i].F = q->factors.as<T>();
-    d[i].Y = q->scratch.as<T>();
+    d[i].Y = local && local[i] ? static_cast<T *>(local[i]) : q->scratch.as<T>();
     d[i].fzero = 9 * q->total_blocks;
     d[i].yzero = q->scratch_elems;
     d[i].voff = voff[i];
@@ -972,7 +981,7 @@ static void ras_batch_prepare_t(const ras *const *R, const long long *voff, int 
   std::vector<int2> work(items.size());
   for (size_t k = 0; k < items.size(); ++k) work[k] = items[k].second;
   out.desc = DevBuf(al, sizeof(RasBatchDesc<T>) * (size_t)count);
-  out.work = DevBuf(al, sizeof(int2) * work.size());
+  out.work = DevBuf(al, sizeof(int2) * std::max<size_t>(work.size(), 1));
   STKKT_HIP(hipMemcpyAsync(out.desc.ptr, d.data(), sizeof(RasBatchDesc<T>) * (size_t)count, hipMemcpyHostToDevice, s));
   STKKT_HIP(hipMemcpyAsync(out.work.ptr, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, s));
   STKKT_HIP(hipStreamSynchronize(s));   // host staging is released on return
@@ -980,19 +989,24 @@ static void ras_batch_prepare_t(const ras *const *R, const long long *voff, int 
   out.lds = lds;
 }
 
-void ras_batch_prepare(const ras *const *R, const long long *voff, int count, const Allocator *al, RasBatch &out,
-                       hipStream_t s) {
+void ras_batch_prepare(const ras *const *R, const long long *voff, void *const *local, int count,
+                       const Allocator *al, RasBatch &out, hipStream_t s) {
+  out = RasBatch{};
   out.count = count;
-  out.precision = R[0]->params.precision;
+  out.precision = -1;
   out.ring = true;
   for (int i = 0; i < count; ++i) {
-    out.ring = out.ring && ras_uses_ring(R[i]) && R[i]->params.precision == out.precision;
     out.members.push_back(R[i]);
     out.voff.push_back(voff[i]);
+    out.local.push_back(local ? local[i] : nullptr);
+    if (!R[i]) continue;
+    if (out.precision < 0) out.precision = R[i]->params.precision;
+    out.ring = out.ring && ras_uses_ring(R[i]) && R[i]->params.precision == out.precision;
   }
+  if (out.precision < 0) out.precision = STKKT_F64;
   if (!out.ring) return;   // per-preconditioner launches
-  if (out.precision == STKKT_F32) ras_batch_prepare_t<float>(R, voff, count, al, out, s);
-  else ras_batch_prepare_t<double>(R, voff, count, al, out, s);
+  if (out.precision == STKKT_F32) ras_batch_prepare_t<float>(R, voff, local, count, al, out, s);
+  else ras_batch_prepare_t<double>(R, voff, local, count, al, out, s);
 }
 
 template <typename T>
@@ -1011,9 +1025,10 @@ void ras_batch_run(const RasBatch &b, const double *r, double *z, const int *act
                    hipStream_t s) {
   if (!b.ring) {
     for (int i = 0; i < b.count; ++i)
-      if (act_host[i]) ras_apply_device(b.members[i], r + b.voff[i], z + b.voff[i], s);
+      if (act_host[i] && b.members[i]) ras_apply_device(b.members[i], r + b.voff[i], z + b.voff[i], s, b.local[i]);
     return;
   }
+  if (b.blocks == 0) return;
   if (b.precision == STKKT_F32) ras_batch_launch<float>(b, r, z, act, s);
   else ras_batch_launch<double>(b, r, z, act, s);
   STKKT_HIP(hipGetLastError());

@@ -60,13 +60,17 @@ struct ras {
 };
 
 namespace stkkt {
-void ras_apply_device(const ras *R, const double *r, double *z, hipStream_t s);
+// local: device buffer for the subdomains' local vectors (ras_local_bytes(R)
+// bytes, the last bytes zero), or NULL for the handle's own.
+void ras_apply_device(const ras *R, const double *r, double *z, hipStream_t s, void *local = nullptr);
 bool ras_uses_ring(const ras *R);
+size_t ras_local_bytes(const ras *R);
 
 // Batched application over preconditioners whose vectors are concatenated
-// (preconditioner i reads r[voff_i ...] and writes z[voff_i ...]): one launch
-// over the (preconditioner, subdomain) work list when every member uses the
-// LDS-ring kernel with the same precision, else one launch per member.
+// (member i reads r[voff_i ...] and writes z[voff_i ...], its local vectors in
+// local[i] when given): one launch over the (member, subdomain) work list
+// when every member uses the LDS-ring kernel with the same precision, else
+// one launch per member.  NULL members are empty slots.
 struct RasBatch {
   DevBuf desc, work;
   int count = 0, blocks = 0, precision = STKKT_F64;
@@ -74,9 +78,10 @@ struct RasBatch {
   size_t lds = 0;
   std::vector<const ras *> members;
   std::vector<long long> voff;
+  std::vector<void *> local;
 };
-void ras_batch_prepare(const ras *const *R, const long long *voff, int count, const Allocator *al, RasBatch &out,
-                       hipStream_t s);
+void ras_batch_prepare(const ras *const *R, const long long *voff, void *const *local, int count,
+                       const Allocator *al, RasBatch &out, hipStream_t s);
 // act: device flags (members with 0 are skipped), act_host: the same flags on the host
 void ras_batch_run(const RasBatch &b, const double *r, double *z, const int *act, const int *act_host,
                    hipStream_t s);

@@ -1,0 +1,169 @@
+"""Served stream on the GPU: continuous batching of requests.
+
+Each request's result must be the same alone and in the mix, match the
+oracle's FGMRES solve of its own right-hand side, and the server must
+respect its device-memory budget when admitting requests.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import kkt, krylov, ras as oras, twolevel
+from workloads.generate import make_custom, make_problem, redraw_noise
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def st():
+    import paper_1508_06103_amd as st_mod
+    assert torch.cuda.is_available()
+    return st_mod
+
+
+@pytest.fixture(scope="module")
+def pool(st):
+    """Two operators with cached factors (requests on the same mesh share them)."""
+    specs = [("cube8x16", make_problem("cube8x16")[0], (2, 2, 2, 2)),
+             ("ragged", make_custom((5, 6, 7), 9, 3, lattice=2), (2, 3, 2, 3))]
+    out = {}
+    for name, prob, parts in specs:
+        op = st.KKTOperator(prob)
+        out[name] = (prob, op, st.RAS(op, parts, 1), parts)
+    return out
+
+
+def requests(pool, count, seed):
+    rng = np.random.default_rng(seed)
+    names = sorted(pool)
+    out = []
+    for k in range(count):
+        name = names[int(rng.integers(len(names)))]
+        prob = pool[name][0]
+        out.append((name, redraw_noise(prob, 4000 + seed * 100 + k)))
+    return out
+
+
+def run(st, srv, pool, reqs, stagger=0):
+    """Submit requests (stagger per step), step until all are done."""
+    tickets, results, k = {}, {}, 0
+    while len(results) < len(reqs):
+        for _ in range(max(1, stagger) if stagger else len(reqs)):
+            if k < len(reqs):
+                name, data = reqs[k]
+                _, op, pre, _ = pool[name]
+                tickets[srv.submit(op, pre, data)] = k
+                k += 1
+        running, pending = srv.step()
+        for t in list(tickets):
+            r = srv.poll(t)
+            if r is not None:
+                results[tickets.pop(t)] = r
+    return [results[i] for i in range(len(reqs))]
+
+
+def test_same_alone_and_in_mix(st, pool):
+    reqs = requests(pool, 6, seed=1)
+    srv = st.Server(restart=20, rtol=1e-6, device_bytes=1 << 28, max_active=8)
+    alone = [run(st, srv, pool, [r])[0] for r in reqs]
+    mix = run(st, srv, pool, reqs, stagger=2)   # two new requests join at every step
+    for i, ((name, data), (xa, sa), (xm, sm)) in enumerate(zip(reqs, alone, mix)):
+        _say(f"  request {i} ({name}): alone {sa.iters} its, in mix {sm.iters} its")
+        assert sa.converged and sm.converged and sa.iters == sm.iters
+        assert np.array_equal(xa.cpu().numpy(), xm.cpu().numpy()), i
+
+
+def test_requests_match_oracle(st, pool):
+    reqs = requests(pool, 4, seed=2)
+    srv = st.Server(restart=20, rtol=1e-6, device_bytes=1 << 28, max_active=8)
+    res = run(st, srv, pool, reqs, stagger=1)
+    for (name, data), (x, s) in zip(reqs, res):
+        prob, _, _, parts = pool[name]
+        p2 = dataclasses.replace(prob, data=data)
+        terms = kkt.kkt_terms(prob)
+        F = kkt.assemble(prob, terms=terms)
+        b = kkt.rhs(p2)
+        R = oras.RAS(prob, parts, 1, terms=terms)
+        xo, so = krylov.gmres(lambda v: F @ v, R.apply, b, restart=20, rtol=1e-6, flexible=True)
+        xg = x.cpu().numpy()
+        res_true = np.linalg.norm(b - F @ xg) / np.linalg.norm(b)
+        _say(f"  {name}: server {s.iters} its, oracle {so.iters}, true res {res_true:.2e}, latency {s.ms:.1f} ms")
+        assert s.converged and res_true <= 1e-6 and abs(s.iters - so.iters) <= 1
+        if s.iters == so.iters:
+            assert np.linalg.norm(xg - xo) <= 1e-7 * np.linalg.norm(xo)
+
+
+def test_admission_respects_memory(st, pool):
+    """A budget for about two cube8x16 requests: never more than that run at once.
+
+    With restart 20 every request here finishes in one cycle (20 steps), so the
+    requests retired by one server step are the ones that ran together."""
+    prob, op, pre, parts = pool["cube8x16"]
+    per_request = 8 * (2 * 20 + 6) * (prob.unknowns + 255) // 256 * 256
+    srv = st.Server(restart=20, rtol=1e-6, device_bytes=int(2.5 * per_request / 0.5), max_active=16)
+    reqs = [("cube8x16", redraw_noise(prob, 4100 + k)) for k in range(5)]
+    tickets = [srv.submit(op, pre, d) for _, d in reqs]
+    most, done, steps = 0, {}, 0
+    while len(done) < len(tickets):
+        running, pending = srv.step()
+        steps += 1
+        now = 0
+        for t in tickets:
+            if t not in done:
+                r = srv.poll(t)
+                if r is not None:
+                    done[t] = r
+                    now += 1
+        most = max(most, now)
+        assert steps <= 10
+    _say(f"  {steps} steps, at most {most} requests together")
+    assert most == 2 and steps == 3
+    for t in tickets:
+        assert done[t][1].converged and done[t][1].iters == 20
+
+
+def test_two_level_request_in_mix(st, pool):
+    prob, op, pre, parts = pool["cube8x16"]
+    C = st.Coarse(op, (2, 2, 2, 2), (2, 2, 2, 2), overlap=1, maxit=4, rtol=0.1)
+    srv = st.Server(restart=30, rtol=1e-6, device_bytes=1 << 28, max_active=8)
+    data = redraw_noise(prob, 4200)
+    t2 = srv.submit(op, pre, data, coarse=C)
+    others = [srv.submit(*pool[n][1:3], redraw_noise(pool[n][0], 4300 + i)) for i, n in enumerate(sorted(pool))]
+    out = {}
+    while len(out) < 1 + len(others):
+        srv.step()
+        for t in [t2] + others:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+    x, s = out[t2]
+    p2 = dataclasses.replace(prob, data=data)
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    b = kkt.rhs(p2)
+    R = oras.RAS(prob, parts, 1, terms=terms)
+    tl = twolevel.TwoLevel(prob, R.apply, lambda v: F @ v, (2, 2, 2, 2), coarse="gmres_ras",
+                           coarse_parts=(2, 2, 2, 2), coarse_overlap=1, coarse_maxit=4, coarse_rtol=0.1)
+    xo, so = krylov.gmres(lambda v: F @ v, tl, b, restart=30, rtol=1e-6, flexible=True)
+    res = np.linalg.norm(b - F @ x.cpu().numpy()) / np.linalg.norm(b)
+    _say(f"  two-level request: {s.iters} its (oracle {so.iters}), true res {res:.2e}")
+    assert s.converged and res <= 1e-6 and abs(s.iters - so.iters) <= 1
+
+
+def test_server_errors(st, pool):
+    prob, op, pre, parts = pool["cube8x16"]
+    srv = st.Server(restart=10, rtol=1e-6, device_bytes=1 << 20, max_active=2)
+    with pytest.raises(st.StkktError):
+        srv.submit(op, pre, prob.data)      # larger than the whole server
+    with pytest.raises(st.StkktError):
+        srv.poll(12345)
