@@ -150,6 +150,174 @@ def kernels_only(op, pre, prob, reps):
                       "copy_bytes_each_way": src.numel() * 8, "reps": reps}), flush=True)
 
 
+def auto_parts(prob, box=8):
+    """Subdomains per axis so that owned boxes are about `box` nodes wide."""
+    L = [k + 1 for k in prob.n] + [prob.M + 1]
+    return tuple(max(1, int(round(l / box))) for l in L)
+
+
+def run_batch(args):
+    """Batched uneven instances: solves/s of the whole batch per step, FP32
+    preconditioners inside FP64 FGMRES(50), against the same instances solved
+    one at a time in plain FP64 GMRES(50)."""
+    import numpy as np
+    import torch
+    import paper_1508_06103_amd as st
+    from workloads.generate import batch_instances, redraw_noise
+    probs = batch_instances(count=args.instances, base_seed=3000)
+    unknowns = sum(p.unknowns for p in probs)
+    print(f"[bench] batch: {len(probs)} instances, {unknowns} unknowns", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ops = [st.KKTOperator(p) for p in probs]
+    pres = [st.RAS(op, auto_parts(p), 1, precision=st.F32) for op, p in zip(ops, probs)]
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    bs = [torch.empty(op.n, dtype=torch.float64, device="cuda") for op in ops]
+    xs = [torch.zeros_like(b) for b in bs]
+    count = len(probs)
+
+    def step(k):
+        for i, (p, op) in enumerate(zip(probs, ops)):
+            op.rhs(redraw_noise(p, 5000 + k * count + i), out=bs[i])
+            xs[i].zero_()
+        return st.solve_batch(ops, pres, bs, xs, restart=50, rtol=1e-6)[1]
+
+    for w in range(args.warmup):
+        step(w)
+    torch.cuda.synchronize()
+    times, its = [], []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        sts = step(args.warmup + k)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        assert all(s.converged and s.rel_res_true <= 1e-6 for s in sts)
+        its += [s.iters for s in sts]
+        print(f"[bench] batch step {k}: {times[-1]*1e3:.0f} ms, iterations {min(its)}..{max(its)}",
+              file=sys.stderr, flush=True)
+    total = time.perf_counter() - t_start
+    value = count * args.steps / total
+    # baseline: the same instances one at a time, plain FP64 (factors rebuilt per instance, setup not timed)
+    base_t, base_its = 0.0, []
+    for i, (p, op) in enumerate(zip(probs, ops)):
+        pre64 = st.RAS(op, auto_parts(p), 1, precision=st.F64)
+        op.rhs(redraw_noise(p, 5000 + args.warmup * count + i), out=bs[i])
+        xs[i].zero_()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _, s = st.solve(op, pre64, bs[i], xs[i], restart=50, rtol=1e-6)
+        torch.cuda.synchronize()
+        base_t += time.perf_counter() - ts
+        base_its.append(s.iters)
+        pre64.close()
+    base = count / base_t
+    print(f"[bench] one at a time FP64: {base_t*1e3:.0f} ms for {count} solves", file=sys.stderr, flush=True)
+    return {
+        "metric": "KKT solves/s at FP64 rel. residual 1e-6; p50/p99 latency; GMRES iterations",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 outer / f32 preconditioner", "data": "synthetic (seeded uneven instances, fresh noise per step)",
+        "config": {"workload": f"batch of {count} uneven instances: n in {{8,12,16,20,24}}, M in {{16,24,32,48}}, "
+                               f"1-3 sources, 27-64 sensors, ~8-node subdomains, overlap 1, FGMRES(50)",
+                   "unknowns": unknowns},
+        "p50_ms": 1e3 * percentile(times, 50), "p99_ms": 1e3 * percentile(times, 99),
+        "gmres_iters": float(np.mean(its)), "setup_ms": 1e3 * t_setup,
+        "baseline_one_at_a_time_fp64": {"value": base, "unit": "solves/s", "gmres_iters": float(np.mean(base_its))},
+        "speedup_vs_one_at_a_time_fp64": value / base,
+    }
+
+
+def run_serve(args):
+    """Poisson request stream through the server (continuous batching, FP32
+    preconditioners, FP64 FGMRES(50)); 90% of requests on 16 operators drawn
+    from the batch distribution, 10% on the 32^3 x 64 operator with the
+    two-level preconditioner.  The one-at-a-time FP64 baseline serves the same
+    arrivals first come first served, one solve at a time."""
+    import numpy as np
+    import torch
+    import paper_1508_06103_amd as st
+    from workloads.generate import batch_instances, make_problem, redraw_noise
+    pool = batch_instances(count=16, base_seed=3000)
+    large, _ = make_problem("cube32x64", seed=4, lattice=3)   # 27 sensors, all on coarse nodes
+    specs = [(p, auto_parts(p), None) for p in pool] + [(large, (4, 4, 4, 8), (4, 4, 4, 4))]
+    t0 = time.perf_counter()
+    built = []
+    for p, parts, fac in specs:
+        op = st.KKTOperator(p)
+        pre = st.RAS(op, parts, 1, precision=st.F32)
+        C = st.Coarse(op, fac, (2, 2, 2, 4), overlap=1, maxit=4, rtol=0.1, precision=st.F32) if fac else None
+        built.append((p, op, pre, C))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    rng = np.random.default_rng(4)
+    n = args.requests
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=n))
+    which = [len(pool) if rng.uniform() < 0.1 else int(rng.integers(len(pool))) for _ in range(n)]
+    datas = [redraw_noise(built[w][0], 4000 + k) for k, w in enumerate(which)]
+    srv = st.Server(restart=50, rtol=1e-6, device_bytes=96 << 30, max_active=64)
+    print(f"[bench] serve: {n} requests at {args.rate}/s, setup {t_setup:.1f} s", file=sys.stderr, flush=True)
+    lat, its, pending = [], [], {}
+    nxt = 0
+    t_begin = time.perf_counter()
+    while len(lat) < n:
+        now = time.perf_counter() - t_begin
+        while nxt < n and arrivals[nxt] <= now:
+            p, op, pre, C = built[which[nxt]]
+            pending[srv.submit(op, pre, datas[nxt], coarse=C)] = nxt
+            nxt += 1
+        if pending:
+            srv.step()
+            tnow = time.perf_counter() - t_begin
+            for t in list(pending):
+                r = srv.poll(t)
+                if r is not None:
+                    k = pending.pop(t)
+                    assert r[1].converged and r[1].rel_res_true <= 1e-6
+                    lat.append(tnow - arrivals[k])
+                    its.append(r[1].iters)
+        elif nxt < n:
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t_begin)))
+    t_end = time.perf_counter() - t_begin
+    value = n / (t_end - arrivals[0])
+    print(f"[bench] served: {value:.2f} solves/s, p50 {1e3*percentile(lat, 50):.0f} ms, "
+          f"p99 {1e3*percentile(lat, 99):.0f} ms", file=sys.stderr, flush=True)
+    # one at a time, plain FP64: measured service times, first come first served
+    svc, base64 = [], {}
+    for k in range(n):
+        p, op, pre, C = built[which[k]]
+        parts, fac = specs[which[k]][1], specs[which[k]][2]
+        if which[k] not in base64:
+            base64[which[k]] = (st.RAS(op, parts, 1, precision=st.F64),
+                                st.Coarse(op, fac, (2, 2, 2, 4), overlap=1, maxit=4, rtol=0.1) if fac else None)
+        pre64, C64 = base64[which[k]]
+        b = op.rhs(datas[k])
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _, s = st.solve(op, pre64, b, x, coarse=C64, restart=50, rtol=1e-6, flexible=C64 is not None)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - ts)
+    finish, blat = 0.0, []
+    for k in range(n):
+        finish = max(finish, arrivals[k]) + svc[k]
+        blat.append(finish - arrivals[k])
+    base = n / (finish - arrivals[0])
+    return {
+        "metric": "KKT solves/s at FP64 rel. residual 1e-6; p50/p99 latency; GMRES iterations",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": n, "warmup": 0,
+        "ms_per_step": 1e3 * (t_end - arrivals[0]) / n, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 outer / f32 preconditioner",
+        "data": "synthetic (seeded request stream, fresh noise per request)",
+        "config": {"workload": f"served stream: {n} Poisson requests at {args.rate}/s; 90% on 16 uneven operators "
+                               f"(n 8-24, M 16-48), 10% on 32^3 x 64 with two-level RAS (coarse 8^3 x 16)"},
+        "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99), "gmres_iters": float(np.mean(its)),
+        "setup_ms": 1e3 * t_setup,
+        "baseline_one_at_a_time_fp64": {"value": base, "unit": "solves/s", "p50_ms": 1e3 * percentile(blat, 50),
+                                        "p99_ms": 1e3 * percentile(blat, 99)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +329,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
                     help="no solves: time ras_apply, kkt_matvec and a plain 1 GiB device copy (for counter runs)")
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"],
+                    help="single: one operator, one solve per step (default); batch: 64 uneven instances per "
+                         "step; serve: Poisson request stream through the server")
+    ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=100)
+    ap.add_argument("--rate", type=float, default=50.0, help="serve mode: arrivals per second")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -173,6 +347,12 @@ def main():
     from workloads.generate import make_problem, redraw_noise
 
     torch.cuda.set_device(0)
+    if args.mode == "batch":
+        print(json.dumps(run_batch(args)), flush=True)
+        return
+    if args.mode == "serve":
+        print(json.dumps(run_serve(args)), flush=True)
+        return
     prob, cfg = make_problem(args.config)
     prec = st.F64 if args.precision == "f64" else st.F32
     print(f"[bench] {args.config}: {prob.unknowns} unknowns, parts {cfg.parts}, overlap {cfg.overlap}",
