@@ -686,6 +686,48 @@ __device__ inline void mac_chunk_ring(const SweepArgs<T> &a, const Phase &p, int
   }
 }
 
+// Final step of a phase, one thread per row: sum the wavefronts' partial
+// products, then y = r - sum (forward, y also kept in global memory for the
+// backward sweep) or z = inv(U_rr)(y - sum) (backward, owned rows written to
+// the output); the result goes into the LDS ring.
+template <typename T, bool kFwd>
+__device__ inline void ring_finish(const SweepArgs<T> &a, const Phase &pc, const uint64_t *crd, T (*part)[kRows][3],
+                                   const T (&pre)[12], T *yring, const Ring &rg) {
+  const int tq = (int)threadIdx.x;
+  if (tq < pc.segR) {
+    const uint64_t fc = crd[tq];
+    T s3[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      T acc = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) acc += part[w][tq][k];
+      s3[k] = acc;
+    }
+    T o[3];
+    int x, y, zc, t;
+    unpack(fc, x, y, zc, t);
+    if (kFwd) {
+      for (int k = 0; k < 3; ++k) o[k] = pre[k] - s3[k];
+      T *yg = a.Y + a.sd.sbase + 3 * yrow_of(a, x, y, zc, t);
+      for (int k = 0; k < 3; ++k) yg[k] = o[k];
+    } else {
+      T v[3];
+      for (int k = 0; k < 3; ++k) v[k] = pre[9 + k] - s3[k];
+      for (int k = 0; k < 3; ++k) o[k] = pre[3 * k] * v[0] + pre[3 * k + 1] * v[1] + pre[3 * k + 2] * v[2];
+      const SubInfo &sd = a.sd;
+      const bool owned = x >= sd.olo[0] && x < sd.ohi[0] && y >= sd.olo[1] && y < sd.ohi[1] && zc >= sd.olo[2] &&
+                         zc < sd.ohi[2] && t >= sd.olo[3] && t < sd.ohi[3];
+      if (owned) {
+        const int64_t gi = global_row(a, x, y, zc, t);
+        for (int k = 0; k < 3; ++k) a.z[gi + k] = (double)o[k];
+      }
+    }
+    T *yr = yring + ((int64_t)(pc.L & 15) * rg.rmax + pc.seg * kRows + tq) * 3;
+    for (int k = 0; k < 3; ++k) yr[k] = o[k];
+  }
+}
+
 // One chunk step: issue the factor loads of the next chunk, multiply the
 // current one, and close the phase if this was its last chunk.
 template <typename T, bool kFwd>
@@ -749,38 +791,7 @@ __device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int n
   }
   // close the phase
   lds_barrier();
-  if (tq < pc.segR) {
-    const uint64_t fc = crd2[par * kRows + tq];
-    T s3[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      T acc = 0;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) acc += part[w][tq][k];
-      s3[k] = acc;
-    }
-    T o[3];
-    int x, y, zc, t;
-    unpack(fc, x, y, zc, t);
-    if (kFwd) {
-      for (int k = 0; k < 3; ++k) o[k] = pre[k] - s3[k];
-      T *yg = a.Y + a.sd.sbase + 3 * yrow_of(a, x, y, zc, t);
-      for (int k = 0; k < 3; ++k) yg[k] = o[k];
-    } else {
-      T v[3];
-      for (int k = 0; k < 3; ++k) v[k] = pre[9 + k] - s3[k];
-      for (int k = 0; k < 3; ++k) o[k] = pre[3 * k] * v[0] + pre[3 * k + 1] * v[1] + pre[3 * k + 2] * v[2];
-      const SubInfo &sd = a.sd;
-      const bool owned = x >= sd.olo[0] && x < sd.ohi[0] && y >= sd.olo[1] && y < sd.ohi[1] && zc >= sd.olo[2] &&
-                         zc < sd.ohi[2] && t >= sd.olo[3] && t < sd.ohi[3];
-      if (owned) {
-        const int64_t gi = global_row(a, x, y, zc, t);
-        for (int k = 0; k < 3; ++k) a.z[gi + k] = (double)o[k];
-      }
-    }
-    T *yr = yring + ((int64_t)(pc.L & 15) * rg.rmax + pc.seg * kRows + tq) * 3;
-    for (int k = 0; k < 3; ++k) yr[k] = o[k];
-  }
+  ring_finish<T, kFwd>(a, pc, crd2 + par * kRows, part, pre, yring, rg);
   if (pc.seg == 0 && tq < rg.ltlz) tzr[(pc.L & 15) * rg.ltlz + tq] = tzrow;
   if (!pnn.done && tq < pnn.segR) crd2[par * kRows + tq] = c2;   // phase after next reuses this buffer
   lds_barrier();
@@ -822,6 +833,143 @@ __device__ inline void sweep_ring(const SweepArgs<T> &a, cptr<int32_t> tzp, T (*
   }
 }
 
+// Depth-2 form of the pipeline (FP32 factors, whose registers allow three
+// chunk buffers): the factor loads of the chunk two steps ahead are issued
+// before the current chunk is multiplied.  That chunk may lie up to two phases
+// ahead, so the coordinates of the current phase and the next two live in
+// three LDS buffers (par, par+1, par+2 mod 3); the phase three ahead is read
+// into registers at the start of a phase and stored into the buffer the
+// closing phase frees.
+template <typename T, bool kFwd>
+__device__ inline void ring_step2(const SweepArgs<T> &a, cptr<int32_t> tzp, int nlev, int wave, Phase &pc, int &cc,
+                                  int &par, Phase &pn, Phase &pnn, Phase &p3, const T (&fcur)[kSlotsPerWave][9],
+                                  T (&fload)[kSlotsPerWave][9], T (*part)[kRows][3], uint64_t *crd3, T *yring,
+                                  int32_t *tzr, const Ring &rg, uint64_t &c3, int &tzrow, T (&pre)[12]) {
+  const int lane = (int)__lane_id();
+  const int tq = (int)threadIdx.x;
+  if (cc == 0) {
+    if (!p3.done && tq < p3.segR) c3 = a.crd[a.sh.coord_off + p3.r0 + p3.seg * kRows + tq];
+    if (pc.seg == 0 && tq < rg.ltlz) tzrow = tzp[(int64_t)pc.L * rg.ltlz + tq];
+    if (tq < pc.segR) {
+      const uint64_t fc = crd3[par * kRows + tq];
+      int x, y, zc, t;
+      unpack(fc, x, y, zc, t);
+      if (kFwd) {
+        const int64_t gi = global_row(a, x, y, zc, t);
+        pre[0] = (T)a.r[gi];
+        pre[1] = (T)a.r[gi + 1];
+        pre[2] = (T)a.r[gi + 2];
+      } else {
+        const int qrow = pc.seg * kRows + tq;
+        int64_t off9, cnt;
+        chunk_slot(a, pc.L, qrow >> 6, 40, off9, cnt);
+        const T *d = a.F + a.sd.fbase + off9 + (qrow & 63);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) pre[e] = *(d + (int64_t)e * cnt);
+        const int64_t yo = a.sd.sbase + 3 * yrow_of(a, x, y, zc, t);
+        pre[9] = a.Y[yo];
+        pre[10] = a.Y[yo + 1];
+        pre[11] = a.Y[yo + 2];
+      }
+    }
+  }
+  // the chunk two steps ahead: (pc, cc+2), (pn, 0), (pn, 1) or (pnn, 0)
+  {
+    const int p1 = par == 2 ? 0 : par + 1, p2 = par == 0 ? 2 : par - 1;
+    const Phase *pt;
+    int ct, tpar;
+    if (cc + 2 < pc.nch) {
+      pt = &pc;
+      ct = cc + 2;
+      tpar = par;
+    } else if (cc + 2 == pc.nch) {
+      pt = &pn;
+      ct = 0;
+      tpar = p1;
+    } else if (!pn.done && pn.nch >= 2) {
+      pt = &pn;
+      ct = 1;
+      tpar = p1;
+    } else {
+      pt = &pnn;
+      ct = 0;
+      tpar = p2;
+    }
+    const uint64_t cw = crd3[tpar * kRows + ct * 64 + lane];
+    load_chunk_f<T, kFwd>(a, *pt, ct, cw, wave, fload);
+  }
+  // multiply the current chunk
+  {
+    const uint64_t cw = crd3[par * kRows + cc * 64 + lane];
+    T a0 = 0, a1 = 0, a2 = 0;
+    mac_chunk_ring<T, kFwd>(a, pc, cc, cw, wave, fcur, yring, tzr, rg, a0, a1, a2);
+    if (cc * 64 + lane < pc.segR) {
+      part[wave][cc * 64 + lane][0] = a0;
+      part[wave][cc * 64 + lane][1] = a1;
+      part[wave][cc * 64 + lane][2] = a2;
+    }
+  }
+  if (cc != pc.nch - 1) {
+    ++cc;
+    return;
+  }
+  // close the phase
+  lds_barrier();
+  ring_finish<T, kFwd>(a, pc, crd3 + par * kRows, part, pre, yring, rg);
+  if (pc.seg == 0 && tq < rg.ltlz) tzr[(pc.L & 15) * rg.ltlz + tq] = tzrow;
+  if (!p3.done && tq < p3.segR) crd3[par * kRows + tq] = c3;   // the phase three ahead reuses this buffer
+  lds_barrier();
+  pc = pn;
+  pn = pnn;
+  pnn = p3;
+  phase_next(p3, pnn, a.lvls, nlev, kFwd);
+  par = par == 2 ? 0 : par + 1;
+  cc = 0;
+}
+
+template <typename T, bool kFwd>
+__device__ inline void sweep_ring2(const SweepArgs<T> &a, cptr<int32_t> tzp, T (*part)[kRows][3], uint64_t *crd3,
+                                   T *yring, int32_t *tzr, const Ring &rg) {
+  const int lane = (int)__lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tq = (int)threadIdx.x;
+  const int nlev = a.sh.nlev;
+  Phase pc, pn, pnn, p3;
+  phase_at(pc, a.lvls, nlev, next_level(a.lvls, nlev, -1, kFwd), 0, kFwd);
+  if (pc.done) return;
+  phase_next(pn, pc, a.lvls, nlev, kFwd);
+  phase_next(pnn, pn, a.lvls, nlev, kFwd);
+  phase_next(p3, pnn, a.lvls, nlev, kFwd);
+  // coordinates of the first three phases
+  if (tq < pc.segR) crd3[tq] = a.crd[a.sh.coord_off + pc.r0 + pc.seg * kRows + tq];
+  if (!pn.done && tq < pn.segR) crd3[kRows + tq] = a.crd[a.sh.coord_off + pn.r0 + pn.seg * kRows + tq];
+  if (!pnn.done && tq < pnn.segR) crd3[2 * kRows + tq] = a.crd[a.sh.coord_off + pnn.r0 + pnn.seg * kRows + tq];
+  __syncthreads();
+  int par = 0, cc = 0;
+  uint64_t c3 = 0;
+  int tzrow = 0;
+  T pre[12];
+  T fA[kSlotsPerWave][9], fB[kSlotsPerWave][9], fC[kSlotsPerWave][9];
+  load_chunk_f<T, kFwd>(a, pc, 0, crd3[lane], wave, fA);
+  if (pc.nch >= 2) load_chunk_f<T, kFwd>(a, pc, 1, crd3[64 + lane], wave, fB);
+  else load_chunk_f<T, kFwd>(a, pn, 0, crd3[kRows + lane], wave, fB);
+  for (;;) {
+    ring_step2<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, p3, fA, fC, part, crd3, yring, tzr, rg, c3, tzrow,
+                        pre);
+    if (pc.done) break;
+    ring_step2<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, p3, fB, fA, part, crd3, yring, tzr, rg, c3, tzrow,
+                        pre);
+    if (pc.done) break;
+    ring_step2<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, p3, fC, fB, part, crd3, yring, tzr, rg, c3, tzrow,
+                        pre);
+    if (pc.done) break;
+  }
+}
+
+// Chunk-coordinate buffers of the apply kernel: two for the depth-1 pipeline
+// (FP64), three for the depth-2 one (FP32).
+template <typename T> constexpr int kCrdBufs = sizeof(T) == 4 ? 3 : 2;
+
 // Both sweeps of subdomain `sub` with the values of the last 16 levels in LDS.
 template <typename T>
 __device__ inline void apply_ring_sub(const OpDev &op, const SubInfo *__restrict__ subs, int sub,
@@ -833,7 +981,7 @@ __device__ inline void apply_ring_sub(const OpDev &op, const SubInfo *__restrict
   extern __shared__ __align__(16) unsigned char smem[];
   T(*part)[kRows][3] = reinterpret_cast<T(*)[kRows][3]>(smem);
   uint64_t *crd2 = reinterpret_cast<uint64_t *>(smem + sizeof(T) * kWaves * kRows * 3);
-  T *yring = reinterpret_cast<T *>(smem + sizeof(T) * kWaves * kRows * 3 + sizeof(uint64_t) * 2 * kRows);
+  T *yring = reinterpret_cast<T *>(smem + sizeof(T) * kWaves * kRows * 3 + sizeof(uint64_t) * kCrdBufs<T> * kRows);
   int32_t *tzr = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(yring) +
                                              sizeof(T) * (size_t)16 * rg.rmax * 3);
   SweepArgs<T> a;
@@ -853,9 +1001,15 @@ __device__ inline void apply_ring_sub(const OpDev &op, const SubInfo *__restrict
   const cptr<int32_t> tzp = as_const(tzpref) + a.sh.tz_off;
   Ring rl = rg;
   rl.ltlz = a.sh.dims[3] * a.sh.dims[2];
-  sweep_ring<T, true>(a, tzp, part, crd2, yring, tzr, rl);
-  __syncthreads();   // forward results in global memory are read by the backward sweep
-  sweep_ring<T, false>(a, tzp, part, crd2, yring, tzr, rl);
+  if (kCrdBufs<T> == 3) {
+    sweep_ring2<T, true>(a, tzp, part, crd2, yring, tzr, rl);
+    __syncthreads();   // forward results in global memory are read by the backward sweep
+    sweep_ring2<T, false>(a, tzp, part, crd2, yring, tzr, rl);
+  } else {
+    sweep_ring<T, true>(a, tzp, part, crd2, yring, tzr, rl);
+    __syncthreads();
+    sweep_ring<T, false>(a, tzp, part, crd2, yring, tzr, rl);
+  }
 }
 
 template <typename T>
@@ -904,7 +1058,8 @@ __global__ void __launch_bounds__(kApplyThreads, 2) apply_ring_batch_kernel(cons
 
 template <typename T>
 static size_t ring_lds_bytes(const ras *R) {
-  return sizeof(T) * kWaves * kRows * 3 + sizeof(uint64_t) * 2 * kRows + sizeof(T) * (size_t)16 * R->ring_rmax * 3 +
+  return sizeof(T) * kWaves * kRows * 3 + sizeof(uint64_t) * kCrdBufs<T> * kRows +
+         sizeof(T) * (size_t)16 * R->ring_rmax * 3 +
          sizeof(int32_t) * (size_t)16 * R->ring_ltlz;
 }
 
