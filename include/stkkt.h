@@ -108,11 +108,19 @@ typedef struct {
  * interpolation I_c^h linear on the coarse mesh (per unknown slot), restriction
  * I_h^c = (I_c^h)^T or injection, coarse KKT system F_c rediscretised on the
  * coarse mesh (element coefficient = mean of the fine ones it covers; every
- * sensor must sit on a coarse node).  F_c^{-1} is applied as in the paper's
- * experiments (Section 4): restarted GMRES from a zero guess with relative
- * tolerance `rtol` and at most `maxit` steps, right-preconditioned by the
- * one-level space-time RAS of the coarse mesh (`p`, `overlap`, ILU(0)). */
+ * sensor must sit on a coarse node).  F_c^{-1} is applied by one of:
+ *  - STKKT_COARSE_GMRES_RAS, as in the paper's experiments (Section 4):
+ *    restarted GMRES from a zero guess with relative tolerance `rtol` and at
+ *    most `maxit` steps, right-preconditioned by the one-level space-time RAS
+ *    of the coarse mesh (`p`, `overlap`, ILU(0); `precision` of its factors);
+ *  - STKKT_COARSE_LU, exactly: F_c is block tridiagonal in time, so
+ *    S_0 = D_0, S_k = D_k - L_k S_{k-1}^{-1} U_{k-1}; the setup forms and
+ *    inverts every S_k densely (FP64 Gauss-Jordan with partial pivoting) and
+ *    keeps S_k^{-1} and S_k^{-1} U_k in `precision`, using
+ *    2 (M_c + 1) (3 N_c)^2 elements of device memory; `p`, `overlap`,
+ *    `maxit`, `rtol` are ignored. */
 #define STKKT_COARSE_GMRES_RAS 0
+#define STKKT_COARSE_LU 1
 typedef struct {
   int32_t factor[4];        /* coarsening in x, y, z, t                    */
   int32_t method;           /* STKKT_COARSE_GMRES_RAS                       */

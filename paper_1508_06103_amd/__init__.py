@@ -23,7 +23,7 @@ OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, EBREAKDOWN = 0, 1, -1, -2, -3, -4
 DTO, OTD = 0, 1
 F64, F32 = 0, 1
 RESTRICT_TRANSPOSE, RESTRICT_INJECTION = 0, 1
-COARSE_GMRES_RAS = 0
+COARSE_GMRES_RAS, COARSE_LU = 0, 1
 
 
 class StkktError(RuntimeError):
@@ -306,17 +306,18 @@ class RAS:
 class Coarse:
     """Coarse space-time level of the two-level preconditioner.
 
-    factor: coarsening in (x, y, z, t); parts/overlap: the coarse mesh's RAS;
-    F_c^{-1} is `maxit` steps of GMRES (relative tolerance `rtol`) from zero.
+    factor: coarsening in (x, y, z, t).  method COARSE_GMRES_RAS: F_c^{-1} is
+    `maxit` steps of GMRES (relative tolerance `rtol`) from zero with the coarse
+    mesh's RAS (parts, overlap); COARSE_LU: exact block elimination in time.
     """
 
-    def __init__(self, op: KKTOperator, factor, parts, overlap=1, maxit=4, rtol=0.1, precision=F64,
-                 restrict=RESTRICT_TRANSPOSE, stream=None):
+    def __init__(self, op: KKTOperator, factor, parts=(1, 1, 1, 1), overlap=1, maxit=4, rtol=0.1, precision=F64,
+                 restrict=RESTRICT_TRANSPOSE, method=COARSE_GMRES_RAS, stream=None):
         self.op = op
         self.alloc = op.alloc
         cp = _CoarseParams()
         cp.factor = (ctypes.c_int32 * 4)(*factor)
-        cp.method = COARSE_GMRES_RAS
+        cp.method = int(method)
         cp.precision = int(precision)
         cp.restrict_kind = int(restrict)
         cp.p = (ctypes.c_int32 * 4)(*parts)

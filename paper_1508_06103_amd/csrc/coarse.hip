@@ -1,13 +1,15 @@
 // Two-level space-time preconditioner (Section 3.2, two-level paragraph):
 // nested coarse space-time mesh, linear interpolation I_c^h and its transpose
 // (or injection) as transfers, and the coarse KKT system rediscretised on the
-// coarse mesh.  F_c^{-1} is applied as in the paper's experiments (Section 4):
-// a few steps of restarted GMRES from zero, right-preconditioned by the
-// one-level space-time RAS of the coarse mesh.
+// coarse mesh.  F_c^{-1} is applied either as in the paper's experiments
+// (Section 4): a few steps of restarted GMRES from zero, right-preconditioned
+// by the one-level space-time RAS of the coarse mesh; or exactly, by block
+// elimination in time with explicitly inverted Schur complements (CoarseLU).
 #include <cmath>
 #include <memory>
 
 #include "coarse.hpp"
+#include "coarse_lu.hpp"
 #include "ras.hpp"
 
 struct coarse {
@@ -20,7 +22,9 @@ struct coarse {
   ras *cras = nullptr;      // owned coarse preconditioner
   stkkt::DevBuf xc, yc;     // coarse vectors
   std::unique_ptr<stkkt::GmresWork> work;   // inner GMRES workspace
+  std::unique_ptr<stkkt::CoarseLU> lu;       // exact coarse solve (method LU)
   ~coarse() {
+    lu.reset();
     work.reset();
     delete cras;
     delete cop;
@@ -123,10 +127,13 @@ __global__ void restrict_kernel(OpDev fo, OpDev co, int fx, int fy, int fz, int 
 }  // namespace
 
 coarse *coarse_create(const kkt_op *fine, const coarse_params_t *cp, hipStream_t s) {
-  STKKT_REQUIRE(cp->method == STKKT_COARSE_GMRES_RAS, "coarse_setup: unknown coarse solver");
+  STKKT_REQUIRE(cp->method == STKKT_COARSE_GMRES_RAS || cp->method == STKKT_COARSE_LU,
+                "coarse_setup: unknown coarse solver");
+  STKKT_REQUIRE(cp->precision == STKKT_F64 || cp->precision == STKKT_F32, "coarse_setup: bad precision");
   STKKT_REQUIRE(cp->restrict_kind == STKKT_RESTRICT_TRANSPOSE || cp->restrict_kind == STKKT_RESTRICT_INJECTION,
                 "coarse_setup: bad restriction");
-  STKKT_REQUIRE(cp->maxit >= 1 && cp->rtol > 0 && cp->rtol < 1, "coarse_setup: bad coarse solver settings");
+  if (cp->method == STKKT_COARSE_GMRES_RAS)
+    STKKT_REQUIRE(cp->maxit >= 1 && cp->rtol > 0 && cp->rtol < 1, "coarse_setup: bad coarse solver settings");
   const OpDev &fd = fine->d;
   const int nf[4] = {fd.n[0], fd.n[1], fd.n[2], fd.M};
   for (int d = 0; d < 4; ++d)
@@ -174,16 +181,20 @@ coarse *coarse_create(const kkt_op *fine, const coarse_params_t *cp, hipStream_t
   p.variant = fd.variant;
   kkt_alloc_t al = fine->al.cb;
   C->cop = op_create(&p, al.alloc ? &al : nullptr, s);
-  ras_params_t rp{};
-  for (int d = 0; d < 4; ++d) rp.p[d] = cp->p[d];
-  rp.overlap = cp->overlap;
-  rp.precision = cp->precision;
-  rp.ilu_level = 0;
-  C->cras = ras_create(C->cop, &rp, s);
   const size_t nvc = 3 * (size_t)C->cop->d.V;
   C->xc = DevBuf(&C->al, sizeof(double) * nvc);
   C->yc = DevBuf(&C->al, sizeof(double) * nvc);
-  C->work = std::make_unique<GmresWork>(&C->cop->al, (long long)nvc, cp->maxit, false, false);
+  if (cp->method == STKKT_COARSE_LU) {
+    C->lu = std::make_unique<CoarseLU>(&C->al, C->cop, cp->precision, s);
+  } else {
+    ras_params_t rp{};
+    for (int d = 0; d < 4; ++d) rp.p[d] = cp->p[d];
+    rp.overlap = cp->overlap;
+    rp.precision = cp->precision;
+    rp.ilu_level = 0;
+    C->cras = ras_create(C->cop, &rp, s);
+    C->work = std::make_unique<GmresWork>(&C->cop->al, (long long)nvc, cp->maxit, false, false);
+  }
   return C.release();
 }
 
@@ -193,16 +204,20 @@ void coarse_apply_device(const coarse *C, const double *x, double *y, hipStream_
                      C->fac[1], C->fac[2], C->fac[3], C->params.restrict_kind == STKKT_RESTRICT_INJECTION ? 1 : 0, x,
                      C->xc.as<double>());
   STKKT_HIP(hipGetLastError());
-  fill_zero(C->yc.as<double>(), 3 * co.V, s);
-  solve_params_t sp{};
-  sp.restart = C->params.maxit;
-  sp.maxit = C->params.maxit;
-  sp.rtol = C->params.rtol;
-  sp.flexible = 0;
-  sp.fixed_iters = 0;
-  const int st = gmres_solve(C->cop, C->cras, nullptr, sp, C->xc.as<double>(), C->yc.as<double>(), s, nullptr,
-                             C->work.get());
-  if (st != STKKT_OK && st != STKKT_NOT_CONVERGED) throw Error(st, "coarse solve failed");
+  if (C->lu) {
+    C->lu->solve(C->xc.as<double>(), C->yc.as<double>(), s);
+  } else {
+    fill_zero(C->yc.as<double>(), 3 * co.V, s);
+    solve_params_t sp{};
+    sp.restart = C->params.maxit;
+    sp.maxit = C->params.maxit;
+    sp.rtol = C->params.rtol;
+    sp.flexible = 0;
+    sp.fixed_iters = 0;
+    const int st = gmres_solve(C->cop, C->cras, nullptr, sp, C->xc.as<double>(), C->yc.as<double>(), s, nullptr,
+                               C->work.get());
+    if (st != STKKT_OK && st != STKKT_NOT_CONVERGED) throw Error(st, "coarse solve failed");
+  }
   hipLaunchKernelGGL(prolong_kernel, dim3(blocks_for(fo.V, 256, 1 << 16)), dim3(256), 0, s, fo, co, C->fac[0],
                      C->fac[1], C->fac[2], C->fac[3], C->yc.as<double>(), y);
   STKKT_HIP(hipGetLastError());

@@ -1,0 +1,454 @@
+// Exact coarse solve F_c^{-1} by block elimination in time (the coarse
+// operator is block tridiagonal in time, Section 3.2; block k = the 3 N_c
+// unknowns of coarse level k):
+//   S_0 = D_0,  S_k = D_k - L_k S_{k-1}^{-1} U_{k-1},
+//   forward   y_0 = S_0^{-1} r_0,  y_k = S_k^{-1} (r_k - L_k y_{k-1}),
+//   backward  x_M = y_M,           x_k = y_k - E_k x_{k+1},  E_k = S_k^{-1} U_k.
+// D_k, L_k, U_k are the stencil blocks of the coarse operator (its 27 spatial
+// neighbours at time offsets 0, -1, +1).  The setup forms every S_k densely
+// and inverts it explicitly (blocked Gauss-Jordan elimination with partial
+// pivoting, the trailing updates as tiled FP64 GEMMs), so one application is
+// two sweeps of dense matrix-vector products streamed from HBM.
+//
+// Dense matrices are stored column-major (entry (r, c) at c * nb + r).  The
+// Gauss-Jordan kernels work on rows of the buffer, i.e. on the transpose; the
+// inverse of the transpose read column-major is the inverse itself.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "coarse_lu.hpp"
+#include "stencil.hpp"
+
+namespace stkkt {
+
+namespace {
+
+constexpr int kPanel = 64;   // Gauss-Jordan panel width (= GEMM inner dimension)
+
+// ---------------------------------------------------------------------------
+// sparse couplings: for every row r = 3 j + a of a level, its 27 spatial
+// neighbours i and slots b (81 entries): column index 3 i + b and the value of
+// the (dt) block; neighbours outside the mesh have value 0
+// ---------------------------------------------------------------------------
+__global__ void coupling_rows_kernel(OpDev op, int n, int dt, int32_t *__restrict__ idx, double *__restrict__ val) {
+  const int N = op.N;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+    const int jx = j % op.nn[0], jy = (j / op.nn[0]) % op.nn[1], jz = j / (op.nn[0] * op.nn[1]);
+    for (int k = 0; k < 27; ++k) {
+      const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+      const int ix = jx + dx, iy = jy + dy, iz = jz + dz;
+      const bool in = ix >= 0 && ix < op.nn[0] && iy >= 0 && iy < op.nn[1] && iz >= 0 && iz < op.nn[2];
+      double blk[9];
+      if (in) kkt_block(op, jx, jy, jz, n, dx, dy, dz, dt, blk);
+      const int i = in ? ix + op.nn[0] * (iy + op.nn[1] * iz) : 0;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          const long long e = (long long)(3 * j + a) * 81 + 3 * k + b;
+          idx[e] = 3 * i + b;
+          val[e] = in ? blk[3 * a + b] : 0.0;
+        }
+    }
+  }
+}
+
+// S = D_k (column-major), from the dt = 0 coupling rows
+__global__ void dense_from_rows_kernel(int nb, const int32_t *__restrict__ idx, const double *__restrict__ val,
+                                       double *__restrict__ S) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nb; r += gridDim.x * blockDim.x)
+    for (int t = 0; t < 81; ++t) {
+      const double v = val[(long long)r * 81 + t];
+      if (v != 0.0) S[(long long)idx[(long long)r * 81 + t] * nb + r] += v;
+    }
+}
+
+// S(r, c) -= sum_t L(r, idx_t) E(idx_t, c)   (column-major S, E; L rows sparse)
+__global__ void schur_update_kernel(int nb, const int32_t *__restrict__ idx, const double *__restrict__ val,
+                                    const double *__restrict__ E, double *__restrict__ S) {
+  const int c = blockIdx.y;
+  const double *Ec = E + (long long)c * nb;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nb; r += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int t = 0; t < 81; ++t) acc += val[(long long)r * 81 + t] * Ec[idx[(long long)r * 81 + t]];
+    S[(long long)c * nb + r] -= acc;
+  }
+}
+
+// E(:, c) = sum_t Sinv(:, row_t) U(row_t, c), the rows of column c of U given
+// as (row index, value) pairs
+__global__ void e_from_cols_kernel(int nb, const int32_t *__restrict__ cidx, const double *__restrict__ cval,
+                                   const double *__restrict__ Sinv, double *__restrict__ E) {
+  const int c = blockIdx.y;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nb; r += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int t = 0; t < 81; ++t) {
+      const double v = cval[(long long)c * 81 + t];
+      if (v != 0.0) acc += v * Sinv[(long long)cidx[(long long)c * 81 + t] * nb + r];
+    }
+    E[(long long)c * nb + r] = acc;
+  }
+}
+
+// transpose the (row r -> 81 columns) table of U into (column -> 81 rows)
+void transpose_rows(int nb, const std::vector<int32_t> &idx, const std::vector<double> &val,
+                    std::vector<int32_t> &cidx, std::vector<double> &cval) {
+  cidx.assign((size_t)nb * 81, 0);
+  cval.assign((size_t)nb * 81, 0.0);
+  std::vector<int> fill(nb, 0);
+  for (int r = 0; r < nb; ++r)
+    for (int t = 0; t < 81; ++t) {
+      const double v = val[(size_t)r * 81 + t];
+      if (v == 0.0) continue;
+      const int c = idx[(size_t)r * 81 + t];
+      const int f = fill[c]++;
+      if (f >= 81) throw Error(STKKT_EINVAL, "coarse LU: coupling column with more than 81 entries");
+      cidx[(size_t)c * 81 + f] = r;
+      cval[(size_t)c * 81 + f] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// blocked Gauss-Jordan inverse of the n x n row-major buffer A (in place)
+// ---------------------------------------------------------------------------
+__device__ inline void block_argmax(double v, int i, double *sv, int *si) {
+  // largest |v|, smallest index on ties, over the workgroup
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_down(v, off, 64);
+    const int oi = __shfl_down(i, off, 64);
+    if (ov > v || (ov == v && oi < i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+  if (lane == 0) {
+    sv[w] = v;
+    si[w] = i;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k)
+      if (sv[k] > sv[0] || (sv[k] == sv[0] && si[k] < si[0])) {
+        sv[0] = sv[k];
+        si[0] = si[k];
+      }
+  }
+  __syncthreads();
+}
+
+// Unblocked Gauss-Jordan on the column panel [k, e) of all rows, with row
+// pivoting over rows >= c (whole rows are swapped).  One workgroup.
+__global__ void __launch_bounds__(1024) gje_panel_kernel(int n, int k, int e, double *__restrict__ A,
+                                                         int32_t *__restrict__ piv, int *__restrict__ status) {
+  __shared__ double sv[16];
+  __shared__ int si[16];
+  __shared__ double prow[kPanel];
+  for (int c = k; c < e; ++c) {
+    const int j = c - k;
+    double best = -1.0;
+    int bi = n;
+    for (int i = c + threadIdx.x; i < n; i += blockDim.x) {
+      const double v = fabs(A[(long long)i * n + c]);
+      if (v > best || (v == best && i < bi)) {
+        best = v;
+        bi = i;
+      }
+    }
+    block_argmax(best, bi, sv, si);
+    const int p = si[0];
+    const double pv = sv[0];
+    if (!(pv > 0.0) || !std::isfinite(pv)) {
+      if (threadIdx.x == 0) *status = 1;
+      return;
+    }
+    if (p != c) {
+      for (int col = threadIdx.x; col < n; col += blockDim.x) {
+        const double t = A[(long long)c * n + col];
+        A[(long long)c * n + col] = A[(long long)p * n + col];
+        A[(long long)p * n + col] = t;
+      }
+      if (threadIdx.x == 0) {
+        const int32_t t = piv[c];
+        piv[c] = piv[p];
+        piv[p] = t;
+      }
+    }
+    __syncthreads();
+    // pivot row of the panel: a_cc <- 1, then the panel row / a_cc
+    const double a = A[(long long)c * n + c];
+    if (threadIdx.x < e - k) {
+      const int col = k + threadIdx.x;
+      const double v = col == c ? 1.0 : A[(long long)c * n + col];
+      prow[threadIdx.x] = v / a;
+    }
+    __syncthreads();
+    if (threadIdx.x < e - k) A[(long long)c * n + k + threadIdx.x] = prow[threadIdx.x];
+    // eliminate column c from every other row, inside the panel
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      if (i == c) continue;
+      double *Ai = A + (long long)i * n + k;
+      const double f = Ai[j];
+      Ai[j] = 0.0;
+      if (f != 0.0)
+        for (int q = 0; q < e - k; ++q) Ai[q] -= f * prow[q];
+    }
+    __syncthreads();
+  }
+}
+
+// Copy the panel rows [k, e) outside the panel columns: R[t][col] = A[k+t][col]
+__global__ void gje_copy_rows_kernel(int n, int k, int e, const double *__restrict__ A, double *__restrict__ R) {
+  const int t = blockIdx.y;
+  for (int col = blockIdx.x * blockDim.x + threadIdx.x; col < n; col += gridDim.x * blockDim.x)
+    R[(long long)t * n + col] = (col >= k && col < e) ? 0.0 : A[(long long)(k + t) * n + col];
+}
+
+// Trailing update outside the panel columns:
+//   rows outside the panel:  A[i][col] += sum_t A[i][k+t] R[t][col]
+//   panel rows:              A[i][col]  = sum_t A[i][k+t] R[t][col]
+// 64 x 64 output tiles, 256 threads with 4 x 4 outputs each, K = panel width.
+__global__ void __launch_bounds__(256) gje_update_kernel(int n, int k, int e, double *__restrict__ A,
+                                                         const double *__restrict__ R) {
+  __shared__ double As[kPanel][64];       // [t][row]
+  __shared__ double Rs[kPanel][64];       // [t][col]
+  const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
+  const int w = e - k;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < 64 * kPanel; q += 256) {
+    const int rr = q / kPanel, t = q % kPanel;
+    const int i = row0 + rr;
+    As[t][rr] = (i < n && t < w) ? A[(long long)i * n + k + t] : 0.0;
+    const int t2 = q / 64, cc = q % 64;
+    const int col = col0 + cc;
+    Rs[t2][cc] = (col < n && t2 < w) ? R[(long long)t2 * n + col] : 0.0;
+  }
+  __syncthreads();
+  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int t = 0; t < w; ++t) {
+    double av[4], rv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = As[t][tr + a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) rv[b] = Rs[t][tc + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * rv[b];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = row0 + tr + a;
+    if (i >= n) continue;
+    const bool prow = i >= k && i < e;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int col = col0 + tc + b;
+      if (col >= n || (col >= k && col < e)) continue;
+      double *dst = A + (long long)i * n + col;
+      *dst = prow ? acc[a][b] : *dst + acc[a][b];
+    }
+  }
+}
+
+// out[i][piv[j]] = A[i][j]
+__global__ void gje_unpermute_kernel(int n, const double *__restrict__ A, const int32_t *__restrict__ piv,
+                                     double *__restrict__ out) {
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+    out[(long long)i * n + piv[j]] = A[(long long)i * n + j];
+}
+
+__global__ void iota_kernel(int n, int32_t *p) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = i;
+}
+
+// ---------------------------------------------------------------------------
+// application
+// ---------------------------------------------------------------------------
+// t = r - L y  (L rows sparse; with y == nullptr: t = r)
+__global__ void lower_rhs_kernel(int nb, const int32_t *__restrict__ idx, const double *__restrict__ val,
+                                 const double *__restrict__ r, const double *__restrict__ y, double *__restrict__ t) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
+    double acc = r[i];
+    if (y)
+      for (int q = 0; q < 81; ++q) acc -= val[(long long)i * 81 + q] * y[idx[(long long)i * 81 + q]];
+    t[i] = acc;
+  }
+}
+
+constexpr int kGvRows = 256, kGvCols = 128;
+
+// partial[chunk][r] = sum over the chunk's columns of A(r, c) x(c)   (column-major A)
+template <typename T>
+__global__ void __launch_bounds__(kGvRows) gemv_partial_kernel(int nb, const T *__restrict__ A,
+                                                               const double *__restrict__ x,
+                                                               double *__restrict__ partial) {
+  __shared__ T xs[kGvCols];
+  const int c0 = blockIdx.y * kGvCols;
+  const int nc = min(kGvCols, nb - c0);
+  if ((int)threadIdx.x < nc) xs[threadIdx.x] = (T)x[c0 + threadIdx.x];
+  __syncthreads();
+  const int r = blockIdx.x * kGvRows + threadIdx.x;
+  if (r >= nb) return;
+  T acc = 0;
+  const T *a = A + (long long)c0 * nb + r;
+  for (int c = 0; c < nc; ++c) acc += a[(long long)c * nb] * xs[c];
+  partial[(long long)blockIdx.y * nb + r] = (double)acc;
+}
+
+// out[r] = base[r] + sign * sum_chunks partial[chunk][r]  (fixed order)
+__global__ void gemv_reduce_kernel(int nb, int nchunk, const double *__restrict__ partial,
+                                   const double *__restrict__ base, double sign, double *__restrict__ out) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nb; r += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int q = 0; q < nchunk; ++q) s += partial[(long long)q * nb + r];
+    out[r] = (base ? base[r] : 0.0) + sign * s;
+  }
+}
+
+__global__ void to_float_kernel(long long n, const double *__restrict__ a, float *__restrict__ b) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
+}  // namespace
+
+// Explicit inverse of the n x n row-major matrix in A (overwritten with the
+// inverse).  tmp: n x n scratch; rows: kPanel x n scratch; piv: n int32.
+static void gje_invert(int n, double *A, double *tmp, double *rows, int32_t *piv, int *status, hipStream_t s) {
+  hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(n, 256, 64)), dim3(256), 0, s, n, piv);
+  for (int k = 0; k < n; k += kPanel) {
+    const int e = std::min(n, k + kPanel);
+    hipLaunchKernelGGL(gje_panel_kernel, dim3(1), dim3(1024), 0, s, n, k, e, A, piv, status);
+    hipLaunchKernelGGL(gje_copy_rows_kernel, dim3(blocks_for(n, 256, 64), e - k), dim3(256), 0, s, n, k, e, A,
+                       rows);
+    hipLaunchKernelGGL(gje_update_kernel, dim3((n + 63) / 64, (n + 63) / 64), dim3(256), 0, s, n, k, e, A, rows);
+  }
+  hipLaunchKernelGGL(gje_unpermute_kernel, dim3(blocks_for(n, 256, 64), n), dim3(256), 0, s, n, A, piv, tmp);
+  STKKT_HIP(hipGetLastError());
+  STKKT_HIP(hipMemcpyAsync(A, tmp, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+}
+
+CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStream_t s) : al_(al), prec_(precision) {
+  const OpDev &d = cop->d;
+  nb_ = 3 * d.N;
+  nlev_ = d.M + 1;
+  STKKT_REQUIRE(nb_ <= 65535, "coarse_setup: coarse level too large for the dense block solve");
+  const size_t nn = (size_t)nb_ * nb_;
+  const size_t esz = precision == STKKT_F32 ? sizeof(float) : sizeof(double);
+  Sinv_ = DevBuf(al, esz * nn * nlev_);
+  E_ = DevBuf(al, esz * nn * std::max(nlev_ - 1, 1));
+  Lidx_ = DevBuf(al, sizeof(int32_t) * (size_t)nb_ * 81 * nlev_);
+  Lval_ = DevBuf(al, sizeof(double) * (size_t)nb_ * 81 * nlev_);
+  partial_ = DevBuf(al, sizeof(double) * (size_t)nb_ * ((nb_ + kGvCols - 1) / kGvCols));
+  t_ = DevBuf(al, sizeof(double) * nb_);
+  // setup work buffers (FP64)
+  DevBuf S(al, sizeof(double) * nn), Ed(al, sizeof(double) * nn),
+      tmp(al, sizeof(double) * nn), rows(al, sizeof(double) * (size_t)kPanel * nb_), piv(al, sizeof(int32_t) * nb_),
+      status(al, 256), ridx(al, sizeof(int32_t) * (size_t)nb_ * 81), rval(al, sizeof(double) * (size_t)nb_ * 81),
+      cidx(al, sizeof(int32_t) * (size_t)nb_ * 81), cval(al, sizeof(double) * (size_t)nb_ * 81);
+  STKKT_HIP(hipMemsetAsync(status.ptr, 0, sizeof(int), s));
+  std::vector<int32_t> hidx((size_t)nb_ * 81), hcidx;
+  std::vector<double> hval((size_t)nb_ * 81), hcval;
+  const int G = blocks_for(d.N, 128, 1024);
+  const dim3 g2(blocks_for(nb_, 256, 64), nb_);
+  for (int k = 0; k < nlev_; ++k) {
+    // lower coupling of level k (to level k-1), kept for the application
+    int32_t *Lk_idx = Lidx_.as<int32_t>() + (size_t)k * nb_ * 81;
+    double *Lk_val = Lval_.as<double>() + (size_t)k * nb_ * 81;
+    if (k > 0) hipLaunchKernelGGL(coupling_rows_kernel, dim3(G), dim3(128), 0, s, d, k, -1, Lk_idx, Lk_val);
+    // S_k = D_k - L_k E_{k-1}
+    fill_zero(S.as<double>(), (long long)nn, s);
+    hipLaunchKernelGGL(coupling_rows_kernel, dim3(G), dim3(128), 0, s, d, k, 0, ridx.as<int32_t>(),
+                       rval.as<double>());
+    hipLaunchKernelGGL(dense_from_rows_kernel, dim3(blocks_for(nb_, 256, 64)), dim3(256), 0, s, nb_,
+                       ridx.as<int32_t>(), rval.as<double>(), S.as<double>());
+    if (k > 0)
+      hipLaunchKernelGGL(schur_update_kernel, g2, dim3(256), 0, s, nb_, Lk_idx, Lk_val, Ed.as<double>(),
+                         S.as<double>());
+    STKKT_HIP(hipGetLastError());
+    // S_k^{-1} (column-major S is the row-major transpose: invert it as is)
+    gje_invert(nb_, S.as<double>(), tmp.as<double>(), rows.as<double>(), piv.as<int32_t>(), status.as<int>(), s);
+    // E_k = S_k^{-1} U_k
+    if (k + 1 < nlev_) {
+      hipLaunchKernelGGL(coupling_rows_kernel, dim3(G), dim3(128), 0, s, d, k, +1, ridx.as<int32_t>(),
+                         rval.as<double>());
+      STKKT_HIP(hipMemcpyAsync(hidx.data(), ridx.ptr, sizeof(int32_t) * hidx.size(), hipMemcpyDeviceToHost, s));
+      STKKT_HIP(hipMemcpyAsync(hval.data(), rval.ptr, sizeof(double) * hval.size(), hipMemcpyDeviceToHost, s));
+      STKKT_HIP(hipStreamSynchronize(s));
+      transpose_rows(nb_, hidx, hval, hcidx, hcval);
+      STKKT_HIP(hipMemcpyAsync(cidx.ptr, hcidx.data(), sizeof(int32_t) * hcidx.size(), hipMemcpyHostToDevice, s));
+      STKKT_HIP(hipMemcpyAsync(cval.ptr, hcval.data(), sizeof(double) * hcval.size(), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(e_from_cols_kernel, g2, dim3(256), 0, s, nb_, cidx.as<int32_t>(), cval.as<double>(),
+                         S.as<double>(), Ed.as<double>());
+      STKKT_HIP(hipGetLastError());
+    }
+    // store S_k^{-1} and E_k in the application precision
+    if (prec_ == STKKT_F32) {
+      hipLaunchKernelGGL(to_float_kernel, dim3(4096), dim3(256), 0, s, (long long)nn, S.as<double>(),
+                         Sinv_.as<float>() + (size_t)k * nn);
+      if (k + 1 < nlev_)
+        hipLaunchKernelGGL(to_float_kernel, dim3(4096), dim3(256), 0, s, (long long)nn, Ed.as<double>(),
+                           E_.as<float>() + (size_t)k * nn);
+    } else {
+      STKKT_HIP(hipMemcpyAsync(Sinv_.as<double>() + (size_t)k * nn, S.ptr, sizeof(double) * nn,
+                               hipMemcpyDeviceToDevice, s));
+      if (k + 1 < nlev_)
+        STKKT_HIP(hipMemcpyAsync(E_.as<double>() + (size_t)k * nn, Ed.ptr, sizeof(double) * nn,
+                                 hipMemcpyDeviceToDevice, s));
+    }
+    STKKT_HIP(hipGetLastError());
+  }
+  int st = 0;
+  STKKT_HIP(hipMemcpyAsync(&st, status.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+  STKKT_HIP(hipStreamSynchronize(s));   // the setup buffers are released on return
+  if (st) throw Error(STKKT_EBREAKDOWN, "coarse LU: singular Schur complement block");
+}
+
+template <typename T>
+static void gemv(int nb, const T *A, const double *x, const double *base, double sign, double *partial, double *out,
+                 hipStream_t s) {
+  const int nch = (nb + kGvCols - 1) / kGvCols;
+  hipLaunchKernelGGL(gemv_partial_kernel<T>, dim3((nb + kGvRows - 1) / kGvRows, nch), dim3(kGvRows), 0, s, nb, A, x,
+                     partial);
+  hipLaunchKernelGGL(gemv_reduce_kernel, dim3(blocks_for(nb, 256, 256)), dim3(256), 0, s, nb, nch, partial, base,
+                     sign, out);
+}
+
+template <typename T> void CoarseLU::solve_t(const double *r, double *x, hipStream_t s) const {
+  const size_t nn = (size_t)nb_ * nb_;
+  const T *Si = static_cast<const T *>(Sinv_.ptr);
+  const T *E = static_cast<const T *>(E_.ptr);
+  double *t = t_.as<double>(), *part = partial_.as<double>();
+  // forward: y_k = S_k^{-1} (r_k - L_k y_{k-1}), y kept in x
+  for (int k = 0; k < nlev_; ++k) {
+    const double *rk = r + (size_t)k * nb_;
+    const double *yprev = k > 0 ? x + (size_t)(k - 1) * nb_ : nullptr;
+    hipLaunchKernelGGL(lower_rhs_kernel, dim3(blocks_for(nb_, 256, 256)), dim3(256), 0, s, nb_,
+                       Lidx_.as<int32_t>() + (size_t)k * nb_ * 81, Lval_.as<double>() + (size_t)k * nb_ * 81, rk,
+                       yprev, t);
+    gemv<T>(nb_, Si + (size_t)k * nn, t, nullptr, 1.0, part, x + (size_t)k * nb_, s);
+  }
+  // backward: x_k = y_k - E_k x_{k+1}
+  for (int k = nlev_ - 2; k >= 0; --k)
+    gemv<T>(nb_, E + (size_t)k * nn, x + (size_t)(k + 1) * nb_, x + (size_t)k * nb_, -1.0, part,
+            x + (size_t)k * nb_, s);
+  STKKT_HIP(hipGetLastError());
+}
+
+void CoarseLU::solve(const double *r, double *x, hipStream_t s) const {
+  if (prec_ == STKKT_F32) solve_t<float>(r, x, s);
+  else solve_t<double>(r, x, s);
+}
+
+size_t CoarseLU::bytes_per_solve() const {
+  const size_t esz = prec_ == STKKT_F32 ? sizeof(float) : sizeof(double);
+  return esz * (size_t)nb_ * nb_ * (2 * nlev_ - 1);
+}
+
+}  // namespace stkkt

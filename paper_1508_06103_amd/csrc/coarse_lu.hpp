@@ -1,0 +1,26 @@
+// Exact block-tridiagonal-in-time solve of the coarse KKT system.
+#pragma once
+
+#include "common.hpp"
+
+namespace stkkt {
+
+class CoarseLU {
+ public:
+  // Forms and inverts every Schur complement of the coarse operator `cop`
+  // (FP64 setup); the inverses and E_k are kept in `precision`.
+  CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStream_t s);
+  // x = F_c^{-1} r (device vectors of 3 N_c (M_c + 1) doubles, no aliasing)
+  void solve(const double *r, double *x, hipStream_t s) const;
+  // bytes of dense blocks streamed by one solve
+  size_t bytes_per_solve() const;
+
+ private:
+  template <typename T> void solve_t(const double *r, double *x, hipStream_t s) const;
+  const Allocator *al_;
+  int prec_;
+  int nb_ = 0, nlev_ = 0;
+  DevBuf Sinv_, E_, Lidx_, Lval_, partial_, t_;
+};
+
+}  // namespace stkkt

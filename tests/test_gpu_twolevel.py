@@ -141,3 +141,45 @@ def test_coarse_errors(st):
     pre_other = st.RAS(other, (2, 2, 2, 2), 1)
     with pytest.raises(st.StkktError):
         st.solve(other, pre_other, coarse=C, flexible=True)
+
+
+@pytest.mark.parametrize("name,precision,tol", [("cube8x16", "f64", 1e-9), ("aniso", "f64", 1e-9),
+                                                ("otd_neumann", "f64", 1e-9), ("cube8x16", "f32", 1e-4)])
+def test_coarse_lu_correction(st, name, precision, tol):
+    """Exact coarse solve (block elimination in time) against the oracle's block LU."""
+    prob, fac, _ = case(name)
+    _say(f"case {name}: coarse LU ({precision}), factor {fac}")
+    op = st.KKTOperator(prob)
+    C = st.Coarse(op, fac, method=st.COARSE_LU, precision=st.F64 if precision == "f64" else st.F32)
+    tl = twolevel.TwoLevel(prob, None, None, fac, coarse="lu")
+    for seed in (1, 2):
+        x = np.random.default_rng(seed).standard_normal(prob.unknowns)
+        y = C.apply(_dev(x)).cpu().numpy()
+        y_ref = tl.coarse_correction(x)
+        err = np.linalg.norm(y - y_ref) / np.linalg.norm(y_ref)
+        _say(f"  seed {seed}: rel err {err:.2e}")
+        assert err <= tol
+
+
+def test_two_level_lu_fgmres_parity(st):
+    prob, fac, cparts = case("cube8x16")
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, (2, 2, 2, 2), 1)
+    C = st.Coarse(op, fac, method=st.COARSE_LU)
+    x, s = st.solve(op, pre, coarse=C, restart=30, rtol=1e-6, flexible=True)
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    b = kkt.rhs(prob)
+    A = lambda v: F @ v
+    R = oras.RAS(prob, (2, 2, 2, 2), 1, terms=terms)
+    tl = twolevel.TwoLevel(prob, R.apply, A, fac, coarse="lu")
+    xo, so = krylov.gmres(A, tl, b, restart=30, rtol=1e-6, flexible=True)
+    res = np.linalg.norm(b - F @ x.cpu().numpy()) / np.linalg.norm(b)
+    _say(f"  two-level (coarse LU): gpu {s.iters} its, oracle {so.iters} its, true res {res:.2e}")
+    assert s.converged and res <= 1e-6 and abs(s.iters - so.iters) <= 1
+    k = so.iters
+    x2, _ = st.solve(op, pre, coarse=C, restart=30, rtol=1e-6, flexible=True, fixed_iters=k)
+    xo2, _ = krylov.gmres(A, tl, b, restart=30, rtol=1e-6, flexible=True, fixed_iters=k)
+    e = np.linalg.norm(x2.cpu().numpy() - xo2) / np.linalg.norm(xo2)
+    _say(f"  fixed {k} steps: rel diff {e:.2e}")
+    assert e <= 1e-7
