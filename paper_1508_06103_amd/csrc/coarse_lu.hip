@@ -136,64 +136,69 @@ __device__ inline void block_argmax(double v, int i, double *sv, int *si) {
   __syncthreads();
 }
 
-// Unblocked Gauss-Jordan on the column panel [k, e) of all rows, with row
-// pivoting over rows >= c (whole rows are swapped).  One workgroup.
-__global__ void __launch_bounds__(1024) gje_panel_kernel(int n, int k, int e, double *__restrict__ A,
-                                                         int32_t *__restrict__ piv, int *__restrict__ status) {
+// Gauss-Jordan step for column c of the panel [k, e), part 1 (one
+// workgroup): pivot search over rows >= c, whole-row swap, and the pivot row's
+// panel segment divided by the pivot (its column-c entry replaced by 1 first);
+// the segment goes to prow.
+__global__ void __launch_bounds__(1024) gje_pivot_kernel(int n, int k, int e, int c, double *__restrict__ A,
+                                                         int32_t *__restrict__ piv, double *__restrict__ prow,
+                                                         int *__restrict__ status) {
   __shared__ double sv[16];
   __shared__ int si[16];
-  __shared__ double prow[kPanel];
-  for (int c = k; c < e; ++c) {
-    const int j = c - k;
-    double best = -1.0;
-    int bi = n;
-    for (int i = c + threadIdx.x; i < n; i += blockDim.x) {
-      const double v = fabs(A[(long long)i * n + c]);
-      if (v > best || (v == best && i < bi)) {
-        best = v;
-        bi = i;
-      }
+  if (*status) return;
+  double best = -1.0;
+  int bi = n;
+  for (int i = c + threadIdx.x; i < n; i += blockDim.x) {
+    const double v = fabs(A[(long long)i * n + c]);
+    if (v > best || (v == best && i < bi)) {
+      best = v;
+      bi = i;
     }
-    block_argmax(best, bi, sv, si);
-    const int p = si[0];
-    const double pv = sv[0];
-    if (!(pv > 0.0) || !std::isfinite(pv)) {
-      if (threadIdx.x == 0) *status = 1;
-      return;
-    }
-    if (p != c) {
-      for (int col = threadIdx.x; col < n; col += blockDim.x) {
-        const double t = A[(long long)c * n + col];
-        A[(long long)c * n + col] = A[(long long)p * n + col];
-        A[(long long)p * n + col] = t;
-      }
-      if (threadIdx.x == 0) {
-        const int32_t t = piv[c];
-        piv[c] = piv[p];
-        piv[p] = t;
-      }
-    }
-    __syncthreads();
-    // pivot row of the panel: a_cc <- 1, then the panel row / a_cc
-    const double a = A[(long long)c * n + c];
-    if (threadIdx.x < e - k) {
-      const int col = k + threadIdx.x;
-      const double v = col == c ? 1.0 : A[(long long)c * n + col];
-      prow[threadIdx.x] = v / a;
-    }
-    __syncthreads();
-    if (threadIdx.x < e - k) A[(long long)c * n + k + threadIdx.x] = prow[threadIdx.x];
-    // eliminate column c from every other row, inside the panel
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      if (i == c) continue;
-      double *Ai = A + (long long)i * n + k;
-      const double f = Ai[j];
-      Ai[j] = 0.0;
-      if (f != 0.0)
-        for (int q = 0; q < e - k; ++q) Ai[q] -= f * prow[q];
-    }
-    __syncthreads();
   }
+  block_argmax(best, bi, sv, si);
+  const int p = si[0];
+  const double pv = sv[0];
+  if (!(pv > 0.0) || !std::isfinite(pv)) {
+    if (threadIdx.x == 0) *status = 1;
+    return;
+  }
+  if (p != c) {
+    for (int col = threadIdx.x; col < n; col += blockDim.x) {
+      const double t = A[(long long)c * n + col];
+      A[(long long)c * n + col] = A[(long long)p * n + col];
+      A[(long long)p * n + col] = t;
+    }
+    if (threadIdx.x == 0) {
+      const int32_t t = piv[c];
+      piv[c] = piv[p];
+      piv[p] = t;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < e - k) {
+    const int col = k + threadIdx.x;
+    const double a = A[(long long)c * n + c];
+    const double v = (col == c ? 1.0 : A[(long long)c * n + col]) / a;
+    prow[threadIdx.x] = v;
+    A[(long long)c * n + col] = v;
+  }
+}
+
+// Part 2 (rows spread over the grid): eliminate column c from every other
+// row inside the panel, A[i][q] -= A[i][c] prow[q] (the column-c entry
+// becoming -A[i][c] prow[c]); one wavefront per row segment.
+__global__ void __launch_bounds__(256) gje_elim_kernel(int n, int k, int e, int c, double *__restrict__ A,
+                                                       const double *__restrict__ prow,
+                                                       const int *__restrict__ status) {
+  if (*status) return;
+  const int q = threadIdx.x & 63, w = e - k, j = c - k;
+  const double pq = q < w ? prow[q] : 0.0;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= n || i == c || q >= w) return;
+  double *Ai = A + (long long)i * n + k;
+  const double f = Ai[j];   // read by all 64 lanes before any lane's store (same instruction stream)
+  __builtin_amdgcn_wave_barrier();
+  Ai[q] = (q == j) ? -f * pq : Ai[q] - f * pq;
 }
 
 // Copy the panel rows [k, e) outside the panel columns: R[t][col] = A[k+t][col]
@@ -320,11 +325,15 @@ __global__ void to_float_kernel(long long n, const double *__restrict__ a, float
 
 // Explicit inverse of the n x n row-major matrix in A (overwritten with the
 // inverse).  tmp: n x n scratch; rows: kPanel x n scratch; piv: n int32.
-static void gje_invert(int n, double *A, double *tmp, double *rows, int32_t *piv, int *status, hipStream_t s) {
+static void gje_invert(int n, double *A, double *tmp, double *rows, int32_t *piv, double *prow, int *status,
+                       hipStream_t s) {
   hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(n, 256, 64)), dim3(256), 0, s, n, piv);
   for (int k = 0; k < n; k += kPanel) {
     const int e = std::min(n, k + kPanel);
-    hipLaunchKernelGGL(gje_panel_kernel, dim3(1), dim3(1024), 0, s, n, k, e, A, piv, status);
+    for (int c = k; c < e; ++c) {
+      hipLaunchKernelGGL(gje_pivot_kernel, dim3(1), dim3(1024), 0, s, n, k, e, c, A, piv, prow, status);
+      hipLaunchKernelGGL(gje_elim_kernel, dim3((n + 3) / 4), dim3(256), 0, s, n, k, e, c, A, prow, status);
+    }
     hipLaunchKernelGGL(gje_copy_rows_kernel, dim3(blocks_for(n, 256, 64), e - k), dim3(256), 0, s, n, k, e, A,
                        rows);
     hipLaunchKernelGGL(gje_update_kernel, dim3((n + 63) / 64, (n + 63) / 64), dim3(256), 0, s, n, k, e, A, rows);
@@ -350,6 +359,7 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
   // setup work buffers (FP64)
   DevBuf S(al, sizeof(double) * nn), Ed(al, sizeof(double) * nn),
       tmp(al, sizeof(double) * nn), rows(al, sizeof(double) * (size_t)kPanel * nb_), piv(al, sizeof(int32_t) * nb_),
+      prow(al, sizeof(double) * kPanel),
       status(al, 256), ridx(al, sizeof(int32_t) * (size_t)nb_ * 81), rval(al, sizeof(double) * (size_t)nb_ * 81),
       cidx(al, sizeof(int32_t) * (size_t)nb_ * 81), cval(al, sizeof(double) * (size_t)nb_ * 81);
   STKKT_HIP(hipMemsetAsync(status.ptr, 0, sizeof(int), s));
@@ -373,7 +383,8 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
                          S.as<double>());
     STKKT_HIP(hipGetLastError());
     // S_k^{-1} (column-major S is the row-major transpose: invert it as is)
-    gje_invert(nb_, S.as<double>(), tmp.as<double>(), rows.as<double>(), piv.as<int32_t>(), status.as<int>(), s);
+    gje_invert(nb_, S.as<double>(), tmp.as<double>(), rows.as<double>(), piv.as<int32_t>(), prow.as<double>(),
+               status.as<int>(), s);
     // E_k = S_k^{-1} U_k
     if (k + 1 < nlev_) {
       hipLaunchKernelGGL(coupling_rows_kernel, dim3(G), dim3(128), 0, s, d, k, +1, ridx.as<int32_t>(),
