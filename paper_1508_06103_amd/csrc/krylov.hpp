@@ -17,6 +17,14 @@ void gs_update(double *w, const double *V, long long ldv, int k, const double *h
 // out = sum_i y[i] V_i (+ out if accumulate)  (y: device)
 void combine(double *out, const double *V, long long ldv, int k, const double *y, long long n, bool accumulate,
              hipStream_t s);
+// Fused CGS2 passes (k <= 64 basis vectors, cgs2_fused_ok):
+//   update_dot:  w -= sum_i h[i] V_i, then out[i] = V_i . w   (V read once)
+//   update_norm: w -= sum_i h[i] V_i, then out[0] = w . w
+bool cgs2_fused_ok(int k);
+void update_dot(double *w, const double *V, long long ldv, int k, const double *h, long long n, double *partial,
+                double *out, hipStream_t s);
+void update_norm(double *w, const double *V, long long ldv, int k, const double *h, long long n, double *partial,
+                 double *out, hipStream_t s);
 void axpby(double *out, double a, const double *x, double b, const double *y, long long n, hipStream_t s);
 void scale(double *out, const double *x, double a, long long n, hipStream_t s);
 

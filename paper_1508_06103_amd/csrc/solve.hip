@@ -124,11 +124,17 @@ int gmres_solve(const kkt_op *op, const ras *R, const coarse *C, const solve_par
       double *zj = flex ? Zd + (long long)j * n : u;
       precond(vj, zj);
       matvec_device(op, zj, w, s);
+      // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; |w|^2
       multidot(Vd, n, j + 1, w, n, partial.as<double>(), hd, s);
-      gs_update(w, Vd, n, j + 1, hd, n, s);
-      multidot(Vd, n, j + 1, w, n, partial.as<double>(), hd + (m + 1), s);
-      gs_update(w, Vd, n, j + 1, hd + (m + 1), n, s);
-      multidot(w, 0, 1, w, n, partial.as<double>(), hd + 2 * (m + 1), s);
+      if (cgs2_fused_ok(j + 1)) {
+        update_dot(w, Vd, n, j + 1, hd, n, partial.as<double>(), hd + (m + 1), s);
+        update_norm(w, Vd, n, j + 1, hd + (m + 1), n, partial.as<double>(), hd + 2 * (m + 1), s);
+      } else {
+        gs_update(w, Vd, n, j + 1, hd, n, s);
+        multidot(Vd, n, j + 1, w, n, partial.as<double>(), hd + (m + 1), s);
+        gs_update(w, Vd, n, j + 1, hd + (m + 1), n, s);
+        multidot(w, 0, 1, w, n, partial.as<double>(), hd + 2 * (m + 1), s);
+      }
       STKKT_HIP(hipMemcpyAsync(hh.p, hd, sizeof(double) * hlen, hipMemcpyDeviceToHost, s));
       STKKT_HIP(hipStreamSynchronize(s));
       const double hn = std::sqrt(hh.p[2 * (m + 1)]);
