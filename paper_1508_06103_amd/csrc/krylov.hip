@@ -125,12 +125,27 @@ __global__ void __launch_bounds__(kThreads) update_dot_kernel(double *__restrict
   const long long hi = lo + per < n ? lo + per : n;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   double acc = 0.0;   // dot of basis vector g = lane over this wave's quarter of every tile
+  // the next tile's basis entries are loaded into registers while the current
+  // tile is processed (entry q = t + 256 r of the k x 64 tile)
+  constexpr int kPre = kFuseMax * kTile / kThreads;
+  double pre[kPre];
+  auto fetch = [&](long long e0) {
+    const int m = (int)(hi - e0 < kTile ? hi - e0 : kTile);
+#pragma unroll
+    for (int r = 0; r < kPre; ++r) {
+      const int q = t + kThreads * r, g = q / kTile, e = q % kTile;
+      pre[r] = (g < k && e < m) ? V[(long long)g * ldv + e0 + e] : 0.0;
+    }
+  };
+  if (lo < hi) fetch(lo);
   for (long long e0 = lo; e0 < hi; e0 += kTile) {
     const int m = (int)(hi - e0 < kTile ? hi - e0 : kTile);
-    for (int q = t; q < k * kTile; q += kThreads) {
-      const int g = q / kTile, e = q % kTile;
-      Vs[g][e] = e < m ? V[(long long)g * ldv + e0 + e] : 0.0;
+#pragma unroll
+    for (int r = 0; r < kPre; ++r) {
+      const int q = t + kThreads * r, g = q / kTile, e = q % kTile;
+      if (g < k) Vs[g][e] = pre[r];
     }
+    if (e0 + kTile < hi) fetch(e0 + kTile);
     __syncthreads();
     // update: each wave sums a quarter of the basis vectors for every element of the tile
     {
