@@ -98,6 +98,7 @@ ShapeHost make_shape(const int dims[4]) {
   // chunk-major factor layout: for level L, 64-row chunk c of the level, slot s,
   // the blocks of the chunk's rows that have neighbour s, entry-major:
   // element (e, k) at ctab.off9 + e * ctab.cnt + k, k = rank inside the chunk
+  if ((size_t)sh.nlev * sh.nchunk * 81 * 2 > (size_t)INT32_MAX) throw Error(STKKT_EINVAL, "ras_setup: subdomain too large");
   sh.ctab.assign((size_t)sh.nlev * sh.nchunk * 81 * 2, 0);
   int64_t off = 0;
   for (int L = 0; L < sh.nlev; ++L) {
@@ -345,10 +346,14 @@ struct SweepArgs {
   double *z;
 };
 
-// (element offset inside the subdomain, count) of the blocks of (level L, chunk cl, slot s)
+// (element offset inside the subdomain, count) of the blocks of (level L, chunk cl, slot s).
+// All arguments are wavefront-uniform; the index is made so explicitly, so that
+// the entry comes through the scalar cache and never queues behind the factor
+// loads in flight (a vector load here would have to drain them before the
+// addresses that depend on it could be formed).
 template <typename T>
 __device__ inline void chunk_slot(const SweepArgs<T> &a, int L, int cl, int s, int64_t &off9, int64_t &cnt) {
-  const int64_t i = (((int64_t)L * a.sh.nchunk + cl) * 81 + s) * 2;
+  const int i = __builtin_amdgcn_readfirstlane(((L * a.sh.nchunk + cl) * 81 + s) * 2);
   off9 = a.ct[i];
   cnt = a.ct[i + 1];
 }
@@ -471,7 +476,7 @@ __device__ inline void sweep(const SweepArgs<T> &a, T (*part)[kRows][3], uint64_
       } else {
         const int qrow = seg * kRows + tq;   // slot 40: every row of the chunk, rank = row & 63
         int64_t off9, cnt;
-        chunk_slot(a, L, qrow >> 6, 40, off9, cnt);
+        chunk_slot(a, L, __builtin_amdgcn_readfirstlane(qrow >> 6), 40, off9, cnt);
         const T *d = a.F + a.sd.fbase + off9 + (qrow & 63);
 #pragma unroll
         for (int e = 0; e < 9; ++e) pre[e] = *(d + (int64_t)e * cnt);
@@ -620,38 +625,71 @@ struct Ring {
   int ltlz;   // (t, z) groups per level
 };
 
+// Boundary code of a row of the subdomain box: bit k set if the row lies on
+// the low face of dimension k, bit 4+k on the high face.  A stencil slot whose
+// offset leaves the box through one of those faces has no neighbour there.
+template <typename T>
+__device__ inline int face_code(const SweepArgs<T> &a, int x, int y, int zc, int t) {
+  return (x == 0 ? 1 : 0) | (y == 0 ? 2 : 0) | (zc == 0 ? 4 : 0) | (t == 0 ? 8 : 0) |
+         (x == a.sh.dims[0] - 1 ? 16 : 0) | (y == a.sh.dims[1] - 1 ? 32 : 0) | (zc == a.sh.dims[2] - 1 ? 64 : 0) |
+         (t == a.sh.dims[3] - 1 ? 128 : 0);
+}
+
+// The faces (same bit layout) through which slot offset (dx, dy, dz, dt) leaves.
+__device__ inline int slot_faces(int dx, int dy, int dz, int dt) {
+  return (dx < 0 ? 1 : 0) | (dy < 0 ? 2 : 0) | (dz < 0 ? 4 : 0) | (dt < 0 ? 8 : 0) | (dx > 0 ? 16 : 0) |
+         (dy > 0 ? 32 : 0) | (dz > 0 ? 64 : 0) | (dt > 0 ? 128 : 0);
+}
+
 // Factor loads of all five slots of this wavefront for chunk c of phase p.
+// The chunk-table entries of the five slots are adjacent and are requested
+// together, so a single scalar round trip precedes the 45 vector loads.
+// The chunk is given by its level L, its chunk index cl inside the level and
+// its number of rows (done: past the last phase, nothing is loaded).
 template <typename T, bool kFwd>
-__device__ inline void load_chunk_f(const SweepArgs<T> &a, const Phase &p, int c, uint64_t cw, int wave,
-                                    T (&f)[kSlotsPerWave][9]) {
+__device__ inline void load_chunk_f(const SweepArgs<T> &a, bool done, int L, int cl, int rows, uint64_t cw,
+                                    int wave, T (&f)[kSlotsPerWave][9]) {
   const int lane = (int)__lane_id();
   int x, y, zc, t;
   unpack(cw, x, y, zc, t);
-  const bool valid = !p.done && c * 64 + lane < p.segR;
-  const int cl = ((p.seg * kRows) >> 6) + c;
+  const bool valid = !done && lane < rows;
+  const int code = face_code(a, x, y, zc, t);
+  const int s0 = (kFwd ? 0 : 41) + kSlotsPerWave * wave;
+  int32_t tab[2 * kSlotsPerWave];
+  if (!done) {
+    const int i0 = __builtin_amdgcn_readfirstlane(((L * a.sh.nchunk + cl) * 81 + s0) * 2);
+#pragma unroll
+    for (int k = 0; k < 2 * kSlotsPerWave; ++k) tab[k] = a.ct[i0 + k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 2 * kSlotsPerWave; ++k) tab[k] = 0;
+  }
 #pragma unroll
   for (int j = 0; j < kSlotsPerWave; ++j) {
-    const int s = (kFwd ? 0 : 41) + kSlotsPerWave * wave + j;
     int dx, dy, dz, dt;
-    slot_off(s, dx, dy, dz, dt);
-    const bool has = valid && inside(x + dx, y + dy, zc + dz, t + dt, a.sh.dims);
+    slot_off(s0 + j, dx, dy, dz, dt);
+    const bool has = valid && (code & slot_faces(dx, dy, dz, dt)) == 0;
     const unsigned long long mask = __ballot(has);
-    int64_t fi = a.fzero, stride = 0;
-    if (!p.done) {
-      int64_t off9, cnt;
-      chunk_slot(a, p.L, cl, s, off9, cnt);
-      if (has) {
-        fi = a.sd.fbase + off9 + (int64_t)lanes_below(mask);
-        stride = cnt;
-      }
-    }
+    const int64_t fi = has ? a.sd.fbase + tab[2 * j] + (int64_t)lanes_below(mask) : a.fzero;
+    const int64_t stride = has ? tab[2 * j + 1] : 0;
     const T *q = a.F + fi;
 #pragma unroll
     for (int e = 0; e < 9; ++e) f[j][e] = *(q + e * stride);
   }
 }
 
-// Multiply chunk c of phase p: neighbour values from the LDS ring.
+template <typename T, bool kFwd>
+__device__ inline void load_chunk_f(const SweepArgs<T> &a, const Phase &p, int c, uint64_t cw, int wave,
+                                    T (&f)[kSlotsPerWave][9]) {
+  load_chunk_f<T, kFwd>(a, p.done, p.L, p.seg * (kRows / 64) + c, p.segR - 64 * c, cw, wave, f);
+}
+
+// Multiply chunk c of phase p: neighbour values from the LDS ring.  All rows
+// of a phase lie on level p.L, so a slot's neighbours all lie on level
+// p.L + dx + 2dy + 4dz + 8dt, and its ring slot is the same for the whole
+// wavefront.  The lookups carry no branches: rows without the neighbour read
+// ring entry 0 and discard the value, so the LDS requests of the five slots
+// can be in flight together.
 template <typename T, bool kFwd>
 __device__ inline void mac_chunk_ring(const SweepArgs<T> &a, const Phase &p, int c, uint64_t cw, int wave,
                                       const T (&f)[kSlotsPerWave][9], const T *yring, const int32_t *tzr,
@@ -660,29 +698,72 @@ __device__ inline void mac_chunk_ring(const SweepArgs<T> &a, const Phase &p, int
   int x, y, zc, t;
   unpack(cw, x, y, zc, t);
   const bool valid = c * 64 + lane < p.segR;
+  const int code = face_code(a, x, y, zc, t);
   const int lx = a.sh.dims[0], lz = a.sh.dims[2];
+  const int xy = x + 2 * y, tz = t * lz + zc;
+  const int s0 = (kFwd ? 0 : 41) + kSlotsPerWave * wave;
+  // all prefix-row lookups first, so that they are in flight together
+  int hb = 0, qv[kSlotsPerWave];
 #pragma unroll
   for (int j = 0; j < kSlotsPerWave; ++j) {
-    const int s = (kFwd ? 0 : 41) + kSlotsPerWave * wave + j;
     int dx, dy, dz, dt;
-    slot_off(s, dx, dy, dz, dt);
-    const int nx = x + dx, ny = y + dy, nz = zc + dz, nt = t + dt;
-    const bool has = valid && inside(nx, ny, nz, nt, a.sh.dims);
-    T v0 = 0, v1 = 0, v2 = 0;
-    if (has) {
-      const int nL = nx + 2 * ny + 4 * nz + 8 * nt;
-      const int slot = nL & 15;
-      const int rem = nx + 2 * ny;   // = nL - 8 nt - 4 nz
-      const int ymin = max(0, (rem - lx + 2) >> 1);
-      const int q = tzr[slot * rg.ltlz + nt * lz + nz] + (ny - ymin);
-      const T *v = yring + ((int64_t)slot * rg.rmax + q) * 3;
-      v0 = v[0];
-      v1 = v[1];
-      v2 = v[2];
-    }
+    slot_off(s0 + j, dx, dy, dz, dt);
+    const bool has = valid && (code & slot_faces(dx, dy, dz, dt)) == 0;
+    hb |= has ? 1 << j : 0;
+    const int slot = (p.L + dx + 2 * dy + 4 * dz + 8 * dt) & 15;
+    qv[j] = tzr[has ? slot * rg.ltlz + tz + dt * lz + dz : 0];
+  }
+#pragma unroll
+  for (int j = 0; j < kSlotsPerWave; ++j) {
+    int dx, dy, dz, dt;
+    slot_off(s0 + j, dx, dy, dz, dt);
+    const bool has = (hb >> j) & 1;
+    const int slot = (p.L + dx + 2 * dy + 4 * dz + 8 * dt) & 15;
+    const int rem = xy + dx + 2 * dy;   // nx + 2 ny of the neighbour
+    const int ymin = max(0, (rem - lx + 2) >> 1);
+    const int vi = has ? (slot * rg.rmax + qv[j] + (y + dy - ymin)) * 3 : 0;
+    const T w0 = yring[vi], w1 = yring[vi + 1], w2 = yring[vi + 2];
+    const T v0 = has ? w0 : (T)0, v1 = has ? w1 : (T)0, v2 = has ? w2 : (T)0;
     a0 += f[j][0] * v0 + f[j][1] * v1 + f[j][2] * v2;
     a1 += f[j][3] * v0 + f[j][4] * v1 + f[j][5] * v2;
     a2 += f[j][6] * v0 + f[j][7] * v1 + f[j][8] * v2;
+  }
+}
+
+// Inputs of the final step of row tq of phase p (coordinates crd), requested
+// at the start of the phase: r (forward; kept in FP64 until it is used, so
+// that no conversion waits on the load while factor loads are in flight), or
+// inv(U_rr) and y (backward).  The chunk-table entry of the diagonal slot is
+// wavefront-uniform (a wavefront holds 64 consecutive rows) and is read
+// through the scalar cache.
+template <typename T, bool kFwd>
+__device__ inline void load_pre(const SweepArgs<T> &a, const Phase &p, const uint64_t *crd, T (&pre)[12],
+                                double (&rin)[3]) {
+  const int tq = (int)threadIdx.x;
+  if (tq >= p.segR) return;
+  int x, y, zc, t;
+  unpack(crd[tq], x, y, zc, t);
+  if (kFwd) {
+    const int64_t gi = global_row(a, x, y, zc, t);
+    rin[0] = a.r[gi];
+    rin[1] = a.r[gi + 1];
+    rin[2] = a.r[gi + 2];
+  } else {
+    const int qrow = p.seg * kRows + tq;
+    int64_t off9, cnt;
+    chunk_slot(a, p.L, qrow >> 6, 40, off9, cnt);
+    // the row's place in its chunk is made opaque here, so that the compiler
+    // forms this address inside the sweep loop instead of keeping a per-lane
+    // pointer alive across it (which does not fit the FP64 register budget)
+    int lrow = qrow & 63;
+    asm volatile("" : "+v"(lrow));
+    const T *d = a.F + a.sd.fbase + off9 + lrow;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) pre[e] = *(d + (int64_t)e * cnt);
+    const int64_t yo = a.sd.sbase + 3 * yrow_of(a, x, y, zc, t);
+    pre[9] = a.Y[yo];
+    pre[10] = a.Y[yo + 1];
+    pre[11] = a.Y[yo + 2];
   }
 }
 
@@ -692,7 +773,7 @@ __device__ inline void mac_chunk_ring(const SweepArgs<T> &a, const Phase &p, int
 // the output); the result goes into the LDS ring.
 template <typename T, bool kFwd>
 __device__ inline void ring_finish(const SweepArgs<T> &a, const Phase &pc, const uint64_t *crd, T (*part)[kRows][3],
-                                   const T (&pre)[12], T *yring, const Ring &rg) {
+                                   const T (&pre)[12], const double (&rin)[3], T *yring, const Ring &rg) {
   const int tq = (int)threadIdx.x;
   if (tq < pc.segR) {
     const uint64_t fc = crd[tq];
@@ -708,7 +789,7 @@ __device__ inline void ring_finish(const SweepArgs<T> &a, const Phase &pc, const
     int x, y, zc, t;
     unpack(fc, x, y, zc, t);
     if (kFwd) {
-      for (int k = 0; k < 3; ++k) o[k] = pre[k] - s3[k];
+      for (int k = 0; k < 3; ++k) o[k] = (T)rin[k] - s3[k];
       T *yg = a.Y + a.sd.sbase + 3 * yrow_of(a, x, y, zc, t);
       for (int k = 0; k < 3; ++k) yg[k] = o[k];
     } else {
@@ -734,45 +815,27 @@ template <typename T, bool kFwd>
 __device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int nlev, int wave, Phase &pc, int &cc,
                                  int &par, Phase &pn, Phase &pnn, const T (&fcur)[kSlotsPerWave][9],
                                  T (&fnext)[kSlotsPerWave][9], T (*part)[kRows][3], uint64_t *crd2, T *yring,
-                                 int32_t *tzr, const Ring &rg, uint64_t &c2, int &tzrow, T (&pre)[12]) {
+                                 int32_t *tzr, const Ring &rg, uint64_t &c2, int &tzrow, T (&pre)[12],
+                                 double (&rin)[3]) {
   const int lane = (int)__lane_id();
   const int tq = (int)threadIdx.x;
   // requests of the phase, issued when its first chunk is multiplied: coordinates
   // two phases ahead, the (t, z) prefix row of a new level, final-step inputs
   if (cc == 0) {
     if (!pnn.done && tq < pnn.segR) c2 = a.crd[a.sh.coord_off + pnn.r0 + pnn.seg * kRows + tq];
-    if (pc.seg == 0 && tq < rg.ltlz) tzrow = tzp[(int64_t)pc.L * rg.ltlz + tq];
-    if (tq < pc.segR) {
-      const uint64_t fc = crd2[par * kRows + tq];
-      int x, y, zc, t;
-      unpack(fc, x, y, zc, t);
-      if (kFwd) {
-        const int64_t gi = global_row(a, x, y, zc, t);
-        pre[0] = (T)a.r[gi];
-        pre[1] = (T)a.r[gi + 1];
-        pre[2] = (T)a.r[gi + 2];
-      } else {
-        const int qrow = pc.seg * kRows + tq;
-        int64_t off9, cnt;
-        chunk_slot(a, pc.L, qrow >> 6, 40, off9, cnt);
-        const T *d = a.F + a.sd.fbase + off9 + (qrow & 63);
-#pragma unroll
-        for (int e = 0; e < 9; ++e) pre[e] = *(d + (int64_t)e * cnt);
-        const int64_t yo = a.sd.sbase + 3 * yrow_of(a, x, y, zc, t);
-        pre[9] = a.Y[yo];
-        pre[10] = a.Y[yo + 1];
-        pre[11] = a.Y[yo + 2];
-      }
-    }
+    if (pc.seg == 0 && tq < rg.ltlz) tzrow = tzp[pc.L * rg.ltlz + tq];
+    load_pre<T, kFwd>(a, pc, crd2 + par * kRows, pre, rin);
   }
   // next chunk: same phase, or the first chunk of the next phase
   const bool last = cc == pc.nch - 1;
   {
-    const Phase &pt = last ? pn : pc;
+    // chosen with selects, field by field, so that the phases stay in registers
+    const bool tdone = last ? pn.done : pc.done;
+    const int tL = last ? pn.L : pc.L, tseg = last ? pn.seg : pc.seg, tsegR = last ? pn.segR : pc.segR;
     const int ct = last ? 0 : cc + 1;
     const int pt_par = last ? par ^ 1 : par;
     const uint64_t cw = crd2[pt_par * kRows + ct * 64 + lane];
-    load_chunk_f<T, kFwd>(a, pt, ct, cw, wave, fnext);
+    load_chunk_f<T, kFwd>(a, tdone, tL, tseg * (kRows / 64) + ct, tsegR - 64 * ct, cw, wave, fnext);
   }
   // multiply the current chunk
   {
@@ -791,7 +854,7 @@ __device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int n
   }
   // close the phase
   lds_barrier();
-  ring_finish<T, kFwd>(a, pc, crd2 + par * kRows, part, pre, yring, rg);
+  ring_finish<T, kFwd>(a, pc, crd2 + par * kRows, part, pre, rin, yring, rg);
   if (pc.seg == 0 && tq < rg.ltlz) tzr[(pc.L & 15) * rg.ltlz + tq] = tzrow;
   if (!pnn.done && tq < pnn.segR) crd2[par * kRows + tq] = c2;   // phase after next reuses this buffer
   lds_barrier();
@@ -823,12 +886,15 @@ __device__ inline void sweep_ring(const SweepArgs<T> &a, cptr<int32_t> tzp, T (*
   uint64_t c2 = 0;
   int tzrow = 0;
   T pre[12];
+  double rin[3];
   T fA[kSlotsPerWave][9], fB[kSlotsPerWave][9];
   load_chunk_f<T, kFwd>(a, pc, 0, crd2[lane], wave, fA);
   for (;;) {
-    ring_step<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, fA, fB, part, crd2, yring, tzr, rg, c2, tzrow, pre);
+    ring_step<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, fA, fB, part, crd2, yring, tzr, rg, c2, tzrow, pre,
+                       rin);
     if (pc.done) break;
-    ring_step<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, fB, fA, part, crd2, yring, tzr, rg, c2, tzrow, pre);
+    ring_step<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, fB, fA, part, crd2, yring, tzr, rg, c2, tzrow, pre,
+                       rin);
     if (pc.done) break;
   }
 }
@@ -844,59 +910,28 @@ template <typename T, bool kFwd>
 __device__ inline void ring_step2(const SweepArgs<T> &a, cptr<int32_t> tzp, int nlev, int wave, Phase &pc, int &cc,
                                   int &par, Phase &pn, Phase &pnn, Phase &p3, const T (&fcur)[kSlotsPerWave][9],
                                   T (&fload)[kSlotsPerWave][9], T (*part)[kRows][3], uint64_t *crd3, T *yring,
-                                  int32_t *tzr, const Ring &rg, uint64_t &c3, int &tzrow, T (&pre)[12]) {
+                                  int32_t *tzr, const Ring &rg, uint64_t &c3, int &tzrow, T (&pre)[12],
+                                  double (&rin)[3]) {
   const int lane = (int)__lane_id();
   const int tq = (int)threadIdx.x;
   if (cc == 0) {
     if (!p3.done && tq < p3.segR) c3 = a.crd[a.sh.coord_off + p3.r0 + p3.seg * kRows + tq];
-    if (pc.seg == 0 && tq < rg.ltlz) tzrow = tzp[(int64_t)pc.L * rg.ltlz + tq];
-    if (tq < pc.segR) {
-      const uint64_t fc = crd3[par * kRows + tq];
-      int x, y, zc, t;
-      unpack(fc, x, y, zc, t);
-      if (kFwd) {
-        const int64_t gi = global_row(a, x, y, zc, t);
-        pre[0] = (T)a.r[gi];
-        pre[1] = (T)a.r[gi + 1];
-        pre[2] = (T)a.r[gi + 2];
-      } else {
-        const int qrow = pc.seg * kRows + tq;
-        int64_t off9, cnt;
-        chunk_slot(a, pc.L, qrow >> 6, 40, off9, cnt);
-        const T *d = a.F + a.sd.fbase + off9 + (qrow & 63);
-#pragma unroll
-        for (int e = 0; e < 9; ++e) pre[e] = *(d + (int64_t)e * cnt);
-        const int64_t yo = a.sd.sbase + 3 * yrow_of(a, x, y, zc, t);
-        pre[9] = a.Y[yo];
-        pre[10] = a.Y[yo + 1];
-        pre[11] = a.Y[yo + 2];
-      }
-    }
+    if (pc.seg == 0 && tq < rg.ltlz) tzrow = tzp[pc.L * rg.ltlz + tq];
+    load_pre<T, kFwd>(a, pc, crd3 + par * kRows, pre, rin);
   }
   // the chunk two steps ahead: (pc, cc+2), (pn, 0), (pn, 1) or (pnn, 0)
   {
     const int p1 = par == 2 ? 0 : par + 1, p2 = par == 0 ? 2 : par - 1;
-    const Phase *pt;
-    int ct, tpar;
-    if (cc + 2 < pc.nch) {
-      pt = &pc;
-      ct = cc + 2;
-      tpar = par;
-    } else if (cc + 2 == pc.nch) {
-      pt = &pn;
-      ct = 0;
-      tpar = p1;
-    } else if (!pn.done && pn.nch >= 2) {
-      pt = &pn;
-      ct = 1;
-      tpar = p1;
-    } else {
-      pt = &pnn;
-      ct = 0;
-      tpar = p2;
-    }
+    // chosen with selects, field by field, so that the phases stay in registers
+    const int which = cc + 2 < pc.nch ? 0 : (cc + 2 == pc.nch || (!pn.done && pn.nch >= 2)) ? 1 : 2;
+    const bool tdone = which == 0 ? pc.done : which == 1 ? pn.done : pnn.done;
+    const int tL = which == 0 ? pc.L : which == 1 ? pn.L : pnn.L;
+    const int tseg = which == 0 ? pc.seg : which == 1 ? pn.seg : pnn.seg;
+    const int tsegR = which == 0 ? pc.segR : which == 1 ? pn.segR : pnn.segR;
+    const int ct = which == 0 ? cc + 2 : which == 1 ? (cc + 2 == pc.nch ? 0 : 1) : 0;
+    const int tpar = which == 0 ? par : which == 1 ? p1 : p2;
     const uint64_t cw = crd3[tpar * kRows + ct * 64 + lane];
-    load_chunk_f<T, kFwd>(a, *pt, ct, cw, wave, fload);
+    load_chunk_f<T, kFwd>(a, tdone, tL, tseg * (kRows / 64) + ct, tsegR - 64 * ct, cw, wave, fload);
   }
   // multiply the current chunk
   {
@@ -915,7 +950,7 @@ __device__ inline void ring_step2(const SweepArgs<T> &a, cptr<int32_t> tzp, int 
   }
   // close the phase
   lds_barrier();
-  ring_finish<T, kFwd>(a, pc, crd3 + par * kRows, part, pre, yring, rg);
+  ring_finish<T, kFwd>(a, pc, crd3 + par * kRows, part, pre, rin, yring, rg);
   if (pc.seg == 0 && tq < rg.ltlz) tzr[(pc.L & 15) * rg.ltlz + tq] = tzrow;
   if (!p3.done && tq < p3.segR) crd3[par * kRows + tq] = c3;   // the phase three ahead reuses this buffer
   lds_barrier();
@@ -949,19 +984,20 @@ __device__ inline void sweep_ring2(const SweepArgs<T> &a, cptr<int32_t> tzp, T (
   uint64_t c3 = 0;
   int tzrow = 0;
   T pre[12];
+  double rin[3];
   T fA[kSlotsPerWave][9], fB[kSlotsPerWave][9], fC[kSlotsPerWave][9];
   load_chunk_f<T, kFwd>(a, pc, 0, crd3[lane], wave, fA);
   if (pc.nch >= 2) load_chunk_f<T, kFwd>(a, pc, 1, crd3[64 + lane], wave, fB);
   else load_chunk_f<T, kFwd>(a, pn, 0, crd3[kRows + lane], wave, fB);
   for (;;) {
     ring_step2<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, p3, fA, fC, part, crd3, yring, tzr, rg, c3, tzrow,
-                        pre);
+                        pre, rin);
     if (pc.done) break;
     ring_step2<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, p3, fB, fA, part, crd3, yring, tzr, rg, c3, tzrow,
-                        pre);
+                        pre, rin);
     if (pc.done) break;
     ring_step2<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, p3, fC, fB, part, crd3, yring, tzr, rg, c3, tzrow,
-                        pre);
+                        pre, rin);
     if (pc.done) break;
   }
 }
@@ -1050,8 +1086,14 @@ __global__ void __launch_bounds__(kApplyThreads, 2) apply_ring_batch_kernel(cons
   const int2 wk = load_uniform(work + blockIdx.x);
   if (!as_const(act)[wk.x]) return;
   const RasBatchDesc<T> d = load_uniform(descs + wk.x);
-  apply_ring_sub<T>(d.op, d.subs, wk.y, d.shapes, d.lvl, d.coords, d.ctab, d.tz, d.F, d.Y, d.fzero, d.yzero, d.rg,
-                    r + d.voff, z + d.voff);
+  // The pointers are read as pointers from the constant address space: the
+  // compiler then takes them to address global memory and emits global loads.
+  // (Pointers rebuilt from copied words would be generic, and generic loads
+  // also count against the LDS counter, so every LDS wait of the sweep would
+  // drain the factor loads in flight.)
+  const cptr<RasBatchDesc<T>> dp = as_const(descs + wk.x);
+  apply_ring_sub<T>(d.op, dp->subs, wk.y, dp->shapes, dp->lvl, dp->coords, dp->ctab, dp->tz, dp->F, dp->Y, d.fzero,
+                    d.yzero, d.rg, r + d.voff, z + d.voff);
 }
 
 }  // namespace
