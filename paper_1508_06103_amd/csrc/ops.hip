@@ -386,8 +386,13 @@ __global__ void __launch_bounds__(kMvThreads) matvec_batch_kernel(const MvBatchD
   int i = 0;
   while (i + 1 < count && cd[i + 1].w0 <= w) ++i;
   if (!as_const(act)[i]) return;
-  const MvBatchDesc d = load_uniform(descs + i);
-  matvec_tile_body<KH>(d.op, d.tl, d.mc, d.atab, x + d.voff, y + d.voff, w - d.w0);
+  MvBatchDesc d = load_uniform(descs + i);
+  // pointers read as pointers from the constant address space are taken to
+  // address global memory (global loads); rebuilt from copied words they
+  // would be generic, and generic loads also wait on the LDS counter
+  d.op.a_elem = cd[i].op.a_elem;
+  d.op.sensor = cd[i].op.sensor;
+  matvec_tile_body<KH>(d.op, d.tl, d.mc, cd[i].atab, x + d.voff, y + d.voff, w - d.w0);
 }
 
 }  // namespace

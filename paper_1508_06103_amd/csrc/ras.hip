@@ -47,6 +47,16 @@ __host__ __device__ inline void unpack(uint64_t c, int &x, int &y, int &z, int &
   t = (int)(c >> 48);
 }
 
+// Place of entry e (row-major 3x3) of block k in a group of cnt blocks: the
+// entries 0-3 of all blocks as consecutive quads, then entries 4-7 as quads,
+// then entry 8.  Groups start on a multiple of kGroupAlign elements, so a
+// lane reads its block with two 16-byte loads plus one (FP32) or four plus
+// one (FP64).
+constexpr int kGroupAlign = 4;
+__host__ __device__ inline int64_t blk_pos(int e, int64_t k, int64_t cnt) {
+  return e < 4 ? 4 * k + e : e < 8 ? 4 * cnt + 4 * k + (e - 4) : 8 * cnt + k;
+}
+
 // Crout-ordered elimination: the entry of row i at slot st is
 //   A_it - sum_k L_ik U_kt  over lower neighbours k of i with t an upper
 // neighbour of k (slot pair (sk, su) with off(sk) + off(su) = off(st), sk < 40
@@ -96,8 +106,8 @@ ShapeHost make_shape(const int dims[4]) {
   sh.nchunk = (sh.rmax + 63) / 64;
   const int32_t d32[4] = {lx, ly, lz, lt};
   // chunk-major factor layout: for level L, 64-row chunk c of the level, slot s,
-  // the blocks of the chunk's rows that have neighbour s, entry-major:
-  // element (e, k) at ctab.off9 + e * ctab.cnt + k, k = rank inside the chunk
+  // the group of the blocks of the chunk's rows that have neighbour s (block k
+  // = rank of its row among them), entry e of block k at ctab.off + blk_pos(e, k, ctab.cnt)
   if ((size_t)sh.nlev * sh.nchunk * 81 * 2 > (size_t)INT32_MAX) throw Error(STKKT_EINVAL, "ras_setup: subdomain too large");
   sh.ctab.assign((size_t)sh.nlev * sh.nchunk * 81 * 2, 0);
   int64_t off = 0;
@@ -113,14 +123,16 @@ ShapeHost make_shape(const int dims[4]) {
           unpack(sh.coords[r0 + q], x, y, z, t);
           if (inside(x + dx, y + dy, z + dz, t + dt, d32)) ++cnt;
         }
-        if (9 * (off + cnt) > INT32_MAX) throw Error(STKKT_EINVAL, "ras_setup: subdomain too large");
+        const int64_t len = (9 * (int64_t)cnt + kGroupAlign - 1) / kGroupAlign * kGroupAlign;
+        if (off + len > INT32_MAX) throw Error(STKKT_EINVAL, "ras_setup: subdomain too large");
         const size_t i = (((size_t)L * sh.nchunk + c) * 81 + s) * 2;
-        sh.ctab[i] = (int32_t)(9 * off);
+        sh.ctab[i] = (int32_t)off;
         sh.ctab[i + 1] = cnt;
-        off += cnt;
+        off += len;
+        sh.nblocks += cnt;
       }
   }
-  sh.nblocks = off;
+  sh.felems = off;
   // tzpref[L][t][z]: rows of level L in earlier (t, z) groups (rows of a level
   // are ordered by (t, z, y), x being implied by the level)
   sh.tzpref.assign((size_t)sh.nlev * lt * lz, 0);
@@ -292,10 +304,10 @@ __global__ void __launch_bounds__(512) compact_kernel(const SubInfo *__restrict_
         const unsigned long long mask = __ballot(has);
         if (has) {
           const int32_t *ct = ctab + sh.ct_off + (((int64_t)L * sh.nchunk + c) * 81 + s) * 2;
-          const int64_t cnt = ct[1];
-          T *dst = F + sd.fbase + ct[0] + (int)lanes_below(mask);
+          const int64_t cnt = ct[1], k = lanes_below(mask);
+          T *dst = F + sd.fbase + ct[0];
           const double *src = Wb + rho * 729 + 9 * s;
-          for (int e = 0; e < 9; ++e) dst[e * cnt] = (T)src[e];
+          for (int e = 0; e < 9; ++e) dst[blk_pos(e, k, cnt)] = (T)src[e];
         }
       }
     }
@@ -358,6 +370,26 @@ __device__ inline void chunk_slot(const SweepArgs<T> &a, int L, int cl, int s, i
   cnt = a.ct[i + 1];
 }
 
+// Block k of a group of cnt blocks starting at g (blk_pos layout; g is
+// 16-byte aligned): two 16-byte loads and one 4-byte load.
+__device__ inline void load_block(const float *g, int64_t k, int64_t cnt, float (&f)[9]) {
+  const float4 a = *reinterpret_cast<const float4 *>(g + 4 * k);
+  const float4 b = *reinterpret_cast<const float4 *>(g + 4 * cnt + 4 * k);
+  f[0] = a.x, f[1] = a.y, f[2] = a.z, f[3] = a.w;
+  f[4] = b.x, f[5] = b.y, f[6] = b.z, f[7] = b.w;
+  f[8] = g[8 * cnt + k];
+}
+// FP64: four 16-byte loads and one 8-byte load.
+__device__ inline void load_block(const double *g, int64_t k, int64_t cnt, double (&f)[9]) {
+  const double2 a = *reinterpret_cast<const double2 *>(g + 4 * k);
+  const double2 b = *reinterpret_cast<const double2 *>(g + 4 * k + 2);
+  const double2 c = *reinterpret_cast<const double2 *>(g + 4 * cnt + 4 * k);
+  const double2 d = *reinterpret_cast<const double2 *>(g + 4 * cnt + 4 * k + 2);
+  f[0] = a.x, f[1] = a.y, f[2] = b.x, f[3] = b.y;
+  f[4] = c.x, f[5] = c.y, f[6] = d.x, f[7] = d.y;
+  f[8] = g[8 * cnt + k];
+}
+
 template <typename T>
 __device__ inline int64_t yrow_of(const SweepArgs<T> &a, int x, int y, int zc, int t) {
   const int L = x + 2 * y + 4 * zc + 8 * t;
@@ -391,12 +423,11 @@ __device__ inline void load_unit(const SweepArgs<T> &a, int L, int cl, bool vali
     int64_t off9, cnt;
     chunk_slot(a, L, cl, s, off9, cnt);
     const int64_t dY = (int64_t)(dx + 2 * dy + 4 * dz + 8 * dt) * a.SL + ((int64_t)dt * a.sh.dims[2] + dz) * a.sh.dims[1] + dy;
-    const int64_t fi = has ? a.sd.fbase + off9 + (int64_t)lanes_below(mask) : a.fzero;
-    const int64_t stride = has ? cnt : 0;
+    // rows without the neighbour read the zero block (k = cnt = 0)
+    const int64_t gi = has ? a.sd.fbase + off9 : a.fzero;
+    const int64_t k = has ? (int64_t)lanes_below(mask) : 0, kc = has ? cnt : 0;
     const int64_t yi = has ? a.sd.sbase + 3 * (own + dY) : a.yzero;
-    const T *p = a.F + fi;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) f[u][e] = *(p + e * stride);
+    load_block(a.F + gi, k, kc, f[u]);
     const T *q = a.Y + yi;
     yv[u][0] = q[0];
     yv[u][1] = q[1];
@@ -477,9 +508,10 @@ __device__ inline void sweep(const SweepArgs<T> &a, T (*part)[kRows][3], uint64_
         const int qrow = seg * kRows + tq;   // slot 40: every row of the chunk, rank = row & 63
         int64_t off9, cnt;
         chunk_slot(a, L, __builtin_amdgcn_readfirstlane(qrow >> 6), 40, off9, cnt);
-        const T *d = a.F + a.sd.fbase + off9 + (qrow & 63);
+        T dg[9];
+        load_block(a.F + a.sd.fbase + off9, qrow & 63, cnt, dg);
 #pragma unroll
-        for (int e = 0; e < 9; ++e) pre[e] = *(d + (int64_t)e * cnt);
+        for (int e = 0; e < 9; ++e) pre[e] = dg[e];
         pre[9] = a.Y[yown];
         pre[10] = a.Y[yown + 1];
         pre[11] = a.Y[yown + 2];
@@ -670,11 +702,10 @@ __device__ inline void load_chunk_f(const SweepArgs<T> &a, bool done, int L, int
     slot_off(s0 + j, dx, dy, dz, dt);
     const bool has = valid && (code & slot_faces(dx, dy, dz, dt)) == 0;
     const unsigned long long mask = __ballot(has);
-    const int64_t fi = has ? a.sd.fbase + tab[2 * j] + (int64_t)lanes_below(mask) : a.fzero;
-    const int64_t stride = has ? tab[2 * j + 1] : 0;
-    const T *q = a.F + fi;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) f[j][e] = *(q + e * stride);
+    // rows without the neighbour read the zero block (k = cnt = 0)
+    const int64_t gi = has ? a.sd.fbase + tab[2 * j] : a.fzero;
+    const int64_t k = has ? (int64_t)lanes_below(mask) : 0, kc = has ? tab[2 * j + 1] : 0;
+    load_block(a.F + gi, k, kc, f[j]);
   }
 }
 
@@ -757,9 +788,10 @@ __device__ inline void load_pre(const SweepArgs<T> &a, const Phase &p, const uin
     // pointer alive across it (which does not fit the FP64 register budget)
     int lrow = qrow & 63;
     asm volatile("" : "+v"(lrow));
-    const T *d = a.F + a.sd.fbase + off9 + lrow;
+    T dg[9];
+    load_block(a.F + a.sd.fbase + off9, lrow, cnt, dg);
 #pragma unroll
-    for (int e = 0; e < 9; ++e) pre[e] = *(d + (int64_t)e * cnt);
+    for (int e = 0; e < 9; ++e) pre[e] = dg[e];
     const int64_t yo = a.sd.sbase + 3 * yrow_of(a, x, y, zc, t);
     pre[9] = a.Y[yo];
     pre[10] = a.Y[yo + 1];
@@ -1120,12 +1152,12 @@ static void launch_apply(const ras *R, const double *r, double *z, T *Y, hipStre
                        R->d_subs.as<SubInfo>(), R->d_order.as<int32_t>(), R->d_shapes.as<ShapeInfo>(),
                        R->d_lvl.as<int32_t>(), R->d_coords.as<uint64_t>(), R->d_ctab.as<int32_t>(),
                        R->d_tz.as<int32_t>(), R->factors.as<T>(), Y,
-                       9 * R->total_blocks, R->scratch_elems, rg, r, z);
+                       R->factor_elems, R->scratch_elems, rg, r, z);
   } else {
     hipLaunchKernelGGL((apply_kernel<T>), dim3(R->nsub), dim3(kApplyThreads), 0, s, R->d, R->d_subs.as<SubInfo>(),
                        R->d_order.as<int32_t>(), R->d_shapes.as<ShapeInfo>(), R->d_lvl.as<int32_t>(),
                        R->d_coords.as<uint64_t>(), R->d_ctab.as<int32_t>(), R->factors.as<T>(), Y,
-                       9 * R->total_blocks, R->scratch_elems, r, z);
+                       R->factor_elems, R->scratch_elems, r, z);
   }
 }
 
@@ -1166,7 +1198,7 @@ static void ras_batch_prepare_t(const ras *const *R, const long long *voff, void
     d[i].tz = q->d_tz.as<int32_t>();
     d[i].F = q->factors.as<T>();
     d[i].Y = local && local[i] ? static_cast<T *>(local[i]) : q->scratch.as<T>();
-    d[i].fzero = 9 * q->total_blocks;
+    d[i].fzero = q->factor_elems;
     d[i].yzero = q->scratch_elems;
     d[i].voff = voff[i];
     d[i].rg = Ring{q->ring_rmax, q->ring_ltlz};
@@ -1297,7 +1329,8 @@ ras *ras_create(const kkt_op *op, const ras_params_t *rp, hipStream_t s) {
           const ShapeHost &sh = R->shapes[sid];
           si.fbase = fb;
           si.sbase = sb;
-          fb += 9 * sh.nblocks;
+          fb += sh.felems;
+          R->total_blocks += sh.nblocks;
           sb += 3LL * sh.nlev * sh.dims[3] * sh.dims[2] * sh.dims[1];
           R->subs.push_back(si);
           for (int d = 0; d < 4; ++d) {
@@ -1307,7 +1340,7 @@ ras *ras_create(const kkt_op *op, const ras_params_t *rp, hipStream_t s) {
           for (int d = 0; d < 4; ++d) R->boxes.push_back(blo[d]);
           for (int d = 0; d < 4; ++d) R->boxes.push_back(bhi[d]);
         }
-  R->total_blocks = fb / 9;
+  R->factor_elems = fb;
   R->scratch_elems = sb;
   // launch order: largest boxes first, so that the last workgroups to start are the short ones
   std::vector<int32_t> order(nsub);
@@ -1412,11 +1445,11 @@ void ras_export(const ras *R, int sub, double *out) {
   STKKT_REQUIRE(sub >= 0 && sub < R->nsub, "ras_export_factors: bad subdomain");
   const SubInfo &sd = R->subs[sub];
   const ShapeHost &sh = R->shapes[sd.shape];
-  const int64_t nb = sh.nblocks;
+  const int64_t nb = sh.felems;
   const bool f32 = R->params.precision == STKKT_F32;
-  std::vector<double> buf(9 * (size_t)nb);
+  std::vector<double> buf((size_t)nb);
   if (f32) {
-    std::vector<float> tmp(9 * (size_t)nb);
+    std::vector<float> tmp((size_t)nb);
     STKKT_HIP(hipMemcpy(tmp.data(), R->factors.as<float>() + sd.fbase, sizeof(float) * tmp.size(),
                         hipMemcpyDeviceToHost));
     for (size_t i = 0; i < tmp.size(); ++i) buf[i] = tmp[i];
@@ -1441,7 +1474,7 @@ void ras_export(const ras *R, int sub, double *out) {
           unpack(sh.coords[r0 + q], x, y, z, t);
           if (!inside(x + dx, y + dy, z + dz, t + dt, d32)) continue;
           const int64_t rho = x + (int64_t)lx * (y + (int64_t)ly * (z + (int64_t)lz * t));
-          for (int e = 0; e < 9; ++e) out[rho * 729 + 9 * s + e] = buf[off9 + e * cnt + k];
+          for (int e = 0; e < 9; ++e) out[rho * 729 + 9 * s + e] = buf[off9 + blk_pos(e, k, cnt)];
           ++k;
         }
         if (k != cnt) throw Error(STKKT_EINVAL, "ras_export_factors: inconsistent layout");

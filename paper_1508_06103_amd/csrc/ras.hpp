@@ -34,8 +34,9 @@ struct ShapeHost {
   int nlev = 0, nchunk = 0, rmax = 0, vol = 0;
   std::vector<int32_t> lvl_start;
   std::vector<uint64_t> coords;
-  std::vector<int32_t> ctab;   // (off9, cnt) per (level, chunk, slot)
-  int64_t nblocks = 0;
+  std::vector<int32_t> ctab;   // (element offset, block count) per (level, chunk, slot)
+  int64_t nblocks = 0;         // 3x3 blocks
+  int64_t felems = 0;          // factor elements including group padding
   std::vector<int32_t> tzpref;
 };
 
@@ -51,11 +52,12 @@ struct ras {
   std::vector<int> shape_of;
   std::vector<stkkt::ShapeHost> shapes;
   std::vector<int32_t> boxes;   // nsub x 16
-  int64_t total_blocks = 0;
+  int64_t total_blocks = 0;    // 3x3 factor blocks of all subdomains
+  int64_t factor_elems = 0;    // factor elements including group padding (zero block follows)
   int64_t scratch_elems = 0;
   int ring_rmax = 0, ring_ltlz = 0;   // LDS ring sizes of the apply kernel
   stkkt::DevBuf d_subs, d_shapes, d_lvl, d_coords, d_ctab, d_order, d_tz;
-  stkkt::DevBuf factors;   // double or float, 9 per block
+  stkkt::DevBuf factors;   // double or float, grouped (blk_pos), 16 zero elements at the end
   stkkt::DevBuf scratch;   // local vectors
 };
 
