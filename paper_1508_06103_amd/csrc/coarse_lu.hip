@@ -136,20 +136,56 @@ __device__ inline void block_argmax(double v, int i, double *sv, int *si) {
   __syncthreads();
 }
 
+// The panel columns [k, k + w) of all rows are eliminated in a column-major
+// copy P (P[q * n + i] = A[i][k + q]), so that the pivot search reads a
+// column contiguously and the elimination is coalesced across rows.
+// Both copies go through a 64 x 64 LDS tile.
+__global__ void gje_panel_gather_kernel(int n, int k, int w, const double *__restrict__ A, double *__restrict__ P) {
+  __shared__ double tile[64][65];
+  const int i0 = blockIdx.x * 64;
+  for (int q = threadIdx.x; q < 64 * 64; q += blockDim.x) {
+    const int r = q / 64, t = q % 64;
+    tile[r][t] = (i0 + r < n && t < w) ? A[(long long)(i0 + r) * n + k + t] : 0.0;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 64 * 64; q += blockDim.x) {
+    const int t = q / 64, r = q % 64;
+    if (i0 + r < n && t < w) P[(long long)t * n + i0 + r] = tile[r][t];
+  }
+}
+
+__global__ void gje_panel_scatter_kernel(int n, int k, int w, const double *__restrict__ P, double *__restrict__ A) {
+  __shared__ double tile[64][65];
+  const int i0 = blockIdx.x * 64;
+  for (int q = threadIdx.x; q < 64 * 64; q += blockDim.x) {
+    const int t = q / 64, r = q % 64;
+    tile[r][t] = (i0 + r < n && t < w) ? P[(long long)t * n + i0 + r] : 0.0;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 64 * 64; q += blockDim.x) {
+    const int r = q / 64, t = q % 64;
+    if (i0 + r < n && t < w) A[(long long)(i0 + r) * n + k + t] = tile[r][t];
+  }
+}
+
 // Gauss-Jordan step for column c of the panel [k, e), part 1 (one
-// workgroup): pivot search over rows >= c, whole-row swap, and the pivot row's
-// panel segment divided by the pivot (its column-c entry replaced by 1 first);
-// the segment goes to prow.
-__global__ void __launch_bounds__(1024) gje_pivot_kernel(int n, int k, int e, int c, double *__restrict__ A,
-                                                         int32_t *__restrict__ piv, double *__restrict__ prow,
+// workgroup): pivot search over rows >= c, swap of the two rows' panel
+// segments (the rest of the rows is swapped once per panel, gje_laswp_kernel;
+// swp[c - k] records the pivot row), and the pivot row's panel segment divided
+// by the pivot (its column-c entry replaced by 1 first); the segment goes to prow.
+__global__ void __launch_bounds__(1024) gje_pivot_kernel(int n, int k, int e, int c, double *__restrict__ P,
+                                                         int32_t *__restrict__ piv, int32_t *__restrict__ swp,
+                                                         double *__restrict__ prow, double *__restrict__ fcol,
                                                          int *__restrict__ status) {
   __shared__ double sv[16];
   __shared__ int si[16];
   if (*status) return;
+  const int j = c - k, w = e - k;
+  const double *Pc = P + (long long)j * n;
   double best = -1.0;
   int bi = n;
   for (int i = c + threadIdx.x; i < n; i += blockDim.x) {
-    const double v = fabs(A[(long long)i * n + c]);
+    const double v = fabs(Pc[i]);
     if (v > best || (v == best && i < bi)) {
       best = v;
       bi = i;
@@ -162,11 +198,13 @@ __global__ void __launch_bounds__(1024) gje_pivot_kernel(int n, int k, int e, in
     if (threadIdx.x == 0) *status = 1;
     return;
   }
+  if (threadIdx.x == 0) swp[j] = p;
   if (p != c) {
-    for (int col = threadIdx.x; col < n; col += blockDim.x) {
-      const double t = A[(long long)c * n + col];
-      A[(long long)c * n + col] = A[(long long)p * n + col];
-      A[(long long)p * n + col] = t;
+    if (threadIdx.x < w) {
+      double *Pq = P + (long long)threadIdx.x * n;
+      const double t = Pq[c];
+      Pq[c] = Pq[p];
+      Pq[p] = t;
     }
     if (threadIdx.x == 0) {
       const int32_t t = piv[c];
@@ -175,30 +213,50 @@ __global__ void __launch_bounds__(1024) gje_pivot_kernel(int n, int k, int e, in
     }
   }
   __syncthreads();
-  if (threadIdx.x < e - k) {
-    const int col = k + threadIdx.x;
-    const double a = A[(long long)c * n + c];
-    const double v = (col == c ? 1.0 : A[(long long)c * n + col]) / a;
+  // the multipliers of the elimination: column j after the swap
+  for (int i = threadIdx.x; i < n; i += blockDim.x) fcol[i] = Pc[i];
+  const double a = Pc[c];
+  __syncthreads();
+  if (threadIdx.x < w) {
+    double *Pq = P + (long long)threadIdx.x * n;
+    const double v = ((int)threadIdx.x == j ? 1.0 : Pq[c]) / a;
     prow[threadIdx.x] = v;
-    A[(long long)c * n + col] = v;
+    Pq[c] = v;
   }
 }
 
-// Part 2 (rows spread over the grid): eliminate column c from every other
-// row inside the panel, A[i][q] -= A[i][c] prow[q] (the column-c entry
-// becoming -A[i][c] prow[c]); one wavefront per row segment.
-__global__ void __launch_bounds__(256) gje_elim_kernel(int n, int k, int e, int c, double *__restrict__ A,
+// Part 2 (one thread per entry, grid rows x panel columns): eliminate column
+// c from every other row of the panel, P[q][i] -= fcol[i] prow[q] (entry
+// j = c - k becoming -fcol[i] prow[j]); the multipliers come from the copy
+// fcol, so no entry is read after another thread has written it.
+__global__ void __launch_bounds__(256) gje_elim_kernel(int n, int k, int c, double *__restrict__ P,
                                                        const double *__restrict__ prow,
+                                                       const double *__restrict__ fcol,
                                                        const int *__restrict__ status) {
   if (*status) return;
-  const int q = threadIdx.x & 63, w = e - k, j = c - k;
-  const double pq = q < w ? prow[q] : 0.0;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= n || i == c || q >= w) return;
-  double *Ai = A + (long long)i * n + k;
-  const double f = Ai[j];   // read by all 64 lanes before any lane's store (same instruction stream)
-  __builtin_amdgcn_wave_barrier();
-  Ai[q] = (q == j) ? -f * pq : Ai[q] - f * pq;
+  const int j = c - k, q = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || i == c) return;
+  const double f = fcol[i], pq = prow[q];
+  double *x = P + (long long)q * n + i;
+  *x = (q == j) ? -f * pq : *x - f * pq;
+}
+
+// The panel's row swaps, in order, on the columns outside the panel (one
+// thread per column).  Skipped after a failed pivot (swp is then incomplete).
+__global__ void gje_laswp_kernel(int n, int k, int e, double *__restrict__ A, const int32_t *__restrict__ swp,
+                                 const int *__restrict__ status) {
+  if (*status) return;
+  for (int col = blockIdx.x * blockDim.x + threadIdx.x; col < n; col += gridDim.x * blockDim.x) {
+    if (col >= k && col < e) continue;
+    for (int c = k; c < e; ++c) {
+      const int p = swp[c - k];
+      if (p == c) continue;
+      const double t = A[(long long)c * n + col];
+      A[(long long)c * n + col] = A[(long long)p * n + col];
+      A[(long long)p * n + col] = t;
+    }
+  }
 }
 
 // Copy the panel rows [k, e) outside the panel columns: R[t][col] = A[k+t][col]
@@ -208,56 +266,85 @@ __global__ void gje_copy_rows_kernel(int n, int k, int e, const double *__restri
     R[(long long)t * n + col] = (col >= k && col < e) ? 0.0 : A[(long long)(k + t) * n + col];
 }
 
-// Trailing update outside the panel columns:
+// Trailing update outside the panel columns, a rank-(e - k) product:
 //   rows outside the panel:  A[i][col] += sum_t A[i][k+t] R[t][col]
 //   panel rows:              A[i][col]  = sum_t A[i][k+t] R[t][col]
-// 64 x 64 output tiles, 256 threads with 4 x 4 outputs each, K = panel width.
-__global__ void __launch_bounds__(256) gje_update_kernel(int n, int k, int e, double *__restrict__ A,
-                                                         const double *__restrict__ R) {
-  __shared__ double As[kPanel][64];       // [t][row]
-  __shared__ double Rs[kPanel][64];       // [t][col]
-  const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
+// on the FP64 matrix cores (v_mfma_f64_16x16x4: lane l supplies a = A[l%16][l/16]
+// and b = B[l/16][l%16] and holds D[l/16 + 4r][l%16], r = 0..3).  A workgroup
+// of 8 wavefronts owns a 128 x 128 output tile; wavefront (wr, wc) a 64 x 32
+// part of it, as 4 x 2 blocks of 16 x 16.  The A panel slice (128 rows x 64,
+// rows padded against bank conflicts) and the R slice (64 x 128) sit in LDS.
+constexpr int kUpdTile = 128;
+constexpr int kUpdThreads = 512;
+constexpr size_t kUpdLds = sizeof(double) * ((size_t)kUpdTile * (kPanel + 1) + (size_t)kPanel * kUpdTile);
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kUpdThreads) gje_update_kernel(int n, int k, int e, double *__restrict__ A,
+                                                                 const double *__restrict__ R) {
+  extern __shared__ double upd_lds[];
+  double(*As)[kPanel + 1] = reinterpret_cast<double(*)[kPanel + 1]>(upd_lds);              // [row][t]
+  double(*Rs)[kUpdTile] = reinterpret_cast<double(*)[kUpdTile]>(upd_lds + kUpdTile * (kPanel + 1));   // [t][col]
+  const int row0 = blockIdx.y * kUpdTile, col0 = blockIdx.x * kUpdTile;
   const int w = e - k;
   const int tid = threadIdx.x;
-  for (int q = tid; q < 64 * kPanel; q += 256) {
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 2, wc = wave & 3;
+  const int li = lane & 15, lk = lane >> 4;
+  // the tile's current values are requested first, so that their latency
+  // overlaps the staging and the products
+  double old[4][2][4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int col = col0 + wc * 32 + bj * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = row0 + wr * 64 + bi * 16 + lk + 4 * r;
+        const bool acc_row = i < n && !(i >= k && i < e) && col < n && !(col >= k && col < e);
+        old[bi][bj][r] = acc_row ? A[(long long)i * n + col] : 0.0;
+      }
+    }
+  for (int q = tid; q < kUpdTile * kPanel; q += kUpdThreads) {
     const int rr = q / kPanel, t = q % kPanel;
     const int i = row0 + rr;
-    As[t][rr] = (i < n && t < w) ? A[(long long)i * n + k + t] : 0.0;
-    const int t2 = q / 64, cc = q % 64;
+    As[rr][t] = (i < n && t < w) ? A[(long long)i * n + k + t] : 0.0;
+    const int t2 = q / kUpdTile, cc = q % kUpdTile;
     const int col = col0 + cc;
     Rs[t2][cc] = (col < n && t2 < w) ? R[(long long)t2 * n + col] : 0.0;
   }
   __syncthreads();
-  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
-  double acc[4][4];
+  f64x4 acc[4][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int t = 0; t < w; ++t) {
-    double av[4], rv[4];
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int t0 = 0; t0 < kPanel; t0 += 4) {
+    double a[4], b[2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) av[a] = As[t][tr + a];
+    for (int bi = 0; bi < 4; ++bi) a[bi] = As[wr * 64 + bi * 16 + li][t0 + lk];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) rv[b] = Rs[t][tc + b];
+    for (int bj = 0; bj < 2; ++bj) b[bj] = Rs[t0 + lk][wc * 32 + bj * 16 + li];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * rv[b];
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = row0 + tr + a;
-    if (i >= n) continue;
-    const bool prow = i >= k && i < e;
+  for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int col = col0 + tc + b;
+    for (int bj = 0; bj < 2; ++bj) {
+      const int col = col0 + wc * 32 + bj * 16 + li;
       if (col >= n || (col >= k && col < e)) continue;
-      double *dst = A + (long long)i * n + col;
-      *dst = prow ? acc[a][b] : *dst + acc[a][b];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = row0 + wr * 64 + bi * 16 + lk + 4 * r;
+        if (i >= n) continue;
+        // panel rows are assigned (their old value is 0 here), other rows accumulate
+        A[(long long)i * n + col] = old[bi][bj][r] + acc[bi][bj][r];
+      }
     }
-  }
 }
 
 // out[i][piv[j]] = A[i][j]
@@ -325,18 +412,31 @@ __global__ void to_float_kernel(long long n, const double *__restrict__ a, float
 
 // Explicit inverse of the n x n row-major matrix in A (overwritten with the
 // inverse).  tmp: n x n scratch; rows: kPanel x n scratch; piv: n int32.
-static void gje_invert(int n, double *A, double *tmp, double *rows, int32_t *piv, double *prow, int *status,
-                       hipStream_t s) {
+static void gje_invert(int n, double *A, double *tmp, double *rows, double *pan, double *fcol, int32_t *piv,
+                       int32_t *swp, double *prow, int *status, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&gje_update_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kUpdLds));
+    attr_set = true;
+  }
   hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(n, 256, 64)), dim3(256), 0, s, n, piv);
+  const int nt = (n + kUpdTile - 1) / kUpdTile;
   for (int k = 0; k < n; k += kPanel) {
     const int e = std::min(n, k + kPanel);
+    const int nrb = (n + 63) / 64;
+    hipLaunchKernelGGL(gje_panel_gather_kernel, dim3(nrb), dim3(256), 0, s, n, k, e - k, A, pan);
     for (int c = k; c < e; ++c) {
-      hipLaunchKernelGGL(gje_pivot_kernel, dim3(1), dim3(1024), 0, s, n, k, e, c, A, piv, prow, status);
-      hipLaunchKernelGGL(gje_elim_kernel, dim3((n + 3) / 4), dim3(256), 0, s, n, k, e, c, A, prow, status);
+      hipLaunchKernelGGL(gje_pivot_kernel, dim3(1), dim3(1024), 0, s, n, k, e, c, pan, piv, swp, prow, fcol,
+                         status);
+      hipLaunchKernelGGL(gje_elim_kernel, dim3((n + 255) / 256, e - k), dim3(256), 0, s, n, k, c, pan, prow, fcol,
+                         status);
     }
+    hipLaunchKernelGGL(gje_panel_scatter_kernel, dim3(nrb), dim3(256), 0, s, n, k, e - k, pan, A);
+    hipLaunchKernelGGL(gje_laswp_kernel, dim3(blocks_for(n, 256, 64)), dim3(256), 0, s, n, k, e, A, swp, status);
     hipLaunchKernelGGL(gje_copy_rows_kernel, dim3(blocks_for(n, 256, 64), e - k), dim3(256), 0, s, n, k, e, A,
                        rows);
-    hipLaunchKernelGGL(gje_update_kernel, dim3((n + 63) / 64, (n + 63) / 64), dim3(256), 0, s, n, k, e, A, rows);
+    hipLaunchKernelGGL(gje_update_kernel, dim3(nt, nt), dim3(kUpdThreads), kUpdLds, s, n, k, e, A, rows);
   }
   hipLaunchKernelGGL(gje_unpermute_kernel, dim3(blocks_for(n, 256, 64), n), dim3(256), 0, s, n, A, piv, tmp);
   STKKT_HIP(hipGetLastError());
@@ -359,7 +459,8 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
   // setup work buffers (FP64)
   DevBuf S(al, sizeof(double) * nn), Ed(al, sizeof(double) * nn),
       tmp(al, sizeof(double) * nn), rows(al, sizeof(double) * (size_t)kPanel * nb_), piv(al, sizeof(int32_t) * nb_),
-      prow(al, sizeof(double) * kPanel),
+      prow(al, sizeof(double) * kPanel), swp(al, sizeof(int32_t) * kPanel), pan(al, sizeof(double) * kPanel * nb_),
+      fcol(al, sizeof(double) * nb_),
       status(al, 256), ridx(al, sizeof(int32_t) * (size_t)nb_ * 81), rval(al, sizeof(double) * (size_t)nb_ * 81),
       cidx(al, sizeof(int32_t) * (size_t)nb_ * 81), cval(al, sizeof(double) * (size_t)nb_ * 81);
   STKKT_HIP(hipMemsetAsync(status.ptr, 0, sizeof(int), s));
@@ -383,8 +484,8 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
                          S.as<double>());
     STKKT_HIP(hipGetLastError());
     // S_k^{-1} (column-major S is the row-major transpose: invert it as is)
-    gje_invert(nb_, S.as<double>(), tmp.as<double>(), rows.as<double>(), piv.as<int32_t>(), prow.as<double>(),
-               status.as<int>(), s);
+    gje_invert(nb_, S.as<double>(), tmp.as<double>(), rows.as<double>(), pan.as<double>(), fcol.as<double>(),
+               piv.as<int32_t>(), swp.as<int32_t>(), prow.as<double>(), status.as<int>(), s);
     // E_k = S_k^{-1} U_k
     if (k + 1 < nlev_) {
       hipLaunchKernelGGL(coupling_rows_kernel, dim3(G), dim3(128), 0, s, d, k, +1, ridx.as<int32_t>(),
