@@ -23,6 +23,7 @@
 #include <memory>
 
 #include "batch.hpp"
+#include "cgs2_dev.hpp"
 #include "krylov.hpp"
 
 namespace stkkt {
@@ -113,6 +114,32 @@ __global__ void __launch_bounds__(kBT) bupdate_kernel(double *__restrict__ w, co
     for (int g = 0; g < k; ++g) s += hi[g] * V[(long long)g * ldv + e];
     w[e] -= s;
   }
+}
+
+// The fused CGS passes over the chunk work list (bodies shared with the single
+// solve): w -= V h_inst with partial[g * nch + chunk] = chunk part of V_g . w_new,
+// and w -= V h_inst with partial[chunk] = chunk part of |w_new|^2.
+__global__ void __launch_bounds__(kCgsThreads) bupdate_dot_kernel(double *__restrict__ w,
+                                                                  const double *__restrict__ V, long long ldv, int k,
+                                                                  const double *__restrict__ h, int hstride,
+                                                                  const Chunk *__restrict__ ch, int nch,
+                                                                  const int *__restrict__ act,
+                                                                  double *__restrict__ partial) {
+  const Chunk c = load_uniform(ch + blockIdx.x);
+  if (!as_const(act)[c.inst]) return;
+  update_dot_range(w, V, ldv, k, h + (long long)c.inst * hstride, c.lo, c.hi, partial + blockIdx.x, nch);
+}
+
+__global__ void __launch_bounds__(kCgsThreads) bupdate_norm_kernel(double *__restrict__ w,
+                                                                   const double *__restrict__ V, long long ldv, int k,
+                                                                   const double *__restrict__ h, int hstride,
+                                                                   const Chunk *__restrict__ ch,
+                                                                   const int *__restrict__ act,
+                                                                   double *__restrict__ partial) {
+  const Chunk c = load_uniform(ch + blockIdx.x);
+  if (!as_const(act)[c.inst]) return;
+  const double s = update_norm_range(w, V, ldv, k, h + (long long)c.inst * hstride, c.lo, c.hi);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
 // out[e] = x[e] / sqrt(nrm2[inst])  (0 when the norm is 0)
@@ -446,11 +473,25 @@ void BatchEngine::cycle(std::vector<int> &finished) {
     double *zj = Zd + (long long)j * N;
     precondition(j, act);
     matvec_batch_run(mv_, zj, Wd, act, s_);
+    // CGS2: h1 = V^T w; w -= V h1 with h2 = V^T w; w -= V h2 with |w|^2
     bdot(Vd, N, j + 1, Wd, act, hd);
-    hipLaunchKernelGGL(bupdate_kernel, dim3(nch_), dim3(kBT), 0, s_, Wd, Vd, N, j + 1, hd, hs, chd, act);
-    bdot(Vd, N, j + 1, Wd, act, hd + (m + 1));
-    hipLaunchKernelGGL(bupdate_kernel, dim3(nch_), dim3(kBT), 0, s_, Wd, Vd, N, j + 1, hd + (m + 1), hs, chd, act);
-    bdot(Wd, 0, 1, Wd, act, hd + 2 * (m + 1));
+    if (cgs2_fused_ok(j + 1) && nch_ > 0) {
+      double *part = partial_.as<double>();
+      const int *cf = cfirst_.as<int>();
+      const unsigned S_ = (unsigned)slots_.size();
+      hipLaunchKernelGGL(bupdate_dot_kernel, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd, hs, chd,
+                         nch_, act, part);
+      hipLaunchKernelGGL(breduce_kernel, dim3(S_, j + 1), dim3(kBT), 0, s_, part, nch_, cf, act, hs, hd + (m + 1));
+      hipLaunchKernelGGL(bupdate_norm_kernel, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd + (m + 1),
+                         hs, chd, act, part);
+      hipLaunchKernelGGL(breduce_kernel, dim3(S_, 1), dim3(kBT), 0, s_, part, nch_, cf, act, hs, hd + 2 * (m + 1));
+      STKKT_HIP(hipGetLastError());
+    } else {
+      hipLaunchKernelGGL(bupdate_kernel, dim3(nch_), dim3(kBT), 0, s_, Wd, Vd, N, j + 1, hd, hs, chd, act);
+      bdot(Vd, N, j + 1, Wd, act, hd + (m + 1));
+      hipLaunchKernelGGL(bupdate_kernel, dim3(nch_), dim3(kBT), 0, s_, Wd, Vd, N, j + 1, hd + (m + 1), hs, chd, act);
+      bdot(Wd, 0, 1, Wd, act, hd + 2 * (m + 1));
+    }
     fetch();
     bool changed = false;
     for (int i = 0; i < S; ++i) {

@@ -3,6 +3,7 @@
 // streaming updates of classical Gram-Schmidt.
 #include "common.hpp"
 #include "krylov.hpp"
+#include "cgs2_dev.hpp"
 
 namespace stkkt {
 
@@ -104,113 +105,34 @@ __global__ void scale_kernel(double *__restrict__ out, const double *__restrict_
     out[e] = a * x[e];
 }
 
-// Second CGS pass fused with the first update: with h the first-pass
-// coefficients, w <- w - sum_g h[g] V_g and partial[g * G + b] = sum over
-// block b's elements of V_g[e] w_new[e], g < k <= 64.  The block's element
-// range is walked in tiles of 64 whose k basis entries are staged in LDS, so
-// V is read from memory once for both the update and the new dots.
-constexpr int kTile = 64;
-constexpr int kFuseMax = 64;
-
-__global__ void __launch_bounds__(kThreads) update_dot_kernel(double *__restrict__ w, const double *__restrict__ V,
-                                                              long long ldv, int k, const double *__restrict__ h,
-                                                              long long n, double *__restrict__ partial) {
-  __shared__ double Vs[kFuseMax][kTile + 1];   // padded: the dots read down a column
-  __shared__ double Ws[kTile];
-  __shared__ double part[kThreads / 64][kTile];
-  __shared__ double red[kThreads / 64][kFuseMax];
+// Second CGS pass fused with the first update (w <- w - V h, partial[g * G +
+// b] = block b's part of V_g . w_new) and the last update fused with the norm
+// (partial[b] = block b's part of |w_new|^2); the bodies are shared with the
+// batched solver.
+__global__ void __launch_bounds__(kCgsThreads) update_dot_kernel(double *__restrict__ w, const double *__restrict__ V,
+                                                                 long long ldv, int k, const double *__restrict__ h,
+                                                                 long long n, double *__restrict__ partial) {
   const int G = gridDim.x;
   const long long per = (n + G - 1) / G;
   const long long lo = (long long)blockIdx.x * per;
   const long long hi = lo + per < n ? lo + per : n;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  double acc = 0.0;   // dot of basis vector g = lane over this wave's quarter of every tile
-  // the next tile's basis entries are loaded into registers while the current
-  // tile is processed (entry q = t + 256 r of the k x 64 tile)
-  constexpr int kPre = kFuseMax * kTile / kThreads;
-  double pre[kPre];
-  auto fetch = [&](long long e0) {
-    const int m = (int)(hi - e0 < kTile ? hi - e0 : kTile);
-#pragma unroll
-    for (int r = 0; r < kPre; ++r) {
-      const int q = t + kThreads * r, g = q / kTile, e = q % kTile;
-      pre[r] = (g < k && e < m) ? V[(long long)g * ldv + e0 + e] : 0.0;
-    }
-  };
-  if (lo < hi) fetch(lo);
-  for (long long e0 = lo; e0 < hi; e0 += kTile) {
-    const int m = (int)(hi - e0 < kTile ? hi - e0 : kTile);
-#pragma unroll
-    for (int r = 0; r < kPre; ++r) {
-      const int q = t + kThreads * r, g = q / kTile, e = q % kTile;
-      if (g < k) Vs[g][e] = pre[r];
-    }
-    if (e0 + kTile < hi) fetch(e0 + kTile);
-    __syncthreads();
-    // update: each wave sums a quarter of the basis vectors for every element of the tile
-    {
-      double s = 0.0;
-      for (int g = wave; g < k; g += kThreads / 64) s += h[g] * Vs[g][lane];
-      part[wave][lane] = s;
-    }
-    __syncthreads();
-    if (t < kTile) {
-      double s = 0.0;
-#pragma unroll
-      for (int wv = 0; wv < kThreads / 64; ++wv) s += part[wv][t];
-      const double wn = t < m ? w[e0 + t] - s : 0.0;
-      if (t < m) w[e0 + t] = wn;
-      Ws[t] = wn;
-    }
-    __syncthreads();
-    // dots: lane g, this wave's 16 elements of the tile
-    if (lane < k) {
-#pragma unroll 4
-      for (int e = wave * (kTile / 4); e < (wave + 1) * (kTile / 4); ++e) acc += Vs[lane][e] * Ws[e];
-    }
-    __syncthreads();
-  }
-  red[wave][lane] = acc;
-  __syncthreads();
-  if (t < k) {
-    double s = 0.0;
-#pragma unroll
-    for (int wv = 0; wv < kThreads / 64; ++wv) s += red[wv][t];
-    partial[(long long)t * G + blockIdx.x] = s;
-  }
+  update_dot_range(w, V, ldv, k, h, lo, hi > lo ? hi : lo, partial + blockIdx.x, G);
 }
 
-// Last CGS update fused with the norm: w <- w - sum_g h[g] V_g and
-// partial[b] = sum over block b's elements of w_new[e]^2.
-__global__ void __launch_bounds__(kThreads) update_norm_kernel(double *__restrict__ w, const double *__restrict__ V,
-                                                               long long ldv, int k, const double *__restrict__ h,
-                                                               long long n, double *__restrict__ partial) {
-  __shared__ double red[kThreads / 64];
+__global__ void __launch_bounds__(kCgsThreads) update_norm_kernel(double *__restrict__ w, const double *__restrict__ V,
+                                                                  long long ldv, int k, const double *__restrict__ h,
+                                                                  long long n, double *__restrict__ partial) {
   const int G = gridDim.x;
   const long long per = (n + G - 1) / G;
   const long long lo = (long long)blockIdx.x * per;
   const long long hi = lo + per < n ? lo + per : n;
-  double acc = 0.0;
-  for (long long e = lo + threadIdx.x; e < hi; e += kThreads) {
-    double s = 0.0;
-    for (int g = 0; g < k; ++g) s += h[g] * V[(long long)g * ldv + e];
-    const double wn = w[e] - s;
-    w[e] = wn;
-    acc += wn * wn;
-  }
-  acc = wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int wv = 0; wv < kThreads / 64; ++wv) s += red[wv];
-    partial[blockIdx.x] = s;
-  }
+  const double s = update_norm_range(w, V, ldv, k, h, lo, hi > lo ? hi : lo);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
 }  // namespace
 
-bool cgs2_fused_ok(int k) { return k <= kFuseMax; }
+bool cgs2_fused_ok(int k) { return k <= kCgsMaxK; }
 
 void update_dot(double *w, const double *V, long long ldv, int k, const double *h, long long n, double *partial,
                 double *out, hipStream_t s) {
