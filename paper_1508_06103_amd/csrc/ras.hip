@@ -626,30 +626,37 @@ __device__ inline void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// A phase: segment seg (kRows rows) of level L, the level's rows starting
+// at r0 (R of them); L < 0 once the sweep has no further phase.  Only these
+// four values are kept (the kernel is short of scalar registers); the rest
+// is derived.
 struct Phase {
-  int li, L, r0, R, seg, segR, nch;
-  bool done;
+  int L, seg, r0, R;
+  __device__ bool done() const { return L < 0; }
+  __device__ int segR() const { return min(kRows, R - seg * kRows); }
+  __device__ int nch() const { return (segR() + 63) >> 6; }
 };
 
+// li: index of the level in sweep order
 __device__ inline void phase_at(Phase &p, cptr<int32_t> lvls, int nlev, int li, int seg, bool fwd) {
-  p.li = li;
-  p.done = li < 0;
-  if (p.done) return;
+  if (li < 0) {
+    p.L = -1, p.seg = 0, p.r0 = 0, p.R = 0;
+    return;
+  }
   p.L = fwd ? li : nlev - 1 - li;
   p.r0 = lvls[p.L];
   p.R = lvls[p.L + 1] - p.r0;
   p.seg = seg;
-  p.segR = min(kRows, p.R - seg * kRows);
-  p.nch = (p.segR + 63) >> 6;
 }
 
 __device__ inline void phase_next(Phase &n, const Phase &p, cptr<int32_t> lvls, int nlev, bool fwd) {
-  if (p.done) {
+  if (p.done()) {
     n = p;
     return;
   }
-  if ((p.seg + 1) * kRows < p.R) phase_at(n, lvls, nlev, p.li, p.seg + 1, fwd);
-  else phase_at(n, lvls, nlev, next_level(lvls, nlev, p.li, fwd), 0, fwd);
+  const int li = fwd ? p.L : nlev - 1 - p.L;
+  if ((p.seg + 1) * kRows < p.R) phase_at(n, lvls, nlev, li, p.seg + 1, fwd);
+  else phase_at(n, lvls, nlev, next_level(lvls, nlev, li, fwd), 0, fwd);
 }
 
 struct Ring {
@@ -712,7 +719,7 @@ __device__ inline void load_chunk_f(const SweepArgs<T> &a, bool done, int L, int
 template <typename T, bool kFwd>
 __device__ inline void load_chunk_f(const SweepArgs<T> &a, const Phase &p, int c, uint64_t cw, int wave,
                                     T (&f)[kSlotsPerWave][9]) {
-  load_chunk_f<T, kFwd>(a, p.done, p.L, p.seg * (kRows / 64) + c, p.segR - 64 * c, cw, wave, f);
+  load_chunk_f<T, kFwd>(a, p.done(), p.L, p.seg * (kRows / 64) + c, p.segR() - 64 * c, cw, wave, f);
 }
 
 // Multiply chunk c of phase p: neighbour values from the LDS ring.  All rows
@@ -728,7 +735,7 @@ __device__ inline void mac_chunk_ring(const SweepArgs<T> &a, const Phase &p, int
   const int lane = (int)__lane_id();
   int x, y, zc, t;
   unpack(cw, x, y, zc, t);
-  const bool valid = c * 64 + lane < p.segR;
+  const bool valid = c * 64 + lane < p.segR();
   const int code = face_code(a, x, y, zc, t);
   const int lx = a.sh.dims[0], lz = a.sh.dims[2];
   const int xy = x + 2 * y, tz = t * lz + zc;
@@ -771,7 +778,7 @@ template <typename T, bool kFwd>
 __device__ inline void load_pre(const SweepArgs<T> &a, const Phase &p, const uint64_t *crd, T (&pre)[12],
                                 double (&rin)[3]) {
   const int tq = (int)threadIdx.x;
-  if (tq >= p.segR) return;
+  if (tq >= p.segR()) return;
   int x, y, zc, t;
   unpack(crd[tq], x, y, zc, t);
   if (kFwd) {
@@ -807,7 +814,7 @@ template <typename T, bool kFwd>
 __device__ inline void ring_finish(const SweepArgs<T> &a, const Phase &pc, const uint64_t *crd, T (*part)[kRows][3],
                                    const T (&pre)[12], const double (&rin)[3], T *yring, const Ring &rg) {
   const int tq = (int)threadIdx.x;
-  if (tq < pc.segR) {
+  if (tq < pc.segR()) {
     const uint64_t fc = crd[tq];
     T s3[3];
 #pragma unroll
@@ -854,16 +861,16 @@ __device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int n
   // requests of the phase, issued when its first chunk is multiplied: coordinates
   // two phases ahead, the (t, z) prefix row of a new level, final-step inputs
   if (cc == 0) {
-    if (!pnn.done && tq < pnn.segR) c2 = a.crd[a.sh.coord_off + pnn.r0 + pnn.seg * kRows + tq];
+    if (!pnn.done() && tq < pnn.segR()) c2 = a.crd[a.sh.coord_off + pnn.r0 + pnn.seg * kRows + tq];
     if (pc.seg == 0 && tq < rg.ltlz) tzrow = tzp[pc.L * rg.ltlz + tq];
     load_pre<T, kFwd>(a, pc, crd2 + par * kRows, pre, rin);
   }
   // next chunk: same phase, or the first chunk of the next phase
-  const bool last = cc == pc.nch - 1;
+  const bool last = cc == pc.nch() - 1;
   {
     // chosen with selects, field by field, so that the phases stay in registers
-    const bool tdone = last ? pn.done : pc.done;
-    const int tL = last ? pn.L : pc.L, tseg = last ? pn.seg : pc.seg, tsegR = last ? pn.segR : pc.segR;
+    const bool tdone = last ? pn.done() : pc.done();
+    const int tL = last ? pn.L : pc.L, tseg = last ? pn.seg : pc.seg, tsegR = last ? pn.segR() : pc.segR();
     const int ct = last ? 0 : cc + 1;
     const int pt_par = last ? par ^ 1 : par;
     const uint64_t cw = crd2[pt_par * kRows + ct * 64 + lane];
@@ -874,7 +881,7 @@ __device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int n
     const uint64_t cw = crd2[par * kRows + cc * 64 + lane];
     T a0 = 0, a1 = 0, a2 = 0;
     mac_chunk_ring<T, kFwd>(a, pc, cc, cw, wave, fcur, yring, tzr, rg, a0, a1, a2);
-    if (cc * 64 + lane < pc.segR) {
+    if (cc * 64 + lane < pc.segR()) {
       part[wave][cc * 64 + lane][0] = a0;
       part[wave][cc * 64 + lane][1] = a1;
       part[wave][cc * 64 + lane][2] = a2;
@@ -888,7 +895,7 @@ __device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int n
   lds_barrier();
   ring_finish<T, kFwd>(a, pc, crd2 + par * kRows, part, pre, rin, yring, rg);
   if (pc.seg == 0 && tq < rg.ltlz) tzr[(pc.L & 15) * rg.ltlz + tq] = tzrow;
-  if (!pnn.done && tq < pnn.segR) crd2[par * kRows + tq] = c2;   // phase after next reuses this buffer
+  if (!pnn.done() && tq < pnn.segR()) crd2[par * kRows + tq] = c2;   // phase after next reuses this buffer
   lds_barrier();
   // advance
   pc = pn;
@@ -907,12 +914,12 @@ __device__ inline void sweep_ring(const SweepArgs<T> &a, cptr<int32_t> tzp, T (*
   const int nlev = a.sh.nlev;
   Phase pc, pn, pnn;
   phase_at(pc, a.lvls, nlev, next_level(a.lvls, nlev, -1, kFwd), 0, kFwd);
-  if (pc.done) return;
+  if (pc.done()) return;
   phase_next(pn, pc, a.lvls, nlev, kFwd);
   phase_next(pnn, pn, a.lvls, nlev, kFwd);
   // coordinates of the first two phases
-  if (tq < pc.segR) crd2[tq] = a.crd[a.sh.coord_off + pc.r0 + pc.seg * kRows + tq];
-  if (!pn.done && tq < pn.segR) crd2[kRows + tq] = a.crd[a.sh.coord_off + pn.r0 + pn.seg * kRows + tq];
+  if (tq < pc.segR()) crd2[tq] = a.crd[a.sh.coord_off + pc.r0 + pc.seg * kRows + tq];
+  if (!pn.done() && tq < pn.segR()) crd2[kRows + tq] = a.crd[a.sh.coord_off + pn.r0 + pn.seg * kRows + tq];
   __syncthreads();
   int par = 0, cc = 0;
   uint64_t c2 = 0;
@@ -924,10 +931,10 @@ __device__ inline void sweep_ring(const SweepArgs<T> &a, cptr<int32_t> tzp, T (*
   for (;;) {
     ring_step<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, fA, fB, part, crd2, yring, tzr, rg, c2, tzrow, pre,
                        rin);
-    if (pc.done) break;
+    if (pc.done()) break;
     ring_step<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, fB, fA, part, crd2, yring, tzr, rg, c2, tzrow, pre,
                        rin);
-    if (pc.done) break;
+    if (pc.done()) break;
   }
 }
 
@@ -947,7 +954,7 @@ __device__ inline void ring_step2(const SweepArgs<T> &a, cptr<int32_t> tzp, int 
   const int lane = (int)__lane_id();
   const int tq = (int)threadIdx.x;
   if (cc == 0) {
-    if (!p3.done && tq < p3.segR) c3 = a.crd[a.sh.coord_off + p3.r0 + p3.seg * kRows + tq];
+    if (!p3.done() && tq < p3.segR()) c3 = a.crd[a.sh.coord_off + p3.r0 + p3.seg * kRows + tq];
     if (pc.seg == 0 && tq < rg.ltlz) tzrow = tzp[pc.L * rg.ltlz + tq];
     load_pre<T, kFwd>(a, pc, crd3 + par * kRows, pre, rin);
   }
@@ -955,12 +962,12 @@ __device__ inline void ring_step2(const SweepArgs<T> &a, cptr<int32_t> tzp, int 
   {
     const int p1 = par == 2 ? 0 : par + 1, p2 = par == 0 ? 2 : par - 1;
     // chosen with selects, field by field, so that the phases stay in registers
-    const int which = cc + 2 < pc.nch ? 0 : (cc + 2 == pc.nch || (!pn.done && pn.nch >= 2)) ? 1 : 2;
-    const bool tdone = which == 0 ? pc.done : which == 1 ? pn.done : pnn.done;
+    const int which = cc + 2 < pc.nch() ? 0 : (cc + 2 == pc.nch() || (!pn.done() && pn.nch() >= 2)) ? 1 : 2;
+    const bool tdone = which == 0 ? pc.done() : which == 1 ? pn.done() : pnn.done();
     const int tL = which == 0 ? pc.L : which == 1 ? pn.L : pnn.L;
     const int tseg = which == 0 ? pc.seg : which == 1 ? pn.seg : pnn.seg;
-    const int tsegR = which == 0 ? pc.segR : which == 1 ? pn.segR : pnn.segR;
-    const int ct = which == 0 ? cc + 2 : which == 1 ? (cc + 2 == pc.nch ? 0 : 1) : 0;
+    const int tsegR = which == 0 ? pc.segR() : which == 1 ? pn.segR() : pnn.segR();
+    const int ct = which == 0 ? cc + 2 : which == 1 ? (cc + 2 == pc.nch() ? 0 : 1) : 0;
     const int tpar = which == 0 ? par : which == 1 ? p1 : p2;
     const uint64_t cw = crd3[tpar * kRows + ct * 64 + lane];
     load_chunk_f<T, kFwd>(a, tdone, tL, tseg * (kRows / 64) + ct, tsegR - 64 * ct, cw, wave, fload);
@@ -970,13 +977,13 @@ __device__ inline void ring_step2(const SweepArgs<T> &a, cptr<int32_t> tzp, int 
     const uint64_t cw = crd3[par * kRows + cc * 64 + lane];
     T a0 = 0, a1 = 0, a2 = 0;
     mac_chunk_ring<T, kFwd>(a, pc, cc, cw, wave, fcur, yring, tzr, rg, a0, a1, a2);
-    if (cc * 64 + lane < pc.segR) {
+    if (cc * 64 + lane < pc.segR()) {
       part[wave][cc * 64 + lane][0] = a0;
       part[wave][cc * 64 + lane][1] = a1;
       part[wave][cc * 64 + lane][2] = a2;
     }
   }
-  if (cc != pc.nch - 1) {
+  if (cc != pc.nch() - 1) {
     ++cc;
     return;
   }
@@ -984,7 +991,7 @@ __device__ inline void ring_step2(const SweepArgs<T> &a, cptr<int32_t> tzp, int 
   lds_barrier();
   ring_finish<T, kFwd>(a, pc, crd3 + par * kRows, part, pre, rin, yring, rg);
   if (pc.seg == 0 && tq < rg.ltlz) tzr[(pc.L & 15) * rg.ltlz + tq] = tzrow;
-  if (!p3.done && tq < p3.segR) crd3[par * kRows + tq] = c3;   // the phase three ahead reuses this buffer
+  if (!p3.done() && tq < p3.segR()) crd3[par * kRows + tq] = c3;   // the phase three ahead reuses this buffer
   lds_barrier();
   pc = pn;
   pn = pnn;
@@ -1003,14 +1010,14 @@ __device__ inline void sweep_ring2(const SweepArgs<T> &a, cptr<int32_t> tzp, T (
   const int nlev = a.sh.nlev;
   Phase pc, pn, pnn, p3;
   phase_at(pc, a.lvls, nlev, next_level(a.lvls, nlev, -1, kFwd), 0, kFwd);
-  if (pc.done) return;
+  if (pc.done()) return;
   phase_next(pn, pc, a.lvls, nlev, kFwd);
   phase_next(pnn, pn, a.lvls, nlev, kFwd);
   phase_next(p3, pnn, a.lvls, nlev, kFwd);
   // coordinates of the first three phases
-  if (tq < pc.segR) crd3[tq] = a.crd[a.sh.coord_off + pc.r0 + pc.seg * kRows + tq];
-  if (!pn.done && tq < pn.segR) crd3[kRows + tq] = a.crd[a.sh.coord_off + pn.r0 + pn.seg * kRows + tq];
-  if (!pnn.done && tq < pnn.segR) crd3[2 * kRows + tq] = a.crd[a.sh.coord_off + pnn.r0 + pnn.seg * kRows + tq];
+  if (tq < pc.segR()) crd3[tq] = a.crd[a.sh.coord_off + pc.r0 + pc.seg * kRows + tq];
+  if (!pn.done() && tq < pn.segR()) crd3[kRows + tq] = a.crd[a.sh.coord_off + pn.r0 + pn.seg * kRows + tq];
+  if (!pnn.done() && tq < pnn.segR()) crd3[2 * kRows + tq] = a.crd[a.sh.coord_off + pnn.r0 + pnn.seg * kRows + tq];
   __syncthreads();
   int par = 0, cc = 0;
   uint64_t c3 = 0;
@@ -1019,18 +1026,18 @@ __device__ inline void sweep_ring2(const SweepArgs<T> &a, cptr<int32_t> tzp, T (
   double rin[3];
   T fA[kSlotsPerWave][9], fB[kSlotsPerWave][9], fC[kSlotsPerWave][9];
   load_chunk_f<T, kFwd>(a, pc, 0, crd3[lane], wave, fA);
-  if (pc.nch >= 2) load_chunk_f<T, kFwd>(a, pc, 1, crd3[64 + lane], wave, fB);
+  if (pc.nch() >= 2) load_chunk_f<T, kFwd>(a, pc, 1, crd3[64 + lane], wave, fB);
   else load_chunk_f<T, kFwd>(a, pn, 0, crd3[kRows + lane], wave, fB);
   for (;;) {
     ring_step2<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, p3, fA, fC, part, crd3, yring, tzr, rg, c3, tzrow,
                         pre, rin);
-    if (pc.done) break;
+    if (pc.done()) break;
     ring_step2<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, p3, fB, fA, part, crd3, yring, tzr, rg, c3, tzrow,
                         pre, rin);
-    if (pc.done) break;
+    if (pc.done()) break;
     ring_step2<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, p3, fC, fB, part, crd3, yring, tzr, rg, c3, tzrow,
                         pre, rin);
-    if (pc.done) break;
+    if (pc.done()) break;
   }
 }
 
