@@ -12,7 +12,7 @@ rtol 1e-6.  The operator assembly and the ILU(0) setup are done once per
 operator and reported separately (setup_ms).  Inputs are resident in HBM
 when the timed region starts.
 
-Prints one JSON line.  --gpus must be 1: this build runs on a single GPU.
+Prints one JSON line.  --gpus must be 1: the solver runs on a single GPU.
 """
 import argparse
 import json
@@ -341,7 +341,7 @@ def main():
     ap.add_argument("--rate", type=float, default=50.0, help="serve mode: arrivals per second")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus}); "
               "sharding across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
