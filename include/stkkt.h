@@ -139,6 +139,14 @@ typedef struct {
   double rtol;              /* stop when ||b - F x|| <= rtol ||b||        */
   int32_t flexible;         /* 0: GMRES, 1: FGMRES                       */
   int32_t fixed_iters;      /* > 0: run exactly this many steps (no test) */
+  int32_t graph;            /* kkt_solve_batch only: 1 = the Arnoldi steps of
+                               a cycle replayed from captured HIP graphs, the
+                               Givens rotations and convergence flags on the
+                               device (one host check per 8 steps); 0 = one
+                               host check per step.  Members with a coarse
+                               level, or whose preconditioners cannot share
+                               one launch, always run with 0.  Ignored by
+                               kkt_solve.                                    */
 } solve_params_t;
 
 typedef struct {

@@ -68,7 +68,7 @@ class _CoarseParams(ctypes.Structure):
 
 class _SolveParams(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double),
-                ("flexible", ctypes.c_int32), ("fixed_iters", ctypes.c_int32)]
+                ("flexible", ctypes.c_int32), ("fixed_iters", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class _ServerParams(ctypes.Structure):
@@ -379,8 +379,11 @@ def _to_stats(st):
 
 
 def solve_batch(ops, pres, bs=None, xs=None, *, restart=30, rtol=1e-6, maxit=10000, fixed_iters=0, stream=None,
-                raise_on_fail=True):
-    """Solve F_i x_i = b_i for every instance together (batched FGMRES); x_i holds x0 on entry."""
+                raise_on_fail=True, graph=True):
+    """Solve F_i x_i = b_i for every instance together (batched FGMRES); x_i holds x0 on entry.
+
+    graph: replay each cycle's Arnoldi steps from captured HIP graphs (rotations
+    and convergence flags on the device) instead of checking on the host every step."""
     torch = _torch()
     count = len(ops)
     if count == 0 or len(pres) != count:
@@ -392,7 +395,7 @@ def solve_batch(ops, pres, bs=None, xs=None, *, restart=30, rtol=1e-6, maxit=100
     h_ras = arr(*[p.handle for p in pres])
     h_b = arr(*[_ptr(b) for b in bs])
     h_x = arr(*[_ptr(x) for x in xs])
-    sp = _SolveParams(int(restart), int(maxit), float(rtol), 1, int(fixed_iters))
+    sp = _SolveParams(int(restart), int(maxit), float(rtol), 1, int(fixed_iters), 1 if graph else 0)
     st = (_Stats * count)()
     rc = _lib.kkt_solve_batch(count, h_ops, h_ras, ctypes.byref(sp), h_b, h_x, _stream(stream), st)
     if raise_on_fail:

@@ -33,6 +33,7 @@ namespace {
 constexpr int kBT = 256;          // threads per block
 constexpr long long kChunk = 4096;   // elements per reduction chunk
 constexpr int kGroup = 8;         // basis vectors per pass of the multi-dot
+constexpr int kGraphSteps = 8;    // Arnoldi steps per captured graph (one host check each)
 
 struct Chunk {
   int32_t inst, pad;
@@ -153,6 +154,86 @@ __global__ void __launch_bounds__(kBT) bnormalize_kernel(double *__restrict__ ou
   for (long long e = c.lo + threadIdx.x; e < c.hi; e += kBT) out[e] = x[e] * inv;
 }
 
+// Givens arithmetic shared by the host (one check per step) and the device
+// (graph form), written out with no fused multiply-adds so that both give
+// the same bits: a member's result does not depend on which form ran it.
+__host__ __device__ inline void rot_apply(double c, double s, double a, double b, double &na, double &nb) {
+#pragma clang fp contract(off)
+  na = c * a + s * b;
+  nb = -s * a + c * b;
+}
+
+// c, s, d with c x + s y = d, -s x + c y = 0 (d = sqrt(x^2 + y^2), scaled)
+__host__ __device__ inline void rot_make(double x, double y, double &c, double &s, double &d) {
+#pragma clang fp contract(off)
+  const double ax = x < 0 ? -x : x, ay = y < 0 ? -y : y;
+  const double big = ax > ay ? ax : ay, small = ax > ay ? ay : ax;
+  if (big == 0.0) {
+    c = 1.0, s = 0.0, d = 0.0;
+    return;
+  }
+  const double r = small / big;
+  d = big * sqrt(1.0 + r * r);
+  c = x / d;
+  s = y / d;
+}
+
+// Arnoldi step j of every member still in its cycle (one thread per member):
+// the new Hessenberg column from the two CGS passes, the member's previous
+// Givens rotations applied to it, the new rotation, the residual estimate
+// |g[j+1]|.  A member leaves the cycle (its flag in act cleared) when the
+// estimate meets its target, at its step limit, at the end of the cycle, or
+// on a zero or non-finite norm (non-finite: breakdown flag).  Per member, st
+// holds cs[m], sn[m], g[m+1], H[(m+1) m] (H[q m + j]); in: iters, kdone,
+// breakdown.
+__global__ void bgivens_kernel(int j, int m, int S, const double *__restrict__ hd, int hs, double *__restrict__ st,
+                               long long stride, int *__restrict__ in, const double *__restrict__ tgt, int limit,
+                               int fixed, int *__restrict__ act) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S || !act[i]) return;
+  const double *h = hd + (long long)i * hs;
+  double *cs = st + i * stride, *sn = cs + m, *g = sn + m, *H = g + (m + 1);
+  int *ci = in + 4 * i;
+  const double hn = sqrt(h[2 * (m + 1)]);
+  // the column is rotated top down with one carried entry: entry q is final
+  // once rotation q has been applied
+  double a = h[0] + h[m + 1];
+  for (int q = 0; q < j; ++q) {
+    const double b = h[q + 1] + h[(m + 1) + q + 1];
+    double na, nb;
+    rot_apply(cs[q], sn[q], a, b, na, nb);
+    H[(long long)q * m + j] = na;
+    a = nb;
+  }
+  double c, sg, d;
+  rot_make(a, hn, c, sg, d);
+  cs[j] = c;
+  sn[j] = sg;
+  H[(long long)j * m + j] = d;
+  H[(long long)(j + 1) * m + j] = 0.0;
+  g[j + 1] = -sg * g[j];
+  g[j] = c * g[j];
+  ci[0] += 1;
+  ci[1] = j + 1;
+  const double est = fabs(g[j + 1]);
+  bool leave = ci[0] >= limit || hn == 0.0 || j + 1 == m;
+  if (!isfinite(est) || !isfinite(hn)) {
+    leave = true;
+    ci[2] = 1;
+  }
+  if (fixed == 0 && est <= tgt[i]) leave = true;
+  if (leave) act[i] = 0;
+}
+
+// start of a cycle: g = (beta, 0, ..., 0) for the members in act
+__global__ void bcycle_init_kernel(int m, int S, double *__restrict__ st, long long stride,
+                                   const double *__restrict__ beta, const int *__restrict__ act) {
+  const int i = blockIdx.y;
+  if (i >= S || !act[i]) return;
+  double *g = st + i * stride + 2 * m;
+  for (int q = threadIdx.x; q <= m; q += blockDim.x) g[q] = q == 0 ? beta[i] : 0.0;
+}
+
 // out = x - y
 __global__ void __launch_bounds__(kBT) bsub_kernel(double *__restrict__ out, const double *__restrict__ x,
                                                    const double *__restrict__ y, const Chunk *__restrict__ ch,
@@ -217,6 +298,12 @@ BatchEngine::BatchEngine(const Allocator *al, const solve_params_t &sp, long lon
   hh_ = std::make_unique<PinnedBlock>(sizeof(double) * (size_t)slots * hs_);
   hy_ = std::make_unique<PinnedBlock>(sizeof(double) * (size_t)slots * m);
   hflags_ = std::make_unique<PinnedBlock>(sizeof(int) * 4 * (size_t)slots);
+  gstride_ = 2 * (long long)m + (m + 1) + (long long)(m + 1) * m;
+  gst_ = DevBuf(al, sizeof(double) * (size_t)slots * gstride_);
+  gin_ = DevBuf(al, sizeof(int) * 4 * (size_t)slots);
+  gtg_ = DevBuf(al, sizeof(double) * 2 * (size_t)slots);
+  hg_ = std::make_unique<PinnedBlock>(sizeof(double) * ((size_t)slots * gstride_ + 2 * (size_t)slots) +
+                                      sizeof(int) * 4 * (size_t)slots);
   fill_zero(V_.as<double>(), (long long)((m + 1) * N), s);
   fill_zero(Z_.as<double>(), (long long)(m * N), s);
   fill_zero(B_.as<double>(), cap_, s);
@@ -225,6 +312,16 @@ BatchEngine::BatchEngine(const Allocator *al, const solve_params_t &sp, long lon
   fill_zero(W_.as<double>(), cap_, s);
   fill_zero(T_.as<double>(), cap_, s);
   free_[0] = cap_;
+}
+
+BatchEngine::~BatchEngine() {
+  drop_graphs();
+  if (cs_) (void)hipStreamDestroy(cs_);
+}
+
+void BatchEngine::drop_graphs() {
+  for (hipGraphExec_t e : graphs_) (void)hipGraphExecDestroy(e);
+  graphs_.clear();
 }
 
 long long BatchEngine::free_elems() const {
@@ -333,6 +430,7 @@ void BatchEngine::rebuild() {
   STKKT_HIP(hipMemcpyAsync(cfirst_.ptr, cf.data(), sizeof(int) * cf.size(), hipMemcpyHostToDevice, s_));
   matvec_batch_prepare(ops.data(), voff.data(), S, al_, mv_, s_);   // synchronises: ch, cf may go
   ras_batch_prepare(rs.data(), voff.data(), loc.data(), S, al_, rb_, s_);
+  drop_graphs();   // captured with the previous composition's work lists
   dirty_ = false;
 }
 
@@ -385,6 +483,120 @@ void BatchEngine::precondition(int j, const int *act_dev) {
     axpby(t, 1.0, vi, -1.0, t, sl.n, s_);
     ras_apply_device(sl.R, t, zi, s_, sl.local.ptr);
     axpby(zi, 1.0, zi, 1.0, y, sl.n, s_);
+  }
+}
+
+// CGS2 of step j for the members in act: h1 = V^T w; w -= V h1 with
+// h2 = V^T w; w -= V h2 with |w|^2 (into hd at 0, m+1 and 2(m+1))
+void BatchEngine::cgs2(int j, const int *act) {
+  const int m = m_, hs = hs_;
+  const long long N = cap_;
+  double *hd = hdev_.as<double>(), *Vd = V_.as<double>(), *Wd = W_.as<double>();
+  const Chunk *chd = chunks_.as<Chunk>();
+  bdot(Vd, N, j + 1, Wd, act, hd);
+  if (cgs2_fused_ok(j + 1) && nch_ > 0) {
+    double *part = partial_.as<double>();
+    const int *cf = cfirst_.as<int>();
+    const unsigned S = (unsigned)slots_.size();
+    hipLaunchKernelGGL(bupdate_dot_kernel, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd, hs, chd, nch_,
+                       act, part);
+    hipLaunchKernelGGL(breduce_kernel, dim3(S, j + 1), dim3(kBT), 0, s_, part, nch_, cf, act, hs, hd + (m + 1));
+    hipLaunchKernelGGL(bupdate_norm_kernel, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd + (m + 1), hs,
+                       chd, act, part);
+    hipLaunchKernelGGL(breduce_kernel, dim3(S, 1), dim3(kBT), 0, s_, part, nch_, cf, act, hs, hd + 2 * (m + 1));
+    STKKT_HIP(hipGetLastError());
+  } else {
+    hipLaunchKernelGGL(bupdate_kernel, dim3(nch_), dim3(kBT), 0, s_, Wd, Vd, N, j + 1, hd, hs, chd, act);
+    bdot(Vd, N, j + 1, Wd, act, hd + (m + 1));
+    hipLaunchKernelGGL(bupdate_kernel, dim3(nch_), dim3(kBT), 0, s_, Wd, Vd, N, j + 1, hd + (m + 1), hs, chd, act);
+    bdot(Wd, 0, 1, Wd, act, hd + 2 * (m + 1));
+  }
+}
+
+// Step j with no host involvement: z_j, w = F z_j, CGS2, the rotations on
+// the device (members leaving the cycle drop out of act_a_), v_{j+1}.
+void BatchEngine::arnoldi_step(int j) {
+  const int S = (int)slots_.size(), m = m_, hs = hs_;
+  const long long N = cap_;
+  int *act = act_a_.as<int>();
+  double *hd = hdev_.as<double>(), *Vd = V_.as<double>(), *Zd = Z_.as<double>(), *Wd = W_.as<double>();
+  ras_batch_run(rb_, Vd + (long long)j * N, Zd + (long long)j * N, act, hflags_->as<int>(), s_);
+  matvec_batch_run(mv_, Zd + (long long)j * N, Wd, act, s_);
+  cgs2(j, act);
+  const int limit = sp_.fixed_iters > 0 ? sp_.fixed_iters : sp_.maxit;
+  hipLaunchKernelGGL(bgivens_kernel, dim3((S + 63) / 64), dim3(64), 0, s_, j, m, S, hd, hs, gst_.as<double>(), gstride_,
+                     gin_.as<int>(), gtg_.as<double>(), limit, sp_.fixed_iters, act);
+  if (j + 1 < m)
+    hipLaunchKernelGGL(bnormalize_kernel, dim3(nch_), dim3(kBT), 0, s_, Vd + (long long)(j + 1) * N, Wd,
+                       hd + 2 * (m + 1), hs, chunks_.as<Chunk>(), act);
+  STKKT_HIP(hipGetLastError());
+}
+
+// One cycle of the running members (flags run[], already in act_a_, v_0
+// formed) from captured graphs of kGraphSteps steps each, captured once per
+// composition on an engine stream and replayed on the engine's stream; one
+// host check of the flags per graph.  Afterwards each member's rotations,
+// Hessenberg columns and step counts are copied back to its slot.
+void BatchEngine::cycle_graph(const int *run, int S) {
+  const int m = m_;
+  double *hgd = hg_->as<double>();
+  int *hgi = reinterpret_cast<int *>(hgd + (size_t)S * gstride_ + 2 * (size_t)S);
+  double *tg = hgd + (size_t)S * gstride_;
+  for (int i = 0; i < S; ++i) {
+    tg[i] = slots_[i].target;
+    tg[S + i] = slots_[i].beta;
+    hgi[4 * i] = slots_[i].st.iters;
+    hgi[4 * i + 1] = hgi[4 * i + 2] = hgi[4 * i + 3] = 0;
+  }
+  STKKT_HIP(hipMemcpyAsync(gtg_.ptr, tg, sizeof(double) * 2 * S, hipMemcpyHostToDevice, s_));
+  STKKT_HIP(hipMemcpyAsync(gin_.ptr, hgi, sizeof(int) * 4 * S, hipMemcpyHostToDevice, s_));
+  hipLaunchKernelGGL(bcycle_init_kernel, dim3(1, S), dim3(64), 0, s_, m, S, gst_.as<double>(), gstride_,
+                     gtg_.as<double>() + S, act_a_.as<int>());
+  STKKT_HIP(hipGetLastError());
+  if (graphs_.empty()) {
+    if (!cs_) STKKT_HIP(hipStreamCreateWithFlags(&cs_, hipStreamNonBlocking));
+    for (int j0 = 0; j0 < m; j0 += kGraphSteps) {
+      hipGraph_t g = nullptr;
+      STKKT_HIP(hipStreamBeginCapture(cs_, hipStreamCaptureModeThreadLocal));
+      std::swap(s_, cs_);
+      try {
+        for (int j = j0; j < std::min(m, j0 + kGraphSteps); ++j) arnoldi_step(j);
+      } catch (...) {
+        std::swap(s_, cs_);
+        (void)hipStreamEndCapture(cs_, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      std::swap(s_, cs_);
+      STKKT_HIP(hipStreamEndCapture(cs_, &g));
+      hipGraphExec_t e = nullptr;
+      const hipError_t rc = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      STKKT_HIP(rc);
+      graphs_.push_back(e);
+    }
+  }
+  int *hact = hflags_->as<int>() + 3 * S;
+  for (hipGraphExec_t e : graphs_) {
+    STKKT_HIP(hipGraphLaunch(e, s_));
+    STKKT_HIP(hipMemcpyAsync(hact, act_a_.ptr, sizeof(int) * S, hipMemcpyDeviceToHost, s_));
+    STKKT_HIP(hipStreamSynchronize(s_));
+    bool any = false;
+    for (int i = 0; i < S; ++i) any = any || hact[i] != 0;
+    if (!any) break;
+  }
+  STKKT_HIP(hipMemcpyAsync(hgd, gst_.ptr, sizeof(double) * (size_t)S * gstride_, hipMemcpyDeviceToHost, s_));
+  STKKT_HIP(hipMemcpyAsync(hgi, gin_.ptr, sizeof(int) * 4 * S, hipMemcpyDeviceToHost, s_));
+  STKKT_HIP(hipStreamSynchronize(s_));
+  for (int i = 0; i < S; ++i) {
+    if (!run[i]) continue;
+    Slot &sl = slots_[i];
+    const double *st = hgd + (size_t)i * gstride_;
+    std::copy(st + 2 * m, st + 3 * m + 1, sl.g.begin());
+    std::copy(st + 3 * m + 1, st + 3 * m + 1 + (size_t)(m + 1) * m, sl.Hm.begin());
+    sl.st.iters = hgi[4 * i];
+    sl.kdone = hgi[4 * i + 1];
+    if (hgi[4 * i + 2]) sl.breakdown = true;
   }
 }
 
@@ -466,32 +678,18 @@ void BatchEngine::cycle(std::vector<int> &finished) {
   // v_0 = r / beta: |r|^2 of every running member is in hd (last residual)
   hipLaunchKernelGGL(bnormalize_kernel, dim3(nch_), dim3(kBT), 0, s_, Vd, Rd, hd, hs, chd, act_a_.as<int>());
   STKKT_HIP(hipGetLastError());
-  int nstep = ncyc;
+  bool graph = sp_.graph != 0 && rb_.ring;
+  for (int i = 0; i < S && graph; ++i)
+    if (h_cyc[i] && slots_[i].C) graph = false;
+  int nstep = graph ? 0 : ncyc;
+  if (graph) cycle_graph(h_cyc, S);
   std::vector<double> col(m + 1);
   for (int j = 0; j < m && nstep > 0; ++j) {
     const int *act = act_a_.as<int>();
     double *zj = Zd + (long long)j * N;
     precondition(j, act);
     matvec_batch_run(mv_, zj, Wd, act, s_);
-    // CGS2: h1 = V^T w; w -= V h1 with h2 = V^T w; w -= V h2 with |w|^2
-    bdot(Vd, N, j + 1, Wd, act, hd);
-    if (cgs2_fused_ok(j + 1) && nch_ > 0) {
-      double *part = partial_.as<double>();
-      const int *cf = cfirst_.as<int>();
-      const unsigned S_ = (unsigned)slots_.size();
-      hipLaunchKernelGGL(bupdate_dot_kernel, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd, hs, chd,
-                         nch_, act, part);
-      hipLaunchKernelGGL(breduce_kernel, dim3(S_, j + 1), dim3(kBT), 0, s_, part, nch_, cf, act, hs, hd + (m + 1));
-      hipLaunchKernelGGL(bupdate_norm_kernel, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd + (m + 1),
-                         hs, chd, act, part);
-      hipLaunchKernelGGL(breduce_kernel, dim3(S_, 1), dim3(kBT), 0, s_, part, nch_, cf, act, hs, hd + 2 * (m + 1));
-      STKKT_HIP(hipGetLastError());
-    } else {
-      hipLaunchKernelGGL(bupdate_kernel, dim3(nch_), dim3(kBT), 0, s_, Wd, Vd, N, j + 1, hd, hs, chd, act);
-      bdot(Vd, N, j + 1, Wd, act, hd + (m + 1));
-      hipLaunchKernelGGL(bupdate_kernel, dim3(nch_), dim3(kBT), 0, s_, Wd, Vd, N, j + 1, hd + (m + 1), hs, chd, act);
-      bdot(Wd, 0, 1, Wd, act, hd + 2 * (m + 1));
-    }
+    cgs2(j, act);
     fetch();
     bool changed = false;
     for (int i = 0; i < S; ++i) {
@@ -502,17 +700,9 @@ void BatchEngine::cycle(std::vector<int> &finished) {
       std::fill(col.begin(), col.end(), 0.0);
       for (int q = 0; q <= j; ++q) col[q] = hi[q] + hi[(m + 1) + q];
       col[j + 1] = hn;
-      for (int q = 0; q < j; ++q) {
-        const double tmp = sl.cs[q] * col[q] + sl.sn[q] * col[q + 1];
-        col[q + 1] = -sl.sn[q] * col[q] + sl.cs[q] * col[q + 1];
-        col[q] = tmp;
-      }
-      const double d = std::hypot(col[j], col[j + 1]);
-      double c = 1.0, sg = 0.0;
-      if (d != 0.0) {
-        c = col[j] / d;
-        sg = col[j + 1] / d;
-      }
+      for (int q = 0; q < j; ++q) rot_apply(sl.cs[q], sl.sn[q], col[q], col[q + 1], col[q], col[q + 1]);
+      double c, sg, d;
+      rot_make(col[j], col[j + 1], c, sg, d);
       sl.cs[j] = c;
       sl.sn[j] = sg;
       col[j] = d;

@@ -64,6 +64,10 @@ class BatchEngine {
     std::chrono::steady_clock::time_point t0;
   };
   void rebuild();
+  void drop_graphs();
+  void cgs2(int j, const int *act);
+  void arnoldi_step(int j);   // the device-only step of the graph form (flags in act_a_)
+  void cycle_graph(const int *run, int S);
   void upload(int *host, DevBuf &dev);
   void bdot(const double *V, long long ldv, int k, const double *w, const int *act, double *out);
   void fetch();
@@ -84,6 +88,18 @@ class BatchEngine {
   int nch_ = 0;
   MvBatch mv_;
   RasBatch rb_;
+  // graph form: per slot cs[m], sn[m], g[m+1], H[(m+1) m] (gst_), iters,
+  // kdone, breakdown, spare (gin_), target (gtg_); captured step graphs of
+  // the current composition (kGraphSteps steps each), captured on cs_
+  DevBuf gst_, gin_, gtg_;
+  std::unique_ptr<PinnedBlock> hg_;
+  hipStream_t cs_ = nullptr;
+  std::vector<hipGraphExec_t> graphs_;
+  long long gstride_ = 0;
+ public:
+  ~BatchEngine();
+  BatchEngine(const BatchEngine &) = delete;
+  BatchEngine &operator=(const BatchEngine &) = delete;
 };
 
 }  // namespace stkkt

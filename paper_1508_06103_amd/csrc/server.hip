@@ -55,6 +55,7 @@ kkt_server *server_create(const server_params_t *p, const kkt_alloc_t *al, hipSt
   srv->sp.maxit = p->maxit;
   srv->sp.rtol = p->rtol;
   srv->sp.flexible = 1;
+  srv->sp.graph = 1;
   srv->s = s;
   // half of the budget for the concatenated Krylov vectors (2m + 6 of them),
   // half for the members' own buffers (RAS local vectors, two-level temporaries)

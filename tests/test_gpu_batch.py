@@ -76,6 +76,27 @@ def test_batch_matches_oracle_and_alone(st):
         assert e <= 1e-7
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_graph_matches_eager(st, prec):
+    """Cycles replayed from captured graphs (rotations and flags on the device,
+    one host check per 8 steps) give the same bits as host-checked steps; with
+    a restart of 12 every cycle replays two graphs, and the solves take several
+    cycles, so graphs are replayed repeatedly with the engine's own work and
+    synchronisations in between."""
+    mix = [m for m in MIX if m[0] != "tall"]   # members that share one apply launch
+    precision = st.F64 if prec == "f64" else st.F32
+    built = [build(st, *m, precision=precision) for m in mix]
+    ops = [b[1] for b in built]
+    pres = [b[2] for b in built]
+    xe, se = st.solve_batch(ops, pres, restart=12, rtol=1e-8, graph=False)
+    xg, sg = st.solve_batch(ops, pres, restart=12, rtol=1e-8, graph=True)
+    for (name, *_), a, b, sa, sb in zip(mix, xe, xg, se, sg):
+        _say(f"  {name} ({prec}): eager {sa.iters} its / {sa.restarts} restarts, graph {sb.iters} / {sb.restarts}")
+        assert sa.converged and sb.converged
+        assert sa.iters == sb.iters and sa.restarts == sb.restarts
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()), name
+
+
 def test_batch_fixed_steps_in_mix(st):
     """Fixed-step mode over the whole mix equals the oracle instance by instance."""
     built = [build(st, *m, precision=st.F64) for m in MIX[:3]]
