@@ -224,10 +224,12 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
       }
     }
   }
-  double cm[KH], c0[KH], gm[KH], g0[KH], fm[KH], f0[KH];
+  // halo values of levels n - 1, n, n + 1 (c, g, f), and level n + 2 in
+  // flight: the loads of a level are issued one level before it is used
+  double cm[KH], c0[KH], gm[KH], g0[KH], fm[KH], f0[KH], c1[KH], g1[KH], f1[KH], c2[KH], g2[KH], f2[KH];
 #pragma unroll
   for (int s = 0; s < KH; ++s) {
-    cm[s] = gm[s] = fm[s] = c0[s] = g0[s] = f0[s] = 0.0;
+    cm[s] = gm[s] = fm[s] = c0[s] = g0[s] = f0[s] = c1[s] = g1[s] = f1[s] = 0.0;
     if (hin[s] && n0 >= 1) {
       const double *p = x + 3LL * (n0 - 1) * N + hoff[s];
       cm[s] = p[0];
@@ -240,6 +242,12 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
       g0[s] = p[1];
       f0[s] = p[2];
     }
+    if (hin[s] && n0 < M) {
+      const double *p = x + 3LL * (n0 + 1) * N + hoff[s];
+      c1[s] = p[0];
+      g1[s] = p[1];
+      f1[s] = p[2];
+    }
   }
 
   for (int n = n0; n < n1; ++n) {
@@ -250,15 +258,21 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
                  stp = hp ? -mc.inv_tau : 0.0;
     const double ttm = hm ? mc.tau6 : 0.0, tt0 = tend ? mc.tau3 : 2.0 * mc.tau3, ttp = hp ? mc.tau6 : 0.0;
     const bool mflag = !dto || hm;
+    // level n + 2, used by the next level (only while that level is in this chunk)
+    const bool pre = n + 2 <= M && n + 1 < n1;
 #pragma unroll
     for (int s = 0; s < KH; ++s) {
-      double cp = 0.0, gp = 0.0, fp = 0.0;
-      if (hin[s] && hp) {
-        const double *p = x + 3LL * (n + 1) * N + hoff[s];
-        cp = p[0];
-        gp = p[1];
-        fp = p[2];
+      c2[s] = g2[s] = f2[s] = 0.0;
+      if (hin[s] && pre) {
+        const double *p = x + 3LL * (n + 2) * N + hoff[s];
+        c2[s] = p[0];
+        g2[s] = p[1];
+        f2[s] = p[2];
       }
+    }
+#pragma unroll
+    for (int s = 0; s < KH; ++s) {
+      const double cp = hp ? c1[s] : 0.0, gp = hp ? g1[s] : 0.0, fp = hp ? f1[s] : 0.0;
       if (hact[s]) {
         const int h = t + kMvThreads * s;
         const double P = hP[s];
@@ -273,10 +287,13 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
       }
       cm[s] = c0[s];
       c0[s] = cp;
+      c1[s] = c2[s];
       gm[s] = g0[s];
       g0[s] = gp;
+      g1[s] = g2[s];
       fm[s] = f0[s];
       f0[s] = fp;
+      f1[s] = f2[s];
     }
     __syncthreads();
     // rebuild the node's stencil weights every level instead of keeping them live
