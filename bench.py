@@ -158,6 +158,15 @@ def auto_parts(prob, box=8):
     return tuple(max(1, int(round(l / box))) for l in L)
 
 
+def batch_parts(prob, how):
+    """(parts, overlap) of an uneven-batch instance: the autotuned table
+    (paper_1508_06103_amd/parts_table.json), or boxes of about 8 nodes with overlap 1."""
+    if how == "tuned":
+        from paper_1508_06103_amd.tune import parts_for
+        return parts_for(prob)
+    return auto_parts(prob), 1
+
+
 def run_batch(args):
     """Batched uneven instances: solves/s of the whole batch per step, FP32
     preconditioners inside FP64 FGMRES(50), against the same instances solved
@@ -171,7 +180,7 @@ def run_batch(args):
     print(f"[bench] batch: {len(probs)} instances, {unknowns} unknowns", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     ops = [st.KKTOperator(p) for p in probs]
-    pres = [st.RAS(op, auto_parts(p), 1, precision=st.F32) for op, p in zip(ops, probs)]
+    pres = [st.RAS(op, *batch_parts(p, args.parts), precision=st.F32) for op, p in zip(ops, probs)]
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     bs = [torch.empty(op.n, dtype=torch.float64, device="cuda") for op in ops]
@@ -200,10 +209,11 @@ def run_batch(args):
               file=sys.stderr, flush=True)
     total = time.perf_counter() - t_start
     value = count * args.steps / total
-    # baseline: the same instances one at a time, plain FP64 (factors rebuilt per instance, setup not timed)
+    # baseline: the same instances one at a time, plain FP64 (factors rebuilt per instance, setup not timed),
+    # with ~8-node boxes, which suit single small solves better than the batch's tuned (larger) boxes
     base_t, base_its = 0.0, []
     for i, (p, op) in enumerate(zip(probs, ops)):
-        pre64 = st.RAS(op, auto_parts(p), 1, precision=st.F64)
+        pre64 = st.RAS(op, *batch_parts(p, "box8"), precision=st.F64)
         op.rhs(redraw_noise(p, 5000 + args.warmup * count + i), out=bs[i])
         xs[i].zero_()
         torch.cuda.synchronize()
@@ -221,7 +231,9 @@ def run_batch(args):
         "ms_per_step": 1e3 * total / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 outer / f32 preconditioner", "data": "synthetic (seeded uneven instances, fresh noise per step)",
         "config": {"workload": f"batch of {count} uneven instances: n in {{8,12,16,20,24}}, M in {{16,24,32,48}}, "
-                               f"1-3 sources, 27-64 sensors, ~8-node subdomains, overlap 1, FGMRES(50)",
+                               f"1-3 sources, 27-64 sensors, "
+                               f"{'autotuned subdomains and overlap per size class' if args.parts == 'tuned' else '~8-node subdomains, overlap 1'}, "
+                               f"FGMRES(50)",
                    "unknowns": unknowns},
         "p50_ms": 1e3 * percentile(times, 50), "p99_ms": 1e3 * percentile(times, 99),
         "gmres_iters": float(np.mean(its)), "setup_ms": 1e3 * t_setup,
@@ -242,12 +254,12 @@ def run_serve(args):
     from workloads.generate import batch_instances, make_problem, redraw_noise
     pool = batch_instances(count=16, base_seed=3000)
     large, _ = make_problem("cube32x64", seed=4, lattice=3)   # 27 sensors, all on coarse nodes
-    specs = [(p, auto_parts(p), None) for p in pool] + [(large, (4, 4, 4, 8), (4, 4, 4, 4))]
+    specs = [(p, batch_parts(p, args.parts), None) for p in pool] + [(large, ((4, 4, 4, 8), 1), (4, 4, 4, 4))]
     t0 = time.perf_counter()
     built = []
-    for p, parts, fac in specs:
+    for p, (parts, delta), fac in specs:
         op = st.KKTOperator(p)
-        pre = st.RAS(op, parts, 1, precision=st.F32)
+        pre = st.RAS(op, parts, delta, precision=st.F32)
         C = st.Coarse(op, fac, (2, 2, 2, 4), overlap=1, maxit=4, rtol=0.1, precision=st.F32) if fac else None
         built.append((p, op, pre, C))
     torch.cuda.synchronize()
@@ -288,9 +300,11 @@ def run_serve(args):
     svc, base64 = [], {}
     for k in range(n):
         p, op, pre, C = built[which[k]]
-        parts, fac = specs[which[k]][1], specs[which[k]][2]
+        (parts, delta), fac = specs[which[k]][1], specs[which[k]][2]
+        if fac is None:
+            parts, delta = batch_parts(p, "box8")   # one at a time: ~8-node boxes suit single small solves
         if which[k] not in base64:
-            base64[which[k]] = (st.RAS(op, parts, 1, precision=st.F64),
+            base64[which[k]] = (st.RAS(op, parts, delta, precision=st.F64),
                                 st.Coarse(op, fac, (2, 2, 2, 4), overlap=1, maxit=4, rtol=0.1) if fac else None)
         pre64, C64 = base64[which[k]]
         b = op.rhs(datas[k])
@@ -312,7 +326,8 @@ def run_serve(args):
         "vs_baseline": None, "dtype": "f64 outer / f32 preconditioner",
         "data": "synthetic (seeded request stream, fresh noise per request)",
         "config": {"workload": f"served stream: {n} Poisson requests at {args.rate}/s; 90% on 16 uneven operators "
-                               f"(n 8-24, M 16-48), 10% on 32^3 x 64 with two-level RAS (coarse 8^3 x 16)"},
+                               f"(n 8-24, M 16-48, {'autotuned' if args.parts == 'tuned' else '~8-node'} subdomains), "
+                               f"10% on 32^3 x 64 with two-level RAS (coarse 8^3 x 16)"},
         "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99), "gmres_iters": float(np.mean(its)),
         "setup_ms": 1e3 * t_setup,
         "baseline_one_at_a_time_fp64": {"value": base, "unit": "solves/s", "p50_ms": 1e3 * percentile(blat, 50),
@@ -337,6 +352,8 @@ def main():
     ap.add_argument("--coarse", default="lu", choices=["lu", "gmres"],
                     help="two-level configurations: exact block-LU coarse solve, or the paper's coarse GMRES(4)+RAS")
     ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--parts", default="tuned", choices=["tuned", "box8"],
+                    help="batch/serve partitions: the autotuned table, or boxes of about 8 nodes with overlap 1")
     ap.add_argument("--requests", type=int, default=100)
     ap.add_argument("--rate", type=float, default=50.0, help="serve mode: arrivals per second")
     args = ap.parse_args()

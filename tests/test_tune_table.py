@@ -1,0 +1,25 @@
+"""The committed partition table of the autotuner (host only)."""
+import pytest
+
+from paper_1508_06103_amd import tune
+from workloads.generate import BATCH_M, BATCH_N, class_instances
+
+
+def test_table_covers_every_class_with_valid_partitions():
+    tab = tune._load()["classes"]
+    for n in BATCH_N:
+        for M in BATCH_M:
+            rec = tab[f"{n}x{M}"]
+            parts, d = rec["parts"], rec["overlap"]
+            assert len(parts) == 4 and all(p >= 1 for p in parts)
+            assert all(p <= n + 1 for p in parts[:3]) and parts[3] <= M + 1
+            assert d in tune.OVERLAPS
+            assert ((tuple(parts), d) in tune.candidates(n, M))
+
+
+@pytest.mark.parametrize("n,M", [(8, 16), (20, 32), (24, 48)])
+def test_parts_for_reads_the_class(n, M):
+    prob = class_instances(n, M, count=1)[0]
+    parts, d = tune.parts_for(prob)
+    rec = tune._load()["classes"][f"{n}x{M}"]
+    assert list(parts) == rec["parts"] and d == rec["overlap"]

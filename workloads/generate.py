@@ -339,6 +339,28 @@ def make_custom(n, M, seed, *, sensors=None, lattice=2, nsrc=1, width=0.15, smoo
                  length=length, T=T)
 
 
+BATCH_N = (8, 12, 16, 20, 24)
+BATCH_M = (16, 24, 32, 48)
+
+
+def _uneven_instance(i, seed, rng, n, M):
+    """One instance of the uneven batch: 1-3 sources, 27-64 sensors, noise 0.5-2%,
+    beta in {1e-5, 1e-4, 1e-3}, drawn from rng after the sizes."""
+    nsrc = int(rng.integers(1, 4))
+    s = int(rng.integers(27, 65))
+    noise = float(rng.uniform(0.005, 0.02))
+    beta = float(rng.choice([1e-5, 1e-4, 1e-3]))
+    nn = n + 1
+    interior = (n - 1) ** 3
+    pick = np.sort(rng.choice(interior, size=s, replace=False))
+    i1 = pick % (n - 1) + 1
+    j1 = (pick // (n - 1)) % (n - 1) + 1
+    k1 = pick // (n - 1) ** 2 + 1
+    sensors = (i1 + nn * (j1 + nn * k1)).astype(np.int32)
+    return _make(f"batch{i}", (n, n, n), M, seed + 10000, smooth_coef=True, nsrc=nsrc,
+                 width=0.08, sin_int=True, sensors=sensors, noise=noise, beta=beta)
+
+
 def batch_instances(count=64, base_seed=3000, max_n=None, max_M=None):
     """Uneven batch: n in {8..24}, M in {16..48}, 1-3 sources, 27-64 sensors.
 
@@ -347,24 +369,21 @@ def batch_instances(count=64, base_seed=3000, max_n=None, max_M=None):
     out = []
     for i in range(count):
         rng = np.random.default_rng(base_seed + i)
-        n = int(rng.choice([8, 12, 16, 20, 24]))
-        M = int(rng.choice([16, 24, 32, 48]))
+        n = int(rng.choice(BATCH_N))
+        M = int(rng.choice(BATCH_M))
         if max_n is not None:
             n = min(n, int(max_n))
         if max_M is not None:
             M = min(M, int(max_M))
-        nsrc = int(rng.integers(1, 4))
-        s = int(rng.integers(27, 65))
-        noise = float(rng.uniform(0.005, 0.02))
-        beta = float(rng.choice([1e-5, 1e-4, 1e-3]))
-        nn = n + 1
-        interior = (n - 1) ** 3
-        pick = np.sort(rng.choice(interior, size=s, replace=False))
-        i1 = pick % (n - 1) + 1
-        j1 = (pick // (n - 1)) % (n - 1) + 1
-        k1 = pick // (n - 1) ** 2 + 1
-        sensors = (i1 + nn * (j1 + nn * k1)).astype(np.int32)
-        prob = _make(f"batch{i}", (n, n, n), M, base_seed + 10000 + i, smooth_coef=True, nsrc=nsrc,
-                     width=0.08, sin_int=True, sensors=sensors, noise=noise, beta=beta)
-        out.append(prob)
+        out.append(_uneven_instance(i, base_seed + i, rng, n, M))
+    return out
+
+
+def class_instances(n, M, count=4, base_seed=9000):
+    """Instances of one size class (n, M) of the uneven batch, the other draws as there."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(base_seed + 101 * n + 7 * M + i)
+        rng.choice(BATCH_N), rng.choice(BATCH_M)   # keep the draw sequence of batch_instances
+        out.append(_uneven_instance(i, base_seed + 101 * n + 7 * M + i, rng, n, M))
     return out
