@@ -137,7 +137,12 @@ typedef struct {
   int32_t restart;          /* Krylov dimension per cycle (>= 1)        */
   int32_t maxit;            /* total Arnoldi steps allowed               */
   double rtol;              /* stop when ||b - F x|| <= rtol ||b||        */
-  int32_t flexible;         /* 0: GMRES, 1: FGMRES                       */
+  int32_t flexible;         /* 0: GMRES, 1: FGMRES.  Both keep the
+                               preconditioned basis in device memory (m more
+                               n-vectors) and update x from it, so GMRES
+                               needs no extra preconditioner application per
+                               restart; its iterates are those of right-
+                               preconditioned GMRES up to rounding.          */
   int32_t fixed_iters;      /* > 0: run exactly this many steps (no test) */
   int32_t graph;            /* kkt_solve_batch only: 1 = the Arnoldi steps of
                                a cycle replayed from captured HIP graphs, the

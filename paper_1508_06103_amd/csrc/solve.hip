@@ -55,7 +55,12 @@ int gmres_solve(const kkt_op *op, const ras *R, const coarse *C, const solve_par
   const auto t0 = std::chrono::steady_clock::now();
   const long long n = 3 * op->d.V;
   const int m = sp.restart;
-  const bool flex = sp.flexible != 0;
+  // Both forms keep the preconditioned vectors z_j = M^{-1} v_j (one more
+  // n-vector per step in device memory) and update x from them, so a restart
+  // needs no further preconditioner application.  With a fixed preconditioner
+  // (sp.flexible == 0) this gives the iterates of right-preconditioned GMRES
+  // up to rounding (M^{-1} is linear); with a varying one it is FGMRES.
+  const bool flex = true;
   std::unique_ptr<GmresWork> own;
   if (!work || !work->fits(n, m, flex, C != nullptr)) {
     own = std::make_unique<GmresWork>(&op->al, n, m, flex, C != nullptr);
