@@ -211,6 +211,23 @@ int coarse_setup(const kkt_op_t *fine, const coarse_params_t *cp, void *stream, 
  * steps is the normal case and not an error).  Synchronises `stream`. */
 int coarse_apply(const coarse_t *c, const double *x, double *y, void *stream);
 
+/* Several applications of the coarse level at once: y_i = coarse_apply(x_i)
+ * for i < q, with x_i = x + i ldx and y_i = y + i ldy (device vectors of
+ * kkt_size(fine) doubles; ldx, ldy >= that size; the x and y ranges must not
+ * overlap).  Two-level preconditioning (Section 3.2) of several right-hand
+ * sides on one operator applies the same F_c^{-1} to each restricted vector:
+ * with the exact block solve (STKKT_COARSE_LU) the q coarse vectors go through
+ * the forward and backward sweeps together, each dense block being read once
+ * per 16 right-hand sides and multiplied on the FP64 matrix cores (FP32
+ * blocks widened to FP64), so that y_i depends on x_i only, not on q or on
+ * the other vectors.  With the inner coarse GMRES the q applications run one
+ * after the other.  The handle keeps a workspace of 2 q coarse vectors, grown
+ * on demand (growing synchronises `stream`); calls on one handle must be
+ * ordered on one stream.  q = 0 does nothing.  Errors: STKKT_EINVAL for
+ * q < 0, NULL pointers, short strides or overlapping x and y. */
+int coarse_apply_multi(const coarse_t *c, int32_t q, const double *x, int64_t ldx, double *y, int64_t ldy,
+                       void *stream);
+
 /* Solve F_h x = b.  coarse == NULL selects the one-level preconditioner;
  * otherwise M^{-1} x = y + M_one^{-1}(x - F_h y), y = coarse_apply(x).
  * x: device, holds x0 on entry (zero it for the paper's x0 = 0) and the

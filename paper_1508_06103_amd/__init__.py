@@ -96,6 +96,7 @@ _sig = {
     "ras_export_factors": (ctypes.c_int, [_vp, ctypes.c_int32, _c_dp]),
     "coarse_setup": (ctypes.c_int, [_vp, ctypes.POINTER(_CoarseParams), _vp, ctypes.POINTER(_vp)]),
     "coarse_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "coarse_apply_multi": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp]),
     "kkt_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_SolveParams), _vp, _vp, _vp,
                                  ctypes.POINTER(_Stats)]),
     "kkt_solve_batch": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
@@ -333,6 +334,21 @@ class Coarse:
         torch = _torch()
         y = torch.empty_like(x) if y is None else y
         _check(_lib.coarse_apply(self.handle, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def apply_multi(self, x, y=None, stream=None):
+        """y[i] = apply(x[i]) for the rows of the 2-D float64 device tensors x, y
+        (q rows of the fine size, unit stride within a row)."""
+        torch = _torch()
+        y = torch.empty_like(x) if y is None else y
+        if x.dim() != 2 or y.shape != x.shape or x.stride(1) != 1 or y.stride(1) != 1:
+            raise ValueError("apply_multi: x and y must be (q, n) tensors with unit stride in a row")
+        for t in (x, y):
+            if not t.is_cuda or t.dtype != torch.float64:
+                raise TypeError("apply_multi: expected float64 CUDA tensors")
+        _check(_lib.coarse_apply_multi(self.handle, int(x.shape[0]), ctypes.c_void_p(x.data_ptr()),
+                                       int(x.stride(0)), ctypes.c_void_p(y.data_ptr()), int(y.stride(0)),
+                                       _stream(stream)))
         return y
 
     def close(self):

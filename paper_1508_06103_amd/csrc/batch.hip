@@ -18,6 +18,7 @@
 // the end of the cycle every instance that took part updates its iterate and
 // computes its true residual; those that have not converged start the next
 // cycle together.  Finished instances are masked out of every launch.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <memory>
@@ -453,7 +454,9 @@ void BatchEngine::fetch() {
 }
 
 // z_j = M^{-1} v_j for the members flagged in act: one-level members through
-// the batched RAS launch, two-level members one by one.
+// the batched RAS launch; for two-level members the coarse corrections of all
+// members on one coarse level go through one multi-right-hand-side coarse
+// application, the rest member by member.
 void BatchEngine::precondition(int j, const int *act_dev) {
   const long long N = cap_;
   const double *v = V_.as<double>() + (long long)j * N;
@@ -472,13 +475,29 @@ void BatchEngine::precondition(int j, const int *act_dev) {
   }
   upload(h_ras, act_c_);
   ras_batch_run(rb_, v, z, act_c_.as<int>(), h_ras, s_);
+  // y = I_c^h F_c^{-1} I_h^c v, grouped by coarse level
+  std::vector<const coarse *> seen;
+  std::vector<const double *> xs;
+  std::vector<double *> ys;
+  for (int i = 0; i < S; ++i) {
+    const coarse *C = slots_[i].C;
+    if (!hf[i] || !C || std::find(seen.begin(), seen.end(), C) != seen.end()) continue;
+    seen.push_back(C);
+    xs.clear();
+    ys.clear();
+    for (int k = i; k < S; ++k)
+      if (hf[k] && slots_[k].C == C) {
+        xs.push_back(v + slots_[k].voff);
+        ys.push_back(slots_[k].y2.as<double>());
+      }
+    coarse_apply_multi_device(C, (int)xs.size(), xs.data(), ys.data(), s_);
+  }
   for (int i = 0; i < S; ++i) {
     const Slot &sl = slots_[i];
     if (!hf[i] || !sl.C) continue;
     const double *vi = v + sl.voff;
     double *zi = z + sl.voff, *y = sl.y2.as<double>(), *t = sl.t2.as<double>();
-    // z = y + M_one^{-1} (v - F y),  y = I_c^h F_c^{-1} I_h^c v
-    coarse_apply_device(sl.C, vi, y, s_);
+    // z = y + M_one^{-1} (v - F y)
     matvec_device(sl.op, y, t, s_);
     axpby(t, 1.0, vi, -1.0, t, sl.n, s_);
     ras_apply_device(sl.R, t, zi, s_, sl.local.ptr);

@@ -219,6 +219,15 @@ int coarse_apply(const coarse_t *c, const double *x, double *y, void *stream) {
   });
 }
 
+int coarse_apply_multi(const coarse_t *c, int32_t q, const double *x, int64_t ldx, double *y, int64_t ldy,
+                       void *stream) {
+  return guarded([&] {
+    STKKT_REQUIRE(c && (q == 0 || (x && y)), "coarse_apply_multi: NULL argument");
+    coarse_apply_strided(c, q, x, ldx, y, ldy, as_stream(stream));
+    return STKKT_OK;
+  });
+}
+
 int kkt_solve(const kkt_op_t *op, const ras_t *R, const coarse_t *C, const solve_params_t *sp, const double *b,
               double *x, void *stream, kkt_stats_t *stats) {
   return guarded([&] {

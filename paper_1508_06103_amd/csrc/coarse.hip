@@ -7,6 +7,7 @@
 // elimination in time with explicitly inverted Schur complements (CoarseLU).
 #include <cmath>
 #include <memory>
+#include <vector>
 
 #include "coarse.hpp"
 #include "coarse_lu.hpp"
@@ -21,6 +22,10 @@ struct coarse {
   kkt_op *cop = nullptr;    // owned coarse operator
   ras *cras = nullptr;      // owned coarse preconditioner
   stkkt::DevBuf xc, yc;     // coarse vectors
+  stkkt::DevBuf rt[2];      // intermediate vectors of the axis-by-axis restriction
+  // coarse vectors of several right-hand sides (exact coarse solve), grown on demand
+  mutable stkkt::DevBuf xcm, ycm;
+  mutable int mcap = 0;
   std::unique_ptr<stkkt::GmresWork> work;   // inner GMRES workspace
   std::unique_ptr<stkkt::CoarseLU> lu;       // exact coarse solve (method LU)
   ~coarse() {
@@ -76,55 +81,94 @@ __global__ void prolong_kernel(OpDev fo, OpDev co, int fx, int fy, int fz, int f
   }
 }
 
-// x_coarse = (I_c^h)^T x_fine (transpose: every coarse node gathers the fine
-// nodes of its support) or injection (the fine value at the coarse node).
-__global__ void restrict_kernel(OpDev fo, OpDev co, int fx, int fy, int fz, int ft, int injection,
-                                const double *__restrict__ x, double *__restrict__ xc) {
+// x_coarse = injection of x_fine (the fine value at every coarse node)
+__global__ void inject_kernel(OpDev fo, OpDev co, int fx, int fy, int fz, int ft, const double *__restrict__ x,
+                              double *__restrict__ xc) {
   for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < co.V;
        g += (long long)gridDim.x * blockDim.x) {
     const int n = (int)(g / co.N);
     const long long j = g - (long long)n * co.N;
-    const int I[4] = {(int)(j % co.nn[0]), (int)((j / co.nn[0]) % co.nn[1]), (int)(j / ((long long)co.nn[0] * co.nn[1])), n};
-    const int f[4] = {fx, fy, fz, ft};
-    const int L[4] = {fo.nn[0], fo.nn[1], fo.nn[2], fo.M + 1};
-    if (injection) {
-      const long long fg = 3 * ((long long)(I[3] * f[3]) * fo.N + I[0] * f[0] +
-                                (long long)fo.nn[0] * (I[1] * f[1] + (long long)fo.nn[1] * (I[2] * f[2])));
-      xc[3 * g] = x[fg];
-      xc[3 * g + 1] = x[fg + 1];
-      xc[3 * g + 2] = x[fg + 2];
-      continue;
+    const int I0 = (int)(j % co.nn[0]), I1 = (int)((j / co.nn[0]) % co.nn[1]),
+              I2 = (int)(j / ((long long)co.nn[0] * co.nn[1]));
+    const long long fg =
+        3 * ((long long)(n * ft) * fo.N + I0 * fx + (long long)fo.nn[0] * (I1 * fy + (long long)fo.nn[1] * (I2 * fz)));
+    xc[3 * g] = x[fg];
+    xc[3 * g + 1] = x[fg + 1];
+    xc[3 * g + 2] = x[fg + 2];
+  }
+}
+
+// One axis of the transposed interpolation (the restriction is the tensor
+// product of the 1-D ones, so it is applied axis by axis): `out` has the node
+// counts `din` of `in` with axis d coarsened by f (D -> (D - 1) / f + 1),
+// components innermost, and out[.., I, .., c] = sum over the fine nodes p of
+// the support of coarse node I of hat(p, I, f) in[.., p, .., c].
+struct Dims4 {
+  int n[4];
+};
+
+__global__ void restrict_axis_kernel(Dims4 din, int d, int f, const double *__restrict__ in,
+                                     double *__restrict__ out) {
+  int dout[4], sin[4];
+  for (int k = 0; k < 4; ++k) dout[k] = din.n[k];
+  dout[d] = (din.n[d] - 1) / f + 1;
+  sin[0] = 3;
+  for (int k = 1; k < 4; ++k) sin[k] = sin[k - 1] * din.n[k - 1];
+  const int total = 3 * dout[0] * dout[1] * dout[2] * dout[3];
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
+    int rest = g / 3, base = g % 3, I = 0;
+    for (int k = 0; k < 4; ++k) {
+      const int o = rest % dout[k];
+      rest /= dout[k];
+      if (k == d) I = o;
+      else base += o * sin[k];
     }
-    int lo[4], hi[4];
-    for (int d = 0; d < 4; ++d) {
-      lo[d] = max(0, I[d] * f[d] - f[d] + 1);
-      hi[d] = min(L[d] - 1, I[d] * f[d] + f[d] - 1);
-    }
-    double a0 = 0, a1 = 0, a2 = 0;
-    for (int p3 = lo[3]; p3 <= hi[3]; ++p3) {
-      const double w3 = hat(p3, I[3], f[3]);
-      for (int p2 = lo[2]; p2 <= hi[2]; ++p2) {
-        const double w2 = w3 * hat(p2, I[2], f[2]);
-        for (int p1 = lo[1]; p1 <= hi[1]; ++p1) {
-          const double w1 = w2 * hat(p1, I[1], f[1]);
-          const long long base = 3 * ((long long)p3 * fo.N + (long long)fo.nn[0] * (p1 + (long long)fo.nn[1] * p2));
-          for (int p0 = lo[0]; p0 <= hi[0]; ++p0) {
-            const double w = w1 * hat(p0, I[0], f[0]);
-            const long long fg = base + 3LL * p0;
-            a0 += w * x[fg];
-            a1 += w * x[fg + 1];
-            a2 += w * x[fg + 2];
-          }
-        }
-      }
-    }
-    xc[3 * g] = a0;
-    xc[3 * g + 1] = a1;
-    xc[3 * g + 2] = a2;
+    const int lo = max(0, I * f - f + 1), hi = min(din.n[d] - 1, I * f + f - 1);
+    double acc = 0.0;
+    for (int p = lo; p <= hi; ++p) acc += hat(p, I, f) * in[(long long)base + (long long)p * sin[d]];
+    out[g] = acc;
   }
 }
 
 }  // namespace
+
+// xc = (I_c^h)^T x, axis by axis (x, y, z, t; axes with factor 1 are skipped)
+static void restrict_transpose(const coarse *C, const double *x, double *xc, hipStream_t s) {
+  const OpDev &fo = C->fine;
+  Dims4 dm{{fo.nn[0], fo.nn[1], fo.nn[2], fo.M + 1}};
+  int axes[4], na = 0;
+  for (int d = 0; d < 4; ++d)
+    if (C->fac[d] > 1) axes[na++] = d;
+  if (na == 0) {
+    STKKT_HIP(hipMemcpyAsync(xc, x, sizeof(double) * 3 * fo.V, hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  const double *src = x;
+  for (int k = 0; k < na; ++k) {
+    const int d = axes[k];
+    double *dst = k == na - 1 ? xc : C->rt[k & 1].as<double>();
+    Dims4 out = dm;
+    out.n[d] = (dm.n[d] - 1) / C->fac[d] + 1;
+    const long long total = 3LL * out.n[0] * out.n[1] * out.n[2] * out.n[3];
+    hipLaunchKernelGGL(restrict_axis_kernel, dim3(blocks_for(total, 256, 1 << 16)), dim3(256), 0, s, dm, d,
+                       C->fac[d], src, dst);
+    dm = out;
+    src = dst;
+  }
+  STKKT_HIP(hipGetLastError());
+}
+
+// xc = I_h^c x: the transposed interpolation or injection
+static void restrict_to_coarse(const coarse *C, const double *x, double *xc, hipStream_t s) {
+  if (C->params.restrict_kind == STKKT_RESTRICT_INJECTION) {
+    const OpDev &fo = C->fine, &co = C->cop->d;
+    hipLaunchKernelGGL(inject_kernel, dim3(blocks_for(co.V, 256, 8192)), dim3(256), 0, s, fo, co, C->fac[0],
+                       C->fac[1], C->fac[2], C->fac[3], x, xc);
+    STKKT_HIP(hipGetLastError());
+  } else {
+    restrict_transpose(C, x, xc, s);
+  }
+}
 
 coarse *coarse_create(const kkt_op *fine, const coarse_params_t *cp, hipStream_t s) {
   STKKT_REQUIRE(cp->method == STKKT_COARSE_GMRES_RAS || cp->method == STKKT_COARSE_LU,
@@ -184,6 +228,18 @@ coarse *coarse_create(const kkt_op *fine, const coarse_params_t *cp, hipStream_t
   const size_t nvc = 3 * (size_t)C->cop->d.V;
   C->xc = DevBuf(&C->al, sizeof(double) * nvc);
   C->yc = DevBuf(&C->al, sizeof(double) * nvc);
+  {
+    // the restriction's intermediates: sizes after the first and second coarsened axes
+    long long dm[4] = {fd.nn[0], fd.nn[1], fd.nn[2], fd.M + 1}, sz[2] = {1, 1};
+    int k = 0;
+    for (int d = 0; d < 4 && k < 2; ++d)
+      if (cp->factor[d] > 1) {
+        dm[d] = (dm[d] - 1) / cp->factor[d] + 1;
+        sz[k++] = 3 * dm[0] * dm[1] * dm[2] * dm[3];
+      }
+    C->rt[0] = DevBuf(&C->al, sizeof(double) * sz[0]);
+    C->rt[1] = DevBuf(&C->al, sizeof(double) * sz[1]);
+  }
   if (cp->method == STKKT_COARSE_LU) {
     C->lu = std::make_unique<CoarseLU>(&C->al, C->cop, cp->precision, s);
   } else {
@@ -200,10 +256,7 @@ coarse *coarse_create(const kkt_op *fine, const coarse_params_t *cp, hipStream_t
 
 void coarse_apply_device(const coarse *C, const double *x, double *y, hipStream_t s) {
   const OpDev &fo = C->fine, &co = C->cop->d;
-  hipLaunchKernelGGL(restrict_kernel, dim3(blocks_for(co.V, 256, 8192)), dim3(256), 0, s, fo, co, C->fac[0],
-                     C->fac[1], C->fac[2], C->fac[3], C->params.restrict_kind == STKKT_RESTRICT_INJECTION ? 1 : 0, x,
-                     C->xc.as<double>());
-  STKKT_HIP(hipGetLastError());
+  restrict_to_coarse(C, x, C->xc.as<double>(), s);
   if (C->lu) {
     C->lu->solve(C->xc.as<double>(), C->yc.as<double>(), s);
   } else {
@@ -221,6 +274,47 @@ void coarse_apply_device(const coarse *C, const double *x, double *y, hipStream_
   hipLaunchKernelGGL(prolong_kernel, dim3(blocks_for(fo.V, 256, 1 << 16)), dim3(256), 0, s, fo, co, C->fac[0],
                      C->fac[1], C->fac[2], C->fac[3], C->yc.as<double>(), y);
   STKKT_HIP(hipGetLastError());
+}
+
+void coarse_apply_multi_device(const coarse *C, int q, const double *const *x, double *const *y, hipStream_t s) {
+  if (q <= 0) return;
+  if (!C->lu) {
+    for (int i = 0; i < q; ++i) coarse_apply_device(C, x[i], y[i], s);
+    return;
+  }
+  const OpDev &fo = C->fine, &co = C->cop->d;
+  const long long nvc = 3 * co.V;
+  if (q > C->mcap) {
+    STKKT_HIP(hipStreamSynchronize(s));   // launches already queued may still use the old vectors
+    C->xcm = DevBuf(&C->al, sizeof(double) * (size_t)nvc * q);
+    C->ycm = DevBuf(&C->al, sizeof(double) * (size_t)nvc * q);
+    C->mcap = q;
+  }
+  double *xc = C->xcm.as<double>(), *yc = C->ycm.as<double>();
+  for (int i = 0; i < q; ++i) restrict_to_coarse(C, x[i], xc + i * nvc, s);
+  C->lu->solve_multi(q, xc, nvc, yc, nvc, s);
+  for (int i = 0; i < q; ++i)
+    hipLaunchKernelGGL(prolong_kernel, dim3(blocks_for(fo.V, 256, 1 << 16)), dim3(256), 0, s, fo, co, C->fac[0],
+                       C->fac[1], C->fac[2], C->fac[3], yc + i * nvc, y[i]);
+  STKKT_HIP(hipGetLastError());
+}
+
+void coarse_apply_strided(const coarse *C, int q, const double *x, long long ldx, double *y, long long ldy,
+                          hipStream_t s) {
+  const long long n = 3 * C->fine.V;
+  STKKT_REQUIRE(q >= 0, "coarse_apply_multi: q must be >= 0");
+  if (q == 0) return;
+  STKKT_REQUIRE(ldx >= n && ldy >= n, "coarse_apply_multi: strides shorter than the fine vector");
+  const double *xe = x + (q - 1) * ldx + n;
+  const double *ye = y + (q - 1) * ldy + n;
+  STKKT_REQUIRE(ye <= x || xe <= y, "coarse_apply_multi: x and y must not overlap");
+  std::vector<const double *> xs(q);
+  std::vector<double *> ys(q);
+  for (int i = 0; i < q; ++i) {
+    xs[i] = x + i * ldx;
+    ys[i] = y + i * ldy;
+  }
+  coarse_apply_multi_device(C, q, xs.data(), ys.data(), s);
 }
 
 void coarse_free(coarse *c) { delete c; }

@@ -42,6 +42,13 @@ void server_step(struct kkt_server *srv, int32_t *n_running, int32_t *n_pending)
 int server_poll(struct kkt_server *srv, int64_t ticket, kkt_stats_t *st);
 void server_free(struct kkt_server *srv);
 void coarse_apply_device(const coarse *C, const double *x, double *y, hipStream_t s);
+// y[i] = coarse_apply(x[i]) for i < q (host arrays of device pointers); with
+// the exact coarse solve the q coarse right-hand sides share one pass over
+// the dense blocks.  Calls on one handle must be ordered on one stream.
+void coarse_apply_multi_device(const coarse *C, int q, const double *const *x, double *const *y, hipStream_t s);
+// the same for x_i = x + i ldx, y_i = y + i ldy (checked: strides, overlap)
+void coarse_apply_strided(const coarse *C, int q, const double *x, long long ldx, double *y, long long ldy,
+                          hipStream_t s);
 coarse *coarse_create(const kkt_op *fine, const coarse_params_t *cp, hipStream_t s);
 void coarse_free(coarse *c);
 bool coarse_built_for(const coarse *c, const kkt_op *op);

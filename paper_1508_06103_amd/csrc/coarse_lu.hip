@@ -375,9 +375,10 @@ __global__ void lower_rhs_kernel(int nb, const int32_t *__restrict__ idx, const 
 
 constexpr int kGvRows = 256, kGvCols = 128;
 
-// partial[chunk][r] = sum over the chunk's columns of A(r, c) x(c)   (column-major A)
+// partial[chunk][r] = sum over the chunk's columns of A(r, c) x(c)
+// (column-major A with leading dimension ld)
 template <typename T>
-__global__ void __launch_bounds__(kGvRows) gemv_partial_kernel(int nb, const T *__restrict__ A,
+__global__ void __launch_bounds__(kGvRows) gemv_partial_kernel(int nb, int ld, const T *__restrict__ A,
                                                                const double *__restrict__ x,
                                                                double *__restrict__ partial) {
   __shared__ T xs[kGvCols];
@@ -388,8 +389,8 @@ __global__ void __launch_bounds__(kGvRows) gemv_partial_kernel(int nb, const T *
   const int r = blockIdx.x * kGvRows + threadIdx.x;
   if (r >= nb) return;
   T acc = 0;
-  const T *a = A + (long long)c0 * nb + r;
-  for (int c = 0; c < nc; ++c) acc += a[(long long)c * nb] * xs[c];
+  const T *a = A + (long long)c0 * ld + r;
+  for (int c = 0; c < nc; ++c) acc += a[(long long)c * ld] * xs[c];
   partial[(long long)blockIdx.y * nb + r] = (double)acc;
 }
 
@@ -403,9 +404,147 @@ __global__ void gemv_reduce_kernel(int nb, int nchunk, const double *__restrict_
   }
 }
 
-__global__ void to_float_kernel(long long n, const double *__restrict__ a, float *__restrict__ b) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    b[i] = (float)a[i];
+// out (leading dimension ld, rows nb..ld-1 zero) = S (nb x nb, leading dimension nb), column c = blockIdx.y
+template <typename T>
+__global__ void store_padded_kernel(int nb, int ld, const double *__restrict__ S, T *__restrict__ out) {
+  const int c = blockIdx.y;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < ld; r += gridDim.x * blockDim.x)
+    out[(long long)c * ld + r] = r < nb ? (T)S[(long long)c * nb + r] : (T)0;
+}
+
+// ---------------------------------------------------------------------------
+// several right-hand sides at once.  The product inputs are kept transposed,
+// XT[col][16] (the value of right-hand side c at column col in XT[16 col + c]),
+// so that the matrix-core operands of 4 consecutive columns x 16 right-hand
+// sides are one contiguous 512-byte read.
+// ---------------------------------------------------------------------------
+constexpr int kMrRows = 64, kMrRhs = 16, kMrThreads = 256, kMrAhead = 8;
+
+// tT[i][c] = r_c[i] - (L y_c)[i] for the right-hand sides c = blockIdx.y
+// (r_c = r + c ldr, y_c = y + c ldy; with y == nullptr: t = r)
+__global__ void lower_rhs_multi_kernel(int nb, const int32_t *__restrict__ idx, const double *__restrict__ val,
+                                       const double *__restrict__ r, long long ldr, const double *__restrict__ y,
+                                       long long ldy, double *__restrict__ tT) {
+  const int c = blockIdx.y;
+  const double *rc = r + c * ldr;
+  const double *yc = y ? y + c * ldy : nullptr;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
+    double acc = rc[i];
+    if (yc)
+      for (int q = 0; q < 81; ++q) acc -= val[(long long)i * 81 + q] * yc[idx[(long long)i * 81 + q]];
+    tT[(long long)i * kMrRhs + c] = acc;
+  }
+}
+
+// Y = A X for up to 16 right-hand sides on the FP64 matrix cores
+// (v_mfma_f64_16x16x4: lane l supplies a = A[l%16][l/16], b = B[l/16][l%16]
+// and holds D[l/16 + 4j][l%16], j = 0..3).  A workgroup of 4 wavefronts owns
+// 64 rows and a chunk of columns (blockIdx.y); step s of wavefront w takes
+// columns 16 s + 4 w .. 16 s + 4 w + 3 of the chunk.  Lane (i, kk) =
+// (l%16, l/16) reads rows 4i .. 4i + 3 of its column with one 16-byte load
+// (float) or two (double) and gives row 4i + m to product m (m = 0..3), so
+// product m covers rows m, 4 + m, .., 60 + m of the tile and each column of
+// the tile is one contiguous 256- or 512-byte read.  Loads run kMrAhead steps
+// ahead of the products, with no branch: a column past the chunk reads the
+// chunk's last column and enters as zero.  The four wavefronts' sums
+// are added in LDS and written to partial[chunk][c][row] (leading dimension
+// ld).  Float blocks are widened to double on load.  Column n of a product
+// depends on column n of X only, so a right-hand side's result does not
+// depend on the others.
+// raw loads of 4 rows, widened and masked only when the products use them
+// (a conversion right after the load would make the wavefront wait for it)
+struct Rows4f {
+  float4 v;
+  __device__ void load(const float *p) { v = *reinterpret_cast<const float4 *>(p); }
+  __device__ void get(bool ok, double a[4]) const {
+    a[0] = ok ? (double)v.x : 0.0;
+    a[1] = ok ? (double)v.y : 0.0;
+    a[2] = ok ? (double)v.z : 0.0;
+    a[3] = ok ? (double)v.w : 0.0;
+  }
+};
+struct Rows4d {
+  double2 u, v;
+  __device__ void load(const double *p) {
+    u = *reinterpret_cast<const double2 *>(p);
+    v = *reinterpret_cast<const double2 *>(p + 2);
+  }
+  __device__ void get(bool ok, double a[4]) const {
+    a[0] = ok ? u.x : 0.0;
+    a[1] = ok ? u.y : 0.0;
+    a[2] = ok ? v.x : 0.0;
+    a[3] = ok ? v.y : 0.0;
+  }
+};
+template <typename T> struct Rows4;
+template <> struct Rows4<float> { using type = Rows4f; };
+template <> struct Rows4<double> { using type = Rows4d; };
+
+template <typename T>
+__global__ void __launch_bounds__(kMrThreads) gemm_partial_kernel(int nb, int ld, int csplit, const T *__restrict__ A,
+                                                                  int q, const double *__restrict__ XT,
+                                                                  double *__restrict__ partial) {
+  __shared__ double red[4 * kMrRhs * kMrRows];   // [wave][rhs][row]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int r0 = blockIdx.x * kMrRows;
+  const int cbeg = blockIdx.y * csplit, cend = min(nb, cbeg + csplit);
+  const int nst = ((cend - cbeg + 15) / 16 + kMrAhead - 1) / kMrAhead * kMrAhead;
+  const T *arow = A + r0 + 4 * li;
+  f64x4 acc[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) acc[m] = f64x4{0.0, 0.0, 0.0, 0.0};
+  typename Rows4<T>::type raw[kMrAhead];
+  double b[kMrAhead];
+  const int c_lane = cbeg + 4 * wave + lk;   // column of step 0
+  auto fetch = [&](int p, int st) {
+    const int cc = min(c_lane + 16 * st, cend - 1);
+    raw[p].load(arow + (long long)cc * ld);
+    b[p] = XT[(long long)cc * kMrRhs + li];
+  };
+#pragma unroll
+  for (int p = 0; p < kMrAhead; ++p) fetch(p, p);
+  // the last kMrAhead fetches read the chunk's last column again (cache hits,
+  // unused): an unconditional fetch keeps the wait counts exact
+  for (int st = 0; st < nst; st += kMrAhead) {
+#pragma unroll
+    for (int p = 0; p < kMrAhead; ++p) {
+      double a[4];
+      raw[p].get(c_lane + 16 * (st + p) < cend, a);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[p], acc[m], 0, 0, 0);
+      fetch(p, st + kMrAhead + p);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[(wave * kMrRhs + li) * kMrRows + 4 * (lk + 4 * j) + m] = acc[m][j];
+  __syncthreads();
+  const int rhs = tid >> 4, rl = 4 * (tid & 15);
+  if (rhs >= q) return;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int row = r0 + rl + u;
+    const double v = red[(0 * kMrRhs + rhs) * kMrRows + rl + u] + red[(1 * kMrRhs + rhs) * kMrRows + rl + u] +
+                     red[(2 * kMrRhs + rhs) * kMrRows + rl + u] + red[(3 * kMrRhs + rhs) * kMrRows + rl + u];
+    if (row < nb) partial[((long long)blockIdx.y * q + rhs) * ld + row] = v;
+  }
+}
+
+// out_c[r] = base_c[r] + sign * sum_chunks partial[chunk][c][r] (fixed order),
+// c = blockIdx.y; the same value also goes to outT[r][c]
+__global__ void gemm_reduce_kernel(int nb, int ld, int q, int nchunk, const double *__restrict__ partial,
+                                   const double *base, long long ldb, double sign, double *out, long long ldo,
+                                   double *__restrict__ outT) {
+  const int c = blockIdx.y;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nb; r += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < nchunk; ++k) s += partial[((long long)k * q + c) * ld + r];
+    const double v = (base ? base[c * ldb + r] : 0.0) + sign * s;
+    out[c * ldo + r] = v;
+    outT[(long long)r * kMrRhs + c] = v;
+  }
 }
 
 }  // namespace
@@ -449,13 +588,23 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
   nlev_ = d.M + 1;
   STKKT_REQUIRE(nb_ <= 65535, "coarse_setup: coarse level too large for the dense block solve");
   const size_t nn = (size_t)nb_ * nb_;
+  ld_ = (nb_ + kMrRows - 1) / kMrRows * kMrRows;
+  const size_t nld = (size_t)ld_ * nb_;
   const size_t esz = precision == STKKT_F32 ? sizeof(float) : sizeof(double);
-  Sinv_ = DevBuf(al, esz * nn * nlev_);
-  E_ = DevBuf(al, esz * nn * std::max(nlev_ - 1, 1));
+  Sinv_ = DevBuf(al, esz * nld * nlev_);
+  E_ = DevBuf(al, esz * nld * std::max(nlev_ - 1, 1));
   Lidx_ = DevBuf(al, sizeof(int32_t) * (size_t)nb_ * 81 * nlev_);
   Lval_ = DevBuf(al, sizeof(double) * (size_t)nb_ * 81 * nlev_);
   partial_ = DevBuf(al, sizeof(double) * (size_t)nb_ * ((nb_ + kGvCols - 1) / kGvCols));
   t_ = DevBuf(al, sizeof(double) * nb_);
+  // multi-RHS products: about 1024 workgroups (64 rows x a column chunk of at
+  // least 256 columns) per block
+  {
+    const int tiles = ld_ / kMrRows, chunks = (nb_ + 255) / 256;
+    nsplit_ = std::min(chunks, std::max(1, (1024 + tiles - 1) / tiles));
+  }
+  mpartial_ = DevBuf(al, sizeof(double) * (size_t)nsplit_ * kMrRhs * ld_);
+  mt_ = DevBuf(al, sizeof(double) * (size_t)3 * kMrRhs * nb_);   // tT, xT[0], xT[1]
   // setup work buffers (FP64)
   DevBuf S(al, sizeof(double) * nn), Ed(al, sizeof(double) * nn),
       tmp(al, sizeof(double) * nn), rows(al, sizeof(double) * (size_t)kPanel * nb_), piv(al, sizeof(int32_t) * nb_),
@@ -500,19 +649,20 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
                          S.as<double>(), Ed.as<double>());
       STKKT_HIP(hipGetLastError());
     }
-    // store S_k^{-1} and E_k in the application precision
+    // store S_k^{-1} and E_k in the application precision, columns padded to ld_
+    const dim3 gp(blocks_for(ld_, 256, 64), nb_);
     if (prec_ == STKKT_F32) {
-      hipLaunchKernelGGL(to_float_kernel, dim3(4096), dim3(256), 0, s, (long long)nn, S.as<double>(),
-                         Sinv_.as<float>() + (size_t)k * nn);
+      hipLaunchKernelGGL(store_padded_kernel<float>, gp, dim3(256), 0, s, nb_, ld_, S.as<double>(),
+                         Sinv_.as<float>() + (size_t)k * nld);
       if (k + 1 < nlev_)
-        hipLaunchKernelGGL(to_float_kernel, dim3(4096), dim3(256), 0, s, (long long)nn, Ed.as<double>(),
-                           E_.as<float>() + (size_t)k * nn);
+        hipLaunchKernelGGL(store_padded_kernel<float>, gp, dim3(256), 0, s, nb_, ld_, Ed.as<double>(),
+                           E_.as<float>() + (size_t)k * nld);
     } else {
-      STKKT_HIP(hipMemcpyAsync(Sinv_.as<double>() + (size_t)k * nn, S.ptr, sizeof(double) * nn,
-                               hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(store_padded_kernel<double>, gp, dim3(256), 0, s, nb_, ld_, S.as<double>(),
+                         Sinv_.as<double>() + (size_t)k * nld);
       if (k + 1 < nlev_)
-        STKKT_HIP(hipMemcpyAsync(E_.as<double>() + (size_t)k * nn, Ed.ptr, sizeof(double) * nn,
-                                 hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(store_padded_kernel<double>, gp, dim3(256), 0, s, nb_, ld_, Ed.as<double>(),
+                           E_.as<double>() + (size_t)k * nld);
     }
     STKKT_HIP(hipGetLastError());
   }
@@ -523,17 +673,17 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
 }
 
 template <typename T>
-static void gemv(int nb, const T *A, const double *x, const double *base, double sign, double *partial, double *out,
-                 hipStream_t s) {
+static void gemv(int nb, int ld, const T *A, const double *x, const double *base, double sign, double *partial,
+                 double *out, hipStream_t s) {
   const int nch = (nb + kGvCols - 1) / kGvCols;
-  hipLaunchKernelGGL(gemv_partial_kernel<T>, dim3((nb + kGvRows - 1) / kGvRows, nch), dim3(kGvRows), 0, s, nb, A, x,
-                     partial);
+  hipLaunchKernelGGL(gemv_partial_kernel<T>, dim3((nb + kGvRows - 1) / kGvRows, nch), dim3(kGvRows), 0, s, nb, ld, A,
+                     x, partial);
   hipLaunchKernelGGL(gemv_reduce_kernel, dim3(blocks_for(nb, 256, 256)), dim3(256), 0, s, nb, nch, partial, base,
                      sign, out);
 }
 
 template <typename T> void CoarseLU::solve_t(const double *r, double *x, hipStream_t s) const {
-  const size_t nn = (size_t)nb_ * nb_;
+  const size_t nn = (size_t)ld_ * nb_;
   const T *Si = static_cast<const T *>(Sinv_.ptr);
   const T *E = static_cast<const T *>(E_.ptr);
   double *t = t_.as<double>(), *part = partial_.as<double>();
@@ -544,11 +694,11 @@ template <typename T> void CoarseLU::solve_t(const double *r, double *x, hipStre
     hipLaunchKernelGGL(lower_rhs_kernel, dim3(blocks_for(nb_, 256, 256)), dim3(256), 0, s, nb_,
                        Lidx_.as<int32_t>() + (size_t)k * nb_ * 81, Lval_.as<double>() + (size_t)k * nb_ * 81, rk,
                        yprev, t);
-    gemv<T>(nb_, Si + (size_t)k * nn, t, nullptr, 1.0, part, x + (size_t)k * nb_, s);
+    gemv<T>(nb_, ld_, Si + (size_t)k * nn, t, nullptr, 1.0, part, x + (size_t)k * nb_, s);
   }
   // backward: x_k = y_k - E_k x_{k+1}
   for (int k = nlev_ - 2; k >= 0; --k)
-    gemv<T>(nb_, E + (size_t)k * nn, x + (size_t)(k + 1) * nb_, x + (size_t)k * nb_, -1.0, part,
+    gemv<T>(nb_, ld_, E + (size_t)k * nn, x + (size_t)(k + 1) * nb_, x + (size_t)k * nb_, -1.0, part,
             x + (size_t)k * nb_, s);
   STKKT_HIP(hipGetLastError());
 }
@@ -556,6 +706,57 @@ template <typename T> void CoarseLU::solve_t(const double *r, double *x, hipStre
 void CoarseLU::solve(const double *r, double *x, hipStream_t s) const {
   if (prec_ == STKKT_F32) solve_t<float>(r, x, s);
   else solve_t<double>(r, x, s);
+}
+
+// out_c = base_c + sign A x_c for q <= 16 right-hand sides given transposed
+// (xT, see above); out_c at stride ldo, and transposed into outT
+template <typename T>
+static void gemm(int nb, int ld, int nsplit, const T *A, int q, const double *xT, const double *base, double sign,
+                 double *partial, double *out, long long ldo, double *outT, hipStream_t s) {
+  const int steps = (nb + 15) / 16;
+  const int csplit = (steps + nsplit - 1) / nsplit * 16;
+  const int nch = (nb + csplit - 1) / csplit;
+  hipLaunchKernelGGL(gemm_partial_kernel<T>, dim3(ld / kMrRows, nch), dim3(kMrThreads), 0, s, nb, ld, csplit, A, q,
+                     xT, partial);
+  hipLaunchKernelGGL(gemm_reduce_kernel, dim3(blocks_for(nb, 256, 64), q), dim3(256), 0, s, nb, ld, q, nch, partial,
+                     base, ldo, sign, out, ldo, outT);
+}
+
+template <typename T>
+void CoarseLU::solve_multi_t(int q, const double *r, long long ldr, double *x, long long ldx, hipStream_t s) const {
+  const size_t nn = (size_t)ld_ * nb_;
+  const T *Si = static_cast<const T *>(Sinv_.ptr);
+  const T *E = static_cast<const T *>(E_.ptr);
+  double *tT = mt_.as<double>(), *part = mpartial_.as<double>();
+  double *xT[2] = {tT + (size_t)kMrRhs * nb_, tT + (size_t)2 * kMrRhs * nb_};
+  for (int c0 = 0; c0 < q; c0 += kMrRhs) {
+    const int qq = std::min(kMrRhs, q - c0);
+    const double *rg = r + c0 * ldr;
+    double *xg = x + c0 * ldx;
+    // forward: y_k = S_k^{-1} (r_k - L_k y_{k-1}), y kept in x (the last one also in xT[0])
+    for (int k = 0; k < nlev_; ++k) {
+      const double *yprev = k > 0 ? xg + (size_t)(k - 1) * nb_ : nullptr;
+      hipLaunchKernelGGL(lower_rhs_multi_kernel, dim3(blocks_for(nb_, 256, 64), qq), dim3(256), 0, s, nb_,
+                         Lidx_.as<int32_t>() + (size_t)k * nb_ * 81, Lval_.as<double>() + (size_t)k * nb_ * 81,
+                         rg + (size_t)k * nb_, ldr, yprev, ldx, tT);
+      gemm<T>(nb_, ld_, nsplit_, Si + (size_t)k * nn, qq, tT, nullptr, 1.0, part, xg + (size_t)k * nb_, ldx, xT[0],
+              s);
+    }
+    // backward: x_k = y_k - E_k x_{k+1}, x_{k+1} read transposed
+    int cur = 0;
+    for (int k = nlev_ - 2; k >= 0; --k) {
+      gemm<T>(nb_, ld_, nsplit_, E + (size_t)k * nn, qq, xT[cur], xg + (size_t)k * nb_, -1.0, part,
+              xg + (size_t)k * nb_, ldx, xT[1 - cur], s);
+      cur = 1 - cur;
+    }
+  }
+  STKKT_HIP(hipGetLastError());
+}
+
+void CoarseLU::solve_multi(int q, const double *r, long long ldr, double *x, long long ldx, hipStream_t s) const {
+  if (q <= 0) return;
+  if (prec_ == STKKT_F32) solve_multi_t<float>(q, r, ldr, x, ldx, s);
+  else solve_multi_t<double>(q, r, ldr, x, ldx, s);
 }
 
 size_t CoarseLU::bytes_per_solve() const {

@@ -12,15 +12,23 @@ class CoarseLU {
   CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStream_t s);
   // x = F_c^{-1} r (device vectors of 3 N_c (M_c + 1) doubles, no aliasing)
   void solve(const double *r, double *x, hipStream_t s) const;
+  // x_c = F_c^{-1} r_c for c < q right-hand sides at r + c ldr and x + c ldx
+  // (no aliasing): every dense block is read once per 16 right-hand sides
+  // and multiplied on the FP64 matrix cores.
+  void solve_multi(int q, const double *r, long long ldr, double *x, long long ldx, hipStream_t s) const;
   // bytes of dense blocks streamed by one solve
   size_t bytes_per_solve() const;
 
  private:
   template <typename T> void solve_t(const double *r, double *x, hipStream_t s) const;
+  template <typename T>
+  void solve_multi_t(int q, const double *r, long long ldr, double *x, long long ldx, hipStream_t s) const;
   const Allocator *al_;
   int prec_;
   int nb_ = 0, nlev_ = 0;
-  DevBuf Sinv_, E_, Lidx_, Lval_, partial_, t_;
+  int ld_ = 0;       // leading dimension of the stored blocks (nb_ rounded up to 64, zero rows below nb_)
+  int nsplit_ = 1;   // column chunks of one multi-RHS block product
+  DevBuf Sinv_, E_, Lidx_, Lval_, partial_, t_, mpartial_, mt_;
 };
 
 }  // namespace stkkt

@@ -167,3 +167,39 @@ def test_server_errors(st, pool):
         srv.submit(op, pre, prob.data)      # larger than the whole server
     with pytest.raises(st.StkktError):
         srv.poll(12345)
+
+
+def test_two_level_requests_share_coarse_level(st, pool):
+    """Three two-level requests on one operator and one exact coarse level (their
+    coarse corrections share each pass over the dense blocks) plus a one-level
+    request: each two-level result is bit for bit the one it gets when served
+    alone, and solves its own system."""
+    prob, op, pre, parts = pool["cube8x16"]
+    C = st.Coarse(op, (2, 2, 2, 2), method=st.COARSE_LU, precision=st.F32)
+    datas = [redraw_noise(prob, 4500 + i) for i in range(3)]
+
+    def serve(items):
+        srv = st.Server(restart=30, rtol=1e-6, device_bytes=1 << 28, max_active=8)
+        tickets = [srv.submit(op, pre, d, coarse=c) for d, c in items]
+        out = {}
+        while len(out) < len(tickets):
+            srv.step()
+            for t in tickets:
+                if t not in out:
+                    r = srv.poll(t)
+                    if r is not None:
+                        out[t] = r
+        return [out[t] for t in tickets]
+
+    mixed = serve([(d, C) for d in datas] + [(redraw_noise(prob, 4600), None)])
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    for i, d in enumerate(datas):
+        x, s = mixed[i]
+        alone, sa = serve([(d, C)])[0]
+        b = kkt.rhs(dataclasses.replace(prob, data=d))
+        res = np.linalg.norm(b - F @ x.cpu().numpy()) / np.linalg.norm(b)
+        _say(f"  request {i}: {s.iters} its (alone {sa.iters}), true res {res:.2e}")
+        assert s.converged and res <= 1e-6
+        assert s.iters == sa.iters and torch.equal(x, alone)
+    assert mixed[3][1].converged

@@ -183,3 +183,71 @@ def test_two_level_lu_fgmres_parity(st):
     e = np.linalg.norm(x2.cpu().numpy() - xo2) / np.linalg.norm(xo2)
     _say(f"  fixed {k} steps: rel diff {e:.2e}")
     assert e <= 1e-7
+
+
+def _mid_case():
+    """16^3 elements x 16 steps with sensors on coarse nodes: coarse level 8^3 x 8
+    (2187 unknowns per level, 9 levels), so the dense block products span many
+    row tiles and column chunks, with ragged tails."""
+    n, fac = (16, 16, 16), (2, 2, 2, 2)
+    sens = _grid_sensors(n, fac, [(1, 1, 1), (4, 4, 4), (6, 2, 5), (3, 7, 2), (5, 5, 6), (2, 6, 3)])
+    return make_custom(n, 16, 5, sensors=sens), fac
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("name,precision,tol", [("cube8x16", "f64", 1e-9), ("aniso", "f64", 1e-9),
+                                                ("cube8x16", "f32", 1e-4), ("mid", "f64", 1e-9),
+                                                ("mid", "f32", 1e-4)])
+def test_coarse_lu_multi_rhs(st, name, precision, tol):
+    """Several coarse right-hand sides in one pass over the dense blocks (matrix
+    cores): sampled columns against the oracle's block LU, every column against
+    the one-vector path, a column independent of the others and of its
+    position (bit for bit), strided operands, more than 16 columns."""
+    prob, fac = _mid_case() if name == "mid" else case(name)[:2]
+    _say(f"case {name}: multi-RHS coarse LU ({precision}), factor {fac}")
+    op = st.KKTOperator(prob)
+    C = st.Coarse(op, fac, method=st.COARSE_LU, precision=st.F64 if precision == "f64" else st.F32)
+    tl = twolevel.TwoLevel(prob, None, None, fac, coarse="lu")
+    q, n = 19, prob.unknowns
+    X = np.random.default_rng(31).standard_normal((q, n))
+    Xd = _dev(X)
+    Yh = C.apply_multi(Xd).cpu().numpy()
+    for i in (0, 7, 16, 18):
+        err = _rel(Yh[i], tl.coarse_correction(X[i]))
+        _say(f"  column {i}: rel err vs oracle {err:.2e}")
+        assert err <= tol
+    worst = max(_rel(Yh[i], C.apply(Xd[i].contiguous()).cpu().numpy()) for i in range(q))
+    _say(f"  largest rel diff to the one-vector path: {worst:.2e}")
+    assert worst <= (1e-12 if precision == "f64" else tol)
+    sub = C.apply_multi(Xd[[18, 3, 7]].contiguous()).cpu().numpy()
+    assert np.array_equal(sub, Yh[[18, 3, 7]])
+    one = C.apply_multi(Xd[5:6].contiguous()).cpu().numpy()
+    assert np.array_equal(one[0], Yh[5])
+    Xs = torch.zeros((q, n + 37), dtype=torch.float64, device="cuda")
+    Xs[:, :n] = Xd
+    Ys = torch.full((q, n + 11), 7.0, dtype=torch.float64, device="cuda")
+    C.apply_multi(Xs[:, :n], Ys[:, :n])
+    assert np.array_equal(Ys[:, :n].cpu().numpy(), Yh)
+    assert bool(torch.all(Ys[:, n:] == 7.0))
+
+
+def test_coarse_multi_rhs_gmres_and_errors(st):
+    """With the inner coarse GMRES the applications run one by one (same result
+    as apply); q = 0 does nothing; short strides and overlapping operands fail."""
+    prob, fac, cparts = case("cube8x16")
+    op = st.KKTOperator(prob)
+    C = st.Coarse(op, fac, cparts, overlap=1, maxit=4, rtol=0.1)
+    n = prob.unknowns
+    Xd = _dev(np.random.default_rng(32).standard_normal((3, n)))
+    Y = C.apply_multi(Xd)
+    for i in range(3):
+        assert torch.equal(Y[i], C.apply(Xd[i].contiguous()))
+    C.apply_multi(Xd[:0])
+    short = torch.as_strided(Xd, (2, n), (n - 1, 1))
+    with pytest.raises(st.StkktError):
+        C.apply_multi(short, torch.empty((2, n), dtype=torch.float64, device="cuda"))
+    with pytest.raises(st.StkktError):
+        C.apply_multi(Xd, Xd)
