@@ -242,6 +242,69 @@ def run_batch(args):
     }
 
 
+def make_coarse(st, op, fac, how, precision):
+    """Coarse level of the served 32^3 x 64 requests: the exact block LU in time
+    (requests on one operator share its passes over the dense blocks), or the
+    paper's coarse GMRES(4) to 0.1 with a coarse RAS 2x2x2x4, overlap 1."""
+    if how == "lu":
+        return st.Coarse(op, fac, method=st.COARSE_LU, precision=precision)
+    return st.Coarse(op, fac, (2, 2, 2, 4), overlap=1, maxit=4, rtol=0.1, precision=precision)
+
+
+def run_coarse(args):
+    """Coarse corrections y = I_c^h F_c^{-1} I_h^c x with the exact block LU:
+    the one-vector path against the multi-right-hand-side path (one pass over
+    the dense blocks for q vectors), for the coarse levels of the served
+    32^3 x 64 requests (8^3 x 16) and of cube48x96 (12^3 x 24), FP32 and FP64
+    blocks.  Times are HIP-event averages on the stream of the launches."""
+    import torch
+    import paper_1508_06103_amd as st
+    from workloads.generate import make_problem
+    out = {}
+    for name, kw in (("cube32x64", dict(seed=4, lattice=3)), ("cube48x96", {})):
+        prob, _ = make_problem(name, **kw)
+        op = st.KKTOperator(prob)
+        fac = (4, 4, 4, 4)
+        nb = 3 * (prob.n[0] // 4 + 1) ** 3
+        nlev = prob.M // 4 + 1
+        for prec, esz in ((st.F32, 4), (st.F64, 8)):
+            C = st.Coarse(op, fac, method=st.COARSE_LU, precision=prec)
+            blocks = esz * nb * nb * (2 * nlev - 1)
+            x = torch.randn(16, op.n, dtype=torch.float64, device="cuda")
+            y = torch.empty_like(x)
+            x0, y0 = x[0].contiguous(), torch.empty_like(x[0])
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+            def timed(fn, reps=5):
+                fn()
+                torch.cuda.synchronize()
+                ev[0].record()
+                for _ in range(reps):
+                    fn()
+                ev[1].record()
+                torch.cuda.synchronize()
+                return ev[0].elapsed_time(ev[1]) / reps
+
+            rec = {"nb": nb, "levels": nlev, "block_bytes": blocks, "one_vector_ms": timed(lambda: C.apply(x0, y0))}
+            for q in (1, 2, 4, 8, 16):
+                rec[f"multi_q{q}_ms"] = timed(lambda: C.apply_multi(x[:q], y[:q]))
+            key = f"{name}_coarse_{'f32' if esz == 4 else 'f64'}"
+            out[key] = rec
+            print(f"[bench] {key}: " + ", ".join(f"{k} {v:.3f}" if isinstance(v, float) else f"{k} {v}"
+                                                  for k, v in rec.items()), file=sys.stderr, flush=True)
+            C.close()
+            del x, y, x0, y0
+            torch.cuda.empty_cache()
+        op.close()
+    top = out["cube48x96_coarse_f32"]
+    return {"metric": "coarse corrections/s (exact block-LU coarse solve, 16 right-hand sides per pass)",
+            "value": 16e3 / top["multi_q16_ms"], "unit": "corrections/s", "n_gpus": 1, "steps": 5, "warmup": 1,
+            "ms_per_step": top["multi_q16_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64 vectors / f32 blocks", "data": "synthetic (random vectors)",
+            "config": {"workload": "coarse level 12^3 x 24 of cube48x96 (6591 unknowns per level, 25 levels)"},
+            "coarse": out}
+
+
 def run_serve(args):
     """Poisson request stream through the server (continuous batching, FP32
     preconditioners, FP64 FGMRES(50)); 90% of requests on 16 operators drawn
@@ -260,7 +323,7 @@ def run_serve(args):
     for p, (parts, delta), fac in specs:
         op = st.KKTOperator(p)
         pre = st.RAS(op, parts, delta, precision=st.F32)
-        C = st.Coarse(op, fac, (2, 2, 2, 4), overlap=1, maxit=4, rtol=0.1, precision=st.F32) if fac else None
+        C = make_coarse(st, op, fac, args.coarse, st.F32) if fac else None
         built.append((p, op, pre, C))
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
@@ -305,7 +368,7 @@ def run_serve(args):
             parts, delta = batch_parts(p, "box8")   # one at a time: ~8-node boxes suit single small solves
         if which[k] not in base64:
             base64[which[k]] = (st.RAS(op, parts, delta, precision=st.F64),
-                                st.Coarse(op, fac, (2, 2, 2, 4), overlap=1, maxit=4, rtol=0.1) if fac else None)
+                                make_coarse(st, op, fac, args.coarse, st.F64) if fac else None)
         pre64, C64 = base64[which[k]]
         b = op.rhs(datas[k])
         x = torch.zeros_like(b)
@@ -327,7 +390,8 @@ def run_serve(args):
         "data": "synthetic (seeded request stream, fresh noise per request)",
         "config": {"workload": f"served stream: {n} Poisson requests at {args.rate}/s; 90% on 16 uneven operators "
                                f"(n 8-24, M 16-48, {'autotuned' if args.parts == 'tuned' else '~8-node'} subdomains), "
-                               f"10% on 32^3 x 64 with two-level RAS (coarse 8^3 x 16)"},
+                               f"10% on 32^3 x 64 with two-level RAS (coarse 8^3 x 16, "
+                               f"{'exact block LU' if args.coarse == 'lu' else 'GMRES(4)+RAS'})"},
         "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99), "gmres_iters": float(np.mean(its)),
         "setup_ms": 1e3 * t_setup,
         "baseline_one_at_a_time_fp64": {"value": base, "unit": "solves/s", "p50_ms": 1e3 * percentile(blat, 50),
@@ -346,9 +410,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
                     help="no solves: time ras_apply, kkt_matvec and a plain 1 GiB device copy (for counter runs)")
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"],
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "coarse"],
                     help="single: one operator, one solve per step (default); batch: 64 uneven instances per "
-                         "step; serve: Poisson request stream through the server")
+                         "step; serve: Poisson request stream through the server; coarse: the exact coarse "
+                         "solve with one and with several right-hand sides")
     ap.add_argument("--coarse", default="lu", choices=["lu", "gmres"],
                     help="two-level configurations: exact block-LU coarse solve, or the paper's coarse GMRES(4)+RAS")
     ap.add_argument("--instances", type=int, default=64)
@@ -373,6 +438,9 @@ def main():
         return
     if args.mode == "serve":
         print(json.dumps(run_serve(args)), flush=True)
+        return
+    if args.mode == "coarse":
+        print(json.dumps(run_coarse(args)), flush=True)
         return
     prob, cfg = make_problem(args.config)
     prec = st.F64 if args.precision == "f64" else st.F32

@@ -5,6 +5,7 @@
 // (Section 4): a few steps of restarted GMRES from zero, right-preconditioned
 // by the one-level space-time RAS of the coarse mesh; or exactly, by block
 // elimination in time with explicitly inverted Schur complements (CoarseLU).
+#include <algorithm>
 #include <cmath>
 #include <memory>
 #include <vector>
@@ -40,44 +41,68 @@ namespace stkkt {
 
 namespace {
 
-// 1-D linear interpolation weight of coarse node I at fine node i (factor f).
-__device__ inline double hat(int i, int I, int f) {
+// 1-D linear interpolation weight of coarse node I at fine node i (factor f,
+// rf = 1 / f): (f - |i - I f|) / f inside the support, else 0.
+__device__ inline double hat(int i, int I, int f, double rf) {
   const int d = i - I * f;
   const int ad = d < 0 ? -d : d;
-  return ad >= f ? 0.0 : 1.0 - (double)ad / f;
+  return ad >= f ? 0.0 : (double)(f - ad) * rf;
 }
 
 // y_fine = I_c^h x_coarse: every fine node interpolates the (up to 16) coarse
-// nodes of the coarse space-time cell that contains it.
-__global__ void prolong_kernel(OpDev fo, OpDev co, int fx, int fy, int fz, int ft, const double *__restrict__ xc,
-                               double *__restrict__ y) {
-  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < fo.V;
-       g += (long long)gridDim.x * blockDim.x) {
-    const int n = (int)(g / fo.N);
-    const long long j = g - (long long)n * fo.N;
-    const int i0 = (int)(j % fo.nn[0]), i1 = (int)((j / fo.nn[0]) % fo.nn[1]), i2 = (int)(j / ((long long)fo.nn[0] * fo.nn[1]));
-    const int f[4] = {fx, fy, fz, ft};
-    const int p[4] = {i0, i1, i2, n};
-    int lo[4], cnt[4];
-    for (int d = 0; d < 4; ++d) {
-      lo[d] = p[d] / f[d];
-      cnt[d] = (p[d] % f[d] == 0) ? 1 : 2;
+// nodes of the coarse space-time cell that contains it.  One wavefront per
+// fine line (nodes (., i1, i2, n), components innermost; four lines per
+// workgroup).  The line's y, z, t interpolation is done once per coarse x
+// node, u[I0][c] = sum over the (up to 8) coarse (I1, I2, I3) of
+// hat_y hat_z hat_t xc[I0, I1, I2, I3, c], kept in LDS; then every fine entry
+// is hat_x(lo) u[lo][c] + hat_x(lo + 1) u[lo + 1][c].
+__global__ void __launch_bounds__(256) prolong_kernel(OpDev fo, OpDev co, int fx, int fy, int fz, int ft,
+                                                      const double *__restrict__ xc, double *__restrict__ y) {
+  extern __shared__ double pro_lds[];
+  const int rows = fo.nn[1] * fo.nn[2] * (fo.M + 1);
+  const int len = 3 * fo.nn[0], clen = 3 * co.nn[0];
+  const double rx = 1.0 / fx, ry = 1.0 / fy, rz = 1.0 / fz, rt = 1.0 / ft;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double *u = pro_lds + wave * clen;
+  // every wavefront of a workgroup makes the same number of passes (barriers)
+  for (int grp = blockIdx.x; grp * 4 < rows; grp += gridDim.x) {
+    const int row = grp * 4 + wave;
+    const bool live = row < rows;
+    if (live) {
+      const int i1 = row % fo.nn[1], i2 = (row / fo.nn[1]) % fo.nn[2], n = row / (fo.nn[1] * fo.nn[2]);
+      const int lo1 = i1 / fy, c1 = i1 % fy == 0 ? 1 : 2;
+      const int lo2 = i2 / fz, c2 = i2 % fz == 0 ? 1 : 2;
+      const int lo3 = n / ft, c3 = n % ft == 0 ? 1 : 2;
+      const double w1[2] = {hat(i1, lo1, fy, ry), hat(i1, lo1 + 1, fy, ry)};
+      const double w2[2] = {hat(i2, lo2, fz, rz), hat(i2, lo2 + 1, fz, rz)};
+      const double w3[2] = {hat(n, lo3, ft, rt), hat(n, lo3 + 1, ft, rt)};
+      for (int t = lane; t < clen; t += 64) {
+        double a = 0.0;
+#pragma unroll
+        for (int b3 = 0; b3 < 2; ++b3)
+#pragma unroll
+          for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+            for (int b1 = 0; b1 < 2; ++b1) {
+              if (b3 >= c3 || b2 >= c2 || b1 >= c1) continue;
+              const long long cg = (long long)(lo3 + b3) * co.N + co.nn[0] * ((lo1 + b1) + co.nn[1] * (lo2 + b2));
+              a += w1[b1] * w2[b2] * w3[b3] * xc[3 * cg + t];
+            }
+        u[t] = a;
+      }
     }
-    double a0 = 0, a1 = 0, a2 = 0;
-    for (int b3 = 0; b3 < cnt[3]; ++b3)
-      for (int b2 = 0; b2 < cnt[2]; ++b2)
-        for (int b1 = 0; b1 < cnt[1]; ++b1)
-          for (int b0 = 0; b0 < cnt[0]; ++b0) {
-            const int I0 = lo[0] + b0, I1 = lo[1] + b1, I2 = lo[2] + b2, I3 = lo[3] + b3;
-            const double w = hat(p[0], I0, f[0]) * hat(p[1], I1, f[1]) * hat(p[2], I2, f[2]) * hat(p[3], I3, f[3]);
-            const long long cg = 3 * ((long long)I3 * co.N + I0 + (long long)co.nn[0] * (I1 + (long long)co.nn[1] * I2));
-            a0 += w * xc[cg];
-            a1 += w * xc[cg + 1];
-            a2 += w * xc[cg + 2];
-          }
-    y[3 * g] = a0;
-    y[3 * g + 1] = a1;
-    y[3 * g + 2] = a2;
+    __syncthreads();
+    if (live) {
+      double *yrow = y + (long long)row * len;
+      for (int t = lane; t < len; t += 64) {
+        const int i0 = t / 3, c = t - 3 * i0;
+        const int lo0 = i0 / fx;
+        double a = hat(i0, lo0, fx, rx) * u[3 * lo0 + c];
+        if (i0 % fx != 0) a += hat(i0, lo0 + 1, fx, rx) * u[3 * (lo0 + 1) + c];
+        yrow[t] = a;
+      }
+    }
+    __syncthreads();   // u is rewritten by the next pass
   }
 }
 
@@ -102,35 +127,54 @@ __global__ void inject_kernel(OpDev fo, OpDev co, int fx, int fy, int fz, int ft
 // product of the 1-D ones, so it is applied axis by axis): `out` has the node
 // counts `din` of `in` with axis d coarsened by f (D -> (D - 1) / f + 1),
 // components innermost, and out[.., I, .., c] = sum over the fine nodes p of
-// the support of coarse node I of hat(p, I, f) in[.., p, .., c].
+// the support of coarse node I of hat(p, I, f) in[.., p, .., c], p ascending.
+// One wavefront per output line (fixed node coordinates on axes 1..3; x and
+// the component vary along the line, contiguous in memory; four lines per
+// workgroup).
 struct Dims4 {
   int n[4];
 };
 
-__global__ void restrict_axis_kernel(Dims4 din, int d, int f, const double *__restrict__ in,
-                                     double *__restrict__ out) {
-  int dout[4], sin[4];
+__global__ void __launch_bounds__(256) restrict_axis_kernel(Dims4 din, int d, int f, const double *__restrict__ in,
+                                                            double *__restrict__ out) {
+  int dout[4];
   for (int k = 0; k < 4; ++k) dout[k] = din.n[k];
   dout[d] = (din.n[d] - 1) / f + 1;
-  sin[0] = 3;
-  for (int k = 1; k < 4; ++k) sin[k] = sin[k - 1] * din.n[k - 1];
-  const int total = 3 * dout[0] * dout[1] * dout[2] * dout[3];
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
-    int rest = g / 3, base = g % 3, I = 0;
-    for (int k = 0; k < 4; ++k) {
-      const int o = rest % dout[k];
-      rest /= dout[k];
-      if (k == d) I = o;
-      else base += o * sin[k];
+  const int lines = dout[1] * dout[2] * dout[3];
+  const int lin = 3 * din.n[0], lout = 3 * dout[0];
+  const double rf = 1.0 / f;
+  const int lane = threadIdx.x & 63;
+  for (int line = blockIdx.x * 4 + (threadIdx.x >> 6); line < lines; line += gridDim.x * 4) {
+    double *orow = out + (long long)line * lout;
+    if (d == 0) {
+      const double *irow = in + (long long)line * lin;   // axes 1..3 unchanged
+      for (int t = lane; t < lout; t += 64) {
+        const int I = t / 3, c = t - 3 * I;
+        const int lo = max(0, I * f - f + 1), hi = min(din.n[0] - 1, I * f + f - 1);
+        double acc = 0.0;
+        for (int p = lo; p <= hi; ++p) acc += hat(p, I, f, rf) * irow[3 * p + c];
+        orow[t] = acc;
+      }
+    } else {
+      // input line of node p on axis d: the output line's coordinates with axis d set to p
+      const int o1 = line % dout[1], o2 = (line / dout[1]) % dout[2], o3 = line / (dout[1] * dout[2]);
+      const int I = d == 1 ? o1 : d == 2 ? o2 : o3;
+      const long long step = d == 1 ? 1 : d == 2 ? din.n[1] : (long long)din.n[1] * din.n[2];
+      const long long line0 = o1 + (long long)din.n[1] * (o2 + (long long)din.n[2] * o3) - (long long)I * step;
+      const int lo = max(0, I * f - f + 1), hi = min(din.n[d] - 1, I * f + f - 1);
+      for (int t = lane; t < lout; t += 64) {
+        double acc = 0.0;
+        for (int p = lo; p <= hi; ++p) acc += hat(p, I, f, rf) * in[(line0 + p * step) * lin + t];
+        orow[t] = acc;
+      }
     }
-    const int lo = max(0, I * f - f + 1), hi = min(din.n[d] - 1, I * f + f - 1);
-    double acc = 0.0;
-    for (int p = lo; p <= hi; ++p) acc += hat(p, I, f) * in[(long long)base + (long long)p * sin[d]];
-    out[g] = acc;
   }
 }
 
 }  // namespace
+
+static int prolong_blocks(const OpDev &fo) { return std::min((fo.nn[1] * fo.nn[2] * (fo.M + 1) + 3) / 4, 1 << 20); }
+static size_t prolong_lds(const OpDev &co) { return sizeof(double) * 4 * 3 * (size_t)co.nn[0]; }
 
 // xc = (I_c^h)^T x, axis by axis (x, y, z, t; axes with factor 1 are skipped)
 static void restrict_transpose(const coarse *C, const double *x, double *xc, hipStream_t s) {
@@ -149,8 +193,8 @@ static void restrict_transpose(const coarse *C, const double *x, double *xc, hip
     double *dst = k == na - 1 ? xc : C->rt[k & 1].as<double>();
     Dims4 out = dm;
     out.n[d] = (dm.n[d] - 1) / C->fac[d] + 1;
-    const long long total = 3LL * out.n[0] * out.n[1] * out.n[2] * out.n[3];
-    hipLaunchKernelGGL(restrict_axis_kernel, dim3(blocks_for(total, 256, 1 << 16)), dim3(256), 0, s, dm, d,
+    const int lines = out.n[1] * out.n[2] * out.n[3];
+    hipLaunchKernelGGL(restrict_axis_kernel, dim3(std::min((lines + 3) / 4, 1 << 20)), dim3(256), 0, s, dm, d,
                        C->fac[d], src, dst);
     dm = out;
     src = dst;
@@ -225,6 +269,7 @@ coarse *coarse_create(const kkt_op *fine, const coarse_params_t *cp, hipStream_t
   p.variant = fd.variant;
   kkt_alloc_t al = fine->al.cb;
   C->cop = op_create(&p, al.alloc ? &al : nullptr, s);
+  STKKT_REQUIRE(C->cop->d.nn[0] <= 512, "coarse_setup: more than 512 coarse nodes along x");
   const size_t nvc = 3 * (size_t)C->cop->d.V;
   C->xc = DevBuf(&C->al, sizeof(double) * nvc);
   C->yc = DevBuf(&C->al, sizeof(double) * nvc);
@@ -271,7 +316,7 @@ void coarse_apply_device(const coarse *C, const double *x, double *y, hipStream_
                                C->work.get());
     if (st != STKKT_OK && st != STKKT_NOT_CONVERGED) throw Error(st, "coarse solve failed");
   }
-  hipLaunchKernelGGL(prolong_kernel, dim3(blocks_for(fo.V, 256, 1 << 16)), dim3(256), 0, s, fo, co, C->fac[0],
+  hipLaunchKernelGGL(prolong_kernel, dim3(prolong_blocks(fo)), dim3(256), prolong_lds(co), s, fo, co, C->fac[0],
                      C->fac[1], C->fac[2], C->fac[3], C->yc.as<double>(), y);
   STKKT_HIP(hipGetLastError());
 }
@@ -294,7 +339,7 @@ void coarse_apply_multi_device(const coarse *C, int q, const double *const *x, d
   for (int i = 0; i < q; ++i) restrict_to_coarse(C, x[i], xc + i * nvc, s);
   C->lu->solve_multi(q, xc, nvc, yc, nvc, s);
   for (int i = 0; i < q; ++i)
-    hipLaunchKernelGGL(prolong_kernel, dim3(blocks_for(fo.V, 256, 1 << 16)), dim3(256), 0, s, fo, co, C->fac[0],
+    hipLaunchKernelGGL(prolong_kernel, dim3(prolong_blocks(fo)), dim3(256), prolong_lds(co), s, fo, co, C->fac[0],
                        C->fac[1], C->fac[2], C->fac[3], yc + i * nvc, y[i]);
   STKKT_HIP(hipGetLastError());
 }

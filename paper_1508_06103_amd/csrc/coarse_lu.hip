@@ -362,14 +362,28 @@ __global__ void iota_kernel(int n, int32_t *p) {
 // ---------------------------------------------------------------------------
 // application
 // ---------------------------------------------------------------------------
-// t = r - L y  (L rows sparse; with y == nullptr: t = r)
-__global__ void lower_rhs_kernel(int nb, const int32_t *__restrict__ idx, const double *__restrict__ val,
-                                 const double *__restrict__ r, const double *__restrict__ y, double *__restrict__ t) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
-    double acc = r[i];
-    if (y)
-      for (int q = 0; q < 81; ++q) acc -= val[(long long)i * 81 + q] * y[idx[(long long)i * 81 + q]];
-    t[i] = acc;
+// t[i tsi + c tsc] = r_c[i] - (L y_c)[i] for the right-hand sides c =
+// blockIdx.y (r_c = r + c ldr, y_c = y + c ldy; with y == nullptr: t = r).
+// One wavefront per row: its 81 couplings spread over the lanes and summed
+// in a fixed order.
+__global__ void __launch_bounds__(256) lower_rhs_kernel(int nb, const int32_t *__restrict__ idx,
+                                                        const double *__restrict__ val, const double *__restrict__ r,
+                                                        long long ldr, const double *__restrict__ y, long long ldy,
+                                                        double *__restrict__ t, int tsi, int tsc) {
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.y;
+  const double *rc = r + c * ldr;
+  const double *yc = y ? y + c * ldy : nullptr;
+  for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < nb; i += gridDim.x * 4) {
+    double s = 0.0;
+    if (yc) {
+      const long long b = (long long)i * 81;
+      s = val[b + lane] * yc[idx[b + lane]];
+      if (lane < 81 - 64) s += val[b + 64 + lane] * yc[idx[b + 64 + lane]];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    }
+    if (lane == 0) t[(long long)i * tsi + (long long)c * tsc] = rc[i] - s;
   }
 }
 
@@ -419,22 +433,6 @@ __global__ void store_padded_kernel(int nb, int ld, const double *__restrict__ S
 // sides are one contiguous 512-byte read.
 // ---------------------------------------------------------------------------
 constexpr int kMrRows = 64, kMrRhs = 16, kMrThreads = 256, kMrAhead = 8;
-
-// tT[i][c] = r_c[i] - (L y_c)[i] for the right-hand sides c = blockIdx.y
-// (r_c = r + c ldr, y_c = y + c ldy; with y == nullptr: t = r)
-__global__ void lower_rhs_multi_kernel(int nb, const int32_t *__restrict__ idx, const double *__restrict__ val,
-                                       const double *__restrict__ r, long long ldr, const double *__restrict__ y,
-                                       long long ldy, double *__restrict__ tT) {
-  const int c = blockIdx.y;
-  const double *rc = r + c * ldr;
-  const double *yc = y ? y + c * ldy : nullptr;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
-    double acc = rc[i];
-    if (yc)
-      for (int q = 0; q < 81; ++q) acc -= val[(long long)i * 81 + q] * yc[idx[(long long)i * 81 + q]];
-    tT[(long long)i * kMrRhs + c] = acc;
-  }
-}
 
 // Y = A X for up to 16 right-hand sides on the FP64 matrix cores
 // (v_mfma_f64_16x16x4: lane l supplies a = A[l%16][l/16], b = B[l/16][l%16]
@@ -691,9 +689,9 @@ template <typename T> void CoarseLU::solve_t(const double *r, double *x, hipStre
   for (int k = 0; k < nlev_; ++k) {
     const double *rk = r + (size_t)k * nb_;
     const double *yprev = k > 0 ? x + (size_t)(k - 1) * nb_ : nullptr;
-    hipLaunchKernelGGL(lower_rhs_kernel, dim3(blocks_for(nb_, 256, 256)), dim3(256), 0, s, nb_,
+    hipLaunchKernelGGL(lower_rhs_kernel, dim3(blocks_for(nb_, 4, 1 << 16)), dim3(256), 0, s, nb_,
                        Lidx_.as<int32_t>() + (size_t)k * nb_ * 81, Lval_.as<double>() + (size_t)k * nb_ * 81, rk,
-                       yprev, t);
+                       0LL, yprev, 0LL, t, 1, 0);
     gemv<T>(nb_, ld_, Si + (size_t)k * nn, t, nullptr, 1.0, part, x + (size_t)k * nb_, s);
   }
   // backward: x_k = y_k - E_k x_{k+1}
@@ -736,9 +734,9 @@ void CoarseLU::solve_multi_t(int q, const double *r, long long ldr, double *x, l
     // forward: y_k = S_k^{-1} (r_k - L_k y_{k-1}), y kept in x (the last one also in xT[0])
     for (int k = 0; k < nlev_; ++k) {
       const double *yprev = k > 0 ? xg + (size_t)(k - 1) * nb_ : nullptr;
-      hipLaunchKernelGGL(lower_rhs_multi_kernel, dim3(blocks_for(nb_, 256, 64), qq), dim3(256), 0, s, nb_,
+      hipLaunchKernelGGL(lower_rhs_kernel, dim3(blocks_for(nb_, 4, 1 << 16), qq), dim3(256), 0, s, nb_,
                          Lidx_.as<int32_t>() + (size_t)k * nb_ * 81, Lval_.as<double>() + (size_t)k * nb_ * 81,
-                         rg + (size_t)k * nb_, ldr, yprev, ldx, tT);
+                         rg + (size_t)k * nb_, ldr, yprev, ldx, tT, kMrRhs, 1);
       gemm<T>(nb_, ld_, nsplit_, Si + (size_t)k * nn, qq, tT, nullptr, 1.0, part, xg + (size_t)k * nb_, ldx, xT[0],
               s);
     }
