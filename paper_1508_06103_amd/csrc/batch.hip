@@ -333,7 +333,7 @@ long long BatchEngine::free_elems() const {
 
 size_t BatchEngine::member_bytes(const kkt_op *op, const ras *R, const coarse *C) {
   size_t b = ras_local_bytes(R);
-  if (C) b += 2 * sizeof(double) * 3 * (size_t)op->d.V;
+  if (C) b += sizeof(double) * 3 * (size_t)op->d.V;   // the coarse correction y
   return b;
 }
 
@@ -365,10 +365,7 @@ int BatchEngine::admit(const kkt_op *op, const ras *R, const coarse *C) {
   sl.n = n;
   sl.local = DevBuf(al_, ras_local_bytes(R));
   STKKT_HIP(hipMemsetAsync(sl.local.ptr, 0, sl.local.bytes, s_));
-  if (C) {
-    sl.y2 = DevBuf(al_, sizeof(double) * n);
-    sl.t2 = DevBuf(al_, sizeof(double) * n);
-  }
+  if (C) sl.y2 = DevBuf(al_, sizeof(double) * n);
   sl.Hm.assign((size_t)(m_ + 1) * m_, 0.0);
   sl.g.assign(m_ + 1, 0.0);
   sl.cs.assign(m_, 0.0);
@@ -453,10 +450,11 @@ void BatchEngine::fetch() {
   STKKT_HIP(hipStreamSynchronize(s_));
 }
 
-// z_j = M^{-1} v_j for the members flagged in act: one-level members through
-// the batched RAS launch; for two-level members the coarse corrections of all
-// members on one coarse level go through one multi-right-hand-side coarse
-// application, the rest member by member.
+// z_j = M^{-1} v_j for the members flagged in act.  Two-level members first
+// get their coarse corrections y (one multi-right-hand-side coarse
+// application per coarse level) and t = v - F y (in T_ at their offsets);
+// then one batched RAS launch applies M_one^{-1} to v (one-level members)
+// and to t (two-level members), and z += y finishes the two-level members.
 void BatchEngine::precondition(int j, const int *act_dev) {
   const long long N = cap_;
   const double *v = V_.as<double>() + (long long)j * N;
@@ -473,8 +471,6 @@ void BatchEngine::precondition(int j, const int *act_dev) {
     ras_batch_run(rb_, v, z, act_dev, hf, s_);
     return;
   }
-  upload(h_ras, act_c_);
-  ras_batch_run(rb_, v, z, act_c_.as<int>(), h_ras, s_);
   // y = I_c^h F_c^{-1} I_h^c v, grouped by coarse level
   std::vector<const coarse *> seen;
   std::vector<const double *> xs;
@@ -492,16 +488,23 @@ void BatchEngine::precondition(int j, const int *act_dev) {
       }
     coarse_apply_multi_device(C, (int)xs.size(), xs.data(), ys.data(), s_);
   }
+  // z = y + M_one^{-1} (v - F y)
+  double *T = T_.as<double>();
   for (int i = 0; i < S; ++i) {
     const Slot &sl = slots_[i];
     if (!hf[i] || !sl.C) continue;
-    const double *vi = v + sl.voff;
-    double *zi = z + sl.voff, *y = sl.y2.as<double>(), *t = sl.t2.as<double>();
-    // z = y + M_one^{-1} (v - F y)
-    matvec_device(sl.op, y, t, s_);
-    axpby(t, 1.0, vi, -1.0, t, sl.n, s_);
-    ras_apply_device(sl.R, t, zi, s_, sl.local.ptr);
-    axpby(zi, 1.0, zi, 1.0, y, sl.n, s_);
+    double *t = T + sl.voff;
+    matvec_device(sl.op, sl.y2.as<double>(), t, s_);
+    axpby(t, 1.0, v + sl.voff, -1.0, t, sl.n, s_);
+    h_ras[i] = 2;
+  }
+  upload(h_ras, act_c_);
+  ras_batch_run(rb_, v, z, act_c_.as<int>(), h_ras, s_, T);
+  for (int i = 0; i < S; ++i) {
+    const Slot &sl = slots_[i];
+    if (!hf[i] || !sl.C) continue;
+    double *zi = z + sl.voff;
+    axpby(zi, 1.0, zi, 1.0, sl.y2.as<double>(), sl.n, s_);
   }
 }
 

@@ -54,7 +54,7 @@ class BatchEngine {
     const ras *R = nullptr;
     const coarse *C = nullptr;
     long long voff = 0, n = 0;
-    DevBuf local, y2, t2;
+    DevBuf local, y2;
     int state = 0;   // 0 new, 1 running, 2 finished
     bool breakdown = false;
     double bnorm = 0, target = 0, beta = 0;

@@ -1121,9 +1121,11 @@ __global__ void __launch_bounds__(kApplyThreads, 2) apply_ring_batch_kernel(cons
                                                                             const int2 *__restrict__ work,
                                                                             const int *__restrict__ act,
                                                                             const double *__restrict__ r,
+                                                                            const double *__restrict__ r2,
                                                                             double *__restrict__ z) {
   const int2 wk = load_uniform(work + blockIdx.x);
-  if (!as_const(act)[wk.x]) return;
+  const int a = as_const(act)[wk.x];
+  if (!a) return;
   const RasBatchDesc<T> d = load_uniform(descs + wk.x);
   // The pointers are read as pointers from the constant address space: the
   // compiler then takes them to address global memory and emits global loads.
@@ -1132,7 +1134,7 @@ __global__ void __launch_bounds__(kApplyThreads, 2) apply_ring_batch_kernel(cons
   // drain the factor loads in flight.)
   const cptr<RasBatchDesc<T>> dp = as_const(descs + wk.x);
   apply_ring_sub<T>(d.op, dp->subs, wk.y, dp->shapes, dp->lvl, dp->coords, dp->ctab, dp->tz, dp->F, dp->Y, d.fzero,
-                    d.yzero, d.rg, r + d.voff, z + d.voff);
+                    d.yzero, d.rg, (a == 2 ? r2 : r) + d.voff, z + d.voff);
 }
 
 }  // namespace
@@ -1246,7 +1248,8 @@ void ras_batch_prepare(const ras *const *R, const long long *voff, void *const *
 }
 
 template <typename T>
-static void ras_batch_launch(const RasBatch &b, const double *r, double *z, const int *act, hipStream_t s) {
+static void ras_batch_launch(const RasBatch &b, const double *r, const double *r2, double *z, const int *act,
+                             hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
     STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_ring_batch_kernel<T>),
@@ -1254,19 +1257,21 @@ static void ras_batch_launch(const RasBatch &b, const double *r, double *z, cons
     attr_set = true;
   }
   hipLaunchKernelGGL((apply_ring_batch_kernel<T>), dim3(b.blocks), dim3(kApplyThreads), b.lds, s,
-                     b.desc.as<RasBatchDesc<T>>(), b.work.as<int2>(), act, r, z);
+                     b.desc.as<RasBatchDesc<T>>(), b.work.as<int2>(), act, r, r2 ? r2 : r, z);
 }
 
 void ras_batch_run(const RasBatch &b, const double *r, double *z, const int *act, const int *act_host,
-                   hipStream_t s) {
+                   hipStream_t s, const double *r2) {
   if (!b.ring) {
     for (int i = 0; i < b.count; ++i)
-      if (act_host[i] && b.members[i]) ras_apply_device(b.members[i], r + b.voff[i], z + b.voff[i], s, b.local[i]);
+      if (act_host[i] && b.members[i])
+        ras_apply_device(b.members[i], (act_host[i] == 2 && r2 ? r2 : r) + b.voff[i], z + b.voff[i], s,
+                         b.local[i]);
     return;
   }
   if (b.blocks == 0) return;
-  if (b.precision == STKKT_F32) ras_batch_launch<float>(b, r, z, act, s);
-  else ras_batch_launch<double>(b, r, z, act, s);
+  if (b.precision == STKKT_F32) ras_batch_launch<float>(b, r, r2, z, act, s);
+  else ras_batch_launch<double>(b, r, r2, z, act, s);
   STKKT_HIP(hipGetLastError());
 }
 

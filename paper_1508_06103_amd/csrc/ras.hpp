@@ -84,7 +84,9 @@ struct RasBatch {
 };
 void ras_batch_prepare(const ras *const *R, const long long *voff, void *const *local, int count,
                        const Allocator *al, RasBatch &out, hipStream_t s);
-// act: device flags (members with 0 are skipped), act_host: the same flags on the host
+// act: device flags (members with 0 are skipped; members with 2 read their
+// input from r2 instead of r, at the same offset), act_host: the same flags on
+// the host
 void ras_batch_run(const RasBatch &b, const double *r, double *z, const int *act, const int *act_host,
-                   hipStream_t s);
+                   hipStream_t s, const double *r2 = nullptr);
 }
