@@ -71,7 +71,8 @@ def test_rhs_and_matvec(st, name):
 @pytest.mark.parametrize("name,parts,delta", [("cube8x16", (2, 2, 2, 2), 1), ("ragged", (2, 3, 2, 3), 1),
                                               ("ragged", (3, 2, 3, 2), 2), ("aniso_otd", (2, 1, 2, 2), 1),
                                               ("neumann_all", (1, 2, 2, 1), 0), ("tall", (1, 1, 1, 1), 0),
-                                              ("tall", (1, 1, 2, 2), 1)])
+                                              ("tall", (1, 1, 2, 2), 1), ("cube8x16", (2, 2, 2, 2), 4),
+                                              ("ragged", (2, 3, 2, 3), 3)])
 def test_boxes_factors_and_apply(st, name, parts, delta):
     prob = small_problem(name)
     _say(f"case {name}: parts={parts} overlap={delta}")
