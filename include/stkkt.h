@@ -49,6 +49,10 @@ extern "C" {
 #define STKKT_DTO 0
 #define STKKT_OTD 1
 
+/* Regularisation of the source (kkt_problem_t.regularization). */
+#define STKKT_REG_H1H1 0   /* eq. (3): beta1 |df/dt|^2 + beta2 |grad f|^2            */
+#define STKKT_REG_H1L2 1   /* Example 2's H1-L2 form: beta1 |df/dt|^2 + beta2 f^2 */
+
 #define STKKT_F64 0
 #define STKKT_F32 1
 
@@ -74,7 +78,9 @@ typedef struct {
  * [0,len0]x[0,len1]x[0,len2], t in (0,T), C = 0 on the Dirichlet faces,
  * a dC/dn = 0 elsewhere, C(.,0) = 0.  Objective (eqs. (2)-(3)): point sensors
  * and the H1-H1 space-time regularisation with weights beta1 (time) and
- * beta2 (space). */
+ * beta2 (space), or the H1-L2 form of Example 2 (beta2 weighs the L2 norm of
+ * f instead of its gradient: the space factor of the beta2 block of W is the
+ * mass matrix instead of the stiffness matrix, Appendix A). */
 typedef struct {
   int32_t n[3];             /* elements per axis (>= 1); nodes = n + 1       */
   int32_t nt;               /* time steps M (>= 1); levels 0..M               */
@@ -89,6 +95,7 @@ typedef struct {
   uint32_t dirichlet_faces; /* bit 0: x=0, 1: x=len0, 2: y=0, 3: y=len1,
                                4: z=0, 5: z=len2                              */
   int32_t variant;          /* STKKT_DTO or STKKT_OTD                         */
+  int32_t regularization;   /* STKKT_REG_H1H1 (0) or STKKT_REG_H1L2 (1)       */
 } kkt_problem_t;
 
 /* One-level space-time restricted additive Schwarz (Section 3.2).

@@ -10,7 +10,10 @@ which is exactly the ordering above.
 Spatial matrices (see ``fem``): A1 = B + tau/2 (A + N), A2 = -B + tau/2 (A + N)
 (Appendix A, with E read as the Galerkin convection matrix N[j,i] =
 (v.grad phi_i, phi_j) for the state and its transpose for the adjoint).
-W = beta1 St x B + beta2 Tt x K (Appendix A, W^{nm} = beta1 L^{nm} + beta2 K^{nm}).
+W = beta1 St x B + beta2 Tt x K (Appendix A, W^{nm} = beta1 L^{nm} + beta2 K^{nm}) for the
+regularisation of eq. (3); for the H1-L2 regularisation of Example 2 (time
+gradient and L2 norm of f) the space factor of the beta2 term is the mass
+matrix: W = beta1 St x B + beta2 Tt x B.
 
 Two variants:
 
@@ -40,6 +43,8 @@ from . import fem
 
 DTO = 0
 OTD = 1
+H1H1 = 0
+H1L2 = 1
 
 
 def _E(c, cp):
@@ -96,7 +101,7 @@ def kkt_terms(prob, ops=None) -> KKTTerms:
     t.add(Tc1 + Tc2, -0.5 * tau * (P @ ops.B), 0, 2)
     # f-slot: f-f coupling W, both variants
     t.add(prob.beta1 * St, ops.B, 2, 2)
-    t.add(prob.beta2 * Tt, ops.K, 2, 2)
+    t.add(prob.beta2 * Tt, ops.B if getattr(prob, "reg", H1H1) == H1L2 else ops.K, 2, 2)
     if prob.variant == DTO:
         t.add(_diag(w), S, 1, 0)
         t.add(Tc1, P @ A1.T @ P, 1, 1)

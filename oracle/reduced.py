@@ -44,13 +44,15 @@ class Reduced:
         St = fem.time_stiff(M, tau)
         self.Wt_beta1 = prob.beta1 * St
         self.Wt_beta2 = prob.beta2 * Tt
+        # space factor of the beta2 term: K (eq. (3)) or the mass matrix (H1-L2 of Example 2)
+        self.Ws = ops.B if getattr(prob, "reg", 0) == 1 else ops.K
         d = np.zeros((M + 1, prob.N))
         d[:, np.asarray(prob.sensor_node)] = prob.data
         self.d = d
 
     def W(self, f):
-        """(beta1 St x B + beta2 Tt x K) f for f of shape (M+1, N)."""
-        return self.Wt_beta1 @ (self.ops.B @ f.T).T + self.Wt_beta2 @ (self.ops.K @ f.T).T
+        """(beta1 St x B + beta2 Tt x K) f (or beta2 Tt x B, H1-L2) for f of shape (M+1, N)."""
+        return self.Wt_beta1 @ (self.ops.B @ f.T).T + self.Wt_beta2 @ (self.Ws @ f.T).T
 
     def forward(self, f):
         M = self.prob.M

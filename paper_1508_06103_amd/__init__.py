@@ -52,7 +52,7 @@ class _Problem(ctypes.Structure):
                 ("T", ctypes.c_double), ("a_elem", _c_dp), ("v", ctypes.c_double * 3),
                 ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("n_sensors", ctypes.c_int32),
                 ("sensor_node", _c_i32p), ("data", _c_dp), ("dirichlet_faces", ctypes.c_uint32),
-                ("variant", ctypes.c_int32)]
+                ("variant", ctypes.c_int32), ("regularization", ctypes.c_int32)]
 
 
 class _RasParams(ctypes.Structure):
@@ -212,6 +212,7 @@ def _problem_struct(prob):
     p.data = data.ctypes.data_as(_c_dp)
     p.dirichlet_faces = int(prob.dirichlet_faces)
     p.variant = int(prob.variant)
+    p.regularization = int(getattr(prob, "reg", 0))
     return p, (a, sn, data)
 
 

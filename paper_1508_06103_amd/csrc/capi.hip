@@ -69,6 +69,8 @@ kkt_op *op_create(const kkt_problem_t *p, const kkt_alloc_t *al, hipStream_t s) 
   STKKT_REQUIRE(p->beta1 > 0 && p->beta2 > 0 && std::isfinite(p->beta1) && std::isfinite(p->beta2),
                 "kkt_assemble: beta1, beta2 must be positive");
   STKKT_REQUIRE(p->variant == STKKT_DTO || p->variant == STKKT_OTD, "kkt_assemble: unknown variant");
+  STKKT_REQUIRE(p->regularization == STKKT_REG_H1H1 || p->regularization == STKKT_REG_H1L2,
+                "kkt_assemble: unknown regularization");
   STKKT_REQUIRE(p->a_elem != nullptr, "kkt_assemble: a_elem is NULL");
   STKKT_REQUIRE(p->n_sensors >= 1 && p->sensor_node != nullptr && p->data != nullptr,
                 "kkt_assemble: at least one sensor with data is required");
@@ -92,6 +94,7 @@ kkt_op *op_create(const kkt_problem_t *p, const kkt_alloc_t *al, hipStream_t s) 
   d.beta2 = p->beta2;
   d.faces = p->dirichlet_faces;
   d.variant = p->variant;
+  d.reg = p->regularization;
   op->T = p->T;
   const long long ne = (long long)p->n[0] * p->n[1] * p->n[2];
   op->a_host.assign(p->a_elem, p->a_elem + ne);

@@ -267,6 +267,7 @@ coarse *coarse_create(const kkt_op *fine, const coarse_params_t *cp, hipStream_t
   p.data = zeros.data();
   p.dirichlet_faces = fd.faces;
   p.variant = fd.variant;
+  p.regularization = fd.reg;
   kkt_alloc_t al = fine->al.cb;
   C->cop = op_create(&p, al.alloc ? &al : nullptr, s);
   STKKT_REQUIRE(C->cop->d.nn[0] <= 512, "coarse_setup: more than 512 coarse nodes along x");

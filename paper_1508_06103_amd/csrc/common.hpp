@@ -78,6 +78,7 @@ struct OpDev {
   double beta1, beta2;
   unsigned faces;  // Dirichlet face bitmask
   int variant;
+  int reg;         // STKKT_REG_H1H1 or STKKT_REG_H1L2
   const double *a_elem;   // device [n2][n1][n0]
   const double *sensor;   // device [N], 1 at sensor nodes
 };

@@ -83,6 +83,7 @@ void stiff_table(const OpDev &d, double *tab, hipStream_t s) {
 //   U1 = P (c^n - c^{n-1}) - tau/2 (f^{n-1} + f^n)       S1 = P (c^n + c^{n-1})
 //   U2 = P (m g^n - p g^{n+1})                          S2 = P (m g^n + p g^{n+1})
 //   U3 = beta1 (St f)^n - { DTO: tau/2 S2 ; OTD: P (Tt g)^n }   T3 = beta2 (Tt f)^n
+//   (H1-L2 regularisation: beta2 (Tt f)^n is added to U3 instead and T3 = 0)
 // (m = [n >= 1] for DTO and 1 for OTD, p = [n < M]; (St f)^n, (Tt f)^n the
 // time stiffness / mass rows of level n), the rows of an interior node j are
 //   C (n >= 1):  sum_i B_ji U1_i + tau/2 (A + N)_ji S1_i
@@ -112,6 +113,7 @@ struct MvConst {
   double v[3];
   double cyz[2][2][4];     // corner rows (dy, dz = +-1): myz, kyz, nyz, v0 myz
   double ht, inv_tau, tau6, tau3, beta1, beta2;
+  int l2;   // H1-L2 regularisation: beta2 (Tt f) joins U3 (mass) instead of T3 (stiffness)
 };
 
 // One operator of a batched matvec: its vectors start at element voff of the
@@ -147,6 +149,7 @@ MvConst make_mv_const(const OpDev &d) {
   c.tau3 = d.tau / 3.0;
   c.beta1 = d.beta1;
   c.beta2 = d.beta2;
+  c.l2 = d.reg == STKKT_REG_H1L2;
   return c;
 }
 
@@ -283,7 +286,7 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
         const double U3 = mc.beta1 * stf - (dto ? ht * S2 : P * (ttm * gm[s] + tt0 * g0[s] + ttp * gp));
         mv_lds[3 * h] = make_double2(P * (c0[s] - cm[s]) - ht * (fm[s] + f0[s]), P * (c0[s] + cm[s]));
         mv_lds[3 * h + 1] = make_double2(P * (gn - gp), S2);
-        mv_lds[3 * h + 2] = make_double2(U3, mc.beta2 * ttf);
+        mv_lds[3 * h + 2] = mc.l2 ? make_double2(U3 + mc.beta2 * ttf, 0.0) : make_double2(U3, mc.beta2 * ttf);
       }
       cm[s] = c0[s];
       c0[s] = cp;

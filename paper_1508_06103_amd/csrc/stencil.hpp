@@ -132,8 +132,9 @@ __host__ __device__ inline void kkt_block_c(const OpDev &op, const SpatialCoef &
     out[0] = Qj * idn + Pj * Pi * (dt == 0 ? A1 : (dt == -1 ? A2 : 0.0));
     if (dt == 0 || dt == -1) out[2] = -Pj * ht * c.B;
   }
-  // f-slot row: regularisation block W
-  out[8] = op.beta1 * tstiff(tau, n, dt, M) * c.B + op.beta2 * tmass(tau, n, dt, M) * c.K;
+  // f-slot row: regularisation block W (beta2 with K, or with B for H1-L2)
+  out[8] = op.beta1 * tstiff(tau, n, dt, M) * c.B +
+           op.beta2 * tmass(tau, n, dt, M) * (op.reg == STKKT_REG_H1L2 ? c.B : c.K);
   if (op.variant == STKKT_DTO) {
     if (dt == 0) out[3] = wtrap(tau, n, M) * sens;
     double g = Qj * idn;

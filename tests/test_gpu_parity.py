@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import kkt, ras as oras, krylov, fem
-from workloads.generate import make_custom, make_problem, DTO, OTD
+from workloads.generate import make_custom, make_problem, DTO, OTD, H1L2
 
 pytestmark = pytest.mark.gpu
 
@@ -35,6 +35,8 @@ SMALL = [
     ("neumann_all", dict(n=(4, 4, 4), M=5, seed=5, lattice=2, faces=0)),
     # one long box: (t, z) groups per level exceed the LDS-ring limits of the apply kernel
     ("tall", dict(n=(2, 2, 40), M=24, seed=6, lattice=1)),
+    # the H1-L2 regularisation of Example 2
+    ("h1l2", dict(n=(4, 5, 3), M=6, seed=7, lattice=2, reg=H1L2)),
 ]
 
 
@@ -72,7 +74,7 @@ def test_rhs_and_matvec(st, name):
                                               ("ragged", (3, 2, 3, 2), 2), ("aniso_otd", (2, 1, 2, 2), 1),
                                               ("neumann_all", (1, 2, 2, 1), 0), ("tall", (1, 1, 1, 1), 0),
                                               ("tall", (1, 1, 2, 2), 1), ("cube8x16", (2, 2, 2, 2), 4),
-                                              ("ragged", (2, 3, 2, 3), 3)])
+                                              ("ragged", (2, 3, 2, 3), 3), ("h1l2", (2, 2, 1, 2), 1)])
 def test_boxes_factors_and_apply(st, name, parts, delta):
     prob = small_problem(name)
     _say(f"case {name}: parts={parts} overlap={delta}")
@@ -116,7 +118,7 @@ def test_apply_f32_factors(st):
 
 
 @pytest.mark.parametrize("name,parts,delta,restart", [("cube8x16", (2, 2, 2, 2), 1, 30), ("ragged", (2, 3, 2, 3), 1, 20),
-                                                      ("aniso_otd", (2, 1, 2, 2), 1, 25)])
+                                                      ("aniso_otd", (2, 1, 2, 2), 1, 25), ("h1l2", (2, 2, 1, 2), 1, 25)])
 def test_solve_parity(st, name, parts, delta, restart):
     prob = small_problem(name)
     _say(f"case {name}: solve")

@@ -6,6 +6,7 @@ against an independent reduced-space solve (forward/adjoint marching + CG),
 against finite differences of J_h, against the forward and backward time
 marches, and by the symmetry of its Lagrangian Hessian.
 """
+import dataclasses
 import os
 
 import numpy as np
@@ -13,7 +14,7 @@ import pytest
 import scipy.sparse.linalg as spla
 
 from oracle import kkt, krylov, ras, reduced, fem
-from workloads.generate import make_custom, OTD, DTO
+from workloads.generate import make_custom, OTD, DTO, H1L2
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -179,3 +180,46 @@ def test_otd_solution_close_to_dto():
     Cd = Ud.reshape(-1, 3)[:, 0]
     Co = Uo.reshape(-1, 3)[:, 0]
     assert np.linalg.norm(Cd - Co) < 0.5 * np.linalg.norm(Cd)
+
+
+def _lumped(nn, h):
+    """Integrals of the 1-D hat functions on a uniform grid: h/2 at the ends, h inside."""
+    w = np.full(nn, h)
+    w[0] = w[-1] = h / 2
+    return w
+
+
+def test_h1l2_regularisation_block_closed_form():
+    """The H1-L2 regularisation of Example 2 changes only the f-f block, by
+    beta2 Tt x (B - K).  On f = 1 (C = G = 0) the f rows change by
+    beta2 (integral of the time hat of level n) (integral of the space hat of
+    node j), since the stiffness matrix annihilates constants: both integrals
+    are products of 1-D lumped weights."""
+    p1 = make_custom((3, 4, 2), 4, 5, lattice=2, length=(1.0, 0.7, 1.3), T=0.8)
+    p2 = dataclasses.replace(p1, reg=H1L2)
+    D = (kkt.assemble(p2) - kkt.assemble(p1)).tocoo()
+    nz = np.abs(D.data) > 0
+    assert nz.any() and np.all(D.row[nz] % 3 == 2) and np.all(D.col[nz] % 3 == 2)
+    e = np.zeros(D.shape[0])
+    e[2::3] = 1.0
+    r = (D.tocsr() @ e).reshape(p1.M + 1, p1.N, 3)
+    assert np.abs(r[:, :, :2]).max() == 0.0
+    nx, ny, nz_ = p1.nodes
+    wx = _lumped(nx, 1.0 / p1.n[0])
+    wy = _lumped(ny, 0.7 / p1.n[1])
+    wz = _lumped(nz_, 1.3 / p1.n[2])
+    wt = _lumped(p1.M + 1, 0.8 / p1.M)
+    space = (wz[:, None, None] * wy[None, :, None] * wx[None, None, :]).ravel()
+    want = p1.beta2 * wt[:, None] * space[None, :]
+    assert np.allclose(r[:, :, 2], want, rtol=1e-12, atol=0.0)
+
+
+@pytest.mark.parametrize("shape", [((3, 2, 2), 3), ((4, 3, 3), 4)])
+def test_h1l2_matches_reduced_cg(shape):
+    """The H1-L2 KKT solution minimises the reduced functional with the L2
+    space term (reduced-space CG on the normal equations)."""
+    prob = make_custom(shape[0], shape[1], 21, lattice=2, reg=H1L2)
+    _, _, U = _solve_direct(prob)
+    f_kkt = U.reshape(prob.M + 1, prob.N, 3)[:, :, 2]
+    f_cg, its = reduced.Reduced(prob).cg(tol=1e-13)
+    assert np.linalg.norm(f_kkt - f_cg) <= 1e-8 * np.linalg.norm(f_cg)

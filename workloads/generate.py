@@ -25,6 +25,8 @@ import scipy.sparse.linalg as spla
 
 DTO = 0
 OTD = 1
+H1H1 = 0   # regularisation of eq. (3): time and space gradients of f
+H1L2 = 1   # the H1-L2 regularisation of Example 2: time gradient and L2 norm of f
 
 
 @dataclass
@@ -42,6 +44,7 @@ class Problem:
     T: float = 1.0
     dirichlet_faces: int = 0b000011
     variant: int = DTO
+    reg: int = H1H1
     name: str = ""
     f_true: Optional[np.ndarray] = None   # float64[M+1, N] when kept (diagnostic)
     data_clean: Optional[np.ndarray] = None  # noise-free sensor values (for fresh noise draws)
@@ -238,7 +241,7 @@ def _forward_fv(n, length, M, T, coef, v, src, faces, sensor_node, substeps=2):
 
 def _make(name, n, M, seed, *, smooth_coef, nsrc, width, sin_int, starts=None, ends=None,
           sensors=None, noise=0.01, beta=1e-4, v=(1.0, 0.5, 0.25), keep_f=False,
-          length=(1.0, 1.0, 1.0), T=1.0, faces=0b000011, variant=DTO):
+          length=(1.0, 1.0, 1.0), T=1.0, faces=0b000011, variant=DTO, reg=H1H1):
     rng = np.random.default_rng(seed)
     n = tuple(int(k) for k in n)
     coef = _Coefficient(rng, n, length) if smooth_coef else None
@@ -264,7 +267,7 @@ def _make(name, n, M, seed, *, smooth_coef, nsrc, width, sin_int, starts=None, e
     return Problem(n=n, M=int(M), a_elem=np.ascontiguousarray(a_elem, dtype=np.float64), v=tuple(v),
                    beta1=float(beta), beta2=float(beta), sensor_node=sensor_node,
                    data=np.ascontiguousarray(data), length=tuple(length), T=float(T),
-                   dirichlet_faces=faces, variant=variant, name=name, f_true=f_true,
+                   dirichlet_faces=faces, variant=variant, reg=reg, name=name, f_true=f_true,
                    data_clean=clean, noise=float(noise))
 
 
@@ -324,7 +327,7 @@ def make_problem(name="cube8x16", *, seed=None, n=None, M=None, keep_f=False, va
 
 def make_custom(n, M, seed, *, sensors=None, lattice=2, nsrc=1, width=0.15, smooth_coef=True,
                 beta=1e-4, noise=0.01, v=(1.0, 0.5, 0.25), faces=0b000011, variant=DTO,
-                length=(1.0, 1.0, 1.0), T=1.0):
+                length=(1.0, 1.0, 1.0), T=1.0, reg=H1H1):
     """Small instances of arbitrary (possibly anisotropic) shape for tests."""
     n = tuple(int(k) for k in n)
     if sensors is None:
@@ -336,7 +339,7 @@ def make_custom(n, M, seed, *, sensors=None, lattice=2, nsrc=1, width=0.15, smoo
         sensors = np.array([cand[p][0] + nn[0] * (cand[p][1] + nn[1] * cand[p][2]) for p in sorted(pick)])
     return _make("custom", n, M, seed, smooth_coef=smooth_coef, nsrc=nsrc, width=width, sin_int=True,
                  sensors=sensors, noise=noise, beta=beta, v=v, faces=faces, variant=variant,
-                 length=length, T=T)
+                 length=length, T=T, reg=reg)
 
 
 BATCH_N = (8, 12, 16, 20, 24)
