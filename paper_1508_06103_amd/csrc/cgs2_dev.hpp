@@ -80,6 +80,8 @@ __device__ inline void update_dot_range(double *__restrict__ w, const double *__
     double v[kCgsHalf];
 #pragma unroll
     for (int j = 0; j < kCgsHalf; ++j) v[j] = (j < kh && valid) ? V[(long long)(g0 + j) * ldv + e] : 0.0;
+    // w is read before the barrier: only this pass writes it, after the barrier
+    const double wold = valid ? w[e] : 0.0;
     double s = 0.0;
 #pragma unroll
     for (int j = 0; j < kCgsHalf; ++j)
@@ -88,7 +90,7 @@ __device__ inline void update_dot_range(double *__restrict__ w, const double *__
     sp[b][wave][lane] = s;
     __syncthreads();
     const double stot = sp[b][2 * pair][lane] + sp[b][2 * pair + 1][lane];
-    const double wn = valid ? w[e] - stot : 0.0;
+    const double wn = valid ? wold - stot : 0.0;
     if (valid && half == 0) w[e] = wn;
 #pragma unroll
     for (int j = 0; j < kCgsHalf; ++j) acc[j] += v[j] * wn;

@@ -47,6 +47,13 @@ def case(name):
         n, fac = (6, 6, 4), (3, 2, 2, 3)
         sens = _grid_sensors(n, fac, [(1, 0, 0), (1, 1, 1), (1, 2, 2), (1, 3, 1), (1, 1, 2)])
         return make_custom(n, 6, 11, sensors=sens), fac, (1, 2, 1, 2)
+    if name == "partial_axes":
+        # coarsening in y and z only: the transfers skip the x and t axes
+        return make_problem("cube8x16")[0], (1, 2, 2, 1), (2, 2, 2, 2)
+    if name == "same_mesh":
+        # factor 1 everywhere: the coarse mesh is the fine mesh
+        n = (3, 2, 3)
+        return make_custom(n, 4, 13, lattice=2), (1, 1, 1, 1), (1, 1, 1, 1)
     if name == "otd_neumann":
         n, fac = (4, 6, 6), (2, 3, 2, 2)
         sens = _grid_sensors(n, fac, [(1, 1, 1), (0, 1, 2), (2, 0, 1), (1, 2, 3)])
@@ -56,7 +63,9 @@ def case(name):
 
 @pytest.mark.parametrize("name,restrict,rtol", [("cube8x16", "transpose", 1e-12), ("cube8x16", "transpose", 0.1),
                                                 ("cube8x16", "injection", 1e-12), ("aniso", "transpose", 1e-12),
-                                                ("otd_neumann", "transpose", 0.1)])
+                                                ("otd_neumann", "transpose", 0.1),
+                                                ("partial_axes", "transpose", 1e-12),
+                                                ("same_mesh", "transpose", 1e-12)])
 def test_coarse_correction(st, name, restrict, rtol):
     prob, fac, cparts = case(name)
     _say(f"case {name}: factor {fac} coarse parts {cparts} restrict {restrict} rtol {rtol}")
@@ -144,7 +153,8 @@ def test_coarse_errors(st):
 
 
 @pytest.mark.parametrize("name,precision,tol", [("cube8x16", "f64", 1e-9), ("aniso", "f64", 1e-9),
-                                                ("otd_neumann", "f64", 1e-9), ("cube8x16", "f32", 1e-4)])
+                                                ("otd_neumann", "f64", 1e-9), ("cube8x16", "f32", 1e-4),
+                                                ("partial_axes", "f64", 1e-9), ("same_mesh", "f64", 1e-9)])
 def test_coarse_lu_correction(st, name, precision, tol):
     """Exact coarse solve (block elimination in time) against the oracle's block LU."""
     prob, fac, _ = case(name)
