@@ -222,3 +222,33 @@ def test_mixed_precision_solve(st, name, parts, delta, two_level):
             assert eC <= 3 * max(rel(xo, 0), 1e-7) and ef <= 3 * max(rel(xo, 2), 1e-7)
         else:
             assert eC <= 1e-5 and ef <= 1e-5
+
+
+def test_allocator_failure_is_enomem(st):
+    """An allocator that refuses memory makes the preconditioner setup fail with
+    ENOMEM, and the memory the setup took before the failure is given back."""
+    prob = small_problem("cube8x16")
+    alloc = st.TorchAllocator()
+    grant = alloc._alloc_cb
+    limit = {"bytes": None}
+
+    def limited(nbytes, ctx):
+        if limit["bytes"] is not None and alloc.bytes_live + nbytes > limit["bytes"]:
+            return None
+        return grant(nbytes, ctx)
+
+    alloc._limited_cb = st.ALLOC_FN(limited)
+    alloc.struct = st._Alloc(alloc._limited_cb, alloc._free_cb, None)
+    op = st.KKTOperator(prob, allocator=alloc)
+    torch.cuda.synchronize()
+    before = alloc.bytes_live
+    limit["bytes"] = before + (1 << 20)   # far less than the factors need
+    with pytest.raises(st.StkktError) as e:
+        st.RAS(op, (2, 2, 2, 2), 1)
+    assert e.value.code == st.ENOMEM
+    torch.cuda.synchronize()
+    assert alloc.bytes_live == before
+    limit["bytes"] = None
+    pre = st.RAS(op, (2, 2, 2, 2), 1)   # the operator is still usable
+    x, s = st.solve(op, pre, restart=30, rtol=1e-6)
+    assert s.converged
