@@ -304,7 +304,9 @@ void coarse_apply_device(const coarse *C, const double *x, double *y, hipStream_
   const OpDev &fo = C->fine, &co = C->cop->d;
   restrict_to_coarse(C, x, C->xc.as<double>(), s);
   if (C->lu) {
-    C->lu->solve(C->xc.as<double>(), C->yc.as<double>(), s);
+    const long long nvc = 3 * co.V;
+    if (C->lu->one_vector_on_mfma()) C->lu->solve_multi(1, C->xc.as<double>(), nvc, C->yc.as<double>(), nvc, s);
+    else C->lu->solve(C->xc.as<double>(), C->yc.as<double>(), s);
   } else {
     fill_zero(C->yc.as<double>(), 3 * co.V, s);
     solve_params_t sp{};

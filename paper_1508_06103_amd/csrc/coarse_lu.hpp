@@ -18,6 +18,10 @@ class CoarseLU {
   void solve_multi(int q, const double *r, long long ldr, double *x, long long ldx, hipStream_t s) const;
   // bytes of dense blocks streamed by one solve
   size_t bytes_per_solve() const;
+  // whether one vector is faster through the matrix-core pass than through
+  // the GEMV sweeps (FP64 blocks: the 16-byte row loads of the matrix-core
+  // pass stream them faster; FP32 blocks: the GEMV is faster)
+  bool one_vector_on_mfma() const { return prec_ == STKKT_F64; }
 
  private:
   template <typename T> void solve_t(const double *r, double *x, hipStream_t s) const;
