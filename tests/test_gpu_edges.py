@@ -94,3 +94,21 @@ def test_restart_one_fixed_steps(st, pair, graph):
         _say(f"  {name} GMRES(1), {s.iters} steps: rel diff {e:.2e}")
         assert s.iters == k and s.restarts == k - 1
         assert e <= 1e-7
+
+
+@pytest.mark.parametrize("where", ["single", "batch"])
+def test_non_finite_initial_guess_is_breakdown(st, pair, where):
+    """A NaN in x0 makes the initial residual non-finite: the solve stops at once
+    with EBREAKDOWN (alone, and for that member only in a batch)."""
+    prob, op, pre, F, xs = pair[0]
+    x = torch.zeros(op.n, dtype=torch.float64, device="cuda")
+    x[17] = float("nan")
+    if where == "single":
+        _, s = st.solve(op, pre, None, x, restart=10, rtol=1e-6, raise_on_fail=False)
+        assert s.status == st.EBREAKDOWN and s.iters == 0 and not s.converged
+        return
+    good = torch.zeros_like(x)
+    _, sts = st.solve_batch([op, op], [pre, pre], None, [x, good], restart=10, rtol=1e-6, raise_on_fail=False)
+    _say(f"  batch statuses {[s.status for s in sts]}, iters {[s.iters for s in sts]}")
+    assert sts[0].status == st.EBREAKDOWN and sts[0].iters == 0
+    assert sts[1].converged and sts[1].status == st.OK
