@@ -413,6 +413,7 @@ __global__ void gemv_reduce_kernel(int nb, int nchunk, const double *__restrict_
                                    const double *__restrict__ base, double sign, double *__restrict__ out) {
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nb; r += gridDim.x * blockDim.x) {
     double s = 0.0;
+#pragma unroll 8
     for (int q = 0; q < nchunk; ++q) s += partial[(long long)q * nb + r];
     out[r] = (base ? base[r] : 0.0) + sign * s;
   }
@@ -538,6 +539,7 @@ __global__ void gemm_reduce_kernel(int nb, int ld, int q, int nchunk, const doub
   const int c = blockIdx.y;
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nb; r += gridDim.x * blockDim.x) {
     double s = 0.0;
+#pragma unroll 8
     for (int k = 0; k < nchunk; ++k) s += partial[((long long)k * q + c) * ld + r];
     const double v = (base ? base[c * ldb + r] : 0.0) + sign * s;
     out[c * ldo + r] = v;
@@ -676,7 +678,7 @@ static void gemv(int nb, int ld, const T *A, const double *x, const double *base
   const int nch = (nb + kGvCols - 1) / kGvCols;
   hipLaunchKernelGGL(gemv_partial_kernel<T>, dim3((nb + kGvRows - 1) / kGvRows, nch), dim3(kGvRows), 0, s, nb, ld, A,
                      x, partial);
-  hipLaunchKernelGGL(gemv_reduce_kernel, dim3(blocks_for(nb, 256, 256)), dim3(256), 0, s, nb, nch, partial, base,
+  hipLaunchKernelGGL(gemv_reduce_kernel, dim3(blocks_for(nb, 64, 4096)), dim3(64), 0, s, nb, nch, partial, base,
                      sign, out);
 }
 
@@ -716,7 +718,7 @@ static void gemm(int nb, int ld, int nsplit, const T *A, int q, const double *xT
   const int nch = (nb + csplit - 1) / csplit;
   hipLaunchKernelGGL(gemm_partial_kernel<T>, dim3(ld / kMrRows, nch), dim3(kMrThreads), 0, s, nb, ld, csplit, A, q,
                      xT, partial);
-  hipLaunchKernelGGL(gemm_reduce_kernel, dim3(blocks_for(nb, 256, 64), q), dim3(256), 0, s, nb, ld, q, nch, partial,
+  hipLaunchKernelGGL(gemm_reduce_kernel, dim3(blocks_for(nb, 64, 4096), q), dim3(64), 0, s, nb, ld, q, nch, partial,
                      base, ldo, sign, out, ldo, outT);
 }
 
