@@ -123,14 +123,15 @@ typedef struct {
  *  - STKKT_COARSE_LU, exactly: F_c is block tridiagonal in time, so
  *    S_0 = D_0, S_k = D_k - L_k S_{k-1}^{-1} U_{k-1}; the setup forms and
  *    inverts every S_k densely (FP64 Gauss-Jordan with partial pivoting) and
- *    keeps S_k^{-1} and S_k^{-1} U_k in `precision`, using
- *    2 (M_c + 1) (3 N_c)^2 elements of device memory; `p`, `overlap`,
- *    `maxit`, `rtol` are ignored. */
+ *    keeps S_k^{-1} and S_k^{-1} U_k in `precision`, using about
+ *    2 (M_c + 1) (3 N_c)^2 elements of device memory (columns padded to a
+ *    multiple of 64 rows); `p`, `overlap`, `maxit`, `rtol` are ignored.
+ * The coarse mesh may have at most 512 nodes along x. */
 #define STKKT_COARSE_GMRES_RAS 0
 #define STKKT_COARSE_LU 1
 typedef struct {
   int32_t factor[4];        /* coarsening in x, y, z, t                    */
-  int32_t method;           /* STKKT_COARSE_GMRES_RAS                       */
+  int32_t method;           /* STKKT_COARSE_GMRES_RAS or STKKT_COARSE_LU    */
   int32_t precision;        /* STKKT_F64 or STKKT_F32 coarse ILU factors    */
   int32_t restrict_kind;    /* STKKT_RESTRICT_TRANSPOSE or _INJECTION       */
   int32_t p[4];             /* coarse subdomains in x, y, z, t              */
@@ -213,9 +214,11 @@ int ras_export_factors(const ras_t *ras, int32_t sub, double *host_out);
  * factor does not divide the mesh or a sensor is not on a coarse node. */
 int coarse_setup(const kkt_op_t *fine, const coarse_params_t *cp, void *stream, coarse_t **out);
 
-/* y = I_c^h F_c^{-1} I_h^c x (device vectors of the fine size), F_c^{-1}
- * being the inner GMRES(maxit) described above (not converging within maxit
- * steps is the normal case and not an error).  Synchronises `stream`. */
+/* y = I_c^h F_c^{-1} I_h^c x (device vectors of the fine size).  F_c^{-1} is
+ * the inner GMRES(maxit) described above (not converging within maxit steps
+ * is the normal case and not an error; this form synchronises `stream`), or
+ * the exact block elimination in time (STKKT_COARSE_LU; stream-ordered, no
+ * synchronisation).  x and y must not alias. */
 int coarse_apply(const coarse_t *c, const double *x, double *y, void *stream);
 
 /* Several applications of the coarse level at once: y_i = coarse_apply(x_i)
