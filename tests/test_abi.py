@@ -35,3 +35,31 @@ def test_error_path_without_gpu():
     rc = st._lib.kkt_assemble(None, None, None, ctypes.byref(h), None)
     assert rc == st.EINVAL
     assert b"NULL" in st._lib.kkt_last_error()
+
+
+def test_header_is_plain_c(tmp_path):
+    """The boundary header compiles as C99 and as C++ with no HIP or torch
+    headers, and its structs have the layout the binding marshals."""
+    import shutil
+    import subprocess
+    import paper_1508_06103_amd as st
+    src = tmp_path / "abi.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "stkkt.h"\n'
+                   "int main(void) {\n"
+                   '  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(kkt_problem_t), offsetof(kkt_problem_t, regularization),\n'
+                   "         sizeof(ras_params_t), sizeof(coarse_params_t), sizeof(solve_params_t), sizeof(kkt_stats_t),\n"
+                   "         sizeof(server_params_t));\n"
+                   "  return 0;\n}\n")
+    inc = os.path.join(ROOT, "include")
+    cc = shutil.which("gcc") or shutil.which("cc")
+    exe = tmp_path / "abi"
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", inc, str(src), "-o", str(exe)], check=True)
+    cxx = shutil.which("g++")
+    if cxx:
+        subprocess.run([cxx, "-x", "c++", "-std=c++17", "-Wall", "-Werror", "-fsyntax-only", "-I", inc, str(src)],
+                       check=True)
+    sizes = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    want = [ctypes.sizeof(st._Problem), st._Problem.regularization.offset, ctypes.sizeof(st._RasParams),
+            ctypes.sizeof(st._CoarseParams), ctypes.sizeof(st._SolveParams), ctypes.sizeof(st._Stats),
+            ctypes.sizeof(st._ServerParams)]
+    assert sizes == want
