@@ -121,6 +121,7 @@ __global__ void __launch_bounds__(kBT) bupdate_kernel(double *__restrict__ w, co
 // The fused CGS passes over the chunk work list (bodies shared with the single
 // solve): w -= V h_inst with partial[g * nch + chunk] = chunk part of V_g . w_new,
 // and w -= V h_inst with partial[chunk] = chunk part of |w_new|^2.
+template <int KR>
 __global__ void __launch_bounds__(kCgsThreads) bupdate_dot_kernel(double *__restrict__ w,
                                                                   const double *__restrict__ V, long long ldv, int k,
                                                                   const double *__restrict__ h, int hstride,
@@ -129,7 +130,7 @@ __global__ void __launch_bounds__(kCgsThreads) bupdate_dot_kernel(double *__rest
                                                                   double *__restrict__ partial) {
   const Chunk c = load_uniform(ch + blockIdx.x);
   if (!as_const(act)[c.inst]) return;
-  update_dot_range(w, V, ldv, k, h + (long long)c.inst * hstride, c.lo, c.hi, partial + blockIdx.x, nch);
+  update_dot_range<KR>(w, V, ldv, k, h + (long long)c.inst * hstride, c.lo, c.hi, partial + blockIdx.x, nch);
 }
 
 __global__ void __launch_bounds__(kCgsThreads) bupdate_norm_kernel(double *__restrict__ w,
@@ -520,8 +521,15 @@ void BatchEngine::cgs2(int j, const int *act) {
     double *part = partial_.as<double>();
     const int *cf = cfirst_.as<int>();
     const unsigned S = (unsigned)slots_.size();
-    hipLaunchKernelGGL(bupdate_dot_kernel, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd, hs, chd, nch_,
-                       act, part);
+    if (j + 1 <= kCgsHalf)
+      hipLaunchKernelGGL(bupdate_dot_kernel<kCgsHalf>, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd, hs,
+                         chd, nch_, act, part);
+    else if (j + 1 <= 48)
+      hipLaunchKernelGGL(bupdate_dot_kernel<48>, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd, hs, chd,
+                         nch_, act, part);
+    else
+      hipLaunchKernelGGL(bupdate_dot_kernel<kCgsMaxK>, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd, hs,
+                         chd, nch_, act, part);
     hipLaunchKernelGGL(breduce_kernel, dim3(S, j + 1), dim3(kBT), 0, s_, part, nch_, cf, act, hs, hd + (m + 1));
     hipLaunchKernelGGL(bupdate_norm_kernel, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd + (m + 1), hs,
                        chd, act, part);

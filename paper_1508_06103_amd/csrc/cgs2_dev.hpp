@@ -18,93 +18,61 @@ __device__ inline double cgs_wave_sum(double v) {
   return v;
 }
 
-// w[e] <- w[e] - sum_{g<k} h[g] V_g[e] for e in [lo, hi), then
-// out[g * ostride] = sum over the range of V_g[e] w_new[e], g < k (k <= 64).
-//
-// Lanes are elements and a wavefront takes 64-element tiles; the basis
-// entries of a tile are loaded once into registers and serve both the update
-// and the dots, so V is read once.  Up to 32 basis vectors every wavefront
-// works on its own tiles with no synchronisation.  Above 32 the two
-// wavefronts of a pair share a tile, each holding half of the basis entries,
-// and add their halves of the update sum through LDS (one barrier per tile).
-__device__ inline void update_dot_range(double *__restrict__ w, const double *__restrict__ V, long long ldv, int k,
-                                        const double *__restrict__ h, long long lo, long long hi,
-                                        double *__restrict__ out, long long ostride) {
-  __shared__ double sp[2][kCgsThreads / 64][64];
-  __shared__ double red[kCgsThreads / 64][kCgsMaxK];
+// Tiles of one wavefront: lanes are elements, a wavefront takes 64-element
+// tiles; the KR >= k basis entries of a tile are loaded once into registers
+// and serve both the update and the dots, so V is read once.  The
+// wavefront's dot sums go to red[wave][g].
+template <int KR>
+__device__ inline void update_dot_tiles(double *__restrict__ w, const double *__restrict__ V, long long ldv, int k,
+                                        cptr<double> hc, long long lo, long long hi,
+                                        double (*red)[kCgsMaxK]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const cptr<double> hc = as_const(h);
   const long long ntiles = (hi - lo + 63) / 64;
-  double acc[kCgsHalf];
+  double acc[KR];
 #pragma unroll
-  for (int j = 0; j < kCgsHalf; ++j) acc[j] = 0.0;
-  if (k <= kCgsHalf) {
-    for (long long t = wave; t < ntiles; t += kCgsThreads / 64) {
-      const long long e = lo + 64 * t + lane;
-      const bool valid = e < hi;
-      double v[kCgsHalf];
-#pragma unroll
-      for (int j = 0; j < kCgsHalf; ++j) v[j] = (j < k && valid) ? V[(long long)j * ldv + e] : 0.0;
-      double s = 0.0;
-#pragma unroll
-      for (int j = 0; j < kCgsHalf; ++j)
-        if (j < k) s += hc[j] * v[j];
-      const double wn = valid ? w[e] - s : 0.0;
-      if (valid) w[e] = wn;
-#pragma unroll
-      for (int j = 0; j < kCgsHalf; ++j) acc[j] += v[j] * wn;
-    }
-#pragma unroll
-    for (int j = 0; j < kCgsHalf; ++j)
-      if (j < k) {
-        const double r = cgs_wave_sum(acc[j]);
-        if (lane == 0) red[wave][j] = r;
-      }
-    __syncthreads();
-    if ((int)threadIdx.x < k) {
-      double s = 0.0;
-#pragma unroll
-      for (int wv = 0; wv < kCgsThreads / 64; ++wv) s += red[wv][threadIdx.x];
-      out[(long long)threadIdx.x * ostride] = s;
-    }
-    return;
-  }
-  const int pair = wave >> 1, half = wave & 1;
-  const int g0 = kCgsHalf * half;
-  const int kh = k - g0 < kCgsHalf ? k - g0 : kCgsHalf;   // basis vectors of this half
-  const long long niter = (ntiles + 1) / 2;                // the same count for every wavefront
-  for (long long it = 0; it < niter; ++it) {
-    const long long t = pair + 2 * it;
+  for (int j = 0; j < KR; ++j) acc[j] = 0.0;
+  for (long long t = wave; t < ntiles; t += kCgsThreads / 64) {
     const long long e = lo + 64 * t + lane;
-    const bool valid = t < ntiles && e < hi;
-    double v[kCgsHalf];
+    const bool valid = e < hi;
+    double v[KR];
 #pragma unroll
-    for (int j = 0; j < kCgsHalf; ++j) v[j] = (j < kh && valid) ? V[(long long)(g0 + j) * ldv + e] : 0.0;
-    // w is read before the barrier: only this pass writes it, after the barrier
+    for (int j = 0; j < KR; ++j) v[j] = (j < k && valid) ? V[(long long)j * ldv + e] : 0.0;
     const double wold = valid ? w[e] : 0.0;
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < kCgsHalf; ++j)
-      if (j < kh) s += hc[g0 + j] * v[j];
-    const int b = (int)(it & 1);
-    sp[b][wave][lane] = s;
-    __syncthreads();
-    const double stot = sp[b][2 * pair][lane] + sp[b][2 * pair + 1][lane];
-    const double wn = valid ? wold - stot : 0.0;
-    if (valid && half == 0) w[e] = wn;
+    for (int j = 0; j < KR; ++j)
+      if (j < k) s += hc[j] * v[j];
+    const double wn = valid ? wold - s : 0.0;
+    if (valid) w[e] = wn;
 #pragma unroll
-    for (int j = 0; j < kCgsHalf; ++j) acc[j] += v[j] * wn;
+    for (int j = 0; j < KR; ++j) acc[j] += v[j] * wn;
   }
 #pragma unroll
-  for (int j = 0; j < kCgsHalf; ++j)
-    if (j < kh) {
+  for (int j = 0; j < KR; ++j)
+    if (j < k) {
       const double r = cgs_wave_sum(acc[j]);
-      if (lane == 0) red[wave][g0 + j] = r;
+      if (lane == 0) red[wave][j] = r;
     }
+}
+
+// w[e] <- w[e] - sum_{g<k} h[g] V_g[e] for e in [lo, hi), then
+// out[g * ostride] = sum over the range of V_g[e] w_new[e], g < k <= KR.
+// Every wavefront works on its own tiles with no synchronisation.  Kernels
+// are instantiated with KR = 32, 48 and 64 (the smallest KR >= k: more
+// registers per wavefront, fewer wavefronts per SIMD, more loads in flight
+// per wavefront).
+template <int KR>
+__device__ inline void update_dot_range(double *__restrict__ w, const double *__restrict__ V, long long ldv, int k,
+                                        const double *__restrict__ h, long long lo, long long hi,
+                                        double *__restrict__ out, long long ostride) {
+  __shared__ double red[kCgsThreads / 64][kCgsMaxK];
+  update_dot_tiles<KR>(w, V, ldv, k, as_const(h), lo, hi, red);
   __syncthreads();
   if ((int)threadIdx.x < k) {
-    const int hf = (int)threadIdx.x >= kCgsHalf ? 1 : 0;
-    out[(long long)threadIdx.x * ostride] = red[hf][threadIdx.x] + red[2 + hf][threadIdx.x];
+    double s = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kCgsThreads / 64; ++wv) s += red[wv][threadIdx.x];
+    out[(long long)threadIdx.x * ostride] = s;
   }
 }
 

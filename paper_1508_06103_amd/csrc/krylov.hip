@@ -109,6 +109,7 @@ __global__ void scale_kernel(double *__restrict__ out, const double *__restrict_
 // b] = block b's part of V_g . w_new) and the last update fused with the norm
 // (partial[b] = block b's part of |w_new|^2); the bodies are shared with the
 // batched solver.
+template <int KR>
 __global__ void __launch_bounds__(kCgsThreads) update_dot_kernel(double *__restrict__ w, const double *__restrict__ V,
                                                                  long long ldv, int k, const double *__restrict__ h,
                                                                  long long n, double *__restrict__ partial) {
@@ -116,7 +117,7 @@ __global__ void __launch_bounds__(kCgsThreads) update_dot_kernel(double *__restr
   const long long per = (n + G - 1) / G;
   const long long lo = (long long)blockIdx.x * per;
   const long long hi = lo + per < n ? lo + per : n;
-  update_dot_range(w, V, ldv, k, h, lo, hi > lo ? hi : lo, partial + blockIdx.x, G);
+  update_dot_range<KR>(w, V, ldv, k, h, lo, hi > lo ? hi : lo, partial + blockIdx.x, G);
 }
 
 __global__ void __launch_bounds__(kCgsThreads) update_norm_kernel(double *__restrict__ w, const double *__restrict__ V,
@@ -137,7 +138,12 @@ bool cgs2_fused_ok(int k) { return k <= kCgsMaxK; }
 void update_dot(double *w, const double *V, long long ldv, int k, const double *h, long long n, double *partial,
                 double *out, hipStream_t s) {
   const int G = reduction_blocks(n);
-  hipLaunchKernelGGL(update_dot_kernel, dim3(G), dim3(kThreads), 0, s, w, V, ldv, k, h, n, partial);
+  if (k <= kCgsHalf)
+    hipLaunchKernelGGL(update_dot_kernel<kCgsHalf>, dim3(G), dim3(kThreads), 0, s, w, V, ldv, k, h, n, partial);
+  else if (k <= 48)
+    hipLaunchKernelGGL(update_dot_kernel<48>, dim3(G), dim3(kThreads), 0, s, w, V, ldv, k, h, n, partial);
+  else
+    hipLaunchKernelGGL(update_dot_kernel<kCgsMaxK>, dim3(G), dim3(kThreads), 0, s, w, V, ldv, k, h, n, partial);
   STKKT_HIP(hipGetLastError());
   hipLaunchKernelGGL(reduce_kernel, dim3(k), dim3(kThreads), 0, s, partial, G, out);
   STKKT_HIP(hipGetLastError());
