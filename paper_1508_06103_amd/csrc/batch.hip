@@ -133,6 +133,7 @@ __global__ void __launch_bounds__(kCgsThreads) bupdate_dot_kernel(double *__rest
   update_dot_range<KR>(w, V, ldv, k, h + (long long)c.inst * hstride, c.lo, c.hi, partial + blockIdx.x, nch);
 }
 
+template <int KR>
 __global__ void __launch_bounds__(kCgsThreads) bupdate_norm_kernel(double *__restrict__ w,
                                                                    const double *__restrict__ V, long long ldv, int k,
                                                                    const double *__restrict__ h, int hstride,
@@ -141,7 +142,7 @@ __global__ void __launch_bounds__(kCgsThreads) bupdate_norm_kernel(double *__res
                                                                    double *__restrict__ partial) {
   const Chunk c = load_uniform(ch + blockIdx.x);
   if (!as_const(act)[c.inst]) return;
-  const double s = update_norm_range(w, V, ldv, k, h + (long long)c.inst * hstride, c.lo, c.hi);
+  const double s = update_norm_range<KR>(w, V, ldv, k, h + (long long)c.inst * hstride, c.lo, c.hi);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
@@ -531,8 +532,15 @@ void BatchEngine::cgs2(int j, const int *act) {
       hipLaunchKernelGGL(bupdate_dot_kernel<kCgsMaxK>, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd, hs,
                          chd, nch_, act, part);
     hipLaunchKernelGGL(breduce_kernel, dim3(S, j + 1), dim3(kBT), 0, s_, part, nch_, cf, act, hs, hd + (m + 1));
-    hipLaunchKernelGGL(bupdate_norm_kernel, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd + (m + 1), hs,
-                       chd, act, part);
+    if (j + 1 <= kCgsHalf)
+      hipLaunchKernelGGL(bupdate_norm_kernel<kCgsHalf>, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1,
+                         hd + (m + 1), hs, chd, act, part);
+    else if (j + 1 <= 48)
+      hipLaunchKernelGGL(bupdate_norm_kernel<48>, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd + (m + 1),
+                         hs, chd, act, part);
+    else
+      hipLaunchKernelGGL(bupdate_norm_kernel<kCgsMaxK>, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1,
+                         hd + (m + 1), hs, chd, act, part);
     hipLaunchKernelGGL(breduce_kernel, dim3(S, 1), dim3(kBT), 0, s_, part, nch_, cf, act, hs, hd + 2 * (m + 1));
     STKKT_HIP(hipGetLastError());
   } else {

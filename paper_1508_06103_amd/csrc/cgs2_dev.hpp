@@ -78,14 +78,22 @@ __device__ inline void update_dot_range(double *__restrict__ w, const double *__
 
 // w[e] <- w[e] - sum_{g<k} h[g] V_g[e] for e in [lo, hi); returns (in thread
 // 0) the range's sum of w_new[e]^2.
+// The basis entries of an element are loaded together (up to KR, KR >= k;
+// instantiated like the update+dot) before the sum, in the same order.
+template <int KR>
 __device__ inline double update_norm_range(double *__restrict__ w, const double *__restrict__ V, long long ldv, int k,
                                            const double *__restrict__ h, long long lo, long long hi) {
   __shared__ double red[kCgsThreads / 64];
   const cptr<double> hc = as_const(h);
   double acc = 0.0;
   for (long long e = lo + threadIdx.x; e < hi; e += kCgsThreads) {
+    double v[KR];
+#pragma unroll
+    for (int g = 0; g < KR; ++g) v[g] = g < k ? V[(long long)g * ldv + e] : 0.0;
     double s = 0.0;
-    for (int g = 0; g < k; ++g) s += hc[g] * V[(long long)g * ldv + e];
+#pragma unroll
+    for (int g = 0; g < KR; ++g)
+      if (g < k) s += hc[g] * v[g];
     const double wn = w[e] - s;
     w[e] = wn;
     acc += wn * wn;

@@ -120,6 +120,7 @@ __global__ void __launch_bounds__(kCgsThreads) update_dot_kernel(double *__restr
   update_dot_range<KR>(w, V, ldv, k, h, lo, hi > lo ? hi : lo, partial + blockIdx.x, G);
 }
 
+template <int KR>
 __global__ void __launch_bounds__(kCgsThreads) update_norm_kernel(double *__restrict__ w, const double *__restrict__ V,
                                                                   long long ldv, int k, const double *__restrict__ h,
                                                                   long long n, double *__restrict__ partial) {
@@ -127,7 +128,7 @@ __global__ void __launch_bounds__(kCgsThreads) update_norm_kernel(double *__rest
   const long long per = (n + G - 1) / G;
   const long long lo = (long long)blockIdx.x * per;
   const long long hi = lo + per < n ? lo + per : n;
-  const double s = update_norm_range(w, V, ldv, k, h, lo, hi > lo ? hi : lo);
+  const double s = update_norm_range<KR>(w, V, ldv, k, h, lo, hi > lo ? hi : lo);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
@@ -152,7 +153,12 @@ void update_dot(double *w, const double *V, long long ldv, int k, const double *
 void update_norm(double *w, const double *V, long long ldv, int k, const double *h, long long n, double *partial,
                  double *out, hipStream_t s) {
   const int G = reduction_blocks(n);
-  hipLaunchKernelGGL(update_norm_kernel, dim3(G), dim3(kThreads), 0, s, w, V, ldv, k, h, n, partial);
+  if (k <= kCgsHalf)
+    hipLaunchKernelGGL(update_norm_kernel<kCgsHalf>, dim3(G), dim3(kThreads), 0, s, w, V, ldv, k, h, n, partial);
+  else if (k <= 48)
+    hipLaunchKernelGGL(update_norm_kernel<48>, dim3(G), dim3(kThreads), 0, s, w, V, ldv, k, h, n, partial);
+  else
+    hipLaunchKernelGGL(update_norm_kernel<kCgsMaxK>, dim3(G), dim3(kThreads), 0, s, w, V, ldv, k, h, n, partial);
   STKKT_HIP(hipGetLastError());
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, partial, G, out);
   STKKT_HIP(hipGetLastError());
