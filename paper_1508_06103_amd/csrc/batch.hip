@@ -528,6 +528,9 @@ void BatchEngine::cgs2(int j, const int *act) {
     else if (j + 1 <= 48)
       hipLaunchKernelGGL(bupdate_dot_kernel<48>, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd, hs, chd,
                          nch_, act, part);
+    else if (j + 1 <= 56)
+      hipLaunchKernelGGL(bupdate_dot_kernel<56>, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd, hs, chd,
+                         nch_, act, part);
     else
       hipLaunchKernelGGL(bupdate_dot_kernel<kCgsMaxK>, dim3(nch_), dim3(kCgsThreads), 0, s_, Wd, Vd, N, j + 1, hd, hs,
                          chd, nch_, act, part);

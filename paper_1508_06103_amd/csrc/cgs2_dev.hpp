@@ -58,7 +58,7 @@ __device__ inline void update_dot_tiles(double *__restrict__ w, const double *__
 // w[e] <- w[e] - sum_{g<k} h[g] V_g[e] for e in [lo, hi), then
 // out[g * ostride] = sum over the range of V_g[e] w_new[e], g < k <= KR.
 // Every wavefront works on its own tiles with no synchronisation.  Kernels
-// are instantiated with KR = 32, 48 and 64 (the smallest KR >= k: more
+// are instantiated with KR = 32, 48, 56 and 64 (the smallest KR >= k: more
 // registers per wavefront, fewer wavefronts per SIMD, more loads in flight
 // per wavefront).
 template <int KR>

@@ -143,6 +143,8 @@ void update_dot(double *w, const double *V, long long ldv, int k, const double *
     hipLaunchKernelGGL(update_dot_kernel<kCgsHalf>, dim3(G), dim3(kThreads), 0, s, w, V, ldv, k, h, n, partial);
   else if (k <= 48)
     hipLaunchKernelGGL(update_dot_kernel<48>, dim3(G), dim3(kThreads), 0, s, w, V, ldv, k, h, n, partial);
+  else if (k <= 56)
+    hipLaunchKernelGGL(update_dot_kernel<56>, dim3(G), dim3(kThreads), 0, s, w, V, ldv, k, h, n, partial);
   else
     hipLaunchKernelGGL(update_dot_kernel<kCgsMaxK>, dim3(G), dim3(kThreads), 0, s, w, V, ldv, k, h, n, partial);
   STKKT_HIP(hipGetLastError());
