@@ -55,6 +55,39 @@ __device__ inline void update_dot_tiles(double *__restrict__ w, const double *__
     }
 }
 
+// out[g * ostride] = sum over [lo, hi) of V_g[e] w[e], g < k <= KR: the same
+// tiles as the update+dot, without the update (the first CGS pass).
+template <int KR>
+__device__ inline void dot_range(const double *__restrict__ w, const double *__restrict__ V, long long ldv, int k,
+                                 long long lo, long long hi, double *__restrict__ out, long long ostride) {
+  __shared__ double red[kCgsThreads / 64][kCgsMaxK];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long ntiles = (hi - lo + 63) / 64;
+  double acc[KR];
+#pragma unroll
+  for (int j = 0; j < KR; ++j) acc[j] = 0.0;
+  for (long long t = wave; t < ntiles; t += kCgsThreads / 64) {
+    const long long e = lo + 64 * t + lane;
+    const bool valid = e < hi;
+    const double we = valid ? w[e] : 0.0;
+#pragma unroll
+    for (int j = 0; j < KR; ++j) acc[j] += ((j < k && valid) ? V[(long long)j * ldv + e] : 0.0) * we;
+  }
+#pragma unroll
+  for (int j = 0; j < KR; ++j)
+    if (j < k) {
+      const double r = cgs_wave_sum(acc[j]);
+      if (lane == 0) red[wave][j] = r;
+    }
+  __syncthreads();
+  if ((int)threadIdx.x < k) {
+    double s = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kCgsThreads / 64; ++wv) s += red[wv][threadIdx.x];
+    out[(long long)threadIdx.x * ostride] = s;
+  }
+}
+
 // w[e] <- w[e] - sum_{g<k} h[g] V_g[e] for e in [lo, hi), then
 // out[g * ostride] = sum over the range of V_g[e] w_new[e], g < k <= KR.
 // Every wavefront works on its own tiles with no synchronisation.  Kernels

@@ -54,6 +54,19 @@ __global__ void __launch_bounds__(kThreads) multidot_kernel(const double *__rest
   }
 }
 
+// The first CGS pass for k <= 64 vectors on the register tiles of the fused
+// passes (partial[i * G + b] as above).
+template <int KR>
+__global__ void __launch_bounds__(kCgsThreads) multidot_tiles_kernel(const double *__restrict__ V, long long ldv,
+                                                                     int k, const double *__restrict__ w, long long n,
+                                                                     double *__restrict__ partial) {
+  const int G = gridDim.x;
+  const long long per = (n + G - 1) / G;
+  const long long lo = (long long)blockIdx.x * per;
+  const long long hi = lo + per < n ? lo + per : n;
+  dot_range<KR>(w, V, ldv, k, lo, hi > lo ? hi : lo, partial + blockIdx.x, G);
+}
+
 // out[i] = sum_b partial[i * G + b] (fixed order), one block per i.
 __global__ void __launch_bounds__(kThreads) reduce_kernel(const double *__restrict__ partial, int G,
                                                           double *__restrict__ out) {
@@ -176,7 +189,16 @@ int reduction_blocks(long long n) {
 void multidot(const double *V, long long ldv, int k, const double *w, long long n, double *partial, double *out,
               hipStream_t s) {
   const int G = reduction_blocks(n);
-  hipLaunchKernelGGL(multidot_kernel, dim3(G), dim3(kThreads), 0, s, V, ldv, k, w, n, partial);
+  if (k <= kCgsHalf)
+    hipLaunchKernelGGL(multidot_tiles_kernel<kCgsHalf>, dim3(G), dim3(kCgsThreads), 0, s, V, ldv, k, w, n, partial);
+  else if (k <= 48)
+    hipLaunchKernelGGL(multidot_tiles_kernel<48>, dim3(G), dim3(kCgsThreads), 0, s, V, ldv, k, w, n, partial);
+  else if (k <= 56)
+    hipLaunchKernelGGL(multidot_tiles_kernel<56>, dim3(G), dim3(kCgsThreads), 0, s, V, ldv, k, w, n, partial);
+  else if (k <= kCgsMaxK)
+    hipLaunchKernelGGL(multidot_tiles_kernel<kCgsMaxK>, dim3(G), dim3(kCgsThreads), 0, s, V, ldv, k, w, n, partial);
+  else
+    hipLaunchKernelGGL(multidot_kernel, dim3(G), dim3(kThreads), 0, s, V, ldv, k, w, n, partial);
   STKKT_HIP(hipGetLastError());
   hipLaunchKernelGGL(reduce_kernel, dim3(k), dim3(kThreads), 0, s, partial, G, out);
   STKKT_HIP(hipGetLastError());
