@@ -47,6 +47,18 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// The same for k <= 64 on the register tiles of the fused passes.
+template <int KR>
+__global__ void __launch_bounds__(kCgsThreads) bmultidot_tiles_kernel(const double *__restrict__ V, long long ldv,
+                                                                      int k, const double *__restrict__ w,
+                                                                      const Chunk *__restrict__ ch, int nch,
+                                                                      const int *__restrict__ act,
+                                                                      double *__restrict__ partial) {
+  const Chunk c = load_uniform(ch + blockIdx.x);
+  if (!as_const(act)[c.inst]) return;
+  dot_range<KR>(w, V, ldv, k, c.lo, c.hi, partial + blockIdx.x, nch);
+}
+
 // partial[g * nch + c] = sum over chunk c of V_g[e] w[e], g < k.
 __global__ void __launch_bounds__(kBT) bmultidot_kernel(const double *__restrict__ V, long long ldv, int k,
                                                         const double *__restrict__ w, const Chunk *__restrict__ ch,
@@ -440,8 +452,22 @@ void BatchEngine::upload(int *host, DevBuf &dev) {
 
 void BatchEngine::bdot(const double *V, long long ldv, int k, const double *w, const int *act, double *out) {
   if (nch_ == 0) return;
-  hipLaunchKernelGGL(bmultidot_kernel, dim3(nch_), dim3(kBT), 0, s_, V, ldv, k, w, chunks_.as<Chunk>(), nch_, act,
-                     partial_.as<double>());
+  const Chunk *chd = chunks_.as<Chunk>();
+  double *part = partial_.as<double>();
+  if (k <= kCgsHalf)
+    hipLaunchKernelGGL(bmultidot_tiles_kernel<kCgsHalf>, dim3(nch_), dim3(kCgsThreads), 0, s_, V, ldv, k, w, chd, nch_,
+                       act, part);
+  else if (k <= 48)
+    hipLaunchKernelGGL(bmultidot_tiles_kernel<48>, dim3(nch_), dim3(kCgsThreads), 0, s_, V, ldv, k, w, chd, nch_, act,
+                       part);
+  else if (k <= 56)
+    hipLaunchKernelGGL(bmultidot_tiles_kernel<56>, dim3(nch_), dim3(kCgsThreads), 0, s_, V, ldv, k, w, chd, nch_, act,
+                       part);
+  else if (k <= kCgsMaxK)
+    hipLaunchKernelGGL(bmultidot_tiles_kernel<kCgsMaxK>, dim3(nch_), dim3(kCgsThreads), 0, s_, V, ldv, k, w, chd, nch_,
+                       act, part);
+  else
+    hipLaunchKernelGGL(bmultidot_kernel, dim3(nch_), dim3(kBT), 0, s_, V, ldv, k, w, chd, nch_, act, part);
   hipLaunchKernelGGL(breduce_kernel, dim3((unsigned)slots_.size(), k), dim3(kBT), 0, s_, partial_.as<double>(), nch_,
                      cfirst_.as<int>(), act, hs_, out);
   STKKT_HIP(hipGetLastError());
