@@ -237,6 +237,7 @@ def run_batch(args):
                    "unknowns": unknowns},
         "p50_ms": 1e3 * percentile(times, 50), "p99_ms": 1e3 * percentile(times, 99),
         "gmres_iters": float(np.mean(its)), "setup_ms": 1e3 * t_setup,
+        "factor_bytes_total": int(sum(p.factor_bytes for p in pres)),
         "baseline_one_at_a_time_fp64": {"value": base, "unit": "solves/s", "gmres_iters": float(np.mean(base_its))},
         "speedup_vs_one_at_a_time_fp64": value / base,
     }
