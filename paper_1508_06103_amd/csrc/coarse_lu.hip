@@ -8,11 +8,15 @@
 // neighbours at time offsets 0, -1, +1).  The setup forms every S_k densely
 // and inverts it explicitly (blocked Gauss-Jordan elimination with partial
 // pivoting, the trailing updates as tiled FP64 GEMMs), so one application is
-// two sweeps of dense matrix-vector products streamed from HBM.
+// two sweeps of dense block products streamed from HBM: matrix-vector
+// products for one vector, matrix-core products for up to 16 vectors per
+// pass.
 //
-// Dense matrices are stored column-major (entry (r, c) at c * nb + r).  The
-// Gauss-Jordan kernels work on rows of the buffer, i.e. on the transpose; the
-// inverse of the transpose read column-major is the inverse itself.
+// Dense matrices are stored column-major (entry (r, c) at c * nb + r during
+// the setup; the kept S_k^{-1} and E_k at c * ld + r, ld = nb rounded up to
+// 64).  The Gauss-Jordan kernels work on rows of the buffer, i.e. on the
+// transpose; the inverse of the transpose read column-major is the inverse
+// itself.
 #include <algorithm>
 #include <cmath>
 #include <vector>
