@@ -9,8 +9,8 @@
 // and inverts it explicitly (blocked Gauss-Jordan elimination with partial
 // pivoting, the trailing updates as tiled FP64 GEMMs), so one application is
 // two sweeps of dense block products streamed from HBM: matrix-vector
-// products for one vector, matrix-core products for up to 16 vectors per
-// pass.
+// products (solve) or matrix-core products for up to 16 vectors per pass
+// (solve_multi).
 //
 // Dense matrices are stored column-major (entry (r, c) at c * nb + r during
 // the setup; the kept S_k^{-1} and E_k at c * ld + r, ld = nb rounded up to
