@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(kBT) bmultidot_kernel(const double *__restrict
       if (lane == 0) red[g][wave] = s;
     }
     __syncthreads();
-    if (threadIdx.x < gk) {
+    if ((int)threadIdx.x < gk) {
       double s = 0.0;
       for (int wv = 0; wv < kBT / 64; ++wv) s += red[threadIdx.x][wv];
       partial[(long long)(i0 + threadIdx.x) * nch + blockIdx.x] = s;

@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(1024) gje_pivot_kernel(int n, int k, int e, in
   }
   if (threadIdx.x == 0) swp[j] = p;
   if (p != c) {
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
       double *Pq = P + (long long)threadIdx.x * n;
       const double t = Pq[c];
       Pq[c] = Pq[p];
@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(1024) gje_pivot_kernel(int n, int k, int e, in
   for (int i = threadIdx.x; i < n; i += blockDim.x) fcol[i] = Pc[i];
   const double a = Pc[c];
   __syncthreads();
-  if (threadIdx.x < w) {
+  if ((int)threadIdx.x < w) {
     double *Pq = P + (long long)threadIdx.x * n;
     const double v = ((int)threadIdx.x == j ? 1.0 : Pq[c]) / a;
     prow[threadIdx.x] = v;
@@ -586,7 +586,7 @@ static void gje_invert(int n, double *A, double *tmp, double *rows, double *pan,
   STKKT_HIP(hipMemcpyAsync(A, tmp, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
 }
 
-CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStream_t s) : al_(al), prec_(precision) {
+CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStream_t s) : prec_(precision) {
   const OpDev &d = cop->d;
   nb_ = 3 * d.N;
   nlev_ = d.M + 1;

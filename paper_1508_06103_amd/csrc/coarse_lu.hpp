@@ -27,7 +27,6 @@ class CoarseLU {
   template <typename T> void solve_t(const double *r, double *x, hipStream_t s) const;
   template <typename T>
   void solve_multi_t(int q, const double *r, long long ldr, double *x, long long ldx, hipStream_t s) const;
-  const Allocator *al_;
   int prec_;
   int nb_ = 0, nlev_ = 0;
   int ld_ = 0;       // leading dimension of the stored blocks (nb_ rounded up to 64, zero rows below nb_)

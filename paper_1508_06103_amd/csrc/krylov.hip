@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(kThreads) multidot_kernel(const double *__rest
       if (lane == 0) red[g][wave] = s;
     }
     __syncthreads();
-    if (threadIdx.x < gk) {
+    if ((int)threadIdx.x < gk) {
       double s = 0.0;
       for (int wv = 0; wv < kThreads / 64; ++wv) s += red[threadIdx.x][wv];
       partial[(long long)(i0 + threadIdx.x) * G + blockIdx.x] = s;
