@@ -261,3 +261,19 @@ def test_coarse_multi_rhs_gmres_and_errors(st):
         C.apply_multi(short, torch.empty((2, n), dtype=torch.float64, device="cuda"))
     with pytest.raises(st.StkktError):
         C.apply_multi(Xd, Xd)
+
+
+def test_coarse_lu_multi_rhs_injection(st):
+    """Several right-hand sides with the injection restriction: columns against
+    the oracle, and bit for bit equal to the one-vector path (FP64 blocks take
+    the same matrix-core pass for one vector)."""
+    prob, fac, _ = case("cube8x16")
+    op = st.KKTOperator(prob)
+    C = st.Coarse(op, fac, method=st.COARSE_LU, restrict=st.RESTRICT_INJECTION)
+    tl = twolevel.TwoLevel(prob, None, None, fac, restrict="injection", coarse="lu")
+    X = np.random.default_rng(33).standard_normal((3, prob.unknowns))
+    Xd = _dev(X)
+    Y = C.apply_multi(Xd)
+    for i in range(3):
+        assert _rel(Y[i].cpu().numpy(), tl.coarse_correction(X[i])) <= 1e-9
+        assert torch.equal(Y[i], C.apply(Xd[i].contiguous()))
