@@ -203,3 +203,35 @@ def test_two_level_requests_share_coarse_level(st, pool):
         assert s.converged and res <= 1e-6
         assert s.iters == sa.iters and torch.equal(x, alone)
     assert mixed[3][1].converged
+
+
+def test_two_coarse_levels_in_one_batch(st, pool):
+    """Two-level requests on two operators, each with its own exact coarse level,
+    served together: the coarse corrections form one group per coarse level and
+    every result is bit for bit the one served alone."""
+    probA, opA, preA, _ = pool["cube8x16"]
+    probB, opB, preB, _ = pool["ragged"]
+    CA = st.Coarse(opA, (2, 2, 2, 2), method=st.COARSE_LU)
+    CB = st.Coarse(opB, (1, 1, 1, 3), method=st.COARSE_LU)
+    items = [(opA, preA, redraw_noise(probA, 4700), CA), (opB, preB, redraw_noise(probB, 4701), CB),
+             (opA, preA, redraw_noise(probA, 4702), CA), (opB, preB, redraw_noise(probB, 4703), CB)]
+
+    def serve(batch):
+        srv = st.Server(restart=30, rtol=1e-6, device_bytes=1 << 28, max_active=8)
+        tickets = [srv.submit(op, pre, d, coarse=c) for op, pre, d, c in batch]
+        out = {}
+        while len(out) < len(tickets):
+            srv.step()
+            for t in tickets:
+                if t not in out:
+                    r = srv.poll(t)
+                    if r is not None:
+                        out[t] = r
+        return [out[t] for t in tickets]
+
+    mixed = serve(items)
+    for i, it in enumerate(items):
+        x, s = mixed[i]
+        alone, sa = serve([it])[0]
+        _say(f"  request {i}: {s.iters} its (alone {sa.iters})")
+        assert s.converged and s.iters == sa.iters and torch.equal(x, alone)
