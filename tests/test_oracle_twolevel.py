@@ -103,3 +103,78 @@ def test_two_level_gmres_ras_coarse_solver():
     x, st2 = krylov.gmres(A, tl, b, restart=50, rtol=1e-6, flexible=True)
     assert st2.converged and st2.iters < st1.iters
     assert np.linalg.norm(b - F @ x) <= 1e-6 * np.linalg.norm(b)
+
+
+def test_gmres_ras_coarse_exact_when_coarse_ras_is_exact():
+    """2 x 2 x 2 coarse nodes: one coarse subdomain's ILU(0) is the exact block
+    LU (every spatial pair is a stencil neighbour), so the paper's coarse
+    solver -- GMRES right-preconditioned by that RAS -- must return
+    F_c^{-1} r after its first step, equal to the exact block solve."""
+    prob = make_custom((2, 2, 2), 8, 6, faces=0, sensors=np.array([0]))
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    R = ras.RAS(prob, (1, 1, 2, 2), 1, terms=terms)
+    fac = (2, 2, 2, 2)
+    gm = twolevel.TwoLevel(prob, R.apply, lambda v: F @ v, fac, coarse="gmres_ras", coarse_parts=(1, 1, 1, 1),
+                           coarse_overlap=1, coarse_maxit=4, coarse_rtol=0.1)
+    lu = twolevel.TwoLevel(prob, R.apply, lambda v: F @ v, fac, coarse="lu")
+    assert gm.cprob.n == (1, 1, 1) and gm.cprob.M == 4
+    r = np.random.default_rng(3).standard_normal(gm.Fc.shape[0])
+    xg, xl = gm.coarse.solve(r), lu.coarse.solve(r)
+    assert np.linalg.norm(xg - xl) <= 1e-12 * np.linalg.norm(xl)
+    assert np.linalg.norm(gm.Fc @ xg - r) <= 1e-12 * np.linalg.norm(r)
+
+
+def _min_residual_iterates(A, Minv, r, kmax):
+    """Iterates of right-preconditioned GMRES from zero, by brute force: the
+    k-th minimises |r - A Minv u| over u in span{r, (A Minv) r, ...,
+    (A Minv)^{k-1} r}.  The basis is orthonormalised by numpy's QR and the
+    least-squares problem solved by lstsq (no Arnoldi, no Givens)."""
+    Q = (r / np.linalg.norm(r))[:, None]
+    out = []
+    for k in range(1, kmax + 1):
+        AMQ = np.stack([A(Minv(Q[:, i])) for i in range(k)], axis=1)
+        c = np.linalg.lstsq(AMQ, r, rcond=None)[0]
+        x = Minv(Q @ c)
+        out.append((x, np.linalg.norm(r - A(x))))
+        Q = np.linalg.qr(np.concatenate([Q, AMQ[:, -1:]], axis=1))[0]
+    return out
+
+
+def test_gmres_ras_coarse_stopping_rule():
+    """The paper's coarse solve (Section 4): GMRES from a zero guess with
+    relative tolerance 0.1 and at most 4 steps.  On a coarse mesh where the
+    coarse RAS is inexact, the result must be the brute-force minimal-residual
+    iterate of the first step k whose residual |r - F_c x_k| (F_c assembled
+    independently) is within rtol |r|, else of step 4: for rtol 0.1, for
+    tolerances placed between consecutive residuals (stop at exactly k = 1..4),
+    and for a tolerance no step reaches (4 steps, not more); with rtol 1 the
+    zero guess is returned."""
+    nn = 9
+    idx = [2, 4, 6]
+    sens = np.array([i + nn * (j + nn * k) for k in idx for j in idx for i in idx], dtype=np.int32)
+    prob = make_custom((8, 8, 8), 8, 4, sensors=sens)
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    R = ras.RAS(prob, (2, 2, 2, 2), 1, terms=terms)
+    tl = twolevel.TwoLevel(prob, R.apply, lambda v: F @ v, (2, 2, 2, 2), coarse="gmres_ras",
+                           coarse_parts=(2, 2, 1, 2), coarse_overlap=1, coarse_maxit=4, coarse_rtol=0.1)
+    cs = tl.coarse
+    Fc = kkt.assemble(tl.cprob)
+    b = kkt.rhs(prob)
+    # a restricted random vector (no step reaches 0.1) and the restricted b (step 1 does)
+    for r in (tl.R @ np.random.default_rng(5).standard_normal(F.shape[0]), tl.R @ b):
+        rn = np.linalg.norm(r)
+        its = _min_residual_iterates(lambda v: Fc @ v, cs.R.apply, r, 4)
+        res = [rho / rn for _, rho in its]
+        assert all(res[k + 1] < (1 - 1e-3) * res[k] for k in range(3)) and res[3] > 1e-4   # decreasing, inexact
+        cases = [(0.1, next((k for k in range(4) if res[k] <= 0.1), 3)), (1e-9, 3)]
+        cases += [(np.sqrt(res[k] * res[k - 1]), k) for k in range(1, 4)]
+        for rtol, k in cases:
+            cs.rtol = rtol
+            x = cs.solve(r)
+            xk, rho = its[k]
+            assert np.linalg.norm(x - xk) <= 1e-8 * np.linalg.norm(xk), (rtol, k)
+            assert abs(np.linalg.norm(r - Fc @ x) - rho) <= 1e-8 * rn, (rtol, k)
+        cs.rtol = 1.0    # the zero guess already meets the tolerance: no step
+        assert not np.any(cs.solve(r))
