@@ -249,7 +249,8 @@ def make_coarse(st, op, fac, how, precision):
     paper's coarse GMRES(4) to 0.1 with a coarse RAS 2x2x2x4, overlap 1."""
     if how == "lu":
         return st.Coarse(op, fac, method=st.COARSE_LU, precision=precision)
-    return st.Coarse(op, fac, (2, 2, 2, 4), overlap=1, maxit=4, rtol=0.1, precision=precision)
+    return st.Coarse(op, fac, (2, 2, 2, 4), overlap=1, maxit=4, rtol=0.1, precision=precision,
+                     method=st.COARSE_GMRES_RAS)
 
 
 def run_coarse(args):
@@ -321,7 +322,7 @@ def run_overlap(args):
     prec = st.F64 if args.precision == "f64" else st.F32
     op = st.KKTOperator(prob)
     parts, fac = (4, 4, 4, 4), (2, 2, 2, 2)
-    C = st.Coarse(op, fac, parts, overlap=1, maxit=4, rtol=0.1, precision=prec)
+    C = st.Coarse(op, fac, parts, overlap=1, maxit=4, rtol=0.1, precision=prec, method=st.COARSE_GMRES_RAS)
     b = op.rhs(redraw_noise(prob, 77))
     rows = []
     for delta in (1, 2, 4):
@@ -515,7 +516,8 @@ def main():
             coarse = st.Coarse(op, cfg.coarse_factor, method=st.COARSE_LU, precision=prec)
         else:
             # coarse RAS with as many subdomains as the fine level, overlap 1; GMRES(4) to 0.1 (Section 4)
-            coarse = st.Coarse(op, cfg.coarse_factor, cfg.parts, overlap=1, maxit=4, rtol=0.1, precision=prec)
+            coarse = st.Coarse(op, cfg.coarse_factor, cfg.parts, overlap=1, maxit=4, rtol=0.1, precision=prec,
+                                  method=st.COARSE_GMRES_RAS)
         torch.cuda.synchronize()
         t_coarse = time.perf_counter() - t0
     print(f"[bench] assemble {t_asm*1e3:.1f} ms, ras_setup {t_setup*1e3:.1f} ms, coarse_setup {t_coarse*1e3:.1f} ms, "

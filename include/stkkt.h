@@ -116,23 +116,23 @@ typedef struct {
  * I_h^c = (I_c^h)^T or injection, coarse KKT system F_c rediscretised on the
  * coarse mesh (element coefficient = mean of the fine ones it covers; every
  * sensor must sit on a coarse node).  F_c^{-1} is applied by one of:
+ *  - STKKT_COARSE_LU (the default, value 0), exactly: F_c is block tridiagonal
+ *    in time, so S_0 = D_0, S_k = D_k - L_k S_{k-1}^{-1} U_{k-1}; the setup
+ *    forms and inverts every S_k densely (FP64 Gauss-Jordan with partial
+ *    pivoting) and keeps S_k^{-1} and S_k^{-1} U_k in `precision`, using about
+ *    2 (M_c + 1) (3 N_c)^2 elements of device memory (columns padded to a
+ *    multiple of 64 rows); `p`, `overlap`, `maxit`, `rtol` are ignored.
  *  - STKKT_COARSE_GMRES_RAS, as in the paper's experiments (Section 4):
  *    restarted GMRES from a zero guess with relative tolerance `rtol` and at
  *    most `maxit` steps, right-preconditioned by the one-level space-time RAS
- *    of the coarse mesh (`p`, `overlap`, ILU(0); `precision` of its factors);
- *  - STKKT_COARSE_LU, exactly: F_c is block tridiagonal in time, so
- *    S_0 = D_0, S_k = D_k - L_k S_{k-1}^{-1} U_{k-1}; the setup forms and
- *    inverts every S_k densely (FP64 Gauss-Jordan with partial pivoting) and
- *    keeps S_k^{-1} and S_k^{-1} U_k in `precision`, using about
- *    2 (M_c + 1) (3 N_c)^2 elements of device memory (columns padded to a
- *    multiple of 64 rows); `p`, `overlap`, `maxit`, `rtol` are ignored.
+ *    of the coarse mesh (`p`, `overlap`, ILU(0); `precision` of its factors).
  * The coarse mesh may have at most 512 nodes along x. */
-#define STKKT_COARSE_GMRES_RAS 0
-#define STKKT_COARSE_LU 1
+#define STKKT_COARSE_LU 0
+#define STKKT_COARSE_GMRES_RAS 1
 typedef struct {
   int32_t factor[4];        /* coarsening in x, y, z, t                    */
-  int32_t method;           /* STKKT_COARSE_GMRES_RAS or STKKT_COARSE_LU    */
-  int32_t precision;        /* STKKT_F64 or STKKT_F32 coarse ILU factors    */
+  int32_t method;           /* STKKT_COARSE_LU (0) or _GMRES_RAS (1)      */
+  int32_t precision;        /* STKKT_F64 or STKKT_F32 coarse blocks/factors */
   int32_t restrict_kind;    /* STKKT_RESTRICT_TRANSPOSE or _INJECTION       */
   int32_t p[4];             /* coarse subdomains in x, y, z, t              */
   int32_t overlap;          /* coarse overlap (paper: 1)                    */
@@ -140,7 +140,12 @@ typedef struct {
   double rtol;              /* coarse GMRES relative tolerance (paper: 0.1) */
 } coarse_params_t;
 
-/* Restarted right-preconditioned GMRES / FGMRES (Sections 3.2 and 4). */
+/* Restarted right-preconditioned GMRES / FGMRES (Sections 3.2 and 4).
+ * Always on, with no switch: the Arnoldi basis is orthogonalised by classical
+ * Gram-Schmidt applied twice (CGS2, FP64), the Hessenberg least-squares
+ * problem is solved by Givens rotations (FP64), and when the Givens estimate
+ * meets rtol the true residual ||b - F x|| is computed in FP64 and decides
+ * convergence (the cycle restarts if it does not meet rtol). */
 typedef struct {
   int32_t restart;          /* Krylov dimension per cycle (>= 1)        */
   int32_t maxit;            /* total Arnoldi steps allowed               */
@@ -183,7 +188,12 @@ int kkt_assemble(const kkt_problem_t *p, const kkt_alloc_t *al, void *stream, kk
  * data_host: [nt+1][n_sensors] host array; b: device. */
 int kkt_rhs(const kkt_op_t *op, const double *data_host, void *stream, double *b);
 
-/* y = F_h x (device vectors, may not alias). */
+/* y = F_h x: the space-time KKT operator of Section 3.1 with the block
+ * structure of Appendix A (block tridiagonal in time; per level and spatial
+ * node the (C, G, f) rows of the state, adjoint and source equations), applied
+ * matrix-free.  x, y: device vectors of kkt_size(op) doubles in the layout
+ * above; they may not alias.  Stream-ordered, no synchronisation.  Errors:
+ * STKKT_EINVAL for NULL arguments. */
 int kkt_matvec(const kkt_op_t *op, const double *x, double *y, void *stream);
 
 /* Number of unknowns 3 N (M+1). */
@@ -192,7 +202,15 @@ int64_t kkt_size(const kkt_op_t *op);
 /* Partition, extract the subdomain matrices and factor them (ILU(0)). */
 int ras_setup(const kkt_op_t *op, const ras_params_t *rp, void *stream, ras_t **out);
 
-/* z = sum_i (R^0_i)^T ILU_i^{-1} R^delta_i r  (device vectors, no aliasing). */
+/* One-level space-time restricted additive Schwarz (Section 3.2, the
+ * one-level preconditioner; restricted form of Cai and Sarkis):
+ *   z = sum_i (R^0_i)^T ILU_i^{-1} R^delta_i r,
+ * i.e. every subdomain gathers r on its overlapped box, solves with its ILU(0)
+ * factors (forward then backward block sweep, in the factors' precision) and
+ * writes z on the nodes it owns only.  r, z: device vectors of kkt_size(op)
+ * doubles; they may not alias.  Uses the handle's local vectors (calls on one
+ * handle must be ordered on one stream).  Stream-ordered, no synchronisation.
+ * Errors: STKKT_EINVAL for NULL arguments. */
 int ras_apply(const ras_t *ras, const double *r, double *z, void *stream);
 
 /* Subdomain count, and the box table: per subdomain 16 int32

@@ -23,7 +23,7 @@ OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, EBREAKDOWN = 0, 1, -1, -2, -3, -4
 DTO, OTD = 0, 1
 F64, F32 = 0, 1
 RESTRICT_TRANSPOSE, RESTRICT_INJECTION = 0, 1
-COARSE_GMRES_RAS, COARSE_LU = 0, 1
+COARSE_LU, COARSE_GMRES_RAS = 0, 1
 
 
 class StkktError(RuntimeError):
@@ -308,13 +308,14 @@ class RAS:
 class Coarse:
     """Coarse space-time level of the two-level preconditioner.
 
-    factor: coarsening in (x, y, z, t).  method COARSE_GMRES_RAS: F_c^{-1} is
-    `maxit` steps of GMRES (relative tolerance `rtol`) from zero with the coarse
-    mesh's RAS (parts, overlap); COARSE_LU: exact block elimination in time.
+    factor: coarsening in (x, y, z, t).  method COARSE_LU (default): exact
+    block elimination in time; COARSE_GMRES_RAS: F_c^{-1} is at most `maxit`
+    steps of GMRES (relative tolerance `rtol`) from zero with the coarse mesh's
+    RAS (parts, overlap), as in the paper's experiments.
     """
 
     def __init__(self, op: KKTOperator, factor, parts=(1, 1, 1, 1), overlap=1, maxit=4, rtol=0.1, precision=F64,
-                 restrict=RESTRICT_TRANSPOSE, method=COARSE_GMRES_RAS, stream=None):
+                 restrict=RESTRICT_TRANSPOSE, method=COARSE_LU, stream=None):
         self.op = op
         self.alloc = op.alloc
         cp = _CoarseParams()

@@ -366,6 +366,12 @@ int BatchEngine::admit(const kkt_op *op, const ras *R, const coarse *C) {
   for (; it != free_.end(); ++it)
     if (it->second >= need) break;
   if (it == free_.end()) return -1;
+  // everything that can fail (allocations, host vectors) is done before the
+  // slot and the vector range are taken, so a failure leaves the engine as it was
+  DevBuf local(al_, ras_local_bytes(R));
+  DevBuf y2 = C ? DevBuf(al_, sizeof(double) * n) : DevBuf();
+  std::vector<double> Hm((size_t)(m_ + 1) * m_, 0.0), g(m_ + 1, 0.0), cs(m_, 0.0), sn(m_, 0.0);
+  STKKT_HIP(hipMemsetAsync(local.ptr, 0, local.bytes, s_));
   const long long off = it->first, len = it->second;
   free_.erase(it);
   if (len > need) free_[off + need] = len - need;
@@ -377,13 +383,12 @@ int BatchEngine::admit(const kkt_op *op, const ras *R, const coarse *C) {
   sl.C = C;
   sl.voff = off;
   sl.n = n;
-  sl.local = DevBuf(al_, ras_local_bytes(R));
-  STKKT_HIP(hipMemsetAsync(sl.local.ptr, 0, sl.local.bytes, s_));
-  if (C) sl.y2 = DevBuf(al_, sizeof(double) * n);
-  sl.Hm.assign((size_t)(m_ + 1) * m_, 0.0);
-  sl.g.assign(m_ + 1, 0.0);
-  sl.cs.assign(m_, 0.0);
-  sl.sn.assign(m_, 0.0);
+  sl.local = std::move(local);
+  sl.y2 = std::move(y2);
+  sl.Hm = std::move(Hm);
+  sl.g = std::move(g);
+  sl.cs = std::move(cs);
+  sl.sn = std::move(sn);
   sl.t0 = std::chrono::steady_clock::now();
   ++nused_;
   dirty_ = true;
@@ -720,7 +725,13 @@ void BatchEngine::cycle(std::vector<int> &finished) {
       if (!std::isfinite(sl.bnorm) || !std::isfinite(sl.beta)) {
         sl.breakdown = true;
         finish(i);
-      } else if (sl.bnorm == 0.0 || sl.beta == 0.0 || (sp_.fixed_iters == 0 && sl.beta <= sl.target)) {
+      } else if (sl.bnorm == 0.0) {
+        // F x = 0 has the solution x = 0 whatever x0 was (as kkt_solve returns)
+        fill_zero(Xd + sl.voff, sl.n, s_);
+        sl.st.rel_res_true = sl.st.rel_res_est = 0.0;
+        sl.st.converged = 1;
+        finish(i);
+      } else if (sl.beta == 0.0 || (sp_.fixed_iters == 0 && sl.beta <= sl.target)) {
         sl.st.converged = 1;
         finish(i);
       }

@@ -100,8 +100,13 @@ void server_step(kkt_server *srv, int32_t *n_running, int32_t *n_pending) {
     if (srv->member_used + q.bytes > srv->member_budget) break;
     const int slot = e.admit(q.op, q.R, q.C);
     if (slot < 0) break;
-    rhs_device(q.op, q.data.data(), srv->s, e.b_of(slot));
-    fill_zero(e.x_of(slot), e.size_of(slot), srv->s);
+    try {
+      rhs_device(q.op, q.data.data(), srv->s, e.b_of(slot));
+      fill_zero(e.x_of(slot), e.size_of(slot), srv->s);
+    } catch (...) {
+      e.release(slot);   // the request stays queued; the slot is free again
+      throw;
+    }
     q.t_admit = std::chrono::steady_clock::now();
     srv->member_used += q.bytes;
     srv->state[q.ticket] = 1;
@@ -112,7 +117,7 @@ void server_step(kkt_server *srv, int32_t *n_running, int32_t *n_pending) {
   if (e.active() > 0) e.cycle(fin);
   const auto now = std::chrono::steady_clock::now();
   for (int slot : fin) {
-    kkt_server::Req &q = srv->running[slot];
+    kkt_server::Req &q = srv->running.at(slot);
     STKKT_HIP(hipMemcpyAsync(q.x_out, e.x_of(slot), sizeof(double) * e.size_of(slot), hipMemcpyDeviceToDevice,
                              srv->s));
     kkt_stats_t st = e.stats(slot);

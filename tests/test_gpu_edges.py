@@ -61,12 +61,14 @@ def test_exact_initial_guess_single(st, pair):
 @pytest.mark.parametrize("graph", [False, True])
 def test_zero_rhs_and_exact_guess_in_batch(st, pair, graph):
     """A zero right-hand side and an exact initial guess leave a batch at once,
-    without changing the result of the member that iterates."""
+    without changing the result of the member that iterates.  The zero-b member
+    starts from x0 = 3 and must come back with the solution x = 0, as kkt_solve
+    returns it."""
     (p0, op0, pre0, F0, xs0), (p1, op1, pre1, F1, xs1) = pair
     b0 = torch.zeros(op0.n, dtype=torch.float64, device="cuda")
     x_exact = torch.from_numpy(xs1.copy()).to("cuda")
     xs, sts = st.solve_batch([op0, op1, op0], [pre0, pre1, pre0], [b0, op1.b, op0.b],
-                             [torch.zeros_like(b0), x_exact, torch.zeros_like(b0)], restart=12, rtol=1e-6,
+                             [torch.full_like(b0, 3.0), x_exact, torch.zeros_like(b0)], restart=12, rtol=1e-6,
                              graph=graph)
     _say(f"  batch: iters {[s.iters for s in sts]}")
     assert sts[0].converged and sts[0].iters == 0 and torch.count_nonzero(xs[0]).item() == 0

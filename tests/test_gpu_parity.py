@@ -202,7 +202,7 @@ def test_mixed_precision_solve(st, name, parts, delta, two_level):
     _say(f"case {name}: mixed precision, two-level={two_level}")
     op = st.KKTOperator(prob)
     pre = st.RAS(op, parts, delta, precision=st.F32)
-    C = st.Coarse(op, (2, 2, 2, 2), (2, 2, 2, 2), precision=st.F32) if two_level else None
+    C = st.Coarse(op, (2, 2, 2, 2), (2, 2, 2, 2), precision=st.F32, method=st.COARSE_GMRES_RAS) if two_level else None
     terms = kkt.kkt_terms(prob)
     F = kkt.assemble(prob, terms=terms).tocsc()
     b = kkt.rhs(prob)

@@ -133,7 +133,7 @@ def test_admission_respects_memory(st, pool):
 
 def test_two_level_request_in_mix(st, pool):
     prob, op, pre, parts = pool["cube8x16"]
-    C = st.Coarse(op, (2, 2, 2, 2), (2, 2, 2, 2), overlap=1, maxit=4, rtol=0.1)
+    C = st.Coarse(op, (2, 2, 2, 2), (2, 2, 2, 2), overlap=1, maxit=4, rtol=0.1, method=st.COARSE_GMRES_RAS)
     srv = st.Server(restart=30, rtol=1e-6, device_bytes=1 << 28, max_active=8)
     data = redraw_noise(prob, 4200)
     t2 = srv.submit(op, pre, data, coarse=C)
@@ -235,3 +235,54 @@ def test_two_coarse_levels_in_one_batch(st, pool):
         alone, sa = serve([it])[0]
         _say(f"  request {i}: {s.iters} its (alone {sa.iters})")
         assert s.converged and s.iters == sa.iters and torch.equal(x, alone)
+
+
+def test_admission_allocation_failure_keeps_server_usable(st, pool):
+    """The device allocation of an admission (the request's RAS local vectors)
+    is refused: the step fails with ENOMEM, the request stays queued, no slot
+    or vector range is lost, and once memory is available again the request is
+    served with the same result as on a server that never failed."""
+    prob, op, pre, parts = pool["cube8x16"]
+    data = redraw_noise(prob, 4321)
+    alloc = st.TorchAllocator()
+    grant = alloc._alloc_cb
+    limit = {"bytes": None}
+
+    def limited(nbytes, ctx):
+        if limit["bytes"] is not None and alloc.bytes_live + nbytes > limit["bytes"]:
+            return None
+        return grant(nbytes, ctx)
+
+    alloc._limited_cb = st.ALLOC_FN(limited)
+    alloc.struct = st._Alloc(alloc._limited_cb, alloc._free_cb, None)
+    srv = st.Server(restart=20, rtol=1e-6, device_bytes=1 << 28, max_active=4, allocator=alloc)
+    torch.cuda.synchronize()
+    limit["bytes"] = alloc.bytes_live          # nothing more may be allocated
+    t = srv.submit(op, pre, data)
+    for _ in range(2):                          # the failure repeats, it does not corrupt the server
+        with pytest.raises(st.StkktError) as e:
+            srv.step()
+        assert e.value.code == st.ENOMEM
+        assert srv.poll(t) is None
+    limit["bytes"] = None
+    res = None
+    for _ in range(20):
+        running, pending = srv.step()
+        res = srv.poll(t)
+        if res is not None:
+            break
+    assert res is not None
+    x, s = res
+    ref = st.Server(restart=20, rtol=1e-6, device_bytes=1 << 28, max_active=4)
+    xr, sr = run(st, ref, {"cube8x16": pool["cube8x16"]}, [("cube8x16", data)])[0]
+    _say(f"  after ENOMEM: {s.iters} its (fresh server {sr.iters})")
+    assert s.converged and s.iters == sr.iters
+    assert np.array_equal(x.cpu().numpy(), xr.cpu().numpy())
+    # a second request on the recovered server runs as well
+    t2 = srv.submit(op, pre, data)
+    for _ in range(20):
+        srv.step()
+        r2 = srv.poll(t2)
+        if r2 is not None:
+            break
+    assert r2 is not None and np.array_equal(r2[0].cpu().numpy(), xr.cpu().numpy())

@@ -71,7 +71,7 @@ def test_coarse_correction(st, name, restrict, rtol):
     _say(f"case {name}: factor {fac} coarse parts {cparts} restrict {restrict} rtol {rtol}")
     op = st.KKTOperator(prob)
     kind = st.RESTRICT_TRANSPOSE if restrict == "transpose" else st.RESTRICT_INJECTION
-    C = st.Coarse(op, fac, cparts, overlap=1, maxit=4, rtol=rtol, restrict=kind)
+    C = st.Coarse(op, fac, cparts, overlap=1, maxit=4, rtol=rtol, restrict=kind, method=st.COARSE_GMRES_RAS)
     F = kkt.assemble(prob)
     tl = twolevel.TwoLevel(prob, None, None, fac, restrict=restrict, coarse="gmres_ras", coarse_parts=cparts,
                            coarse_overlap=1, coarse_maxit=4, coarse_rtol=rtol)
@@ -91,7 +91,7 @@ def test_two_level_fgmres_parity(st, name, restart):
     _say(f"case {name}: two-level FGMRES({restart}), fine parts {parts}")
     op = st.KKTOperator(prob)
     pre = st.RAS(op, parts, 1)
-    C = st.Coarse(op, fac, cparts, overlap=1, maxit=4, rtol=0.1)
+    C = st.Coarse(op, fac, cparts, overlap=1, maxit=4, rtol=0.1, method=st.COARSE_GMRES_RAS)
     x, s = st.solve(op, pre, coarse=C, restart=restart, rtol=1e-6, flexible=True)
     terms = kkt.kkt_terms(prob)
     F = kkt.assemble(prob, terms=terms)
@@ -123,7 +123,7 @@ def test_two_level_cuts_iterations(st):
     op = st.KKTOperator(prob)
     pre = st.RAS(op, (3, 3, 3, 4), 1)
     _, s1 = st.solve(op, pre, restart=50, rtol=1e-6)
-    C = st.Coarse(op, (3, 3, 3, 4), (2, 2, 2, 2), overlap=1, maxit=4, rtol=0.1)
+    C = st.Coarse(op, (3, 3, 3, 4), (2, 2, 2, 2), overlap=1, maxit=4, rtol=0.1, method=st.COARSE_GMRES_RAS)
     x, s2 = st.solve(op, pre, coarse=C, restart=50, rtol=1e-6, flexible=True)
     _say(f"  one-level {s1.iters} its, two-level {s2.iters} its")
     assert s1.converged and s2.converged and s2.iters < s1.iters
@@ -136,16 +136,16 @@ def test_coarse_errors(st):
     prob, fac, cparts = case("cube8x16")
     op = st.KKTOperator(prob)
     with pytest.raises(st.StkktError) as e:
-        st.Coarse(op, (3, 2, 2, 2), cparts)          # 3 does not divide 8
+        st.Coarse(op, (3, 2, 2, 2), cparts, method=st.COARSE_GMRES_RAS)          # 3 does not divide 8
     assert e.value.code == st.EINVAL
     n = (8, 8, 8)
     odd = make_custom(n, 8, 5, sensors=np.array([3 + 9 * (2 + 9 * 2)], dtype=np.int32))
     op_odd = st.KKTOperator(odd)
     with pytest.raises(st.StkktError):
-        st.Coarse(op_odd, (2, 2, 2, 2), cparts)      # sensor at x = 3 is not a coarse node
+        st.Coarse(op_odd, (2, 2, 2, 2), cparts, method=st.COARSE_GMRES_RAS)      # sensor at x = 3 is not a coarse node
     with pytest.raises(st.StkktError):
-        st.Coarse(op, fac, cparts, maxit=0)
-    C = st.Coarse(op, fac, cparts)
+        st.Coarse(op, fac, cparts, maxit=0, method=st.COARSE_GMRES_RAS)
+    C = st.Coarse(op, fac, cparts, method=st.COARSE_GMRES_RAS)
     other = st.KKTOperator(prob)
     pre_other = st.RAS(other, (2, 2, 2, 2), 1)
     with pytest.raises(st.StkktError):
@@ -249,7 +249,7 @@ def test_coarse_multi_rhs_gmres_and_errors(st):
     as apply); q = 0 does nothing; short strides and overlapping operands fail."""
     prob, fac, cparts = case("cube8x16")
     op = st.KKTOperator(prob)
-    C = st.Coarse(op, fac, cparts, overlap=1, maxit=4, rtol=0.1)
+    C = st.Coarse(op, fac, cparts, overlap=1, maxit=4, rtol=0.1, method=st.COARSE_GMRES_RAS)
     n = prob.unknowns
     Xd = _dev(np.random.default_rng(32).standard_normal((3, n)))
     Y = C.apply_multi(Xd)
