@@ -20,8 +20,6 @@ from dataclasses import dataclass, field
 from typing import Optional
 
 import numpy as np
-import scipy.sparse as sp
-import scipy.sparse.linalg as spla
 
 DTO = 0
 OTD = 1
@@ -163,75 +161,52 @@ def _dirichlet_nodes(n, faces):
     return m
 
 
-def _forward_fv(n, length, M, T, coef, v, src, faces, sensor_node, substeps=2):
-    """Observation generator: node-centred finite volumes + Crank-Nicolson substeps.
+def _forward_fv(n, length, M, T, coef, v, src, faces, sensor_node, substeps=2, refine=2):
+    """Observation generator: the model of eq. (1) forward-solved on a finer mesh.
 
-    Deliberately a different scheme from the inversion's discretisation (the paper
-    also produces its data with a separate forward solve).  Diffusion uses dual
-    cells (half cells on the boundary, zero flux through Neumann faces) with a(x)
-    at edge midpoints; convection -v.grad C uses central differences inside and
-    one-sided ones on boundary nodes.  Returns C at the sensor nodes for t^m,
-    m = 0..M, with C(.,0) = 0.
+    Node-centred finite volumes on the mesh refined ``refine`` times per axis
+    (every inversion node is a node of it), advanced by the Douglas
+    alternating-direction scheme with ``refine * substeps`` steps per time
+    step of the inversion (C implementation in ``fvgen.c``).  Diffusion uses
+    dual cells with a(x) at edge midpoints, convection -v.grad C central
+    differences inside and one-sided ones on boundary nodes; Dirichlet nodes
+    hold C = 0.  A different discretisation on a finer mesh than the
+    inversion's, as the paper produces its data (Section 4).  Returns C at the
+    sensor nodes for t^m = m T / M, m = 0..M, with C(., 0) = 0.
     """
-    nn = tuple(k + 1 for k in n)
-    h = [length[d] / n[d] for d in range(3)]
-    N = nn[0] * nn[1] * nn[2]
-    X, Y, Z = _node_coords(n, length)
-    coords = (X, Y, Z)
-    g = np.arange(N)
-    pos = (g % nn[0], (g // nn[0]) % nn[1], g // (nn[0] * nn[1]))
-    stride = (1, nn[0], nn[0] * nn[1])
-    rows, cols, vals = [], [], []
-    diag = np.zeros(N)
+    import ctypes
+    from . import clib
+    r = int(refine)
+    nn = [r * n[d] + 1 for d in range(3)]
+    h = [length[d] / (r * n[d]) for d in range(3)]
+    xs = [np.arange(nn[d]) * h[d] for d in range(3)]
+    mids = [0.5 * (xs[d][:-1] + xs[d][1:]) for d in range(3)]
+    amid = []
     for d in range(3):
-        w = np.where((pos[d] == 0) | (pos[d] == nn[d] - 1), 0.5, 1.0)
-        lo = g[pos[d] < nn[d] - 1]
-        hi = lo + stride[d]
-        midpt = [0.5 * (coords[e][lo] + coords[e][hi]) for e in range(3)]
-        a_mid = coef(*midpt) if coef is not None else np.ones(lo.size)
-        c_lo = a_mid / (h[d] ** 2 * w[lo])
-        c_hi = a_mid / (h[d] ** 2 * w[hi])
-        rows += [lo, hi]
-        cols += [hi, lo]
-        vals += [c_lo, c_hi]
-        np.subtract.at(diag, lo, c_lo)
-        np.subtract.at(diag, hi, c_hi)
-        vd = float(v[d])
-        if vd != 0.0:
-            inner_lo = w[lo] == 1.0
-            inner_hi = w[hi] == 1.0
-            # row hi gets +v/(2h) C_lo (central) or +v/h C_lo (one-sided, hi on the high face)
-            rows.append(hi)
-            cols.append(lo)
-            vals.append(np.where(inner_hi, vd / (2 * h[d]), vd / h[d]))
-            # row lo gets -v/(2h) C_hi (central) or -v/h C_hi (one-sided, lo on the low face)
-            rows.append(lo)
-            cols.append(hi)
-            vals.append(np.where(inner_lo, -vd / (2 * h[d]), -vd / h[d]))
-            np.add.at(diag, lo[~inner_lo], vd / h[d])
-            np.add.at(diag, hi[~inner_hi], -vd / h[d])
-    rows.append(g)
-    cols.append(g)
-    vals.append(diag)
-    L = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
-    dmask = _dirichlet_nodes(n, faces)
-    keep = sp.diags((~dmask).astype(np.float64))
-    L = (keep @ L @ keep).tocsr()
-    dt = T / (M * substeps)
-    I = sp.identity(N, format="csr")
-    lu = spla.splu((I - 0.5 * dt * L).tocsc(), permc_spec="MMD_AT_PLUS_A")
-    rhs_op = (I + 0.5 * dt * L).tocsr()
-    C = np.zeros(N)
-    out = np.zeros((M + 1, len(sensor_node)))
-    f_old = src(X, Y, Z, 0.0) * (~dmask)
-    step = 0
-    for m in range(1, M + 1):
-        for _ in range(substeps):
-            step += 1
-            f_new = src(X, Y, Z, step * dt) * (~dmask)
-            C = lu.solve(rhs_op @ C + 0.5 * dt * (f_old + f_new))
-            f_old = f_new
-        out[m] = C[sensor_node]
+        ax = [mids[e] if e == d else xs[e] for e in range(3)]
+        Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+        a = coef(X.ravel(), Y.ravel(), Z.ravel()) if coef is not None else np.ones(X.size)
+        amid.append(np.ascontiguousarray(a, dtype=np.float64))
+    dmask = np.ascontiguousarray(_dirichlet_nodes(tuple(k - 1 for k in nn), faces).astype(np.uint8))
+    NX, NY = n[0] + 1, n[1] + 1
+    sn = np.asarray(sensor_node, dtype=np.int64)
+    i, j, k = sn % NX, (sn // NX) % NY, sn // (NX * NY)
+    sens = np.ascontiguousarray(r * i + nn[0] * (r * j + nn[1] * r * k), dtype=np.int32)
+    out = np.zeros((M + 1, sens.size))
+    nsteps = M * r * substeps
+    P = ctypes.c_void_p
+    arr = lambda a: a.ctypes.data_as(P)
+    nn_c = np.array(nn, dtype=np.int32)
+    h_c = np.array(h, dtype=np.float64)
+    v_c = np.array(v, dtype=np.float64)
+    p_c = np.ascontiguousarray(src.p, dtype=np.float64)
+    q_c = np.ascontiguousarray(src.q, dtype=np.float64)
+    rc = clib.lib().fv_forward(arr(nn_c), arr(h_c), float(T), int(nsteps), int(r * substeps), arr(amid[0]),
+                               arr(amid[1]), arr(amid[2]), arr(v_c), arr(dmask), int(src.p.shape[0]), arr(p_c),
+                               arr(q_c), float(src.w), float(src.amp), int(bool(src.sin_intensity)),
+                               int(sens.size), arr(sens), arr(out))
+    if rc != 0:
+        raise RuntimeError("fv_forward failed")
     return out
 
 
