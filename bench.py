@@ -1,16 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark: KKT solves/s at FP64 relative residual 1e-6 on one MI355X.
 
-Workload (default): 32^3 hex elements x 64 time steps (7,007,715 unknowns),
-a = exp(0.5 g) with g a seeded smooth random field, two moving Gaussian
-sources, 64 lattice sensors, 1% noise, beta = 1e-4; one-level space-time RAS
-with 4x4x4x8 subdomains, overlap 2, ILU(0); GMRES(50) to rtol 1e-6; FP64.
+Workload (default, the largest single-GPU configuration): 48^3 hex elements x
+96 time steps (34,235,859 unknowns), a = exp(0.5 g) with g a seeded smooth
+random field, two moving Gaussian sources, 125 lattice sensors, 1% noise,
+beta = 1e-4; two-level space-time RAS: fine 4x4x4x8 subdomains, overlap 1,
+ILU(0) with FP64 factors; coarse mesh 12^3 x 24 with the exact block LU in
+time (FP64); FGMRES(50) to rtol 1e-6.
 
 One step = one source-identification solve: new noisy sensor data for the
-same operator (fresh noise draw) -> right-hand side -> GMRES from x0 = 0 to
-rtol 1e-6.  The operator assembly and the ILU(0) setup are done once per
-operator and reported separately (setup_ms).  Inputs are resident in HBM
-when the timed region starts.
+same operator (fresh noise draw) -> right-hand side -> FGMRES from x0 = 0 to
+rtol 1e-6.  The operator assembly, the ILU(0) setup and the coarse setup are
+done once per operator and reported separately (setup_ms).  Inputs are
+resident in HBM when the timed region starts.
 
 Prints one JSON line.  --gpus must be 1: the solver runs on a single GPU.
 """
@@ -68,19 +70,47 @@ def algorithmic_apply_bytes(pre, prob):
     return int(pre.factor_bytes + 24 * int(vol.sum()) + 24 * prob.V)
 
 
-def cpu_baseline(prob, cfg, iters, sample_subs=2, seed=0):
-    """The CPU oracle on a bounded sample of the same workload, scaled to one solve.
+def host_info():
+    """Host CPU: threads this process may use and the CPU model."""
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return threads, model
 
-    Per Arnoldi step the oracle does one preconditioner application (all
-    subdomain ILU(0) solves), one matvec and one CGS2 orthogonalisation; the
-    sample times one full matvec, the subdomain solves of `sample_subs` seeded
-    random subdomains (scaled by the subdomain count) and one CGS2 step at
-    half the restart length, then multiplies by the GPU's iteration count.
+
+def cpu_baseline(prob, cfg, iters, sample_subs=2, seed=0):
+    """The CPU oracle on a bounded sample of the same workload, on all host cores.
+
+    Per Arnoldi step the oracle does one fine RAS application (every
+    subdomain's ILU(0) solve), one matvec (two with the coarse level, whose
+    multiplicative combination needs F y), one CGS2 orthogonalisation and, for
+    two-level, one exact coarse solve (forward and backward block sweeps with
+    the dense LU factors of the Schur complements).  Sample: one full matvec;
+    the ILU(0) factors of `sample_subs` of the largest subdomains, solved by
+    as many threads as the host gives this process at once (the oracle's C
+    solves release the GIL), scaled to every subdomain; one CGS2 step at half
+    the restart length on 1/8 of the vector, scaled by 8; two triangular solve
+    pairs with a dense LU of the coarse block order, scaled to the block
+    sweeps.  The sum, times the GPU's iteration count, gives solves/s.  Setup
+    (factorisations) and the coarse transfers are not included.
     """
     import numpy as np
+    import scipy.linalg as sla
+    from concurrent.futures import ThreadPoolExecutor
     from threadpoolctl import threadpool_limits
     from oracle import kkt, ras as oras
-    with threadpool_limits(limits=1):
+    threads, model = host_info()
+    with threadpool_limits(limits=threads):
         terms = kkt.kkt_terms(prob)
         rng = np.random.default_rng(seed)
         x = rng.standard_normal(prob.unknowns)
@@ -88,60 +118,129 @@ def cpu_baseline(prob, cfg, iters, sample_subs=2, seed=0):
         kkt.apply_terms(terms, x)
         t_mv = time.perf_counter() - t
         subs = oras.subdomains(prob, cfg.parts, cfg.overlap)
-        pick = sorted(rng.choice(len(subs), size=sample_subs, replace=False).tolist())
+        vols = np.array([sd.rows for sd in subs])
+        pick = sorted(np.argsort(-vols, kind="stable")[:sample_subs].tolist())
         R = oras.RAS(prob, cfg.parts, cfg.overlap, terms=terms, subset=pick)
-        t = time.perf_counter()
-        for sid in pick:
-            R.solve_sub(sid, x)
-        t_sub = (time.perf_counter() - t) / len(pick)
-        t_ras = t_sub * len(subs)
+        work = [pick[i % len(pick)] for i in range(threads)]
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(lambda sid: R.solve_sub(sid, x), work))   # warm
+            t = time.perf_counter()
+            list(ex.map(lambda sid: R.solve_sub(sid, x), work))
+            t_round = time.perf_counter() - t
+        rounds = -(-len(subs) // threads)
+        t_ras = t_round * rounds
         j = cfg.restart // 2
-        V = rng.standard_normal((j + 1, prob.unknowns))
-        w = rng.standard_normal(prob.unknowns)
+        n8 = prob.unknowns // 8
+        V = rng.standard_normal((j + 1, n8))
+        w = rng.standard_normal(n8)
         t = time.perf_counter()
         h1 = V @ w
         w = w - V.T @ h1
         h2 = V @ w
         w = w - V.T @ h2
         np.linalg.norm(w)
-        t_orth = time.perf_counter() - t
-    per_iter = t_mv + t_ras + t_orth
+        t_orth = 8 * (time.perf_counter() - t)
+        del V
+        t_coarse, nmv, coarse_txt = 0.0, 1, ""
+        if cfg.coarse_factor:
+            fac = cfg.coarse_factor
+            nb = 3 * np.prod([k // f + 1 for k, f in zip(prob.n, fac[:3])])
+            nlev = prob.M // fac[3] + 1
+            A = rng.standard_normal((nb, nb)) + nb * np.eye(nb)
+            lu = sla.lu_factor(A)
+            rhs = rng.standard_normal(nb)
+            sla.lu_solve(lu, rhs)
+            t = time.perf_counter()
+            for _ in range(2):
+                sla.lu_solve(lu, rhs)
+            t_ls = (time.perf_counter() - t) / 2
+            t_coarse = (2 * nlev - 1) * t_ls
+            nmv = 2
+            coarse_txt = (f", coarse block sweeps {2 * nlev - 1} x {t_ls * 1e3:.1f} ms triangular solve pairs of order "
+                          f"{nb}")
+    per_iter = t_ras + nmv * t_mv + t_orth + t_coarse
     return {
-        "value": 1.0 / (iters * per_iter), "unit": "solves/s", "cores": 1, "kind": "oracle",
-        "sample": (f"one full matvec ({t_mv:.2f} s), ILU(0) solves of {len(pick)} of {len(subs)} subdomains "
-                   f"({t_sub:.2f} s each, scaled x{len(subs)}), one CGS2 step at j={j} ({t_orth:.2f} s); "
-                   f"per-iteration {per_iter:.1f} s x {iters} GPU iterations; factorisation not included"),
+        "value": 1.0 / (iters * per_iter), "unit": "solves/s", "cores": threads, "kind": "oracle",
+        "cpu_model": model,
+        "sample": (f"{nmv} x one full matvec ({t_mv:.2f} s, SciPy, one thread), ILU(0) solves of the {len(pick)} "
+                   f"largest of {len(subs)} subdomains on {threads} threads at once ({t_round:.3f} s per round, "
+                   f"x{rounds} rounds), one CGS2 step at j={j} ({t_orth:.2f} s, scaled from 1/8 of the vector)"
+                   f"{coarse_txt}; per-iteration {per_iter:.2f} s x {iters} GPU iterations; setup (factorisations) "
+                   f"and coarse transfers not included"),
     }
 
 
-def time_kernels(op, pre, reps):
-    """Average ras_apply and kkt_matvec durations, from events recorded on the
-    stream the library launches on (torch's current stream)."""
+def oracle_full_solve(st, seed=0):
+    """A complete oracle solve of the small configuration (8^3 x 16, 37,179
+    unknowns, one-level RAS 2x2x2x2 overlap 1, GMRES(30) to 1e-6), setup and
+    solve timed separately, next to the GPU solving the same system."""
+    import numpy as np
+    import torch
+    from threadpoolctl import threadpool_limits
+    from oracle import kkt, ras as oras, krylov
+    from workloads.generate import make_problem
+    prob, cfg = make_problem("cube8x16")
+    threads, _ = host_info()
+    with threadpool_limits(limits=threads):
+        t = time.perf_counter()
+        terms = kkt.kkt_terms(prob)
+        F = kkt.assemble(prob, terms=terms)
+        b = kkt.rhs(prob)
+        R = oras.RAS(prob, cfg.parts, cfg.overlap, terms=terms)
+        t_setup = time.perf_counter() - t
+        t = time.perf_counter()
+        xo, so = krylov.gmres(lambda v: F @ v, R.apply, b, restart=cfg.restart, rtol=cfg.rtol)
+        t_solve = time.perf_counter() - t
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, cfg.parts, cfg.overlap)
+    x = torch.zeros_like(op.b)
+    times = []
+    for _ in range(6):
+        x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, sg = st.solve(op, pre, op.b, x, restart=cfg.restart, rtol=cfg.rtol)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    err = float(np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
+    pre.close()
+    op.close()
+    return {"workload": "cube8x16: " + WORKLOADS["cube8x16"], "oracle_setup_s": t_setup, "oracle_solve_s": t_solve,
+            "oracle_iters": so.iters, "oracle_solves_per_s": 1.0 / t_solve, "gpu_solve_ms": 1e3 * min(times[1:]),
+            "gpu_iters": sg.iters, "gpu_vs_oracle_rel_l2": err}
+
+
+def time_kernels(op, pre, reps, coarse=None):
+    """Average ras_apply, kkt_matvec and coarse_apply durations, from HIP
+    events recorded on the stream the library launches on (torch's current
+    stream)."""
     import torch
     stream = torch.cuda.current_stream()
     r = torch.randn(op.n, dtype=torch.float64, device="cuda")
     z = torch.empty_like(r)
-    pre.apply(r, z, stream=stream)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(reps):
-        pre.apply(r, z, stream=stream)
-    ev1.record(stream)
-    ev1.synchronize()
-    apply_ms = ev0.elapsed_time(ev1) / reps
-    ev0.record(stream)
-    for _ in range(reps):
-        op.matvec(r, z, stream=stream)
-    ev1.record(stream)
-    ev1.synchronize()
-    return apply_ms, ev0.elapsed_time(ev1) / reps
+
+    def timed(fn):
+        fn()
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+    out = {"ras_apply": timed(lambda: pre.apply(r, z, stream=stream)),
+           "kkt_matvec": timed(lambda: op.matvec(r, z, stream=stream))}
+    if coarse is not None:
+        out["coarse_apply"] = timed(lambda: coarse.apply(r, z, stream=stream))
+    return out
 
 
 def kernels_only(op, pre, prob, reps):
     """Kernel timing plus a plain copy of known size (the reference point that
     converts the FETCH_SIZE / WRITE_SIZE counters to bytes)."""
     import torch
-    apply_ms, matvec_ms = time_kernels(op, pre, reps)
+    km = time_kernels(op, pre, reps)
+    apply_ms, matvec_ms = km["ras_apply"], km["kkt_matvec"]
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
     dst = torch.empty_like(src)
     for _ in range(reps):
@@ -448,15 +547,225 @@ def run_serve(args):
     }
 
 
+def build_single(st, prob, cfg, precision, coarse_how):
+    """Operator, preconditioner and coarse level of one workload, timed."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = st.KKTOperator(prob)
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pre = st.RAS(op, cfg.parts, cfg.overlap, precision=precision)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    coarse, t_coarse = None, 0.0
+    if cfg.coarse_factor:
+        t0 = time.perf_counter()
+        if coarse_how == "lu":
+            coarse = st.Coarse(op, cfg.coarse_factor, method=st.COARSE_LU, precision=precision)
+        else:
+            # coarse RAS with as many subdomains as the fine level, overlap 1; GMRES(4) to 0.1 (Section 4)
+            coarse = st.Coarse(op, cfg.coarse_factor, cfg.parts, overlap=1, maxit=4, rtol=0.1, precision=precision,
+                               method=st.COARSE_GMRES_RAS)
+        torch.cuda.synchronize()
+        t_coarse = time.perf_counter() - t0
+    setup = {"assemble": 1e3 * t_asm, "ras_setup": 1e3 * t_setup, "coarse_setup": 1e3 * t_coarse}
+    print(f"[bench] assemble {t_asm*1e3:.1f} ms, ras_setup {t_setup*1e3:.1f} ms, coarse_setup {t_coarse*1e3:.1f} ms, "
+          f"factors {pre.factor_bytes/1e9:.2f} GB, apply kernel rows per phase {pre.apply_rows}", file=sys.stderr,
+          flush=True)
+    return op, pre, coarse, setup
+
+
+def timed_solves(st, prob, cfg, op, pre, coarse, steps, warmup, flexible, tag, seed0=1000):
+    """warmup + steps solves with fresh noise; per-step wall times (s) and iterations."""
+    import torch
+    from workloads.generate import redraw_noise
+    b = torch.empty(op.n, dtype=torch.float64, device="cuda")
+    x = torch.zeros(op.n, dtype=torch.float64, device="cuda")
+
+    def step(k):
+        op.rhs(redraw_noise(prob, seed0 + k), out=b)
+        x.zero_()
+        return st.solve(op, pre, b, x, coarse=coarse, restart=cfg.restart, rtol=cfg.rtol, maxit=cfg.maxit,
+                        flexible=flexible)[1]
+
+    for w in range(warmup):
+        s = step(w)
+        print(f"[bench] {tag} warmup {w}: {s.iters} its, {s.ms:.1f} ms, res {s.rel_res_true:.2e}", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    times, its = [], []
+    t_start = time.perf_counter()
+    for k in range(steps):
+        ts = time.perf_counter()
+        s = step(warmup + k)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        its.append(s.iters)
+        assert s.converged and s.rel_res_true <= cfg.rtol, s
+        print(f"[bench] {tag} step {k}: {s.iters} its, {times[-1]*1e3:.1f} ms, res {s.rel_res_true:.2e}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return times, its, time.perf_counter() - t_start
+
+
+def apply_kernel_name(pre, prec_name):
+    t = "double" if prec_name == "f64" else "float"
+    rows = pre.apply_rows
+    return f"apply_ring_kernel<{t}, {rows}>" if rows else f"apply_kernel<{t}>"
+
+
+def roofline_of(prob, pre, apply_ms, config, prec_name):
+    apply_bytes = algorithmic_apply_bytes(pre, prob)
+    achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
+    return {"kernel": f"ras_apply ({apply_kernel_name(pre, prec_name)})", "bound": "hbm", "achieved": achieved,
+            "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+            "traffic": counted_traffic(config, prec_name), "algorithmic_bytes": apply_bytes}
+
+
+def mixed_precision_extra(st, prob, cfg, args, op, pre, coarse):
+    """The same workload with FP32 ILU factors and FP32 coarse blocks inside FP64
+    FGMRES: solves/s, and the C and f error of the mixed solution against the
+    plain FP64 one (same data; op, pre, coarse are the FP64 handles) and
+    against a tight FP64 solve (rtol 1e-10).  Closes the FP64 handles before
+    building the FP32 ones."""
+    import numpy as np
+    import torch
+    from workloads.generate import redraw_noise
+    out = {}
+    b = op.rhs(redraw_noise(prob, 999))
+    sols = {}
+
+    def solve(tag, op, pre, coarse, rtol):
+        x = torch.zeros_like(b)
+        _, s = st.solve(op, pre, b, x, coarse=coarse, restart=cfg.restart, rtol=rtol, maxit=cfg.maxit, flexible=True)
+        assert s.converged, (tag, s)
+        sols[tag] = x.cpu().numpy().reshape(-1, 3)
+        out[f"{tag}_iters"] = s.iters
+        out[f"{tag}_rel_res_true"] = s.rel_res_true
+        print(f"[bench] {tag}: {s.iters} its, res {s.rel_res_true:.2e}", file=sys.stderr, flush=True)
+
+    solve("f64", op, pre, coarse, cfg.rtol)
+    solve("f64_tight", op, pre, coarse, 1e-10)
+    pre.close()
+    if coarse is not None:
+        coarse.close()
+    op.close()
+    torch.cuda.empty_cache()
+    op, pre, coarse, setup = build_single(st, prob, cfg, st.F32, args.coarse)
+    solve("mixed", op, pre, coarse, cfg.rtol)
+    times, its, total = timed_solves(st, prob, cfg, op, pre, coarse, 3, 1, True, "mixed", seed0=2000)
+    out.update({"value": 3 / total, "unit": "solves/s", "ms_per_step": 1e3 * total / 3,
+                "gmres_iters": float(np.mean(its)), "setup_ms": setup})
+    km = time_kernels(op, pre, args.apply_reps, coarse)
+    out["kernels_ms"] = km
+    out["roofline"] = roofline_of(prob, pre, km["ras_apply"], args.config, "f32")
+    pre.close()
+    if coarse is not None:
+        coarse.close()
+    op.close()
+    torch.cuda.empty_cache()
+
+    def rel(a, ref, c):
+        return float(np.linalg.norm(a[:, c] - ref[:, c]) / np.linalg.norm(ref[:, c]))
+    out["error"] = {"C_vs_f64": rel(sols["mixed"], sols["f64"], 0), "f_vs_f64": rel(sols["mixed"], sols["f64"], 2),
+                    "C_vs_tight": rel(sols["mixed"], sols["f64_tight"], 0),
+                    "f_vs_tight": rel(sols["mixed"], sols["f64_tight"], 2),
+                    "f64_C_vs_tight": rel(sols["f64"], sols["f64_tight"], 0),
+                    "f64_f_vs_tight": rel(sols["f64"], sols["f64_tight"], 2)}
+    print(f"[bench] mixed vs FP64: {out['error']}", file=sys.stderr, flush=True)
+    return out
+
+
+def one_level_extra(st, args):
+    """cube32x64 (7.0 M unknowns), one-level FP64 GMRES(50): a short run."""
+    import numpy as np
+    import torch
+    from workloads.generate import make_problem
+    prob, cfg = make_problem("cube32x64")
+    op, pre, coarse, setup = build_single(st, prob, cfg, st.F64, "lu")
+    times, its, total = timed_solves(st, prob, cfg, op, pre, None, 3, 1, False, "cube32x64")
+    km = time_kernels(op, pre, args.apply_reps)
+    out = {"workload": "cube32x64: " + WORKLOADS["cube32x64"], "value": 3 / total, "unit": "solves/s",
+           "ms_per_step": 1e3 * total / 3, "gmres_iters": float(np.mean(its)), "setup_ms": setup, "kernels_ms": km,
+           "roofline": roofline_of(prob, pre, km["ras_apply"], "cube32x64", "f64")}
+    pre.close()
+    op.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_kernels_only(args):
+    import paper_1508_06103_amd as st
+    from workloads.generate import make_problem
+    prob, cfg = make_problem(args.config)
+    prec = st.F64 if args.precision == "f64" else st.F32
+    op, pre, coarse, setup = build_single(st, prob, cfg, prec, args.coarse)
+    kernels_only(op, pre, prob, args.apply_reps)
+
+
+def run_single(args):
+    import numpy as np
+    import torch
+    import paper_1508_06103_amd as st
+    from workloads.generate import make_problem
+    t0 = time.perf_counter()
+    prob, cfg = make_problem(args.config)
+    t_gen = time.perf_counter() - t0
+    prec = st.F64 if args.precision == "f64" else st.F32
+    print(f"[bench] {args.config}: {prob.unknowns} unknowns, parts {cfg.parts}, overlap {cfg.overlap}, "
+          f"generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    op, pre, coarse, setup = build_single(st, prob, cfg, prec, args.coarse)
+    flexible = prec == st.F32 or coarse is not None
+    times, its, total = timed_solves(st, prob, cfg, op, pre, coarse, args.steps, args.warmup, flexible, "main")
+    km = time_kernels(op, pre, args.apply_reps, coarse)
+    value = args.steps / total
+    mean_its = float(np.mean(its))
+    coarse_txt = ("exact block LU in time, FP64" if prec == st.F64 else "exact block LU in time, FP32") \
+        if args.coarse == "lu" else "GMRES(4) rtol 0.1 with coarse RAS 4x4x4x8 overlap 1"
+    res = {
+        "metric": "KKT solves/s at FP64 rel. residual 1e-6; p50/p99 latency; GMRES iterations",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == st.F64 else "f64 outer / f32 preconditioner",
+        "data": "synthetic (seeded moving-Gaussian sources, lattice sensors, fresh 1% noise per step)",
+        "config": {"workload": f"{args.config}: " + WORKLOADS[args.config].format(coarse=coarse_txt),
+                   "unknowns": prob.unknowns, "subdomains": pre.nsub, "precision": args.precision},
+        "p50_ms": 1e3 * percentile(times, 50), "p99_ms": 1e3 * percentile(times, 99),
+        "gmres_iters": mean_its, "setup_ms": setup, "kernels_ms": km,
+        "roofline": roofline_of(prob, pre, km["ras_apply"], args.config, args.precision),
+    }
+    if not args.no_extras and args.config == "cube48x96" and args.precision == "f64":
+        res["mixed_f32_preconditioner"] = mixed_precision_extra(st, prob, cfg, args, op, pre, coarse)
+    else:
+        pre.close()
+        if coarse is not None:
+            coarse.close()
+        op.close()
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        if args.config != "cube32x64":
+            res["cube32x64_one_level_f64"] = one_level_extra(st, args)
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(prob, cfg, int(round(mean_its)))
+        print("[bench] oracle full solve of cube8x16", file=sys.stderr, flush=True)
+        res["oracle_full_solve_cube8x16"] = oracle_full_solve(st)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="cube32x64", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="cube48x96", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--apply-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="single mode: skip the FP32-preconditioner run of cube48x96 and the cube32x64 run")
     ap.add_argument("--kernels-only", action="store_true",
                     help="no solves: time ras_apply, kkt_matvec and a plain 1 GiB device copy (for counter runs)")
     ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "coarse", "overlap"],
@@ -477,10 +786,7 @@ def main():
               "sharding across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    import paper_1508_06103_amd as st
-    from workloads.generate import make_problem, redraw_noise
 
     torch.cuda.set_device(0)
     if args.mode == "batch":
@@ -495,95 +801,10 @@ def main():
     if args.mode == "overlap":
         print(json.dumps(run_overlap(args)), flush=True)
         return
-    prob, cfg = make_problem(args.config)
-    prec = st.F64 if args.precision == "f64" else st.F32
-    print(f"[bench] {args.config}: {prob.unknowns} unknowns, parts {cfg.parts}, overlap {cfg.overlap}",
-          file=sys.stderr, flush=True)
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    op = st.KKTOperator(prob)
-    torch.cuda.synchronize()
-    t_asm = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    pre = st.RAS(op, cfg.parts, cfg.overlap, precision=prec)
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
-    coarse, t_coarse = None, 0.0
-    if cfg.coarse_factor:
-        t0 = time.perf_counter()
-        if args.coarse == "lu":
-            coarse = st.Coarse(op, cfg.coarse_factor, method=st.COARSE_LU, precision=prec)
-        else:
-            # coarse RAS with as many subdomains as the fine level, overlap 1; GMRES(4) to 0.1 (Section 4)
-            coarse = st.Coarse(op, cfg.coarse_factor, cfg.parts, overlap=1, maxit=4, rtol=0.1, precision=prec,
-                                  method=st.COARSE_GMRES_RAS)
-        torch.cuda.synchronize()
-        t_coarse = time.perf_counter() - t0
-    print(f"[bench] assemble {t_asm*1e3:.1f} ms, ras_setup {t_setup*1e3:.1f} ms, coarse_setup {t_coarse*1e3:.1f} ms, "
-          f"factors {pre.factor_bytes/1e9:.2f} GB", file=sys.stderr, flush=True)
-
     if args.kernels_only:
-        kernels_only(op, pre, prob, args.apply_reps)
+        run_kernels_only(args)
         return
-    b = torch.empty(op.n, dtype=torch.float64, device="cuda")
-    x = torch.zeros(op.n, dtype=torch.float64, device="cuda")
-    flexible = prec == st.F32 or coarse is not None
-
-    def step(k):
-        data = redraw_noise(prob, 1000 + k)
-        op.rhs(data, out=b)
-        x.zero_()
-        return st.solve(op, pre, b, x, coarse=coarse, restart=cfg.restart, rtol=cfg.rtol, maxit=cfg.maxit,
-                        flexible=flexible)[1]
-
-    for w in range(args.warmup):
-        s = step(w)
-        print(f"[bench] warmup {w}: {s.iters} its, {s.ms:.1f} ms, res {s.rel_res_true:.2e}", file=sys.stderr,
-              flush=True)
-    torch.cuda.synchronize()
-    times, its = [], []
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        ts = time.perf_counter()
-        s = step(args.warmup + k)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - ts)
-        its.append(s.iters)
-        assert s.converged and s.rel_res_true <= cfg.rtol, s
-        print(f"[bench] step {k}: {s.iters} its, {times[-1]*1e3:.1f} ms, res {s.rel_res_true:.2e}",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-
-    apply_ms, matvec_ms = time_kernels(op, pre, args.apply_reps)
-    apply_bytes = algorithmic_apply_bytes(pre, prob)
-    achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
-
-    value = args.steps / total
-    mean_its = float(np.mean(its))
-    res = {
-        "metric": "KKT solves/s at FP64 rel. residual 1e-6; p50/p99 latency; GMRES iterations",
-        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1e3 * total / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if prec == st.F64 else "f64 outer / f32 preconditioner",
-        "data": "synthetic (seeded moving-Gaussian sources, lattice sensors, fresh 1% noise per step)",
-        "config": {"workload": f"{args.config}: " + WORKLOADS[args.config].format(
-                       coarse="exact block LU in time" if args.coarse == "lu" else
-                       "GMRES(4) rtol 0.1 with coarse RAS 4x4x4x8 overlap 1"), "unknowns": prob.unknowns,
-                   "subdomains": pre.nsub, "precision": args.precision},
-        "p50_ms": 1e3 * percentile(times, 50), "p99_ms": 1e3 * percentile(times, 99),
-        "gmres_iters": mean_its, "setup_ms": {"assemble": 1e3 * t_asm, "ras_setup": 1e3 * t_setup, "coarse_setup": 1e3 * t_coarse},
-        "kernels_ms": {"ras_apply": apply_ms, "kkt_matvec": matvec_ms},
-        "roofline": {"kernel": "ras_apply", "bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                     "frac": achieved / 8000.0, "traffic": counted_traffic(args.config, args.precision),
-                     "algorithmic_bytes": apply_bytes},
-    }
-    if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
-        cfg_base = cfg
-        res["cpu_baseline"] = cpu_baseline(prob, cfg_base, int(round(mean_its)))
-    print(json.dumps(res), flush=True)
+    print(json.dumps(run_single(args)), flush=True)
 
 
 if __name__ == "__main__":

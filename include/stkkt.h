@@ -221,6 +221,13 @@ int ras_query_boxes(const ras_t *ras, int32_t *host_out);
 /* Bytes of factor data streamed by one ras_apply (all L, U and inv(D) blocks). */
 int64_t ras_factor_bytes(const ras_t *ras);
 
+/* Which sweep kernel ras_apply runs: the rows of a wavefront level handled
+ * per phase, 256 or 64, when the values of the last 16 levels of every box fit
+ * in the 160 KB LDS of a workgroup (64 for boxes with many rows per level,
+ * e.g. 14^4 nodes with FP64 factors); 0 when they do not and the sweeps keep
+ * them in the local vector in global memory.  -1 for a NULL handle. */
+int32_t ras_query_apply_rows(const ras_t *ras);
+
 /* Copy the factors of one subdomain to host memory as [rows][81][9] doubles:
  * slot s = (dx+1) + 3(dy+1) + 9(dz+1) + 27(dt+1) of local row rho
  * (rho = x + lx (y + ly (z + lz t))) holds L (s < 40), inv(U_rr) (s = 40) or

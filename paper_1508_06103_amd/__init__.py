@@ -93,6 +93,7 @@ _sig = {
     "ras_num_subdomains": (ctypes.c_int, [_vp]),
     "ras_query_boxes": (ctypes.c_int, [_vp, _c_i32p]),
     "ras_factor_bytes": (ctypes.c_int64, [_vp]),
+    "ras_query_apply_rows": (ctypes.c_int32, [_vp]),
     "ras_export_factors": (ctypes.c_int, [_vp, ctypes.c_int32, _c_dp]),
     "coarse_setup": (ctypes.c_int, [_vp, ctypes.POINTER(_CoarseParams), _vp, ctypes.POINTER(_vp)]),
     "coarse_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -287,6 +288,11 @@ class RAS:
     @property
     def factor_bytes(self):
         return int(_lib.ras_factor_bytes(self.handle))
+
+    @property
+    def apply_rows(self):
+        """Rows per phase of the sweep kernel: 256 or 64 (LDS ring), 0 (local vector in global memory)."""
+        return int(_lib.ras_query_apply_rows(self.handle))
 
     def export_factors(self, sub):
         b = self.boxes()[sub]

@@ -196,6 +196,8 @@ int64_t ras_factor_bytes(const ras_t *R) {
   return R->total_blocks * 9 * (R->params.precision == STKKT_F32 ? 4 : 8);
 }
 
+int32_t ras_query_apply_rows(const ras_t *R) { return R ? stkkt::ras_apply_rows_per_phase(R) : -1; }
+
 int ras_export_factors(const ras_t *R, int32_t sub, double *host_out) {
   return guarded([&] {
     STKKT_REQUIRE(R && host_out, "ras_export_factors: NULL argument");

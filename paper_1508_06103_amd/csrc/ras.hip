@@ -626,19 +626,21 @@ __device__ inline void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// A phase: segment seg (kRows rows) of level L, the level's rows starting
+// A phase: segment seg (KR rows) of level L, the level's rows starting
 // at r0 (R of them); L < 0 once the sweep has no further phase.  Only these
 // four values are kept (the kernel is short of scalar registers); the rest
 // is derived.
+template <int KR>
 struct Phase {
   int L, seg, r0, R;
   __device__ bool done() const { return L < 0; }
-  __device__ int segR() const { return min(kRows, R - seg * kRows); }
+  __device__ int segR() const { return min(KR, R - seg * KR); }
   __device__ int nch() const { return (segR() + 63) >> 6; }
 };
 
 // li: index of the level in sweep order
-__device__ inline void phase_at(Phase &p, cptr<int32_t> lvls, int nlev, int li, int seg, bool fwd) {
+template <int KR>
+__device__ inline void phase_at(Phase<KR> &p, cptr<int32_t> lvls, int nlev, int li, int seg, bool fwd) {
   if (li < 0) {
     p.L = -1, p.seg = 0, p.r0 = 0, p.R = 0;
     return;
@@ -649,13 +651,14 @@ __device__ inline void phase_at(Phase &p, cptr<int32_t> lvls, int nlev, int li, 
   p.seg = seg;
 }
 
-__device__ inline void phase_next(Phase &n, const Phase &p, cptr<int32_t> lvls, int nlev, bool fwd) {
+template <int KR>
+__device__ inline void phase_next(Phase<KR> &n, const Phase<KR> &p, cptr<int32_t> lvls, int nlev, bool fwd) {
   if (p.done()) {
     n = p;
     return;
   }
   const int li = fwd ? p.L : nlev - 1 - p.L;
-  if ((p.seg + 1) * kRows < p.R) phase_at(n, lvls, nlev, li, p.seg + 1, fwd);
+  if ((p.seg + 1) * KR < p.R) phase_at(n, lvls, nlev, li, p.seg + 1, fwd);
   else phase_at(n, lvls, nlev, next_level(lvls, nlev, li, fwd), 0, fwd);
 }
 
@@ -716,10 +719,10 @@ __device__ inline void load_chunk_f(const SweepArgs<T> &a, bool done, int L, int
   }
 }
 
-template <typename T, bool kFwd>
-__device__ inline void load_chunk_f(const SweepArgs<T> &a, const Phase &p, int c, uint64_t cw, int wave,
+template <typename T, bool kFwd, int KR>
+__device__ inline void load_chunk_f(const SweepArgs<T> &a, const Phase<KR> &p, int c, uint64_t cw, int wave,
                                     T (&f)[kSlotsPerWave][9]) {
-  load_chunk_f<T, kFwd>(a, p.done(), p.L, p.seg * (kRows / 64) + c, p.segR() - 64 * c, cw, wave, f);
+  load_chunk_f<T, kFwd>(a, p.done(), p.L, p.seg * (KR / 64) + c, p.segR() - 64 * c, cw, wave, f);
 }
 
 // Multiply chunk c of phase p: neighbour values from the LDS ring.  All rows
@@ -728,8 +731,8 @@ __device__ inline void load_chunk_f(const SweepArgs<T> &a, const Phase &p, int c
 // wavefront.  The lookups carry no branches: rows without the neighbour read
 // ring entry 0 and discard the value, so the LDS requests of the five slots
 // can be in flight together.
-template <typename T, bool kFwd>
-__device__ inline void mac_chunk_ring(const SweepArgs<T> &a, const Phase &p, int c, uint64_t cw, int wave,
+template <typename T, bool kFwd, int KR>
+__device__ inline void mac_chunk_ring(const SweepArgs<T> &a, const Phase<KR> &p, int c, uint64_t cw, int wave,
                                       const T (&f)[kSlotsPerWave][9], const T *yring, const int32_t *tzr,
                                       const Ring &rg, T &a0, T &a1, T &a2) {
   const int lane = (int)__lane_id();
@@ -774,8 +777,8 @@ __device__ inline void mac_chunk_ring(const SweepArgs<T> &a, const Phase &p, int
 // inv(U_rr) and y (backward).  The chunk-table entry of the diagonal slot is
 // wavefront-uniform (a wavefront holds 64 consecutive rows) and is read
 // through the scalar cache.
-template <typename T, bool kFwd>
-__device__ inline void load_pre(const SweepArgs<T> &a, const Phase &p, const uint64_t *crd, T (&pre)[12],
+template <typename T, bool kFwd, int KR>
+__device__ inline void load_pre(const SweepArgs<T> &a, const Phase<KR> &p, const uint64_t *crd, T (&pre)[12],
                                 double (&rin)[3]) {
   const int tq = (int)threadIdx.x;
   if (tq >= p.segR()) return;
@@ -787,7 +790,7 @@ __device__ inline void load_pre(const SweepArgs<T> &a, const Phase &p, const uin
     rin[1] = a.r[gi + 1];
     rin[2] = a.r[gi + 2];
   } else {
-    const int qrow = p.seg * kRows + tq;
+    const int qrow = p.seg * KR + tq;
     int64_t off9, cnt;
     chunk_slot(a, p.L, qrow >> 6, 40, off9, cnt);
     // the row's place in its chunk is made opaque here, so that the compiler
@@ -810,8 +813,8 @@ __device__ inline void load_pre(const SweepArgs<T> &a, const Phase &p, const uin
 // products, then y = r - sum (forward, y also kept in global memory for the
 // backward sweep) or z = inv(U_rr)(y - sum) (backward, owned rows written to
 // the output); the result goes into the LDS ring.
-template <typename T, bool kFwd>
-__device__ inline void ring_finish(const SweepArgs<T> &a, const Phase &pc, const uint64_t *crd, T (*part)[kRows][3],
+template <typename T, bool kFwd, int KR>
+__device__ inline void ring_finish(const SweepArgs<T> &a, const Phase<KR> &pc, const uint64_t *crd, T (*part)[KR][3],
                                    const T (&pre)[12], const double (&rin)[3], T *yring, const Ring &rg) {
   const int tq = (int)threadIdx.x;
   if (tq < pc.segR()) {
@@ -843,17 +846,17 @@ __device__ inline void ring_finish(const SweepArgs<T> &a, const Phase &pc, const
         for (int k = 0; k < 3; ++k) a.z[gi + k] = (double)o[k];
       }
     }
-    T *yr = yring + ((int64_t)(pc.L & 15) * rg.rmax + pc.seg * kRows + tq) * 3;
+    T *yr = yring + ((int64_t)(pc.L & 15) * rg.rmax + pc.seg * KR + tq) * 3;
     for (int k = 0; k < 3; ++k) yr[k] = o[k];
   }
 }
 
 // One chunk step: issue the factor loads of the next chunk, multiply the
 // current one, and close the phase if this was its last chunk.
-template <typename T, bool kFwd>
-__device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int nlev, int wave, Phase &pc, int &cc,
-                                 int &par, Phase &pn, Phase &pnn, const T (&fcur)[kSlotsPerWave][9],
-                                 T (&fnext)[kSlotsPerWave][9], T (*part)[kRows][3], uint64_t *crd2, T *yring,
+template <typename T, bool kFwd, int KR>
+__device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int nlev, int wave, Phase<KR> &pc, int &cc,
+                                 int &par, Phase<KR> &pn, Phase<KR> &pnn, const T (&fcur)[kSlotsPerWave][9],
+                                 T (&fnext)[kSlotsPerWave][9], T (*part)[KR][3], uint64_t *crd2, T *yring,
                                  int32_t *tzr, const Ring &rg, uint64_t &c2, int &tzrow, T (&pre)[12],
                                  double (&rin)[3]) {
   const int lane = (int)__lane_id();
@@ -861,9 +864,9 @@ __device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int n
   // requests of the phase, issued when its first chunk is multiplied: coordinates
   // two phases ahead, the (t, z) prefix row of a new level, final-step inputs
   if (cc == 0) {
-    if (!pnn.done() && tq < pnn.segR()) c2 = a.crd[a.sh.coord_off + pnn.r0 + pnn.seg * kRows + tq];
+    if (!pnn.done() && tq < pnn.segR()) c2 = a.crd[a.sh.coord_off + pnn.r0 + pnn.seg * KR + tq];
     if (pc.seg == 0 && tq < rg.ltlz) tzrow = tzp[pc.L * rg.ltlz + tq];
-    load_pre<T, kFwd>(a, pc, crd2 + par * kRows, pre, rin);
+    load_pre<T, kFwd>(a, pc, crd2 + par * KR, pre, rin);
   }
   // next chunk: same phase, or the first chunk of the next phase
   const bool last = cc == pc.nch() - 1;
@@ -873,12 +876,12 @@ __device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int n
     const int tL = last ? pn.L : pc.L, tseg = last ? pn.seg : pc.seg, tsegR = last ? pn.segR() : pc.segR();
     const int ct = last ? 0 : cc + 1;
     const int pt_par = last ? par ^ 1 : par;
-    const uint64_t cw = crd2[pt_par * kRows + ct * 64 + lane];
-    load_chunk_f<T, kFwd>(a, tdone, tL, tseg * (kRows / 64) + ct, tsegR - 64 * ct, cw, wave, fnext);
+    const uint64_t cw = crd2[pt_par * KR + ct * 64 + lane];
+    load_chunk_f<T, kFwd>(a, tdone, tL, tseg * (KR / 64) + ct, tsegR - 64 * ct, cw, wave, fnext);
   }
   // multiply the current chunk
   {
-    const uint64_t cw = crd2[par * kRows + cc * 64 + lane];
+    const uint64_t cw = crd2[par * KR + cc * 64 + lane];
     T a0 = 0, a1 = 0, a2 = 0;
     mac_chunk_ring<T, kFwd>(a, pc, cc, cw, wave, fcur, yring, tzr, rg, a0, a1, a2);
     if (cc * 64 + lane < pc.segR()) {
@@ -893,9 +896,9 @@ __device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int n
   }
   // close the phase
   lds_barrier();
-  ring_finish<T, kFwd>(a, pc, crd2 + par * kRows, part, pre, rin, yring, rg);
+  ring_finish<T, kFwd>(a, pc, crd2 + par * KR, part, pre, rin, yring, rg);
   if (pc.seg == 0 && tq < rg.ltlz) tzr[(pc.L & 15) * rg.ltlz + tq] = tzrow;
-  if (!pnn.done() && tq < pnn.segR()) crd2[par * kRows + tq] = c2;   // phase after next reuses this buffer
+  if (!pnn.done() && tq < pnn.segR()) crd2[par * KR + tq] = c2;   // phase after next reuses this buffer
   lds_barrier();
   // advance
   pc = pn;
@@ -905,21 +908,21 @@ __device__ inline void ring_step(const SweepArgs<T> &a, cptr<int32_t> tzp, int n
   cc = 0;
 }
 
-template <typename T, bool kFwd>
-__device__ inline void sweep_ring(const SweepArgs<T> &a, cptr<int32_t> tzp, T (*part)[kRows][3], uint64_t *crd2,
+template <typename T, bool kFwd, int KR>
+__device__ inline void sweep_ring(const SweepArgs<T> &a, cptr<int32_t> tzp, T (*part)[KR][3], uint64_t *crd2,
                                   T *yring, int32_t *tzr, const Ring &rg) {
   const int lane = (int)__lane_id();
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int tq = (int)threadIdx.x;
   const int nlev = a.sh.nlev;
-  Phase pc, pn, pnn;
+  Phase<KR> pc, pn, pnn;
   phase_at(pc, a.lvls, nlev, next_level(a.lvls, nlev, -1, kFwd), 0, kFwd);
   if (pc.done()) return;
   phase_next(pn, pc, a.lvls, nlev, kFwd);
   phase_next(pnn, pn, a.lvls, nlev, kFwd);
   // coordinates of the first two phases
-  if (tq < pc.segR()) crd2[tq] = a.crd[a.sh.coord_off + pc.r0 + pc.seg * kRows + tq];
-  if (!pn.done() && tq < pn.segR()) crd2[kRows + tq] = a.crd[a.sh.coord_off + pn.r0 + pn.seg * kRows + tq];
+  if (tq < pc.segR()) crd2[tq] = a.crd[a.sh.coord_off + pc.r0 + pc.seg * KR + tq];
+  if (!pn.done() && tq < pn.segR()) crd2[KR + tq] = a.crd[a.sh.coord_off + pn.r0 + pn.seg * KR + tq];
   __syncthreads();
   int par = 0, cc = 0;
   uint64_t c2 = 0;
@@ -945,18 +948,18 @@ __device__ inline void sweep_ring(const SweepArgs<T> &a, cptr<int32_t> tzp, T (*
 // three LDS buffers (par, par+1, par+2 mod 3); the phase three ahead is read
 // into registers at the start of a phase and stored into the buffer the
 // closing phase frees.
-template <typename T, bool kFwd>
-__device__ inline void ring_step2(const SweepArgs<T> &a, cptr<int32_t> tzp, int nlev, int wave, Phase &pc, int &cc,
-                                  int &par, Phase &pn, Phase &pnn, Phase &p3, const T (&fcur)[kSlotsPerWave][9],
-                                  T (&fload)[kSlotsPerWave][9], T (*part)[kRows][3], uint64_t *crd3, T *yring,
+template <typename T, bool kFwd, int KR>
+__device__ inline void ring_step2(const SweepArgs<T> &a, cptr<int32_t> tzp, int nlev, int wave, Phase<KR> &pc, int &cc,
+                                  int &par, Phase<KR> &pn, Phase<KR> &pnn, Phase<KR> &p3, const T (&fcur)[kSlotsPerWave][9],
+                                  T (&fload)[kSlotsPerWave][9], T (*part)[KR][3], uint64_t *crd3, T *yring,
                                   int32_t *tzr, const Ring &rg, uint64_t &c3, int &tzrow, T (&pre)[12],
                                   double (&rin)[3]) {
   const int lane = (int)__lane_id();
   const int tq = (int)threadIdx.x;
   if (cc == 0) {
-    if (!p3.done() && tq < p3.segR()) c3 = a.crd[a.sh.coord_off + p3.r0 + p3.seg * kRows + tq];
+    if (!p3.done() && tq < p3.segR()) c3 = a.crd[a.sh.coord_off + p3.r0 + p3.seg * KR + tq];
     if (pc.seg == 0 && tq < rg.ltlz) tzrow = tzp[pc.L * rg.ltlz + tq];
-    load_pre<T, kFwd>(a, pc, crd3 + par * kRows, pre, rin);
+    load_pre<T, kFwd>(a, pc, crd3 + par * KR, pre, rin);
   }
   // the chunk two steps ahead: (pc, cc+2), (pn, 0), (pn, 1) or (pnn, 0)
   {
@@ -969,12 +972,12 @@ __device__ inline void ring_step2(const SweepArgs<T> &a, cptr<int32_t> tzp, int 
     const int tsegR = which == 0 ? pc.segR() : which == 1 ? pn.segR() : pnn.segR();
     const int ct = which == 0 ? cc + 2 : which == 1 ? (cc + 2 == pc.nch() ? 0 : 1) : 0;
     const int tpar = which == 0 ? par : which == 1 ? p1 : p2;
-    const uint64_t cw = crd3[tpar * kRows + ct * 64 + lane];
-    load_chunk_f<T, kFwd>(a, tdone, tL, tseg * (kRows / 64) + ct, tsegR - 64 * ct, cw, wave, fload);
+    const uint64_t cw = crd3[tpar * KR + ct * 64 + lane];
+    load_chunk_f<T, kFwd>(a, tdone, tL, tseg * (KR / 64) + ct, tsegR - 64 * ct, cw, wave, fload);
   }
   // multiply the current chunk
   {
-    const uint64_t cw = crd3[par * kRows + cc * 64 + lane];
+    const uint64_t cw = crd3[par * KR + cc * 64 + lane];
     T a0 = 0, a1 = 0, a2 = 0;
     mac_chunk_ring<T, kFwd>(a, pc, cc, cw, wave, fcur, yring, tzr, rg, a0, a1, a2);
     if (cc * 64 + lane < pc.segR()) {
@@ -989,9 +992,9 @@ __device__ inline void ring_step2(const SweepArgs<T> &a, cptr<int32_t> tzp, int 
   }
   // close the phase
   lds_barrier();
-  ring_finish<T, kFwd>(a, pc, crd3 + par * kRows, part, pre, rin, yring, rg);
+  ring_finish<T, kFwd>(a, pc, crd3 + par * KR, part, pre, rin, yring, rg);
   if (pc.seg == 0 && tq < rg.ltlz) tzr[(pc.L & 15) * rg.ltlz + tq] = tzrow;
-  if (!p3.done() && tq < p3.segR()) crd3[par * kRows + tq] = c3;   // the phase three ahead reuses this buffer
+  if (!p3.done() && tq < p3.segR()) crd3[par * KR + tq] = c3;   // the phase three ahead reuses this buffer
   lds_barrier();
   pc = pn;
   pn = pnn;
@@ -1001,23 +1004,23 @@ __device__ inline void ring_step2(const SweepArgs<T> &a, cptr<int32_t> tzp, int 
   cc = 0;
 }
 
-template <typename T, bool kFwd>
-__device__ inline void sweep_ring2(const SweepArgs<T> &a, cptr<int32_t> tzp, T (*part)[kRows][3], uint64_t *crd3,
+template <typename T, bool kFwd, int KR>
+__device__ inline void sweep_ring2(const SweepArgs<T> &a, cptr<int32_t> tzp, T (*part)[KR][3], uint64_t *crd3,
                                    T *yring, int32_t *tzr, const Ring &rg) {
   const int lane = (int)__lane_id();
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int tq = (int)threadIdx.x;
   const int nlev = a.sh.nlev;
-  Phase pc, pn, pnn, p3;
+  Phase<KR> pc, pn, pnn, p3;
   phase_at(pc, a.lvls, nlev, next_level(a.lvls, nlev, -1, kFwd), 0, kFwd);
   if (pc.done()) return;
   phase_next(pn, pc, a.lvls, nlev, kFwd);
   phase_next(pnn, pn, a.lvls, nlev, kFwd);
   phase_next(p3, pnn, a.lvls, nlev, kFwd);
   // coordinates of the first three phases
-  if (tq < pc.segR()) crd3[tq] = a.crd[a.sh.coord_off + pc.r0 + pc.seg * kRows + tq];
-  if (!pn.done() && tq < pn.segR()) crd3[kRows + tq] = a.crd[a.sh.coord_off + pn.r0 + pn.seg * kRows + tq];
-  if (!pnn.done() && tq < pnn.segR()) crd3[2 * kRows + tq] = a.crd[a.sh.coord_off + pnn.r0 + pnn.seg * kRows + tq];
+  if (tq < pc.segR()) crd3[tq] = a.crd[a.sh.coord_off + pc.r0 + pc.seg * KR + tq];
+  if (!pn.done() && tq < pn.segR()) crd3[KR + tq] = a.crd[a.sh.coord_off + pn.r0 + pn.seg * KR + tq];
+  if (!pnn.done() && tq < pnn.segR()) crd3[2 * KR + tq] = a.crd[a.sh.coord_off + pnn.r0 + pnn.seg * KR + tq];
   __syncthreads();
   int par = 0, cc = 0;
   uint64_t c3 = 0;
@@ -1027,7 +1030,7 @@ __device__ inline void sweep_ring2(const SweepArgs<T> &a, cptr<int32_t> tzp, T (
   T fA[kSlotsPerWave][9], fB[kSlotsPerWave][9], fC[kSlotsPerWave][9];
   load_chunk_f<T, kFwd>(a, pc, 0, crd3[lane], wave, fA);
   if (pc.nch() >= 2) load_chunk_f<T, kFwd>(a, pc, 1, crd3[64 + lane], wave, fB);
-  else load_chunk_f<T, kFwd>(a, pn, 0, crd3[kRows + lane], wave, fB);
+  else load_chunk_f<T, kFwd>(a, pn, 0, crd3[KR + lane], wave, fB);
   for (;;) {
     ring_step2<T, kFwd>(a, tzp, nlev, wave, pc, cc, par, pn, pnn, p3, fA, fC, part, crd3, yring, tzr, rg, c3, tzrow,
                         pre, rin);
@@ -1046,7 +1049,7 @@ __device__ inline void sweep_ring2(const SweepArgs<T> &a, cptr<int32_t> tzp, T (
 template <typename T> constexpr int kCrdBufs = sizeof(T) == 4 ? 3 : 2;
 
 // Both sweeps of subdomain `sub` with the values of the last 16 levels in LDS.
-template <typename T>
+template <typename T, int KR>
 __device__ inline void apply_ring_sub(const OpDev &op, const SubInfo *__restrict__ subs, int sub,
                                       const ShapeInfo *__restrict__ shapes, const int32_t *__restrict__ lvl_start,
                                       const uint64_t *__restrict__ coords, const int32_t *__restrict__ ctab,
@@ -1054,9 +1057,9 @@ __device__ inline void apply_ring_sub(const OpDev &op, const SubInfo *__restrict
                                       T *__restrict__ Y, int64_t fzero, int64_t yzero, const Ring &rg,
                                       const double *__restrict__ r, double *__restrict__ z) {
   extern __shared__ __align__(16) unsigned char smem[];
-  T(*part)[kRows][3] = reinterpret_cast<T(*)[kRows][3]>(smem);
-  uint64_t *crd2 = reinterpret_cast<uint64_t *>(smem + sizeof(T) * kWaves * kRows * 3);
-  T *yring = reinterpret_cast<T *>(smem + sizeof(T) * kWaves * kRows * 3 + sizeof(uint64_t) * kCrdBufs<T> * kRows);
+  T(*part)[KR][3] = reinterpret_cast<T(*)[KR][3]>(smem);
+  uint64_t *crd2 = reinterpret_cast<uint64_t *>(smem + sizeof(T) * kWaves * KR * 3);
+  T *yring = reinterpret_cast<T *>(smem + sizeof(T) * kWaves * KR * 3 + sizeof(uint64_t) * kCrdBufs<T> * KR);
   int32_t *tzr = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(yring) +
                                              sizeof(T) * (size_t)16 * rg.rmax * 3);
   SweepArgs<T> a;
@@ -1087,14 +1090,14 @@ __device__ inline void apply_ring_sub(const OpDev &op, const SubInfo *__restrict
   }
 }
 
-template <typename T>
+template <typename T, int KR>
 __global__ void __launch_bounds__(kApplyThreads, 2) apply_ring_kernel(
     OpDev op, const SubInfo *__restrict__ subs, const int32_t *__restrict__ order,
     const ShapeInfo *__restrict__ shapes, const int32_t *__restrict__ lvl_start,
     const uint64_t *__restrict__ coords, const int32_t *__restrict__ ctab, const int32_t *__restrict__ tzpref, const T *__restrict__ F, T *__restrict__ Y, int64_t fzero, int64_t yzero,
     Ring rg, const double *__restrict__ r, double *__restrict__ z) {
   const int sub = as_const(order)[blockIdx.x];
-  apply_ring_sub<T>(op, subs, sub, shapes, lvl_start, coords, ctab, tzpref, F, Y, fzero, yzero, rg, r, z);
+  apply_ring_sub<T, KR>(op, subs, sub, shapes, lvl_start, coords, ctab, tzpref, F, Y, fzero, yzero, rg, r, z);
 }
 
 // One preconditioner of a batched application; its vectors start at element
@@ -1116,7 +1119,7 @@ struct RasBatchDesc {
 
 // Work list entry (preconditioner, subdomain), ordered largest box first
 // over the whole batch.
-template <typename T>
+template <typename T, int KR>
 __global__ void __launch_bounds__(kApplyThreads, 2) apply_ring_batch_kernel(const RasBatchDesc<T> *__restrict__ descs,
                                                                             const int2 *__restrict__ work,
                                                                             const int *__restrict__ act,
@@ -1133,35 +1136,54 @@ __global__ void __launch_bounds__(kApplyThreads, 2) apply_ring_batch_kernel(cons
   // also count against the LDS counter, so every LDS wait of the sweep would
   // drain the factor loads in flight.)
   const cptr<RasBatchDesc<T>> dp = as_const(descs + wk.x);
-  apply_ring_sub<T>(d.op, dp->subs, wk.y, dp->shapes, dp->lvl, dp->coords, dp->ctab, dp->tz, dp->F, dp->Y, d.fzero,
+  apply_ring_sub<T, KR>(d.op, dp->subs, wk.y, dp->shapes, dp->lvl, dp->coords, dp->ctab, dp->tz, dp->F, dp->Y, d.fzero,
                     d.yzero, d.rg, (a == 2 ? r2 : r) + d.voff, z + d.voff);
 }
 
 }  // namespace
 
-template <typename T>
+// LDS of the ring kernel with KR rows per phase: partial sums, phase
+// coordinates, the 16-level value ring and the (t, z) prefix rows of its levels.
+template <typename T, int KR>
 static size_t ring_lds_bytes(const ras *R) {
-  return sizeof(T) * kWaves * kRows * 3 + sizeof(uint64_t) * kCrdBufs<T> * kRows +
+  return sizeof(T) * kWaves * KR * 3 + sizeof(uint64_t) * kCrdBufs<T> * KR +
          sizeof(T) * (size_t)16 * R->ring_rmax * 3 +
          sizeof(int32_t) * (size_t)16 * R->ring_ltlz;
 }
 
+template <typename T, int KR>
+static void launch_ring(const ras *R, const double *r, double *z, T *Y, size_t lds, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_ring_kernel<T, KR>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRingLdsLimit));
+    attr_set = true;
+  }
+  Ring rg{R->ring_rmax, R->ring_ltlz};
+  hipLaunchKernelGGL((apply_ring_kernel<T, KR>), dim3(R->nsub), dim3(kApplyThreads), lds, s, R->d,
+                     R->d_subs.as<SubInfo>(), R->d_order.as<int32_t>(), R->d_shapes.as<ShapeInfo>(),
+                     R->d_lvl.as<int32_t>(), R->d_coords.as<uint64_t>(), R->d_ctab.as<int32_t>(),
+                     R->d_tz.as<int32_t>(), R->factors.as<T>(), Y, R->factor_elems, R->scratch_elems, rg, r, z);
+}
+
+// Rows per phase of the ring kernel for this preconditioner: 256 when the ring
+// fits with them, else 64 (boxes with more rows per level, e.g. 14^4 nodes in
+// FP64), else 0 (no ring: the kernel with the local vector in global memory).
+template <typename T>
+static int ring_rows(const ras *R) {
+  if (R->ring_ltlz > kApplyThreads) return 0;
+  if (ring_lds_bytes<T, 256>(R) <= kRingLdsLimit) return 256;
+  if (ring_lds_bytes<T, 64>(R) <= kRingLdsLimit) return 64;
+  return 0;
+}
+
 template <typename T>
 static void launch_apply(const ras *R, const double *r, double *z, T *Y, hipStream_t s) {
-  const size_t lds = ring_lds_bytes<T>(R);
-  if (lds <= kRingLdsLimit && R->ring_ltlz <= kApplyThreads) {
-    static bool attr_set = false;
-    if (!attr_set) {
-      STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_ring_kernel<T>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRingLdsLimit));
-      attr_set = true;
-    }
-    Ring rg{R->ring_rmax, R->ring_ltlz};
-    hipLaunchKernelGGL((apply_ring_kernel<T>), dim3(R->nsub), dim3(kApplyThreads), lds, s, R->d,
-                       R->d_subs.as<SubInfo>(), R->d_order.as<int32_t>(), R->d_shapes.as<ShapeInfo>(),
-                       R->d_lvl.as<int32_t>(), R->d_coords.as<uint64_t>(), R->d_ctab.as<int32_t>(),
-                       R->d_tz.as<int32_t>(), R->factors.as<T>(), Y,
-                       R->factor_elems, R->scratch_elems, rg, r, z);
+  const int kr = ring_rows<T>(R);
+  if (kr == 256) {
+    launch_ring<T, 256>(R, r, z, Y, ring_lds_bytes<T, 256>(R), s);
+  } else if (kr == 64) {
+    launch_ring<T, 64>(R, r, z, Y, ring_lds_bytes<T, 64>(R), s);
   } else {
     hipLaunchKernelGGL((apply_kernel<T>), dim3(R->nsub), dim3(kApplyThreads), 0, s, R->d, R->d_subs.as<SubInfo>(),
                        R->d_order.as<int32_t>(), R->d_shapes.as<ShapeInfo>(), R->d_lvl.as<int32_t>(),
@@ -1176,8 +1198,11 @@ size_t ras_local_bytes(const ras *R) {
 }
 
 bool ras_uses_ring(const ras *R) {
-  return (R->params.precision == STKKT_F32 ? ring_lds_bytes<float>(R) : ring_lds_bytes<double>(R)) <= kRingLdsLimit &&
-         R->ring_ltlz <= kApplyThreads;
+  return (R->params.precision == STKKT_F32 ? ring_rows<float>(R) : ring_rows<double>(R)) == 256;
+}
+
+int ras_apply_rows_per_phase(const ras *R) {
+  return R->params.precision == STKKT_F32 ? ring_rows<float>(R) : ring_rows<double>(R);
 }
 
 void ras_apply_device(const ras *R, const double *r, double *z, hipStream_t s, void *local) {
@@ -1211,7 +1236,7 @@ static void ras_batch_prepare_t(const ras *const *R, const long long *voff, void
     d[i].yzero = q->scratch_elems;
     d[i].voff = voff[i];
     d[i].rg = Ring{q->ring_rmax, q->ring_ltlz};
-    lds = std::max(lds, ring_lds_bytes<T>(q));
+    lds = std::max(lds, ring_lds_bytes<T, 256>(q));
     for (int k = 0; k < q->nsub; ++k)
       items.push_back({q->shapes[q->subs[k].shape].nblocks, make_int2(i, k)});
   }
@@ -1252,11 +1277,11 @@ static void ras_batch_launch(const RasBatch &b, const double *r, const double *r
                              hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_ring_batch_kernel<T>),
+    STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_ring_batch_kernel<T, 256>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRingLdsLimit));
     attr_set = true;
   }
-  hipLaunchKernelGGL((apply_ring_batch_kernel<T>), dim3(b.blocks), dim3(kApplyThreads), b.lds, s,
+  hipLaunchKernelGGL((apply_ring_batch_kernel<T, 256>), dim3(b.blocks), dim3(kApplyThreads), b.lds, s,
                      b.desc.as<RasBatchDesc<T>>(), b.work.as<int2>(), act, r, r2 ? r2 : r, z);
 }
 

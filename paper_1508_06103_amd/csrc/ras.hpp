@@ -65,7 +65,9 @@ namespace stkkt {
 // local: device buffer for the subdomains' local vectors (ras_local_bytes(R)
 // bytes, the last bytes zero), or NULL for the handle's own.
 void ras_apply_device(const ras *R, const double *r, double *z, hipStream_t s, void *local = nullptr);
-bool ras_uses_ring(const ras *R);
+bool ras_uses_ring(const ras *R);   // the 256-row ring kernel (the one batched launches share)
+// rows per phase of the kernel ras_apply runs: 256 or 64 (LDS ring), 0 (local vector in global memory)
+int ras_apply_rows_per_phase(const ras *R);
 size_t ras_local_bytes(const ras *R);
 
 // Batched application over preconditioners whose vectors are concatenated

@@ -35,6 +35,8 @@ SMALL = [
     ("neumann_all", dict(n=(4, 4, 4), M=5, seed=5, lattice=2, faces=0)),
     # one long box: (t, z) groups per level exceed the LDS-ring limits of the apply kernel
     ("tall", dict(n=(2, 2, 40), M=24, seed=6, lattice=1)),
+    # two 13^4 boxes: with FP64 factors the LDS ring only fits with 64 rows per phase
+    ("ring64", dict(n=(12, 12, 12), M=25, seed=8, lattice=2)),
     # the H1-L2 regularisation of Example 2
     ("h1l2", dict(n=(4, 5, 3), M=6, seed=7, lattice=2, reg=H1L2)),
 ]
@@ -51,6 +53,25 @@ def small_problem(name):
 
 def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _slot_errors(z, z_ref):
+    """Elementwise: per unknown slot (C, G, f), the largest |z - z_ref| over the
+    largest |z_ref| of that slot."""
+    zs, zr = z.reshape(-1, 3), z_ref.reshape(-1, 3)
+    return np.abs(zs - zr).max(axis=0) / np.maximum(np.abs(zr).max(axis=0), 1e-300)
+
+
+def _worst_subdomain(R, z, z_ref):
+    """(subdomain, error) of the owned rows with the largest elementwise deviation."""
+    best = (-1, 0.0)
+    scale = np.abs(z_ref).max()
+    for sid, gi in R.gidx.items():
+        own = gi[R.own[sid]]
+        e = np.abs(z[own] - z_ref[own]).max() / scale if own.size else 0.0
+        if e > best[1]:
+            best = (sid, e)
+    return best
 
 
 @pytest.mark.parametrize("name", [s[0] for s in SMALL])
@@ -74,7 +95,8 @@ def test_rhs_and_matvec(st, name):
                                               ("ragged", (3, 2, 3, 2), 2), ("aniso_otd", (2, 1, 2, 2), 1),
                                               ("neumann_all", (1, 2, 2, 1), 0), ("tall", (1, 1, 1, 1), 0),
                                               ("tall", (1, 1, 2, 2), 1), ("cube8x16", (2, 2, 2, 2), 4),
-                                              ("ragged", (2, 3, 2, 3), 3), ("h1l2", (2, 2, 1, 2), 1)])
+                                              ("ragged", (2, 3, 2, 3), 3), ("h1l2", (2, 2, 1, 2), 1),
+                                              ("ring64", (1, 1, 1, 2), 0)])
 def test_boxes_factors_and_apply(st, name, parts, delta):
     prob = small_problem(name)
     _say(f"case {name}: parts={parts} overlap={delta}")
@@ -101,8 +123,11 @@ def test_boxes_factors_and_apply(st, name, parts, delta):
     z = pre.apply(_dev(r)).cpu().numpy()
     z_ref = R.apply(r)
     err = np.linalg.norm(z - z_ref) / np.linalg.norm(z_ref)
-    _say(f"  apply rel err {err:.2e}")
-    assert err <= 1e-11
+    slot_err = _slot_errors(z, z_ref)
+    worst = _worst_subdomain(R, z, z_ref)
+    _say(f"  apply ({pre.apply_rows} rows per phase) rel err {err:.2e}, per slot (C, G, f) max "
+         f"{', '.join(f'{e:.1e}' for e in slot_err)}, worst subdomain {worst[0]} ({worst[1]:.1e})")
+    assert err <= 1e-11 and slot_err.max() <= 1e-10
 
 
 def test_apply_f32_factors(st):
@@ -252,3 +277,17 @@ def test_allocator_failure_is_enomem(st):
     pre = st.RAS(op, (2, 2, 2, 2), 1)   # the operator is still usable
     x, s = st.solve(op, pre, restart=30, rtol=1e-6)
     assert s.converged
+
+
+def test_apply_kernel_choice(st):
+    """The sweep kernel ras_apply picks: the 256-row LDS ring for 12^4 boxes,
+    the 64-row ring for 13^4 boxes in FP64 (the 256-row one does not fit the
+    LDS), the 256-row ring for the same boxes in FP32, and the global-memory
+    form for a box whose levels hold more (t, z) groups than the ring allows."""
+    cases = [("ring64", (1, 1, 1, 2), 0, "f64", 64), ("ring64", (1, 1, 1, 2), 0, "f32", 256),
+             ("tall", (1, 1, 1, 1), 0, "f64", 0), ("cube8x16", (2, 2, 2, 2), 1, "f64", 256)]
+    for name, parts, delta, prec, rows in cases:
+        op = st.KKTOperator(small_problem(name))
+        pre = st.RAS(op, parts, delta, precision=st.F64 if prec == "f64" else st.F32)
+        _say(f"  {name} {prec}: {pre.apply_rows} rows per phase")
+        assert pre.apply_rows == rows
