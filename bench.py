@@ -548,7 +548,8 @@ def run_serve(args):
 
 
 def build_single(st, prob, cfg, precision, coarse_how):
-    """Operator, preconditioner and coarse level of one workload, timed."""
+    """Operator, preconditioner and coarse level of one workload, timed
+    (coarse_how None: no coarse level)."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -560,7 +561,7 @@ def build_single(st, prob, cfg, precision, coarse_how):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     coarse, t_coarse = None, 0.0
-    if cfg.coarse_factor:
+    if cfg.coarse_factor and coarse_how is not None:
         t0 = time.perf_counter()
         if coarse_how == "lu":
             coarse = st.Coarse(op, cfg.coarse_factor, method=st.COARSE_LU, precision=precision)
@@ -701,7 +702,7 @@ def run_kernels_only(args):
     from workloads.generate import make_problem
     prob, cfg = make_problem(args.config)
     prec = st.F64 if args.precision == "f64" else st.F32
-    op, pre, coarse, setup = build_single(st, prob, cfg, prec, args.coarse)
+    op, pre, coarse, setup = build_single(st, prob, cfg, prec, None)   # no coarse level: its setup is not timed here
     kernels_only(op, pre, prob, args.apply_reps)
 
 

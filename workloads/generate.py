@@ -365,3 +365,30 @@ def class_instances(n, M, count=4, base_seed=9000):
         rng.choice(BATCH_N), rng.choice(BATCH_M)   # keep the draw sequence of batch_instances
         out.append(_uneven_instance(i, base_seed + 101 * n + 7 * M + i, rng, n, M))
     return out
+
+
+def manufactured_solution(prob, seed=0, terms=3):
+    """A seeded smooth space-time vector in the unknown layout (level, node, slot):
+    per slot a sum of `terms` separable products cos(2 pi (k.x) + phase) in
+    x, y, z and t with integer wave numbers 0..2, the C and G slots multiplied
+    by sin(pi x / len0) (zero on the x = 0 and x = len0 faces, the Dirichlet
+    faces of the benchmark problems).  Used as the exact solution x* of a
+    manufactured system F x* = b."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = prob.nodes
+    axes = [np.linspace(0.0, prob.length[0], nx), np.linspace(0.0, prob.length[1], ny),
+            np.linspace(0.0, prob.length[2], nz), np.linspace(0.0, prob.T, prob.M + 1)]
+    lens = list(prob.length) + [prob.T]
+    out = np.zeros((prob.M + 1, nz, ny, nx, 3))
+    for c in range(3):
+        acc = np.zeros((prob.M + 1, nz, ny, nx))
+        for _ in range(terms):
+            amp = rng.standard_normal()
+            f = [np.cos(2 * np.pi * rng.integers(0, 3) * axes[d] / lens[d] + rng.uniform(0, 2 * np.pi))
+                 for d in range(4)]
+            acc += amp * f[3][:, None, None, None] * f[2][None, :, None, None] * f[1][None, None, :, None] \
+                * f[0][None, None, None, :]
+        if c < 2:
+            acc *= np.sin(np.pi * axes[0] / lens[0])[None, None, None, :]
+        out[..., c] = acc
+    return out.ravel()
