@@ -34,13 +34,13 @@ WORKLOADS = {
 
 
 # HBM bytes per ras_apply launch measured with the FETCH_SIZE and WRITE_SIZE
-# counters (one pass each, `bench.py --kernels-only`), each scaled by what the
+# counters (one pass each, `bench.py --kernels-only --config cube48x96`), each scaled by what the
 # same counter reads for a 1 GiB device-to-device copy (FETCH x 2.000,
 # WRITE x 1.000).  Valid only for the apply-kernel source the counters were
 # taken on: a different source hash reports null.
 COUNTED_TRAFFIC = {
-    ("cube32x64", "f64"): {"ras_hip_sha256": "204c8b9e2b4ffc2d7a1ea1c61777937c7d02bf5cfe4070e6d49c16d62893039e",
-                      "read_bytes": 20005203.8 * 2.0 * 1024, "write_bytes": 362281.2 * 1.0 * 1024},
+    ("cube48x96", "f64"): {"ras_hip_sha256": "6ab371c71401c7ebb0c2d02e0b68e8cb9efd284592b1f1888e88f711207c3f92",
+                           "read_bytes": 45318414.2 * 2.0 * 1024, "write_bytes": 1059706.2 * 1.0 * 1024},
 }
 
 
