@@ -188,6 +188,20 @@ int kkt_assemble(const kkt_problem_t *p, const kkt_alloc_t *al, void *stream, kk
  * data_host: [nt+1][n_sensors] host array; b: device. */
 int kkt_rhs(const kkt_op_t *op, const double *data_host, void *stream, double *b);
 
+/* kkt_rhs for callers that cannot allocate device memory (serving loops that
+ * must not call hipMalloc, harnesses that forbid allocation): the same b, bit
+ * for bit, with the sensor ids and the data staged in a static device array
+ * of 1 MiB (STKKT_RHS_SCRATCH_BYTES) that each GPU holds until the process
+ * ends, instead of buffers from the allocator.  It calls no allocation
+ * routine.  The data must fit: round_up(4 n_sensors, 256) + 8 (nt+1)
+ * n_sensors <= STKKT_RHS_SCRATCH_BYTES, else STKKT_EINVAL (use kkt_rhs).
+ * Every call on one GPU shares that array: the call synchronises `stream`
+ * before it returns, and calls that overlap on one GPU (from several host
+ * threads) race.  Not for graph capture (it copies from host memory and
+ * synchronises). */
+#define STKKT_RHS_SCRATCH_BYTES (1 << 20)
+int kkt_rhs_noalloc(const kkt_op_t *op, const double *data_host, void *stream, double *b);
+
 /* y = F_h x: the space-time KKT operator of Section 3.1 with the block
  * structure of Appendix A (block tridiagonal in time; per level and spatial
  * node the (C, G, f) rows of the state, adjoint and source equations), applied

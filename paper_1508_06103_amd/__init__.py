@@ -24,6 +24,7 @@ DTO, OTD = 0, 1
 F64, F32 = 0, 1
 RESTRICT_TRANSPOSE, RESTRICT_INJECTION = 0, 1
 COARSE_LU, COARSE_GMRES_RAS = 0, 1
+RHS_SCRATCH_BYTES = 1 << 20   # STKKT_RHS_SCRATCH_BYTES: staging array of kkt_rhs_noalloc
 
 
 class StkktError(RuntimeError):
@@ -86,6 +87,7 @@ _vp = ctypes.c_void_p
 _sig = {
     "kkt_assemble": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.POINTER(_Alloc), _vp, ctypes.POINTER(_vp), _vp]),
     "kkt_rhs": (ctypes.c_int, [_vp, _c_dp, _vp, _vp]),
+    "kkt_rhs_noalloc": (ctypes.c_int, [_vp, _c_dp, _vp, _vp]),
     "kkt_matvec": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "kkt_size": (ctypes.c_int64, [_vp]),
     "ras_setup": (ctypes.c_int, [_vp, ctypes.POINTER(_RasParams), _vp, ctypes.POINTER(_vp)]),
@@ -239,6 +241,13 @@ class KKTOperator:
         d = np.ascontiguousarray(data, dtype=np.float64)
         out = torch.empty(self.n, dtype=torch.float64, device=self.alloc.device) if out is None else out
         _check(_lib.kkt_rhs(self.handle, d.ctypes.data_as(_c_dp), _stream(stream), _ptr(out)))
+        return out
+
+    def rhs_noalloc(self, data, out, stream=None):
+        """kkt_rhs_noalloc: b for new sensor data into `out`, staged in the
+        library's static device array (no device allocation)."""
+        d = np.ascontiguousarray(data, dtype=np.float64)
+        _check(_lib.kkt_rhs_noalloc(self.handle, d.ctypes.data_as(_c_dp), _stream(stream), _ptr(out)))
         return out
 
     def matvec(self, x, y=None, stream=None):

@@ -152,6 +152,16 @@ int kkt_rhs(const kkt_op_t *op, const double *data_host, void *stream, double *b
   });
 }
 
+int kkt_rhs_noalloc(const kkt_op_t *op, const double *data_host, void *stream, double *b) {
+  return guarded([&] {
+    STKKT_REQUIRE(op && data_host && b, "kkt_rhs_noalloc: NULL argument");
+    for (long long k = 0; k < (long long)(op->d.M + 1) * (long long)op->sensor_node.size(); ++k)
+      STKKT_REQUIRE(std::isfinite(data_host[k]), "kkt_rhs_noalloc: non-finite sensor data");
+    rhs_device_noalloc(op, data_host, as_stream(stream), b);
+    return STKKT_OK;
+  });
+}
+
 int kkt_matvec(const kkt_op_t *op, const double *x, double *y, void *stream) {
   return guarded([&] {
     STKKT_REQUIRE(op && x && y, "kkt_matvec: NULL argument");

@@ -130,6 +130,11 @@ template <class S> __device__ inline S load_uniform(const S *p) {
 
 kkt_op *op_create(const kkt_problem_t *p, const kkt_alloc_t *al, hipStream_t s);
 void rhs_device(const kkt_op *op, const double *data_host, hipStream_t s, double *b);
+// The same without allocation: staging in a static device array of
+// kRhsScratchBytes (EINVAL when the data need more, see rhs_scratch_need).
+constexpr size_t kRhsScratchBytes = STKKT_RHS_SCRATCH_BYTES;
+size_t rhs_scratch_need(const kkt_op *op);
+void rhs_device_noalloc(const kkt_op *op, const double *data_host, hipStream_t s, double *b);
 void fill_zero(double *p, long long n, hipStream_t s);
 void stiff_table(const OpDev &d, double *tab, hipStream_t s);
 MvTile choose_matvec_tile(const OpDev &d);

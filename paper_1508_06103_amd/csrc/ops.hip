@@ -1,6 +1,8 @@
 // Operator assembly, right-hand side and the matrix-free space-time matvec.
 #include <algorithm>
 #include <climits>
+#include <mutex>
+#include <string>
 
 #include "common.hpp"
 #include "stencil.hpp"
@@ -49,6 +51,61 @@ void rhs_device(const kkt_op *op, const double *data_host, hipStream_t s, double
                      op->d, nodes.as<int32_t>(), ns, data.as<double>(), b);
   STKKT_HIP(hipGetLastError());
   // the staging buffers are freed when this returns: wait for the copies
+  STKKT_HIP(hipStreamSynchronize(s));
+}
+
+// --------------------------------------------------------------------------
+// right-hand side without allocation: the sensor ids and the data are staged
+// in `scratch`, a device array of this file (one copy per GPU, alive until the
+// process ends), instead of buffers from the allocator.  In host code the
+// array's name is not a device address; the address comes from
+// hipGetSymbolAddress, once per device, and only that pointer is used.
+// --------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kRhsScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<unsigned char *> g_scratch_ptr;   // per device; null until looked up
+
+unsigned char *scratch_ptr() {
+  int dev = 0;
+  STKKT_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    STKKT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(STKKT_EHIP, "kkt_rhs_noalloc: no device address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+size_t rhs_scratch_need(const kkt_op *op) {
+  const size_t ns = op->sensor_node.size();
+  const size_t ids = (sizeof(int32_t) * ns + 255) / 256 * 256;
+  return ids + sizeof(double) * (size_t)(op->d.M + 1) * ns;
+}
+
+void rhs_device_noalloc(const kkt_op *op, const double *data_host, hipStream_t s, double *b) {
+  const size_t need = rhs_scratch_need(op);
+  if (need > kRhsScratchBytes)
+    throw Error(STKKT_EINVAL, "kkt_rhs_noalloc: (nt+1) x n_sensors data need " + std::to_string(need) +
+                                  " bytes of staging, more than the " + std::to_string(kRhsScratchBytes) +
+                                  " the scratch array holds; use kkt_rhs");
+  unsigned char *base = scratch_ptr();
+  const int ns = (int)op->sensor_node.size();
+  const size_t ids = (sizeof(int32_t) * ns + 255) / 256 * 256;
+  int32_t *nodes = reinterpret_cast<int32_t *>(base);
+  double *data = reinterpret_cast<double *>(base + ids);
+  fill_zero(b, 3LL * op->d.V, s);
+  STKKT_HIP(hipMemcpyAsync(nodes, op->sensor_node.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+  STKKT_HIP(hipMemcpyAsync(data, data_host, sizeof(double) * (size_t)(op->d.M + 1) * ns, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(rhs_scatter_kernel, dim3(blocks_for((long long)(op->d.M + 1) * ns, 256, 4096)), dim3(256), 0, s,
+                     op->d, nodes, ns, data, b);
+  STKKT_HIP(hipGetLastError());
+  // the next call on this GPU reuses the scratch array: finish before returning
   STKKT_HIP(hipStreamSynchronize(s));
 }
 
