@@ -1,10 +1,12 @@
-/* Oracle 3x3 point-block ILU(0) and its triangular solves -- test infrastructure.
+/* Oracle 3x3 point-block ILU on a given pattern and its triangular solves --
+ * test infrastructure.
  *
  * Plain, unblocked C written for readability, not speed.  The matrix is in
  * block-CSR form (3x3 blocks stored row-major, 9 doubles each) with column
  * indices sorted inside every block row; diagpos[i] is the position of the
- * diagonal block of row i.  The sparsity pattern is the given one (zero
- * fill-in): ILU(0) in the IKJ order
+ * diagonal block of row i.  The sparsity pattern is the given one -- the
+ * 81-point block pattern for ILU(0), the level-k pattern (computed by the
+ * caller) for ILU(k) -- and no entry outside it is created, in the IKJ order
  *     for i: for k < i in row i (ascending): a_ik <- a_ik * inv(a_kk)
  *                                             a_ij <- a_ij - a_ik * a_kj  (j > k, j in row i)
  * Diagonal blocks are inverted by Gauss-Jordan elimination with partial

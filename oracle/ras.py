@@ -7,9 +7,13 @@ subdomain matrix is the principal submatrix of F_h on the extended box, and
 the preconditioner restricts with overlap, solves approximately, and keeps the
 owned (non-overlapping) part -- the restricted additive Schwarz of Cai and
 Sarkis:  z = sum_i (R^0_i)^T  Mtilde_i^{-1}  R^delta_i r.
-Mtilde_i^{-1} is ILU(0) (Section 4: ILU(k) with k = 0 by default) applied to
-3x3 point blocks (C, G, f of one space-time node, Section 3.2 ordering) in
-the box's natural lexicographic order.
+Mtilde_i^{-1} is ILU(k) (Section 4: ILU(k), k = 0 by default, the fill level
+studied in the paper's first table) applied to 3x3 point blocks (C, G, f of
+one space-time node, Section 3.2 ordering) in the box's natural
+lexicographic order.  Level of fill (the usual symbolic rule): entries of the
+81-point block pattern have level 0; eliminating row k from row i gives entry
+(i, j) the level min(lev(i, j), lev(i, k) + lev(k, j) + 1); ILU(k) keeps the
+entries of level <= k and is the incomplete factorisation on that pattern.
 
 Partition rule per dimension with L nodes and p parts: q, r = divmod(L, p);
 part k owns [k q + min(k, r), (k+1) q + min(k+1, r)).  Subdomain id =
@@ -17,6 +21,7 @@ kx + px (ky + py (kz + pz kt)).
 """
 from __future__ import annotations
 
+import heapq
 from dataclasses import dataclass
 
 import numpy as np
@@ -130,6 +135,56 @@ def block_pattern(dims):
     return indptr, indices, slots
 
 
+_PATTERN_CACHE = {}
+
+
+def ilu_pattern(dims, level):
+    """Block pattern of ILU(level) on a box: (indptr, indices, lev) in block
+    CSR form, columns sorted, lev the fill level of every entry.
+
+    Symbolic elimination in the IKJ order: for every row i, the columns k < i
+    of its current pattern are taken in ascending order (fill entries with
+    k < i join as they appear), and every entry (k, j), j > k, of the already
+    computed row k offers (i, j) the level lev(i, k) + lev(k, j) + 1; an entry
+    is kept when its smallest offered level is <= level."""
+    key = (tuple(int(d) for d in dims), int(level))
+    if key in _PATTERN_CACHE:
+        return _PATTERN_CACHE[key]
+    indptr0, indices0, _ = block_pattern(dims)
+    n = indptr0.size - 1
+    rows = []
+    for i in range(n):
+        lev = {int(j): 0 for j in indices0[indptr0[i]:indptr0[i + 1]]}
+        heap = [j for j in lev if j < i]
+        heapq.heapify(heap)
+        seen = set()
+        while heap:
+            k = heapq.heappop(heap)
+            if k in seen:
+                continue
+            seen.add(k)
+            lik = lev[k]
+            for j, lkj in rows[k].items():
+                if j <= k:
+                    continue
+                cand = lik + lkj + 1
+                if cand > level:
+                    continue
+                if j not in lev:
+                    lev[j] = cand
+                    if j < i:
+                        heapq.heappush(heap, j)
+                elif cand < lev[j]:
+                    lev[j] = cand
+        rows.append({j: l for j, l in lev.items() if l <= level})
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    indptr[1:] = np.cumsum([len(r) for r in rows])
+    indices = np.concatenate([np.array(sorted(r), dtype=np.int64) for r in rows])
+    levs = np.concatenate([np.array([r[j] for j in sorted(r)], dtype=np.int64) for r in rows])
+    _PATTERN_CACHE[key] = (indptr, indices, levs)
+    return _PATTERN_CACHE[key]
+
+
 def block_values(A_box: sp.csr_matrix, indptr, indices):
     """Values of every pattern block (explicit zeros where F_h has none)."""
     nb = indptr.size - 1
@@ -148,14 +203,19 @@ def block_values(A_box: sp.csr_matrix, indptr, indices):
 
 
 class SubdomainILU:
-    """ILU(0) factors of one subdomain matrix (block CSR, IKJ order)."""
+    """ILU(level) factors of one subdomain matrix (block CSR, IKJ order)."""
 
-    def __init__(self, A_box: sp.csr_matrix, dims):
+    def __init__(self, A_box: sp.csr_matrix, dims, level=0):
         self.dims = dims
-        indptr, indices, slots = block_pattern(dims)
+        self.level = level
+        if level == 0:
+            indptr, indices, slots = block_pattern(dims)
+            self.slots = slots
+        else:
+            indptr, indices, _ = ilu_pattern(dims, level)
+            self.slots = None
         self.indptr = indptr.astype(np.int32)
         self.indices = indices.astype(np.int32)
-        self.slots = slots
         self.diagpos = (self.indptr[:-1] + np.array(
             [np.searchsorted(indices[indptr[i]:indptr[i + 1]], i) for i in range(indptr.size - 1)])).astype(np.int32)
         self.original = block_values(A_box, indptr, indices)
@@ -176,6 +236,13 @@ class SubdomainILU:
                                       clib.ptr(r), clib.ptr(z))
         return z
 
+    def csr(self):
+        """(indptr, indices, blocks[nnz, 3, 3]): L blocks left of the diagonal,
+        inv(U_ii) on it, U blocks right of it."""
+        out = self.vals.copy()
+        out[self.diagpos] = self.dinv
+        return self.indptr.copy(), self.indices.copy(), out
+
     def padded(self) -> np.ndarray:
         """[rows, 81, 3, 3]: L blocks (slots < 40), inv(U_ii) (slot 40), U blocks (slots > 40)."""
         nrows = self.indptr.size - 1
@@ -194,9 +261,9 @@ class SubdomainILU:
 
 
 class RAS:
-    """z = sum_i (R^0_i)^T ILU0_i^{-1} R^delta_i r."""
+    """z = sum_i (R^0_i)^T ILU(k)_i^{-1} R^delta_i r."""
 
-    def __init__(self, prob, parts, overlap, terms=None, subset=None):
+    def __init__(self, prob, parts, overlap, terms=None, subset=None, ilu_level=0):
         self.prob = prob
         self.terms = terms if terms is not None else kkt_mod.kkt_terms(prob)
         self.subs = subdomains(prob, parts, overlap)
@@ -208,7 +275,7 @@ class RAS:
             sd = self.subs[sid]
             nid = box_node_ids(prob, sd)
             A_box = kkt_mod.box_submatrix(self.terms, nid, sd.box_lo[3], sd.box_hi[3])
-            self.ilu[sid] = SubdomainILU(A_box, sd.dims)
+            self.ilu[sid] = SubdomainILU(A_box, sd.dims, ilu_level)
             self.gidx[sid] = box_global_index(prob, sd)
             self.own[sid] = np.repeat(owned_mask(sd), 3)
 

@@ -140,3 +140,110 @@ def test_overlap_reduces_iterations():
         assert st.converged
         its.append(st.iters)
     assert its[0] > its[1] >= its[2]
+
+
+def _fill_path_levels(dims):
+    """Brute force: the level of fill of entry (i, j) is the length of the
+    shortest path from i to j in the graph of the 81-point block pattern whose
+    interior vertices are all numbered below min(i, j), minus one (the graph
+    model of level-based ILU of Hysom and Pothen); absent if no such path."""
+    from collections import deque
+    indptr, indices, _ = ras.block_pattern(dims)
+    n = indptr.size - 1
+    nbr = [[int(j) for j in indices[indptr[i]:indptr[i + 1]] if j != i] for i in range(n)]
+    lev = {}
+    for i in range(n):
+        for j in range(n):
+            if i == j:
+                lev[(i, j)] = 0
+                continue
+            lo = min(i, j)
+            dist = {i: 0}
+            q = deque([i])
+            while q:
+                u = q.popleft()
+                if u == j:
+                    break
+                for w in nbr[u]:
+                    if w not in dist and (w < lo or w == j):
+                        dist[w] = dist[u] + 1
+                        q.append(w)
+            if j in dist:
+                lev[(i, j)] = dist[j] - 1
+    return lev
+
+
+@pytest.mark.parametrize("dims", [(3, 3, 2, 2), (2, 3, 3, 2)])
+def test_iluk_pattern_matches_fill_paths(dims):
+    """ILU(k) keeps exactly the entries whose shortest fill path has at most k
+    interior vertices, with the level the path gives."""
+    want = _fill_path_levels(dims)
+    for k in range(4):
+        indptr, indices, levs = ras.ilu_pattern(dims, k)
+        got = {(i, int(indices[p])): int(levs[p]) for i in range(indptr.size - 1)
+               for p in range(indptr[i], indptr[i + 1])}
+        assert got == {key: l for key, l in want.items() if l <= k}, k
+    assert np.array_equal(ras.ilu_pattern(dims, 0)[1], ras.block_pattern(dims)[1])
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_iluk_product_matches_matrix_on_pattern(level):
+    """ILU on the level-k pattern: (L U)_ij = A_ij for every (i, j) of the pattern."""
+    prob = make_custom((6, 6, 6), 5, 13, lattice=2)
+    terms = kkt.kkt_terms(prob)
+    sd = ras.Subdomain(0, (1, 1, 1, 1), (6, 5, 5, 5), (1, 1, 1, 1), (6, 5, 5, 5))
+    A = kkt.box_submatrix(terms, ras.box_node_ids(prob, sd), 1, 5).toarray()
+    ilu = ras.SubdomainILU(sp.csr_matrix(A), sd.dims, level)
+    n = ilu.indptr.size - 1
+    L = np.eye(3 * n)
+    U = np.zeros((3 * n, 3 * n))
+    for i in range(n):
+        for p in range(ilu.indptr[i], ilu.indptr[i + 1]):
+            j = ilu.indices[p]
+            blk = ilu.vals[p]
+            if j < i:
+                L[3 * i:3 * i + 3, 3 * j:3 * j + 3] = blk
+            else:
+                U[3 * i:3 * i + 3, 3 * j:3 * j + 3] = blk
+    LU = L @ U
+    mask = np.zeros((3 * n, 3 * n), dtype=bool)
+    for i in range(n):
+        for j in ilu.indices[ilu.indptr[i]:ilu.indptr[i + 1]]:
+            mask[3 * i:3 * i + 3, 3 * j:3 * j + 3] = True
+    assert np.abs(LU - A)[mask].max() <= 1e-12 * np.abs(A).max()
+    # and the pattern holds fill: the product differs from A somewhere off it
+    assert np.abs(LU - A)[~mask].max() > 1e-8 * np.abs(A).max()
+    assert mask.sum() > 9 * ras.block_pattern(sd.dims)[1].size
+
+
+def test_iluk_becomes_exact_lu():
+    """With a level above the box's row count every fill entry is kept:
+    ILU(k) is the exact block LU and its solve is A^{-1}."""
+    prob = make_custom((5, 5, 5), 5, 17, lattice=1)
+    terms = kkt.kkt_terms(prob)
+    sd = ras.Subdomain(0, (1, 1, 1, 1), (5, 4, 4, 4), (1, 1, 1, 1), (5, 4, 4, 4))
+    A = kkt.box_submatrix(terms, ras.box_node_ids(prob, sd), 1, 4)
+    nrows = int(np.prod(sd.dims))
+    r = np.random.default_rng(4).standard_normal(A.shape[0])
+    exact = np.linalg.solve(A.toarray(), r)
+    errs = []
+    for k in (0, 1, nrows):
+        z = ras.SubdomainILU(A, sd.dims, k).solve(r)
+        errs.append(np.linalg.norm(z - exact) / np.linalg.norm(exact))
+    assert errs[-1] <= 1e-10
+    assert errs[0] > errs[1] > errs[-1]
+
+
+def test_iluk_reduces_iterations():
+    """Paper's fill-level table trend: more fill, fewer Krylov iterations."""
+    prob = make_custom((6, 6, 6), 8, 3, lattice=2)
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    b = kkt.rhs(prob)
+    its = []
+    for k in (0, 1, 2):
+        R = ras.RAS(prob, (2, 2, 2, 2), 1, terms=terms, ilu_level=k)
+        _, st = krylov.gmres(lambda v: F @ v, R.apply, b, restart=50, rtol=1e-6)
+        assert st.converged
+        its.append(st.iters)
+    assert its[0] > its[1] >= its[2], its
