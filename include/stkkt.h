@@ -102,12 +102,18 @@ typedef struct {
  * p[d] subdomains along x, y, z, t (node-based split: part k of L nodes owns
  * [k q + min(k,r), (k+1) q + min(k+1,r)), q,r = divmod(L, p)), each extended
  * by `overlap` nodes per side and trimmed at the global box.  Subdomain
- * solves: 3x3 point-block ILU(0) in the box's lexicographic order. */
+ * solves: 3x3 point-block ILU(k) in the box's lexicographic order (Section 4:
+ * k = 0 by default; the paper's first table varies k).  Level of fill on the
+ * 81-point block pattern: its entries have level 0, eliminating row k from
+ * row i offers entry (i, j) the level lev(i,k) + lev(k,j) + 1, and entries of
+ * level <= k are kept.  k = 0 uses the stencil-specialised sweep kernels;
+ * k > 0 a general level-scheduled form (its factor storage grows with k:
+ * about 3.9x the ILU(0) blocks per interior row at k = 1, 6.4x at k = 2). */
 typedef struct {
   int32_t p[4];
   int32_t overlap;          /* >= 0 */
   int32_t precision;        /* STKKT_F64 or STKKT_F32 factors and local solve */
-  int32_t ilu_level;        /* must be 0 */
+  int32_t ilu_level;        /* k: 0, 1, 2 or 3 (STKKT_EINVAL otherwise) */
 } ras_params_t;
 
 /* Two-level preconditioner (Section 3.2, two-level paragraph): nested coarse
@@ -242,10 +248,22 @@ int64_t ras_factor_bytes(const ras_t *ras);
  * them in the local vector in global memory.  -1 for a NULL handle. */
 int32_t ras_query_apply_rows(const ras_t *ras);
 
+/* Factor blocks of one subdomain (the size of ras_export_factors_csr's
+ * `blocks`, in 3x3 blocks); -1 for a bad handle or index. */
+int64_t ras_subdomain_blocks(const ras_t *ras, int32_t sub);
+
+/* Copy the factors of one subdomain to host memory as block CSR in the box's
+ * natural order (rho = x + lx (y + ly (z + lz t))): indptr[rows + 1],
+ * indices[n] (sorted columns of every row), blocks[9 n] doubles (row-major
+ * 3x3: L left of the diagonal, inv(U_rr) on it, U right of it), n =
+ * ras_subdomain_blocks(ras, sub).  Any ILU level; FP32 factors widened. */
+int ras_export_factors_csr(const ras_t *ras, int32_t sub, int32_t *indptr, int32_t *indices, double *blocks);
+
 /* Copy the factors of one subdomain to host memory as [rows][81][9] doubles:
  * slot s = (dx+1) + 3(dy+1) + 9(dz+1) + 27(dt+1) of local row rho
  * (rho = x + lx (y + ly (z + lz t))) holds L (s < 40), inv(U_rr) (s = 40) or
- * U (s > 40); blocks outside the box are zero. */
+ * U (s > 40); blocks outside the box are zero.  ILU(0) only (STKKT_EINVAL for
+ * k > 0, whose fill lies outside the 81 slots). */
 int ras_export_factors(const ras_t *ras, int32_t sub, double *host_out);
 
 /* Coarse level: build F_c on the coarse mesh, its one-level RAS (ILU(0)

@@ -101,3 +101,104 @@ void oracle_bilu0_solve(int nrows, const int *indptr, const int *indices, const 
     for (int c = 0; c < 3; ++c) z[3 * i + c] = d[3 * c] * s[0] + d[3 * c + 1] * s[1] + d[3 * c + 2] * s[2];
   }
 }
+
+/* Symbolic ILU(level) on a block pattern (test infrastructure).
+ *
+ * Input: the level-0 pattern in block CSR (indptr0, indices0, columns sorted,
+ * diagonal included), n rows.  For every row i, in order: the entries of the
+ * level-0 pattern get level 0; the columns k < i of the row are taken in
+ * ascending order (fill columns k < i join as they appear) and every entry
+ * (k, j), j > k, of the already computed row k offers (i, j) the level
+ * lev(i, k) + lev(k, j) + 1; entries whose smallest offered level is <= level
+ * are kept.  Output: indptr[n + 1], indices and levs (sorted columns) with
+ * room for `cap` entries.  Returns the number of entries, or -1 if cap is too
+ * small (or out of memory). */
+#include <stdlib.h>
+
+static void heap_push(int *h, int *len, int v) {
+  int i = (*len)++;
+  h[i] = v;
+  while (i > 0) {
+    int p = (i - 1) / 2;
+    if (h[p] <= h[i]) break;
+    int t = h[p]; h[p] = h[i]; h[i] = t;
+    i = p;
+  }
+}
+
+static int heap_pop(int *h, int *len) {
+  int top = h[0];
+  h[0] = h[--(*len)];
+  int i = 0;
+  for (;;) {
+    int l = 2 * i + 1, r = l + 1, m = i;
+    if (l < *len && h[l] < h[m]) m = l;
+    if (r < *len && h[r] < h[m]) m = r;
+    if (m == i) break;
+    int t = h[m]; h[m] = h[i]; h[i] = t;
+    i = m;
+  }
+  return top;
+}
+
+static int cmp_int(const void *a, const void *b) {
+  int x = *(const int *)a, y = *(const int *)b;
+  return (x > y) - (x < y);
+}
+
+long oracle_iluk_symbolic(int n, const int *indptr0, const int *indices0, int level, long cap, long *indptr,
+                          int *indices, int *levs) {
+  int *lev = malloc(sizeof(int) * (size_t)n);
+  int *done = malloc(sizeof(int) * (size_t)n);
+  int *touched = malloc(sizeof(int) * (size_t)n);
+  int *heap = malloc(sizeof(int) * (size_t)n);
+  if (!lev || !done || !touched || !heap) {
+    free(lev); free(done); free(touched); free(heap);
+    return -1;
+  }
+  for (int j = 0; j < n; ++j) { lev[j] = -1; done[j] = -1; }
+  long nnz = 0;
+  indptr[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    int nt = 0, hl = 0;
+    for (int p = indptr0[i]; p < indptr0[i + 1]; ++p) {
+      int j = indices0[p];
+      lev[j] = 0;
+      touched[nt++] = j;
+      if (j < i) heap_push(heap, &hl, j);
+    }
+    while (hl > 0) {
+      int k = heap_pop(heap, &hl);
+      if (done[k] == i) continue;
+      done[k] = i;
+      int lik = lev[k];
+      for (long q = indptr[k]; q < indptr[k + 1]; ++q) {
+        int j = indices[q];
+        if (j <= k) continue;
+        int cand = lik + levs[q] + 1;
+        if (cand > level) continue;
+        if (lev[j] < 0) {
+          lev[j] = cand;
+          touched[nt++] = j;
+          if (j < i) heap_push(heap, &hl, j);
+        } else if (cand < lev[j]) {
+          lev[j] = cand;
+        }
+      }
+    }
+    qsort(touched, (size_t)nt, sizeof(int), cmp_int);
+    if (nnz + nt > cap) {
+      free(lev); free(done); free(touched); free(heap);
+      return -1;
+    }
+    for (int t = 0; t < nt; ++t) {
+      indices[nnz + t] = touched[t];
+      levs[nnz + t] = lev[touched[t]];
+      lev[touched[t]] = -1;
+    }
+    nnz += nt;
+    indptr[i + 1] = nnz;
+  }
+  free(lev); free(done); free(touched); free(heap);
+  return nnz;
+}

@@ -31,6 +31,8 @@ def lib():
         L.oracle_bilu0.restype = ctypes.c_int
         L.oracle_bilu0_solve.argtypes = [ctypes.c_int, P, P, P, P, P, P, P]
         L.oracle_bilu0_solve.restype = None
+        L.oracle_iluk_symbolic.argtypes = [ctypes.c_int, P, P, ctypes.c_int, ctypes.c_long, P, P, P]
+        L.oracle_iluk_symbolic.restype = ctypes.c_long
         L.oracle_inv33.argtypes = [P, P]
         L.oracle_inv33.restype = ctypes.c_int
         _lib = L

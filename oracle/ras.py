@@ -21,7 +21,6 @@ kx + px (ky + py (kz + pz kt)).
 """
 from __future__ import annotations
 
-import heapq
 from dataclasses import dataclass
 
 import numpy as np
@@ -142,47 +141,34 @@ def ilu_pattern(dims, level):
     """Block pattern of ILU(level) on a box: (indptr, indices, lev) in block
     CSR form, columns sorted, lev the fill level of every entry.
 
-    Symbolic elimination in the IKJ order: for every row i, the columns k < i
-    of its current pattern are taken in ascending order (fill entries with
-    k < i join as they appear), and every entry (k, j), j > k, of the already
-    computed row k offers (i, j) the level lev(i, k) + lev(k, j) + 1; an entry
-    is kept when its smallest offered level is <= level."""
+    Symbolic elimination in the IKJ order (``oracle_iluk_symbolic`` in
+    bilu.c): for every row i, the columns k < i of its current pattern are
+    taken in ascending order (fill entries with k < i join as they appear),
+    and every entry (k, j), j > k, of the already computed row k offers (i, j)
+    the level lev(i, k) + lev(k, j) + 1; an entry is kept when its smallest
+    offered level is <= level."""
     key = (tuple(int(d) for d in dims), int(level))
     if key in _PATTERN_CACHE:
         return _PATTERN_CACHE[key]
     indptr0, indices0, _ = block_pattern(dims)
     n = indptr0.size - 1
-    rows = []
-    for i in range(n):
-        lev = {int(j): 0 for j in indices0[indptr0[i]:indptr0[i + 1]]}
-        heap = [j for j in lev if j < i]
-        heapq.heapify(heap)
-        seen = set()
-        while heap:
-            k = heapq.heappop(heap)
-            if k in seen:
-                continue
-            seen.add(k)
-            lik = lev[k]
-            for j, lkj in rows[k].items():
-                if j <= k:
-                    continue
-                cand = lik + lkj + 1
-                if cand > level:
-                    continue
-                if j not in lev:
-                    lev[j] = cand
-                    if j < i:
-                        heapq.heappush(heap, j)
-                elif cand < lev[j]:
-                    lev[j] = cand
-        rows.append({j: l for j, l in lev.items() if l <= level})
-    indptr = np.zeros(n + 1, dtype=np.int64)
-    indptr[1:] = np.cumsum([len(r) for r in rows])
-    indices = np.concatenate([np.array(sorted(r), dtype=np.int64) for r in rows])
-    levs = np.concatenate([np.array([r[j] for j in sorted(r)], dtype=np.int64) for r in rows])
-    _PATTERN_CACHE[key] = (indptr, indices, levs)
-    return _PATTERN_CACHE[key]
+    ip0 = np.ascontiguousarray(indptr0, dtype=np.int32)
+    ix0 = np.ascontiguousarray(indices0, dtype=np.int32)
+    cap = max(4 * ix0.size, 1024)
+    while True:
+        indptr = np.zeros(n + 1, dtype=np.int64)
+        indices = np.zeros(cap, dtype=np.int32)
+        levs = np.zeros(cap, dtype=np.int32)
+        nnz = clib.lib().oracle_iluk_symbolic(n, clib.ptr(ip0), clib.ptr(ix0), int(level), cap, clib.ptr(indptr),
+                                              clib.ptr(indices), clib.ptr(levs))
+        if nnz >= 0:
+            break
+        if cap > 64 * n * n:
+            raise MemoryError("ilu_pattern")
+        cap *= 2
+    out = (indptr, indices[:nnz].astype(np.int64), levs[:nnz].astype(np.int64))
+    _PATTERN_CACHE[key] = out
+    return out
 
 
 def block_values(A_box: sp.csr_matrix, indptr, indices):

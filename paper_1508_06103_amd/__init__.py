@@ -96,6 +96,8 @@ _sig = {
     "ras_query_boxes": (ctypes.c_int, [_vp, _c_i32p]),
     "ras_factor_bytes": (ctypes.c_int64, [_vp]),
     "ras_query_apply_rows": (ctypes.c_int32, [_vp]),
+    "ras_subdomain_blocks": (ctypes.c_int64, [_vp, ctypes.c_int32]),
+    "ras_export_factors_csr": (ctypes.c_int, [_vp, ctypes.c_int32, _c_i32p, _c_i32p, _c_dp]),
     "ras_export_factors": (ctypes.c_int, [_vp, ctypes.c_int32, _c_dp]),
     "coarse_setup": (ctypes.c_int, [_vp, ctypes.POINTER(_CoarseParams), _vp, ctypes.POINTER(_vp)]),
     "coarse_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -269,14 +271,15 @@ class KKTOperator:
 class RAS:
     """One-level space-time restricted additive Schwarz preconditioner."""
 
-    def __init__(self, op: KKTOperator, parts, overlap, precision=F64, stream=None):
+    def __init__(self, op: KKTOperator, parts, overlap, precision=F64, stream=None, ilu_level=0):
         self.op = op
         self.alloc = op.alloc   # the library frees this handle's memory through these callbacks
         rp = _RasParams()
         rp.p = (ctypes.c_int32 * 4)(*parts)
         rp.overlap = int(overlap)
         rp.precision = int(precision)
-        rp.ilu_level = 0
+        rp.ilu_level = int(ilu_level)
+        self.ilu_level = int(ilu_level)
         h = ctypes.c_void_p()
         _check(_lib.ras_setup(op.handle, ctypes.byref(rp), _stream(stream), ctypes.byref(h)))
         self.handle = h
@@ -297,6 +300,21 @@ class RAS:
     @property
     def factor_bytes(self):
         return int(_lib.ras_factor_bytes(self.handle))
+
+    def export_factors_csr(self, sub):
+        """(indptr, indices, blocks[n, 3, 3]) of one subdomain in natural row order
+        (L left of the diagonal, inv(U_rr) on it, U right of it), any ILU level."""
+        n = int(_lib.ras_subdomain_blocks(self.handle, int(sub)))
+        if n < 0:
+            raise ValueError("bad subdomain")
+        b = self.boxes()[sub]
+        rows = int(np.prod(b[12:16] - b[8:12]))
+        indptr = np.zeros(rows + 1, dtype=np.int32)
+        indices = np.zeros(n, dtype=np.int32)
+        blocks = np.zeros((n, 3, 3))
+        _check(_lib.ras_export_factors_csr(self.handle, int(sub), indptr.ctypes.data_as(_c_i32p),
+                                           indices.ctypes.data_as(_c_i32p), blocks.ctypes.data_as(_c_dp)))
+        return indptr, indices, blocks
 
     @property
     def apply_rows(self):

@@ -11,6 +11,8 @@
 namespace stkkt {
 
 void ras_export(const ras *R, int sub, double *out);
+int64_t ras_sub_blocks(const ras *R, int sub);
+void ras_export_csr(const ras *R, int sub, int32_t *indptr, int32_t *indices, double *blocks);
 
 namespace {
 thread_local std::string g_last_error;
@@ -212,6 +214,19 @@ int ras_export_factors(const ras_t *R, int32_t sub, double *host_out) {
   return guarded([&] {
     STKKT_REQUIRE(R && host_out, "ras_export_factors: NULL argument");
     ras_export(R, sub, host_out);
+    return STKKT_OK;
+  });
+}
+
+int64_t ras_subdomain_blocks(const ras_t *R, int32_t sub) {
+  if (!R || sub < 0 || sub >= R->nsub) return -1;
+  return ras_sub_blocks(R, sub);
+}
+
+int ras_export_factors_csr(const ras_t *R, int32_t sub, int32_t *indptr, int32_t *indices, double *blocks) {
+  return guarded([&] {
+    STKKT_REQUIRE(R && indptr && indices && blocks, "ras_export_factors_csr: NULL argument");
+    ras_export_csr(R, sub, indptr, indices, blocks);
     return STKKT_OK;
   });
 }

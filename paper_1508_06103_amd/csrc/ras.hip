@@ -19,6 +19,8 @@
 #include <memory>
 #include <tuple>
 
+#include "block33.hpp"
+#include "iluk.hpp"
 #include "ras.hpp"
 #include "stencil.hpp"
 
@@ -156,40 +158,6 @@ ShapeHost make_shape(const int dims[4]) {
 // workgroup per subdomain, rows of a level in parallel (one thread per row).
 // W holds the subdomain's rows padded to 81 blocks: W[rho][s][e].
 // --------------------------------------------------------------------------
-__device__ inline void inv33_pivot(const double *a, double *out, bool &ok) {
-  double m[3][6];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) {
-      m[r][c] = a[3 * r + c];
-      m[r][3 + c] = (r == c) ? 1.0 : 0.0;
-    }
-  ok = true;
-  for (int col = 0; col < 3; ++col) {
-    int piv = col;
-    for (int r = col + 1; r < 3; ++r)
-      if (fabs(m[r][col]) > fabs(m[piv][col])) piv = r;
-    if (!(fabs(m[piv][col]) > 0.0)) {
-      ok = false;
-      return;
-    }
-    if (piv != col)
-      for (int c = 0; c < 6; ++c) {
-        double t = m[col][c];
-        m[col][c] = m[piv][c];
-        m[piv][c] = t;
-      }
-    const double dinv = 1.0 / m[col][col];
-    for (int c = 0; c < 6; ++c) m[col][c] *= dinv;
-    for (int r = 0; r < 3; ++r) {
-      if (r == col) continue;
-      const double f = m[r][col];
-      for (int c = 0; c < 6; ++c) m[r][c] -= f * m[col][c];
-    }
-  }
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) out[3 * r + c] = m[r][3 + c];
-}
-
 __global__ void __launch_bounds__(256) factor_kernel(OpDev op, const SubInfo *__restrict__ subs,
                                                      const ShapeInfo *__restrict__ shapes,
                                                      const int32_t *__restrict__ lvl_start,
@@ -1193,19 +1161,26 @@ static void launch_apply(const ras *R, const double *r, double *z, T *Y, hipStre
 }
 
 size_t ras_local_bytes(const ras *R) {
+  if (R->iluk) return iluk_local_bytes(R);
   const size_t esz = R->params.precision == STKKT_F32 ? sizeof(float) : sizeof(double);
   return esz * ((size_t)R->scratch_elems + 4);
 }
 
 bool ras_uses_ring(const ras *R) {
+  if (R->iluk) return false;
   return (R->params.precision == STKKT_F32 ? ring_rows<float>(R) : ring_rows<double>(R)) == 256;
 }
 
 int ras_apply_rows_per_phase(const ras *R) {
+  if (R->iluk) return 0;
   return R->params.precision == STKKT_F32 ? ring_rows<float>(R) : ring_rows<double>(R);
 }
 
 void ras_apply_device(const ras *R, const double *r, double *z, hipStream_t s, void *local) {
+  if (R->iluk) {
+    iluk_apply(R, r, z, local, s);
+    return;
+  }
   if (R->params.precision == STKKT_F32)
     launch_apply<float>(R, r, z, local ? static_cast<float *>(local) : R->scratch.as<float>(), s);
   else
@@ -1315,7 +1290,7 @@ template <class V> static void upload(const Allocator *al, DevBuf &buf, const st
 
 ras *ras_create(const kkt_op *op, const ras_params_t *rp, hipStream_t s) {
   STKKT_REQUIRE(rp != nullptr, "ras_setup: params is NULL");
-  STKKT_REQUIRE(rp->ilu_level == 0, "ras_setup: only ILU(0) is supported");
+  STKKT_REQUIRE(rp->ilu_level >= 0 && rp->ilu_level <= 3, "ras_setup: ilu_level must be 0, 1, 2 or 3");
   STKKT_REQUIRE(rp->precision == STKKT_F64 || rp->precision == STKKT_F32, "ras_setup: bad precision");
   STKKT_REQUIRE(rp->overlap >= 0, "ras_setup: negative overlap");
   const int L[4] = {op->d.nn[0], op->d.nn[1], op->d.nn[2], op->d.M + 1};
@@ -1379,6 +1354,11 @@ ras *ras_create(const kkt_op *op, const ras_params_t *rp, hipStream_t s) {
         }
   R->factor_elems = fb;
   R->scratch_elems = sb;
+  if (rp->ilu_level > 0) {   // ILU(k): its own pattern, layout and kernels
+    R->total_blocks = 0;
+    iluk_create(R.get(), op, s);
+    return R.release();
+  }
   // launch order: largest boxes first, so that the last workgroups to start are the short ones
   std::vector<int32_t> order(nsub);
   for (int i = 0; i < nsub; ++i) order[i] = i;
@@ -1480,6 +1460,7 @@ ras *ras_create(const kkt_op *op, const ras_params_t *rp, hipStream_t s) {
 
 void ras_export(const ras *R, int sub, double *out) {
   STKKT_REQUIRE(sub >= 0 && sub < R->nsub, "ras_export_factors: bad subdomain");
+  STKKT_REQUIRE(!R->iluk, "ras_export_factors: ILU(k) factors have no 81-slot layout; use ras_export_factors_csr");
   const SubInfo &sd = R->subs[sub];
   const ShapeHost &sh = R->shapes[sd.shape];
   const int64_t nb = sh.felems;
@@ -1516,6 +1497,39 @@ void ras_export(const ras *R, int sub, double *out) {
         }
         if (k != cnt) throw Error(STKKT_EINVAL, "ras_export_factors: inconsistent layout");
       }
+  }
+}
+
+int64_t ras_sub_blocks(const ras *R, int sub) {
+  STKKT_REQUIRE(sub >= 0 && sub < R->nsub, "ras_subdomain_blocks: bad subdomain");
+  if (R->iluk) return iluk_subdomain_blocks(R, sub);
+  return R->shapes[R->subs[sub].shape].nblocks;
+}
+
+void ras_export_csr(const ras *R, int sub, int32_t *indptr, int32_t *indices, double *blocks) {
+  STKKT_REQUIRE(sub >= 0 && sub < R->nsub, "ras_export_factors_csr: bad subdomain");
+  if (R->iluk) {
+    iluk_export_csr(R, sub, indptr, indices, blocks);
+    return;
+  }
+  const ShapeHost &sh = R->shapes[R->subs[sub].shape];
+  std::vector<double> pad((size_t)sh.vol * 729);
+  ras_export(R, sub, pad.data());
+  const int lx = sh.dims[0], ly = sh.dims[1], lz = sh.dims[2];
+  const int32_t d32[4] = {sh.dims[0], sh.dims[1], sh.dims[2], sh.dims[3]};
+  int64_t k = 0;
+  indptr[0] = 0;
+  for (int rho = 0; rho < sh.vol; ++rho) {
+    const int x = rho % lx, y = (rho / lx) % ly, z = (rho / (lx * ly)) % lz, t = rho / (lx * ly * lz);
+    for (int s = 0; s < 81; ++s) {   // ascending slot = ascending column
+      int dx, dy, dz, dt;
+      slot_off(s, dx, dy, dz, dt);
+      if (!inside(x + dx, y + dy, z + dz, t + dt, d32)) continue;
+      indices[k] = (x + dx) + lx * ((y + dy) + ly * ((z + dz) + lz * (t + dt)));
+      for (int e = 0; e < 9; ++e) blocks[9 * k + e] = pad[(size_t)rho * 729 + 9 * s + e];
+      ++k;
+    }
+    indptr[rho + 1] = (int32_t)k;
   }
 }
 

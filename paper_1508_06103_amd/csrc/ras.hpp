@@ -1,9 +1,13 @@
 // One-level space-time restricted additive Schwarz: data structures.
 #pragma once
 
+#include <memory>
+
 #include "common.hpp"
 
 namespace stkkt {
+
+struct IlukData;
 
 // Per subdomain (device table).
 struct SubInfo {
@@ -59,6 +63,7 @@ struct ras {
   stkkt::DevBuf d_subs, d_shapes, d_lvl, d_coords, d_ctab, d_order, d_tz;
   stkkt::DevBuf factors;   // double or float, grouped (blk_pos), 16 zero elements at the end
   stkkt::DevBuf scratch;   // local vectors
+  std::shared_ptr<stkkt::IlukData> iluk;   // ILU(k), k > 0: factors, tables and local vectors (else null)
 };
 
 namespace stkkt {

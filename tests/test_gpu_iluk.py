@@ -1,0 +1,156 @@
+"""GPU parity of the ILU(k) subdomain solves (k = 1, 2) against the oracle:
+the level-k pattern bit for bit, the factors, the RAS application per slot,
+the solve, and the batched form."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import kkt, krylov, ras as oras
+from workloads.generate import make_custom, make_problem, OTD, H1L2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def st():
+    import paper_1508_06103_amd as st_mod
+    assert torch.cuda.is_available()
+    return st_mod
+
+
+CASES = {
+    "cube8x16": None,
+    "ragged": dict(n=(5, 6, 7), M=9, seed=3, lattice=2),
+    "aniso_otd": dict(n=(7, 3, 4), M=6, seed=4, lattice=2, variant=OTD, faces=0b010011),
+    "neumann_all": dict(n=(4, 4, 4), M=5, seed=5, lattice=2, faces=0),
+    "h1l2": dict(n=(4, 5, 3), M=6, seed=7, lattice=2, reg=H1L2),
+}
+
+
+def problem(name):
+    spec = CASES[name]
+    if spec is None:
+        return make_problem("cube8x16")[0]
+    spec = dict(spec)
+    n, M, seed = spec.pop("n"), spec.pop("M"), spec.pop("seed")
+    return make_custom(n, M, seed, **spec)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.mark.parametrize("name,parts,delta,level", [("cube8x16", (2, 2, 2, 2), 1, 1), ("cube8x16", (2, 2, 2, 2), 1, 2),
+                                                    ("ragged", (2, 3, 2, 3), 1, 2), ("aniso_otd", (2, 1, 2, 2), 1, 1),
+                                                    ("neumann_all", (1, 2, 2, 1), 0, 2), ("h1l2", (2, 2, 1, 2), 1, 1),
+                                                    ("neumann_all", (1, 2, 2, 1), 1, 3)])
+def test_iluk_pattern_factors_and_apply(st, name, parts, delta, level):
+    prob = problem(name)
+    _say(f"case {name}: parts={parts} overlap={delta} ILU({level})")
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, parts, delta, ilu_level=level)
+    terms = kkt.kkt_terms(prob)
+    R = oras.RAS(prob, parts, delta, terms=terms, ilu_level=level)
+    ref = np.array([list(s.own_lo) + list(s.own_hi) + list(s.box_lo) + list(s.box_hi) for s in R.subs])
+    assert np.array_equal(pre.boxes(), ref)
+    assert pre.factor_bytes == 72 * sum(int(R.ilu[i].indices.size) for i in R.ilu)
+    for sid in sorted({0, len(R.subs) // 2, len(R.subs) - 1}):
+        ip, ix, blk = pre.export_factors_csr(sid)
+        wp, wx, wb = R.ilu[sid].csr()
+        assert np.array_equal(ip, wp) and np.array_equal(ix, wx)   # the level-k pattern, bit for bit
+        rows = np.repeat(np.arange(ip.size - 1), np.diff(ip))
+        scale = np.zeros(ip.size - 1)
+        np.maximum.at(scale, rows, np.abs(wb).max(axis=(1, 2)))
+        err = (np.abs(blk - wb).max(axis=(1, 2)) / scale[rows]).max()
+        _say(f"  sub {sid}: {ix.size} blocks, factor max rel err (per row) {err:.2e}")
+        assert err <= 1e-11
+    r = np.random.default_rng(2).standard_normal(prob.unknowns)
+    z = pre.apply(_dev(r)).cpu().numpy()
+    z_ref = R.apply(r)
+    err = np.linalg.norm(z - z_ref) / np.linalg.norm(z_ref)
+    zs, zr = z.reshape(-1, 3), z_ref.reshape(-1, 3)
+    slot = np.abs(zs - zr).max(axis=0) / np.abs(zr).max(axis=0)
+    _say(f"  apply rel err {err:.2e}, per slot {', '.join(f'{e:.1e}' for e in slot)}")
+    assert err <= 1e-11 and slot.max() <= 1e-10
+
+
+def test_ilu0_csr_export_matches_oracle(st):
+    """The block-CSR export of ILU(0) factors: the 81-point pattern and the values."""
+    prob = problem("ragged")
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, (2, 3, 2, 3), 1)
+    R = oras.RAS(prob, (2, 3, 2, 3), 1)
+    for sid in (0, 17):
+        ip, ix, blk = pre.export_factors_csr(sid)
+        wp, wx, wb = R.ilu[sid].csr()
+        assert np.array_equal(ip, wp) and np.array_equal(ix, wx)
+        assert np.abs(blk - wb).max() <= 1e-11 * np.abs(wb).max()
+
+
+def test_iluk_f32_factors(st):
+    prob = problem("cube8x16")
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, (2, 2, 2, 2), 1, precision=st.F32, ilu_level=1)
+    R = oras.RAS(prob, (2, 2, 2, 2), 1, ilu_level=1)
+    r = np.random.default_rng(3).standard_normal(prob.unknowns)
+    z = pre.apply(_dev(r)).cpu().numpy()
+    z_ref = R.apply(r)
+    err = np.linalg.norm(z - z_ref) / np.linalg.norm(z_ref)
+    _say(f"  ILU(1) f32 apply rel err {err:.2e}")
+    assert err <= 1e-3
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_iluk_solve_parity(st, level):
+    prob = problem("cube8x16")
+    parts, restart = (2, 2, 2, 2), 30
+    op = st.KKTOperator(prob)
+    pre = st.RAS(op, parts, 1, ilu_level=level)
+    terms = kkt.kkt_terms(prob)
+    F = kkt.assemble(prob, terms=terms)
+    b = kkt.rhs(prob)
+    R = oras.RAS(prob, parts, 1, terms=terms, ilu_level=level)
+    x, s = st.solve(op, pre, restart=restart, rtol=1e-6)
+    xo, so = krylov.gmres(lambda v: F @ v, R.apply, b, restart=restart, rtol=1e-6)
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(b - F @ xg) / np.linalg.norm(b)
+    _say(f"  ILU({level}): gpu its {s.iters} oracle its {so.iters} true res {res:.2e}")
+    assert s.converged and res <= 1e-6 and abs(s.iters - so.iters) <= 1
+    k = so.iters
+    x2, _ = st.solve(op, pre, restart=restart, rtol=1e-6, fixed_iters=k)
+    xo2, _ = krylov.gmres(lambda v: F @ v, R.apply, b, restart=restart, rtol=1e-6, fixed_iters=k)
+    e = np.linalg.norm(x2.cpu().numpy() - xo2) / np.linalg.norm(xo2)
+    _say(f"  fixed {k} iterations: rel diff {e:.2e}")
+    assert e <= 1e-7
+
+
+def test_iluk_in_batch_equals_alone(st):
+    """ILU(1) preconditioners in a batch (one launch per member) give the
+    members' results bit for bit as when each is solved alone."""
+    probs = [problem("cube8x16"), problem("ragged")]
+    parts = [(2, 2, 2, 2), (2, 3, 2, 3)]
+    ops = [st.KKTOperator(p) for p in probs]
+    pres = [st.RAS(op, pp, 1, ilu_level=1) for op, pp in zip(ops, parts)]
+    xs, sts = st.solve_batch(ops, pres, restart=20, rtol=1e-6)
+    for i in range(2):
+        xa, sa = st.solve_batch([ops[i]], [pres[i]], restart=20, rtol=1e-6)
+        _say(f"  member {i}: {sts[i].iters} its in the batch, {sa[0].iters} alone")
+        assert sts[i].converged and sa[0].iters == sts[i].iters
+        assert torch.equal(xa[0], xs[i])
+
+
+def test_iluk_level_out_of_range(st):
+    op = st.KKTOperator(problem("neumann_all"))
+    with pytest.raises(st.StkktError) as e:
+        st.RAS(op, (1, 2, 2, 1), 0, ilu_level=4)
+    assert e.value.code == st.EINVAL
+    pre = st.RAS(op, (1, 2, 2, 1), 0, ilu_level=1)
+    with pytest.raises(st.StkktError):
+        pre.export_factors(0)
