@@ -453,6 +453,77 @@ def run_overlap(args):
             "sweep": rows}
 
 
+def run_ilu(args):
+    """The fill-level study of the paper's two-level method (Section 4, the
+    table of ILU(k) levels).  Default mesh: the paper's 41^3 nodes x 41 time
+    levels (8,477,283 unknowns, `--ilu-mesh 40`), 4x4x4x4 = 256 subdomains with
+    overlap 1, coarse mesh 21^3 x 21 (factor 2 in space and time) with the
+    paper's coarse GMRES(4) to 0.1 and coarse RAS 4x4x4x4 overlap 1, ILU(0);
+    FGMRES(50) to 1e-6.  Fine subdomain solves ILU(k) for the levels given per
+    factor precision (the default levels are those whose factors fit the
+    device at this mesh).  Synthetic cube32x64-style sources and 64 lattice
+    sensors (on coarse nodes).  Reports iterations, solve time, time per
+    iteration, factor bytes and the apply's bandwidth per k."""
+    import numpy as np
+    import torch
+    import paper_1508_06103_amd as st
+    from workloads.generate import make_problem, redraw_noise
+    m = args.ilu_mesh
+    prob, _ = make_problem("cube32x64", n=m, M=m, lattice=4 if m % 5 == 0 else 3)
+    op = st.KKTOperator(prob)
+    parts, fac = (4, 4, 4, 4), (2, 2, 2, 2)
+    b = op.rhs(redraw_noise(prob, 78))
+    rows = []
+    plan = [("f32", args.ilu_levels_f32), ("f64", args.ilu_levels_f64)]
+    for prec_name, levels in plan:
+        levels = [int(k) for k in levels.split(",") if k != ""]
+        if not levels:
+            continue
+        prec = st.F32 if prec_name == "f32" else st.F64
+        C = st.Coarse(op, fac, parts, overlap=1, maxit=4, rtol=0.1, precision=prec, method=st.COARSE_GMRES_RAS)
+        for k in levels:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pre = st.RAS(op, parts, 1, precision=prec, ilu_level=k)
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+            times = []
+            for rep in range(2):
+                x = torch.zeros_like(b)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, s = st.solve(op, pre, b, x, coarse=C, restart=50, rtol=1e-6, flexible=True)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                assert s.converged and s.rel_res_true <= 1e-6
+            km = time_kernels(op, pre, 5)
+            abytes = algorithmic_apply_bytes(pre, prob)
+            kname = apply_kernel_name(pre, prec_name) if k == 0 else \
+                f"iluk_apply_kernel<{'float' if prec == st.F32 else 'double'}>"
+            row = {"precision": prec_name, "ilu_level": k, "iters": s.iters, "solve_ms": 1e3 * min(times),
+                   "ms_per_iter": 1e3 * min(times) / s.iters, "ras_setup_ms": 1e3 * t_setup,
+                   "factor_gb": pre.factor_bytes / 1e9, "ras_apply_ms": km["ras_apply"],
+                   "ras_apply_gbs": abytes / (km["ras_apply"] * 1e-3) / 1e9, "ras_apply_kernel": kname}
+            rows.append(row)
+            print(f"[bench] {prec_name} ILU({k}): {s.iters} its, solve {row['solve_ms']:.0f} ms "
+                  f"({row['ms_per_iter']:.2f} ms/it), setup {row['ras_setup_ms']:.0f} ms, factors "
+                  f"{row['factor_gb']:.1f} GB, apply {row['ras_apply_ms']:.2f} ms ({row['ras_apply_gbs']:.0f} GB/s)",
+                  file=sys.stderr, flush=True)
+            pre.close()
+            torch.cuda.empty_cache()
+        C.close()
+    first = rows[0]
+    return {"metric": "FGMRES iterations and time per iteration vs ILU fill level k (two-level)",
+            "value": first["iters"], "unit": f"iterations at ILU({first['ilu_level']}), {first['precision']} factors",
+            "n_gpus": 1, "steps": 2, "warmup": 0, "ms_per_step": first["solve_ms"], "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64 outer / f32 and f64 factors",
+            "data": "synthetic (seeded moving-Gaussian sources, lattice sensors, 1% noise)",
+            "config": {"workload": f"{m + 1}^3 nodes x {m + 1} levels ({prob.unknowns} unknowns), RAS 4x4x4x4 overlap 1 "
+                                   f"ILU(k), coarse {m // 2 + 1}^3 x {m // 2 + 1} GMRES(4) rtol 0.1 with coarse RAS "
+                                   "4x4x4x4 overlap 1, FGMRES(50), rtol 1e-6"},
+            "sweep": rows}
+
+
 def run_serve(args):
     """Poisson request stream through the server (continuous batching, FP32
     preconditioners, FP64 FGMRES(50)); 90% of requests on 16 operators drawn
@@ -769,13 +840,16 @@ def main():
                     help="single mode: skip the FP32-preconditioner run of cube48x96 and the cube32x64 run")
     ap.add_argument("--kernels-only", action="store_true",
                     help="no solves: time ras_apply, kkt_matvec and a plain 1 GiB device copy (for counter runs)")
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "coarse", "overlap"],
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "coarse", "overlap", "ilu"],
                     help="single: one operator, one solve per step (default); batch: 64 uneven instances per "
                          "step; serve: Poisson request stream through the server; coarse: the exact coarse "
                          "solve with one and with several right-hand sides; overlap: the paper's overlap study "
-                         "of the two-level method")
+                         "of the two-level method; ilu: the paper's ILU fill-level study of the two-level method")
     ap.add_argument("--coarse", default="lu", choices=["lu", "gmres"],
                     help="two-level configurations: exact block-LU coarse solve, or the paper's coarse GMRES(4)+RAS")
+    ap.add_argument("--ilu-mesh", type=int, default=40, help="ilu mode: elements per axis and time steps")
+    ap.add_argument("--ilu-levels-f32", default="0,1,2", help="ilu mode: fill levels k run with FP32 factors")
+    ap.add_argument("--ilu-levels-f64", default="0,1", help="ilu mode: fill levels k run with FP64 factors")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--parts", default="tuned", choices=["tuned", "box8"],
                     help="batch/serve partitions: the autotuned table, or boxes of about 8 nodes with overlap 1")
@@ -801,6 +875,9 @@ def main():
         return
     if args.mode == "overlap":
         print(json.dumps(run_overlap(args)), flush=True)
+        return
+    if args.mode == "ilu":
+        print(json.dumps(run_ilu(args)), flush=True)
         return
     if args.kernels_only:
         run_kernels_only(args)

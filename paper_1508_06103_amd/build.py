@@ -52,7 +52,7 @@ def build(verbose: bool = True) -> str:
     if failed:
         raise RuntimeError("hipcc failed")
     tmp = LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -2,9 +2,12 @@
 // numeric factorisation and the two triangular sweeps (device).  Layout and
 // ordering are described in iluk.hpp.
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstdlib>
+#include <exception>
 #include <queue>
+#include <thread>
 
 #include "block33.hpp"
 #include "iluk.hpp"
@@ -152,8 +155,8 @@ IlukShapeHost make_iluk_shape(const int dims[4], int level) {
       }
       ch.foff = foff;
       ch.coff = coff;
-      foff += (int64_t)(ch.lmax + 1 + ch.umax) * 9 * 64;
-      coff += (int64_t)(ch.lmax + ch.umax) * 64;
+      foff += (int64_t)(ch.lmax + 1 + ch.umax) * 9 * ch.rows;
+      coff += (int64_t)(ch.lmax + ch.umax) * ch.rows;
       sh.chunks.push_back(ch);
     }
     p = end;
@@ -167,8 +170,8 @@ IlukShapeHost make_iluk_shape(const int dims[4], int level) {
       const int i = order[ch.pos0 + q];
       int e = 0, u = 0;
       for (int j : rows[i].col) {
-        if (j < i) sh.cols[ch.coff + (int64_t)e++ * 64 + q] = pos[j];
-        else if (j > i) sh.cols[ch.coff + (int64_t)(ch.lmax + u++) * 64 + q] = pos[j];
+        if (j < i) sh.cols[ch.coff + (int64_t)e++ * ch.rows + q] = pos[j];
+        else if (j > i) sh.cols[ch.coff + (int64_t)(ch.lmax + u++) * ch.rows + q] = pos[j];
       }
     }
   sh.indptr.assign(n + 1, 0);
@@ -187,22 +190,20 @@ IlukShapeHost make_iluk_shape(const int dims[4], int level) {
 //   then inv(U_ii).
 // W is the FP64 ELL layout of the factors.
 // ---------------------------------------------------------------------------
-struct RowRef {
-  const IlukChunk *ch;
-  int lane;
-};
-
+// Blocks of a chunk: entry e of the chunk's row q, element v, at
+// foff + (e 9 + v) rows + q (L entries, then the diagonal, then U entries).
 __device__ inline double *lblk(double *Wb, const IlukChunk &ch, int e, int lane) {
-  return Wb + ch.foff + (int64_t)e * 9 * 64 + lane;
+  return Wb + ch.foff + (int64_t)e * 9 * ch.rows + lane;
 }
 __device__ inline double *dblk(double *Wb, const IlukChunk &ch, int lane) {
-  return Wb + ch.foff + (int64_t)ch.lmax * 9 * 64 + lane;
+  return Wb + ch.foff + (int64_t)ch.lmax * 9 * ch.rows + lane;
 }
 __device__ inline double *ublk(double *Wb, const IlukChunk &ch, int e, int lane) {
-  return Wb + ch.foff + (int64_t)(ch.lmax + 1 + e) * 9 * 64 + lane;
+  return Wb + ch.foff + (int64_t)(ch.lmax + 1 + e) * 9 * ch.rows + lane;
 }
 
-__device__ inline void init_block(const OpDev &op, const SubInfo &sd, uint64_t ci, uint64_t cj, double *dst) {
+__device__ inline void init_block(const OpDev &op, const SubInfo &sd, uint64_t ci, uint64_t cj, double *dst,
+                                  int rs) {
   int xi, yi, zi, ti, xj, yj, zj, tj;
   unpack4(ci, xi, yi, zi, ti);
   unpack4(cj, xj, yj, zj, tj);
@@ -213,10 +214,10 @@ __device__ inline void init_block(const OpDev &op, const SubInfo &sd, uint64_t c
   } else {
     for (int e = 0; e < 9; ++e) blk[e] = 0.0;   // fill entry: zero in F_h
   }
-  for (int e = 0; e < 9; ++e) dst[e * 64] = blk[e];
+  for (int e = 0; e < 9; ++e) dst[e * rs] = blk[e];
 }
 
-__global__ void __launch_bounds__(256) iluk_factor_kernel(OpDev op, const SubInfo *__restrict__ subs,
+__global__ void __launch_bounds__(256) iluk_factor_kernel(OpDev op, const SubInfo *__restrict__ subs, int sub0,
                                                           const IlukShapeDev *__restrict__ shapes,
                                                           const IlukChunk *__restrict__ chunks,
                                                           const int32_t *__restrict__ lvl_chunk,
@@ -227,9 +228,9 @@ __global__ void __launch_bounds__(256) iluk_factor_kernel(OpDev op, const SubInf
                                                           const int16_t *__restrict__ nU,
                                                           const int32_t *__restrict__ cols, double *W,
                                                           int *status) {
-  const SubInfo sd = subs[blockIdx.x];
+  const SubInfo sd = subs[sub0 + blockIdx.x];
   const IlukShapeDev sh = shapes[sd.shape];
-  double *Wb = W + sd.fbase;
+  double *Wb = W + sd.wbase;
   const IlukChunk *chs = chunks + sh.chunk_off;
   const uint64_t *crd = coords + sh.pos_off;
   const int32_t *rh = rho + sh.pos_off, *pc = pchunk + sh.pos_off, *cl = cols + sh.col_off;
@@ -239,19 +240,20 @@ __global__ void __launch_bounds__(256) iluk_factor_kernel(OpDev op, const SubInf
     const int p0 = chs[c0].pos0, p1 = chs[c1 - 1].pos0 + chs[c1 - 1].rows;
     for (int pi = p0 + (int)threadIdx.x; pi < p1; pi += blockDim.x) {
       const IlukChunk ch = chs[pc[pi]];
-      const int q = pi - ch.pos0;
+      const int q = pi - ch.pos0, rs = ch.rows;
       const int ni = nl[pi], mi = nu[pi];
       const uint64_t ci = crd[pi];
-      for (int e = 0; e < ni; ++e) init_block(op, sd, ci, crd[cl[ch.coff + (int64_t)e * 64 + q]], lblk(Wb, ch, e, q));
-      init_block(op, sd, ci, ci, dblk(Wb, ch, q));
+      for (int e = 0; e < ni; ++e)
+        init_block(op, sd, ci, crd[cl[ch.coff + (int64_t)e * rs + q]], lblk(Wb, ch, e, q), rs);
+      init_block(op, sd, ci, ci, dblk(Wb, ch, q), rs);
       for (int e = 0; e < mi; ++e)
-        init_block(op, sd, ci, crd[cl[ch.coff + (int64_t)(ch.lmax + e) * 64 + q]], ublk(Wb, ch, e, q));
+        init_block(op, sd, ci, crd[cl[ch.coff + (int64_t)(ch.lmax + e) * rs + q]], ublk(Wb, ch, e, q), rs);
       const int ri = rh[pi];
       // natural column of position t of row i's sequence: L entries, diagonal, U entries
       auto rho_at = [&](int t) -> int {
-        if (t < ni) return rh[cl[ch.coff + (int64_t)t * 64 + q]];
+        if (t < ni) return rh[cl[ch.coff + (int64_t)t * rs + q]];
         if (t == ni) return ri;
-        return rh[cl[ch.coff + (int64_t)(ch.lmax + t - ni - 1) * 64 + q]];
+        return rh[cl[ch.coff + (int64_t)(ch.lmax + t - ni - 1) * rs + q]];
       };
       auto blk_at = [&](int t) -> double * {
         if (t < ni) return lblk(Wb, ch, t, q);
@@ -260,24 +262,24 @@ __global__ void __launch_bounds__(256) iluk_factor_kernel(OpDev op, const SubInf
       };
       const int len = ni + 1 + mi;
       for (int e = 0; e < ni; ++e) {
-        const int pk = cl[ch.coff + (int64_t)e * 64 + q];
+        const int pk = cl[ch.coff + (int64_t)e * rs + q];
         const IlukChunk chk = chs[pc[pk]];
-        const int qk = pk - chk.pos0;
+        const int qk = pk - chk.pos0, rk = chk.rows;
         double *wl = lblk(Wb, ch, e, q);
         const double *dk = dblk(Wb, chk, qk);
         double a[9], d[9], l[9];
         for (int v = 0; v < 9; ++v) {
-          a[v] = wl[v * 64];
-          d[v] = dk[v * 64];
+          a[v] = wl[v * rs];
+          d[v] = dk[v * rk];
         }
         for (int r = 0; r < 3; ++r)
           for (int c = 0; c < 3; ++c) l[3 * r + c] = a[3 * r] * d[c] + a[3 * r + 1] * d[3 + c] + a[3 * r + 2] * d[6 + c];
-        for (int v = 0; v < 9; ++v) wl[v * 64] = l[v];
+        for (int v = 0; v < 9; ++v) wl[v * rs] = l[v];
         int t = e + 1;
         int rt = t < len ? rho_at(t) : INT_MAX;
         const int mk = nu[pk];
         for (int f = 0; f < mk; ++f) {
-          const int pj = cl[chk.coff + (int64_t)(chk.lmax + f) * 64 + qk];
+          const int pj = cl[chk.coff + (int64_t)(chk.lmax + f) * rk + qk];
           const int rj = rh[pj];
           while (rt < rj) {
             ++t;
@@ -286,25 +288,25 @@ __global__ void __launch_bounds__(256) iluk_factor_kernel(OpDev op, const SubInf
           if (rt != rj) continue;
           const double *u = ublk(Wb, chk, f, qk);
           double ub[9];
-          for (int v = 0; v < 9; ++v) ub[v] = u[v * 64];
+          for (int v = 0; v < 9; ++v) ub[v] = u[v * rk];
           double *w = blk_at(t);
           for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) {
               const double s = l[3 * r] * ub[c] + l[3 * r + 1] * ub[3 + c] + l[3 * r + 2] * ub[6 + c];
-              w[(3 * r + c) * 64] -= s;
+              w[(3 * r + c) * rs] -= s;
             }
         }
       }
       double *wd = dblk(Wb, ch, q);
       double dd[9], inv[9];
-      for (int v = 0; v < 9; ++v) dd[v] = wd[v * 64];
+      for (int v = 0; v < 9; ++v) dd[v] = wd[v * rs];
       bool ok;
       inv33_pivot(dd, inv, ok);
       if (!ok) {
         atomicMax(status, 1);
         for (int v = 0; v < 9; ++v) inv[v] = 0.0;
       }
-      for (int v = 0; v < 9; ++v) wd[v * 64] = inv[v];
+      for (int v = 0; v < 9; ++v) wd[v * rs] = inv[v];
     }
     __syncthreads();
   }
@@ -343,18 +345,19 @@ __device__ inline void iluk_sweep(const OpDev &op, const SubInfo &sd, const Iluk
         const bool valid = lane < ch.rows;
         const int n = valid ? (int)cnt[ch.pos0 + lane] : 0;
         const int base = kFwd ? 0 : ch.lmax;                       // column block of the entries
-        const int64_t fo = ch.foff + (kFwd ? 0 : (int64_t)(ch.lmax + 1) * 9 * 64);
+        const int rs = ch.rows;
+        const int64_t fo = ch.foff + (kFwd ? 0 : (int64_t)(ch.lmax + 1) * 9 * rs);
         const int emax = kFwd ? ch.lmax : ch.umax;
         T a0 = 0, a1 = 0, a2 = 0;
         for (int e = wave; e < emax; e += kWaves) {
           if (e < n) {
-            const int col = cl[ch.coff + (int64_t)(base + e) * 64 + lane];
-            const T *f = Fb + fo + (int64_t)e * 9 * 64 + lane;
+            const int col = cl[ch.coff + (int64_t)(base + e) * rs + lane];
+            const T *f = Fb + fo + (int64_t)e * 9 * rs + lane;
             const T *y = Yb + 3 * (int64_t)col;
             const T y0 = y[0], y1 = y[1], y2 = y[2];
-            a0 += f[0] * y0 + f[64] * y1 + f[128] * y2;
-            a1 += f[192] * y0 + f[256] * y1 + f[320] * y2;
-            a2 += f[384] * y0 + f[448] * y1 + f[512] * y2;
+            a0 += f[0] * y0 + f[rs] * y1 + f[2 * rs] * y2;
+            a1 += f[3 * rs] * y0 + f[4 * rs] * y1 + f[5 * rs] * y2;
+            a2 += f[6 * rs] * y0 + f[7 * rs] * y1 + f[8 * rs] * y2;
           }
         }
         part[wave][cc * 64 + lane][0] = a0;
@@ -382,10 +385,12 @@ __device__ inline void iluk_sweep(const OpDev &op, const SubInfo &sd, const Iluk
           if (kFwd) {
             for (int k = 0; k < 3; ++k) yr[k] = (T)r[gi + k] - s[k];
           } else {
-            const T *d = Fb + ch.foff + (int64_t)ch.lmax * 9 * 64 + q;
+            const int rs = ch.rows;
+            const T *d = Fb + ch.foff + (int64_t)ch.lmax * 9 * rs + q;
             T v[3], o[3];
             for (int k = 0; k < 3; ++k) v[k] = yr[k] - s[k];
-            for (int k = 0; k < 3; ++k) o[k] = d[(3 * k) * 64] * v[0] + d[(3 * k + 1) * 64] * v[1] + d[(3 * k + 2) * 64] * v[2];
+            for (int k = 0; k < 3; ++k)
+              o[k] = d[(3 * k) * rs] * v[0] + d[(3 * k + 1) * rs] * v[1] + d[(3 * k + 2) * rs] * v[2];
             for (int k = 0; k < 3; ++k) yr[k] = o[k];
             const bool owned = x >= sd.olo[0] && x < sd.ohi[0] && y >= sd.olo[1] && y < sd.ohi[1] &&
                                zc >= sd.olo[2] && zc < sd.ohi[2] && t >= sd.olo[3] && t < sd.ohi[3];
@@ -430,7 +435,26 @@ template <class V> void upload_vec(const Allocator *al, DevBuf &buf, const std::
 void iluk_create(ras *R, const kkt_op *op, hipStream_t s) {
   auto K = std::make_shared<IlukData>();
   K->level = R->params.ilu_level;
-  for (const ShapeHost &sh0 : R->shapes) K->shapes.push_back(make_iluk_shape(sh0.dims, K->level));
+  // the symbolic factorisations of the distinct box shapes are independent: host threads
+  const int nsh = (int)R->shapes.size();
+  K->shapes.resize(nsh);
+  std::vector<std::exception_ptr> err(nsh);
+  std::atomic<int> next{0};
+  const int nthr = std::max(1, std::min(nsh, (int)std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (int w = 0; w < nthr; ++w)
+    pool.emplace_back([&] {
+      for (int i = next++; i < nsh; i = next++) {
+        try {
+          K->shapes[i] = make_iluk_shape(R->shapes[i].dims, K->level);
+        } catch (...) {
+          err[i] = std::current_exception();
+        }
+      }
+    });
+  for (auto &t : pool) t.join();
+  for (auto &e : err)
+    if (e) std::rethrow_exception(e);
   // subdomain offsets in the ELL layout
   int64_t fb = 0, sb = 0;
   for (SubInfo &si : R->subs) {
@@ -492,28 +516,59 @@ void iluk_create(ras *R, const kkt_op *op, hipStream_t s) {
   upload_vec(al, R->d_order, order, s);
   const bool f32 = R->params.precision == STKKT_F32;
   const size_t esz = f32 ? sizeof(float) : sizeof(double);
-  DevBuf work(al, sizeof(double) * ((size_t)fb + 1));
   DevBuf d_status(al, 256);
   STKKT_HIP(hipMemsetAsync(d_status.ptr, 0, sizeof(int), s));
-  hipLaunchKernelGGL(iluk_factor_kernel, dim3(R->nsub), dim3(256), 0, s, op->d, R->d_subs.as<SubInfo>(),
-                     K->d_shapes.as<IlukShapeDev>(), K->d_chunks.as<IlukChunk>(), K->d_lvl.as<int32_t>(),
-                     K->d_coords.as<uint64_t>(), K->d_rho.as<int32_t>(), K->d_pchunk.as<int32_t>(),
-                     K->d_nL.as<int16_t>(), K->d_nU.as<int16_t>(), K->d_cols.as<int32_t>(), work.as<double>(),
-                     d_status.as<int>());
-  STKKT_HIP(hipGetLastError());
-  if (f32) {
-    K->factors = DevBuf(al, esz * ((size_t)fb + 1));
-    hipLaunchKernelGGL(to_float_kernel, dim3(blocks_for(fb, 256, 16384)), dim3(256), 0, s, work.as<double>(),
-                       K->factors.as<float>(), (long long)fb);
+  K->factors = DevBuf(al, esz * ((size_t)fb + 1));
+  auto factor = [&](int first, int count, double *W) {
+    hipLaunchKernelGGL(iluk_factor_kernel, dim3(count), dim3(256), 0, s, op->d, R->d_subs.as<SubInfo>(), first,
+                       K->d_shapes.as<IlukShapeDev>(), K->d_chunks.as<IlukChunk>(), K->d_lvl.as<int32_t>(),
+                       K->d_coords.as<uint64_t>(), K->d_rho.as<int32_t>(), K->d_pchunk.as<int32_t>(),
+                       K->d_nL.as<int16_t>(), K->d_nU.as<int16_t>(), K->d_cols.as<int32_t>(), W,
+                       d_status.as<int>());
     STKKT_HIP(hipGetLastError());
+  };
+  if (!f32) {
+    // FP64: factor in place
+    for (SubInfo &si : R->subs) si.wbase = si.fbase;
+    STKKT_HIP(hipMemcpyAsync(R->d_subs.ptr, R->subs.data(), sizeof(SubInfo) * R->subs.size(),
+                             hipMemcpyHostToDevice, s));
+    factor(0, R->nsub, K->factors.as<double>());
   } else {
-    K->factors = std::move(work);
+    // FP32: subdomains factored in FP64 in batches that fit a workspace budget, then narrowed
+    size_t budget = (size_t)64 << 30;
+    if (const char *e = getenv("STKKT_SETUP_WORK_GB")) budget = (size_t)(atof(e) * (double)(1ull << 30));
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) budget = std::min(budget, free_b / 2);
+    int first = 0;
+    while (first < R->nsub) {
+      size_t used = 0;
+      int last = first;
+      while (last < R->nsub) {
+        const size_t need = sizeof(double) * (size_t)K->shapes[R->subs[last].shape].felems;
+        if (last > first && used + need > budget) break;
+        R->subs[last].wbase = (int64_t)(used / sizeof(double));
+        used += need;
+        ++last;
+      }
+      STKKT_HIP(hipMemcpyAsync(R->d_subs.ptr, R->subs.data(), sizeof(SubInfo) * R->subs.size(),
+                               hipMemcpyHostToDevice, s));
+      DevBuf work(al, used + sizeof(double));
+      factor(first, last - first, work.as<double>());
+      // the batch's subdomains are contiguous in both layouts
+      const int64_t n0 = R->subs[first].fbase;
+      const int64_t n1 = last < R->nsub ? R->subs[last].fbase : fb;
+      hipLaunchKernelGGL(to_float_kernel, dim3(blocks_for(n1 - n0, 256, 16384)), dim3(256), 0, s, work.as<double>(),
+                         K->factors.as<float>() + n0, (long long)(n1 - n0));
+      STKKT_HIP(hipGetLastError());
+      STKKT_HIP(hipStreamSynchronize(s));   // the workspace is released at the end of this scope
+      first = last;
+    }
   }
   K->scratch = DevBuf(al, esz * ((size_t)sb + 4));
   STKKT_HIP(hipMemsetAsync(K->scratch.ptr, 0, esz * ((size_t)sb + 4), s));
   int status = 0;
   STKKT_HIP(hipMemcpyAsync(&status, d_status.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
-  STKKT_HIP(hipStreamSynchronize(s));   // the FP64 workspace of an FP32 setup is released on return
+  STKKT_HIP(hipStreamSynchronize(s));
   if (status != 0) throw Error(STKKT_EBREAKDOWN, "ras_setup: singular 3x3 pivot block in ILU(k)");
   R->iluk = K;
 }
@@ -574,10 +629,11 @@ void iluk_export_csr(const ras *R, int sub, int32_t *indptr, int32_t *indices, d
     for (int k = sh.indptr[i]; k < sh.indptr[i + 1]; ++k) {
       const int j = sh.indices[k];
       int64_t at;
-      if (j < i) at = ch.foff + (int64_t)e++ * 9 * 64 + q;
-      else if (j == i) at = ch.foff + (int64_t)ch.lmax * 9 * 64 + q;
-      else at = ch.foff + (int64_t)(ch.lmax + 1 + u++) * 9 * 64 + q;
-      for (int v = 0; v < 9; ++v) blocks[9 * (int64_t)k + v] = buf[at + (int64_t)v * 64];
+      const int rs = ch.rows;
+      if (j < i) at = ch.foff + (int64_t)e++ * 9 * rs + q;
+      else if (j == i) at = ch.foff + (int64_t)ch.lmax * 9 * rs + q;
+      else at = ch.foff + (int64_t)(ch.lmax + 1 + u++) * 9 * rs + q;
+      for (int v = 0; v < 9; ++v) blocks[9 * (int64_t)k + v] = buf[at + (int64_t)v * rs];
     }
   }
 }

@@ -19,5 +19,5 @@ def test_help_lists_the_modes():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 0
-    for mode in ("single", "batch", "serve", "coarse", "overlap"):
+    for mode in ("single", "batch", "serve", "coarse", "overlap", "ilu"):
         assert mode in r.stdout

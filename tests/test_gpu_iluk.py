@@ -105,6 +105,16 @@ def test_iluk_f32_factors(st):
     err = np.linalg.norm(z - z_ref) / np.linalg.norm(z_ref)
     _say(f"  ILU(1) f32 apply rel err {err:.2e}")
     assert err <= 1e-3
+    # the FP64 workspace of the FP32 setup in batches of one subdomain: the same factors
+    import os
+    os.environ["STKKT_SETUP_WORK_GB"] = "1e-6"
+    try:
+        pre1 = st.RAS(op, (2, 2, 2, 2), 1, precision=st.F32, ilu_level=1)
+    finally:
+        del os.environ["STKKT_SETUP_WORK_GB"]
+    for sid in (0, 9, 15):
+        assert np.array_equal(pre1.export_factors_csr(sid)[2], pre.export_factors_csr(sid)[2])
+    assert torch.equal(pre1.apply(_dev(r)), pre.apply(_dev(r)))
 
 
 @pytest.mark.parametrize("level", [1, 2])
