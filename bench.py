@@ -487,6 +487,8 @@ def run_ilu(args):
             pre = st.RAS(op, parts, 1, precision=prec, ilu_level=k)
             torch.cuda.synchronize()
             t_setup = time.perf_counter() - t0
+            print(f"[bench] {prec_name} ILU({k}) setup {t_setup:.1f} s, factors {pre.factor_bytes / 1e9:.1f} GB",
+                  file=sys.stderr, flush=True)
             times = []
             for rep in range(2):
                 x = torch.zeros_like(b)

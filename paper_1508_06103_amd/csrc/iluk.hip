@@ -21,6 +21,7 @@ namespace {
 constexpr int kApplyThreads = 512;
 constexpr int kWaves = kApplyThreads / 64;
 constexpr int kPhaseChunks = 4;   // 64-row chunks per phase of the sweeps
+constexpr size_t kFactorLds = 160 * 1024;   // LDS of one gfx950 workgroup
 
 __host__ __device__ inline void unpack4(uint64_t c, int &x, int &y, int &z, int &t) {
   x = (int)(c & 0xffff);
@@ -183,38 +184,41 @@ IlukShapeHost make_iluk_shape(const int dims[4], int level) {
 }
 
 // ---------------------------------------------------------------------------
-// numeric factorisation: one workgroup per subdomain, the rows of a level in
-// parallel (one thread per row), IKJ order inside a row:
+// numeric factorisation: one workgroup per subdomain, one wavefront per row
+// (wavefront w of the workgroup takes the rows w, w + waves, ... of a level),
+// IKJ order inside a row:
 //   for the columns k < i of row i, ascending: L_ik = W_ik inv(U_kk),
-//     W_ij -= L_ik U_kj for every j > k of row k that is in row i;
+//     W_ij -= L_ik U_kj for every j > k of row k that is in row i
+//     (the lanes take the entries of row k; each finds its column in row i by
+//     binary search),
 //   then inv(U_ii).
-// W is the FP64 ELL layout of the factors.
+// The row being factored lives in LDS (its sorted natural columns and its
+// blocks); rows of earlier levels are read from W, the FP64 ELL layout.
 // ---------------------------------------------------------------------------
-// Blocks of a chunk: entry e of the chunk's row q, element v, at
-// foff + (e 9 + v) rows + q (L entries, then the diagonal, then U entries).
-__device__ inline double *lblk(double *Wb, const IlukChunk &ch, int e, int lane) {
-  return Wb + ch.foff + (int64_t)e * 9 * ch.rows + lane;
-}
-__device__ inline double *dblk(double *Wb, const IlukChunk &ch, int lane) {
-  return Wb + ch.foff + (int64_t)ch.lmax * 9 * ch.rows + lane;
-}
-__device__ inline double *ublk(double *Wb, const IlukChunk &ch, int e, int lane) {
-  return Wb + ch.foff + (int64_t)(ch.lmax + 1 + e) * 9 * ch.rows + lane;
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ inline void init_block(const OpDev &op, const SubInfo &sd, uint64_t ci, uint64_t cj, double *dst,
-                                  int rs) {
+// Blocks of a chunk: entry e of the chunk's row q, element v, at
+// foff + (e 9 + v) rows + q (L entries, then the diagonal, then U entries).
+__device__ inline int64_t lpos(const IlukChunk &ch, int e, int lane) { return ch.foff + (int64_t)e * 9 * ch.rows + lane; }
+__device__ inline int64_t dpos(const IlukChunk &ch, int lane) { return ch.foff + (int64_t)ch.lmax * 9 * ch.rows + lane; }
+__device__ inline int64_t upos(const IlukChunk &ch, int e, int lane) {
+  return ch.foff + (int64_t)(ch.lmax + 1 + e) * 9 * ch.rows + lane;
+}
+
+__device__ inline void block_of(const OpDev &op, const SubInfo &sd, uint64_t ci, uint64_t cj, double *blk) {
   int xi, yi, zi, ti, xj, yj, zj, tj;
   unpack4(ci, xi, yi, zi, ti);
   unpack4(cj, xj, yj, zj, tj);
   const int dx = xj - xi, dy = yj - yi, dz = zj - zi, dt = tj - ti;
-  double blk[9];
   if (abs(dx) <= 1 && abs(dy) <= 1 && abs(dz) <= 1 && abs(dt) <= 1) {
     kkt_block(op, sd.org[0] + xi, sd.org[1] + yi, sd.org[2] + zi, sd.org[3] + ti, dx, dy, dz, dt, blk);
   } else {
     for (int e = 0; e < 9; ++e) blk[e] = 0.0;   // fill entry: zero in F_h
   }
-  for (int e = 0; e < 9; ++e) dst[e * rs] = blk[e];
 }
 
 __global__ void __launch_bounds__(256) iluk_factor_kernel(OpDev op, const SubInfo *__restrict__ subs, int sub0,
@@ -226,8 +230,14 @@ __global__ void __launch_bounds__(256) iluk_factor_kernel(OpDev op, const SubInf
                                                           const int32_t *__restrict__ pchunk,
                                                           const int16_t *__restrict__ nL,
                                                           const int16_t *__restrict__ nU,
-                                                          const int32_t *__restrict__ cols, double *W,
+                                                          const int32_t *__restrict__ cols, int maxlen, double *W,
                                                           int *status) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int waves = (int)(blockDim.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = (int)__lane_id();
+  double *rowb = reinterpret_cast<double *>(smem) + (size_t)wave * maxlen * 9;
+  int32_t *rcol = reinterpret_cast<int32_t *>(smem + sizeof(double) * (size_t)waves * maxlen * 9) + (size_t)wave * maxlen;
   const SubInfo sd = subs[sub0 + blockIdx.x];
   const IlukShapeDev sh = shapes[sd.shape];
   double *Wb = W + sd.wbase;
@@ -238,77 +248,78 @@ __global__ void __launch_bounds__(256) iluk_factor_kernel(OpDev op, const SubInf
   for (int L = 0; L < sh.nlev; ++L) {
     const int c0 = lvl_chunk[sh.lvl_off + L], c1 = lvl_chunk[sh.lvl_off + L + 1];
     const int p0 = chs[c0].pos0, p1 = chs[c1 - 1].pos0 + chs[c1 - 1].rows;
-    for (int pi = p0 + (int)threadIdx.x; pi < p1; pi += blockDim.x) {
+    for (int pi = p0 + wave; pi < p1; pi += waves) {
       const IlukChunk ch = chs[pc[pi]];
       const int q = pi - ch.pos0, rs = ch.rows;
-      const int ni = nl[pi], mi = nu[pi];
+      const int ni = nl[pi], mi = nu[pi], len = ni + 1 + mi;
       const uint64_t ci = crd[pi];
-      for (int e = 0; e < ni; ++e)
-        init_block(op, sd, ci, crd[cl[ch.coff + (int64_t)e * rs + q]], lblk(Wb, ch, e, q), rs);
-      init_block(op, sd, ci, ci, dblk(Wb, ch, q), rs);
-      for (int e = 0; e < mi; ++e)
-        init_block(op, sd, ci, crd[cl[ch.coff + (int64_t)(ch.lmax + e) * rs + q]], ublk(Wb, ch, e, q), rs);
-      const int ri = rh[pi];
-      // natural column of position t of row i's sequence: L entries, diagonal, U entries
-      auto rho_at = [&](int t) -> int {
-        if (t < ni) return rh[cl[ch.coff + (int64_t)t * rs + q]];
-        if (t == ni) return ri;
-        return rh[cl[ch.coff + (int64_t)(ch.lmax + t - ni - 1) * rs + q]];
-      };
-      auto blk_at = [&](int t) -> double * {
-        if (t < ni) return lblk(Wb, ch, t, q);
-        if (t == ni) return dblk(Wb, ch, q);
-        return ublk(Wb, ch, t - ni - 1, q);
-      };
-      const int len = ni + 1 + mi;
+      // natural columns (L entries, the diagonal, U entries: ascending) and A's blocks
+      for (int t = lane; t < len; t += 64) {
+        const int pj = t < ni ? cl[ch.coff + (int64_t)t * rs + q]
+                              : t == ni ? pi : cl[ch.coff + (int64_t)(ch.lmax + t - ni - 1) * rs + q];
+        rcol[t] = rh[pj];
+        double blk[9];
+        block_of(op, sd, ci, crd[pj], blk);
+        for (int v = 0; v < 9; ++v) rowb[9 * t + v] = blk[v];
+      }
+      wave_sync();
       for (int e = 0; e < ni; ++e) {
         const int pk = cl[ch.coff + (int64_t)e * rs + q];
         const IlukChunk chk = chs[pc[pk]];
-        const int qk = pk - chk.pos0, rk = chk.rows;
-        double *wl = lblk(Wb, ch, e, q);
-        const double *dk = dblk(Wb, chk, qk);
+        const int qk = pk - chk.pos0, rk = chk.rows, mk = nu[pk];
         double a[9], d[9], l[9];
+        const double *dk = Wb + dpos(chk, qk);
         for (int v = 0; v < 9; ++v) {
-          a[v] = wl[v * rs];
-          d[v] = dk[v * rk];
+          a[v] = rowb[9 * e + v];
+          d[v] = dk[(int64_t)v * rk];
         }
         for (int r = 0; r < 3; ++r)
           for (int c = 0; c < 3; ++c) l[3 * r + c] = a[3 * r] * d[c] + a[3 * r + 1] * d[3 + c] + a[3 * r + 2] * d[6 + c];
-        for (int v = 0; v < 9; ++v) wl[v * rs] = l[v];
-        int t = e + 1;
-        int rt = t < len ? rho_at(t) : INT_MAX;
-        const int mk = nu[pk];
-        for (int f = 0; f < mk; ++f) {
+        wave_sync();
+        if (lane == 0)
+          for (int v = 0; v < 9; ++v) rowb[9 * e + v] = l[v];
+        for (int f = lane; f < mk; f += 64) {
           const int pj = cl[chk.coff + (int64_t)(chk.lmax + f) * rk + qk];
           const int rj = rh[pj];
-          while (rt < rj) {
-            ++t;
-            rt = t < len ? rho_at(t) : INT_MAX;
+          int lo = e + 1, hi = len;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (rcol[mid] < rj) lo = mid + 1;
+            else hi = mid;
           }
-          if (rt != rj) continue;
-          const double *u = ublk(Wb, chk, f, qk);
-          double ub[9];
-          for (int v = 0; v < 9; ++v) ub[v] = u[v * rk];
-          double *w = blk_at(t);
-          for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) {
-              const double s = l[3 * r] * ub[c] + l[3 * r + 1] * ub[3 + c] + l[3 * r + 2] * ub[6 + c];
-              w[(3 * r + c) * rs] -= s;
-            }
+          if (lo < len && rcol[lo] == rj) {
+            const double *u = Wb + upos(chk, f, qk);
+            double ub[9];
+            for (int v = 0; v < 9; ++v) ub[v] = u[(int64_t)v * rk];
+            double *w = rowb + 9 * lo;
+            for (int r = 0; r < 3; ++r)
+              for (int c = 0; c < 3; ++c) {
+                const double sm = l[3 * r] * ub[c] + l[3 * r + 1] * ub[3 + c] + l[3 * r + 2] * ub[6 + c];
+                w[3 * r + c] -= sm;
+              }
+          }
         }
+        wave_sync();
       }
-      double *wd = dblk(Wb, ch, q);
-      double dd[9], inv[9];
-      for (int v = 0; v < 9; ++v) dd[v] = wd[v * rs];
-      bool ok;
-      inv33_pivot(dd, inv, ok);
-      if (!ok) {
-        atomicMax(status, 1);
-        for (int v = 0; v < 9; ++v) inv[v] = 0.0;
+      if (lane == 0) {
+        double dd[9], inv[9];
+        for (int v = 0; v < 9; ++v) dd[v] = rowb[9 * ni + v];
+        bool ok;
+        inv33_pivot(dd, inv, ok);
+        if (!ok) {
+          atomicMax(status, 1);
+          for (int v = 0; v < 9; ++v) inv[v] = 0.0;
+        }
+        for (int v = 0; v < 9; ++v) rowb[9 * ni + v] = inv[v];
       }
-      for (int v = 0; v < 9; ++v) wd[v * rs] = inv[v];
+      wave_sync();
+      for (int t = lane; t < len; t += 64) {
+        const int64_t at = t < ni ? lpos(ch, t, q) : t == ni ? dpos(ch, q) : upos(ch, t - ni - 1, q);
+        for (int v = 0; v < 9; ++v) Wb[at + (int64_t)v * rs] = rowb[9 * t + v];
+      }
+      wave_sync();
     }
-    __syncthreads();
+    __syncthreads();   // the next level reads these rows from W
   }
 }
 
@@ -519,12 +530,21 @@ void iluk_create(ras *R, const kkt_op *op, hipStream_t s) {
   DevBuf d_status(al, 256);
   STKKT_HIP(hipMemsetAsync(d_status.ptr, 0, sizeof(int), s));
   K->factors = DevBuf(al, esz * ((size_t)fb + 1));
+  // LDS of the factorisation: per wavefront, the longest row's blocks and columns
+  int maxlen = 1;
+  for (const IlukShapeHost &sh : K->shapes)
+    for (int p = 0; p < sh.nrows; ++p) maxlen = std::max(maxlen, sh.nL[p] + sh.nU[p] + 1);
+  const size_t per_wave = (size_t)maxlen * (9 * sizeof(double) + sizeof(int32_t));
+  const int fwaves = (int)std::min<size_t>(4, kFactorLds / per_wave);
+  STKKT_REQUIRE(fwaves >= 1, "ras_setup: ILU(k) rows too long for the factorisation's LDS");
+  STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&iluk_factor_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFactorLds));
   auto factor = [&](int first, int count, double *W) {
-    hipLaunchKernelGGL(iluk_factor_kernel, dim3(count), dim3(256), 0, s, op->d, R->d_subs.as<SubInfo>(), first,
-                       K->d_shapes.as<IlukShapeDev>(), K->d_chunks.as<IlukChunk>(), K->d_lvl.as<int32_t>(),
-                       K->d_coords.as<uint64_t>(), K->d_rho.as<int32_t>(), K->d_pchunk.as<int32_t>(),
-                       K->d_nL.as<int16_t>(), K->d_nU.as<int16_t>(), K->d_cols.as<int32_t>(), W,
-                       d_status.as<int>());
+    hipLaunchKernelGGL(iluk_factor_kernel, dim3(count), dim3(64 * fwaves), per_wave * fwaves, s, op->d,
+                       R->d_subs.as<SubInfo>(), first, K->d_shapes.as<IlukShapeDev>(), K->d_chunks.as<IlukChunk>(),
+                       K->d_lvl.as<int32_t>(), K->d_coords.as<uint64_t>(), K->d_rho.as<int32_t>(),
+                       K->d_pchunk.as<int32_t>(), K->d_nL.as<int16_t>(), K->d_nU.as<int16_t>(),
+                       K->d_cols.as<int32_t>(), maxlen, W, d_status.as<int>());
     STKKT_HIP(hipGetLastError());
   };
   if (!f32) {
