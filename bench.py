@@ -408,26 +408,33 @@ def run_coarse(args):
 
 def run_overlap(args):
     """The overlap study of the paper's two-level method (Section 4, the table
-    of overlap sizes): fine mesh 40^3 elements x 40 time steps, coarse mesh
-    20^3 x 20 (factor 2 in space and time), ILU(0) subdomain solves on both
-    levels, coarse GMRES(4) to 0.1 with the coarse RAS on the same 4x4x4x4
-    subdomains and coarse overlap 1, FGMRES(50) to 1e-6; fine overlap 1, 2, 4.
-    Synthetic cube32x64-style sources and 64 lattice sensors (all on coarse
-    nodes).  Reports iterations and solve time per overlap."""
+    of overlap sizes): fine mesh 40^3 elements x 40 time steps (--overlap-mesh),
+    coarse mesh 20^3 x 20 (factor 2 in space and time), FGMRES(50) to 1e-6;
+    fine overlap 1, 2, 4.  Subdomain solves ILU(k) with k = --overlap-ilu (the paper: 0); coarse
+    solve the paper's GMRES(4) to 0.1 with the coarse RAS on the same 4x4x4x4
+    subdomains, coarse overlap 1 (--coarse gmres, default here), or the exact
+    block LU (--coarse lu).  Synthetic cube32x64-style sources and 64 lattice
+    sensors (all on coarse nodes).  Reports iterations and solve time per
+    overlap."""
     import torch
     import paper_1508_06103_amd as st
     from workloads.generate import make_problem, redraw_noise
-    prob, _ = make_problem("cube32x64", n=40, M=40, lattice=4)
+    m = args.overlap_mesh
+    prob, _ = make_problem("cube32x64", n=m, M=m, lattice=4 if m % 5 == 0 else 3)
     prec = st.F64 if args.precision == "f64" else st.F32
     op = st.KKTOperator(prob)
     parts, fac = (4, 4, 4, 4), (2, 2, 2, 2)
-    C = st.Coarse(op, fac, parts, overlap=1, maxit=4, rtol=0.1, precision=prec, method=st.COARSE_GMRES_RAS)
+    coarse_how = args.coarse if args.coarse_set else "gmres"
+    if coarse_how == "lu":
+        C = st.Coarse(op, fac, method=st.COARSE_LU, precision=prec)
+    else:
+        C = st.Coarse(op, fac, parts, overlap=1, maxit=4, rtol=0.1, precision=prec, method=st.COARSE_GMRES_RAS)
     b = op.rhs(redraw_noise(prob, 77))
     rows = []
     for delta in (1, 2, 4):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pre = st.RAS(op, parts, delta, precision=prec)
+        pre = st.RAS(op, parts, delta, precision=prec, ilu_level=args.overlap_ilu)
         torch.cuda.synchronize()
         t_setup = time.perf_counter() - t0
         times = []
@@ -441,15 +448,18 @@ def run_overlap(args):
             assert s.converged and s.rel_res_true <= 1e-6
         rows.append({"overlap": delta, "iters": s.iters, "solve_ms": 1e3 * min(times), "ras_setup_ms": 1e3 * t_setup,
                      "factor_gb": pre.factor_bytes / 1e9})
-        print(f"[bench] overlap {delta}: {s.iters} its, solve {1e3 * min(times):.1f} ms, "
-              f"setup {1e3 * t_setup:.1f} ms, factors {pre.factor_bytes / 1e9:.2f} GB", file=sys.stderr, flush=True)
+        print(f"[bench] overlap {delta}, ILU({args.overlap_ilu}), coarse {coarse_how}: {s.iters} its, solve "
+              f"{1e3 * min(times):.1f} ms, setup {1e3 * t_setup:.1f} ms, factors {pre.factor_bytes / 1e9:.2f} GB",
+              file=sys.stderr, flush=True)
         pre.close()
-    return {"metric": "FGMRES iterations and solve time vs fine overlap (two-level, ILU(0))",
+    coarse_txt = "exact block LU" if coarse_how == "lu" else \
+        "GMRES(4) rtol 0.1 with coarse RAS 4x4x4x4 overlap 1"
+    return {"metric": f"FGMRES iterations and solve time vs fine overlap (two-level, ILU({args.overlap_ilu}))",
             "value": rows[0]["iters"], "unit": "iterations at overlap 1", "n_gpus": 1, "steps": 2, "warmup": 0,
             "ms_per_step": rows[0]["solve_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
             "dtype": args.precision, "data": "synthetic (seeded moving-Gaussian sources, 64 lattice sensors, 1% noise)",
-            "config": {"workload": f"40^3 x 40 ({prob.unknowns} unknowns), RAS 4x4x4x4 ILU(0), coarse 20^3 x 20 "
-                                   "GMRES(4) rtol 0.1 with coarse RAS 4x4x4x4 overlap 1, FGMRES(50), rtol 1e-6"},
+            "config": {"workload": f"{m}^3 x {m} ({prob.unknowns} unknowns), RAS 4x4x4x4 ILU({args.overlap_ilu}), "
+                                   f"coarse {m // 2}^3 x {m // 2} {coarse_txt}, FGMRES(50), rtol 1e-6"},
             "sweep": rows}
 
 
@@ -849,6 +859,8 @@ def main():
                          "of the two-level method; ilu: the paper's ILU fill-level study of the two-level method")
     ap.add_argument("--coarse", default="lu", choices=["lu", "gmres"],
                     help="two-level configurations: exact block-LU coarse solve, or the paper's coarse GMRES(4)+RAS")
+    ap.add_argument("--overlap-ilu", type=int, default=0, help="overlap mode: ILU level of the fine subdomain solves")
+    ap.add_argument("--overlap-mesh", type=int, default=40, help="overlap mode: elements per axis and time steps")
     ap.add_argument("--ilu-mesh", type=int, default=40, help="ilu mode: elements per axis and time steps")
     ap.add_argument("--ilu-levels-f32", default="0,1,2", help="ilu mode: fill levels k run with FP32 factors")
     ap.add_argument("--ilu-levels-f64", default="0,1", help="ilu mode: fill levels k run with FP64 factors")
@@ -858,6 +870,7 @@ def main():
     ap.add_argument("--requests", type=int, default=100)
     ap.add_argument("--rate", type=float, default=50.0, help="serve mode: arrivals per second")
     args = ap.parse_args()
+    args.coarse_set = any(a == "--coarse" or a.startswith("--coarse=") for a in sys.argv[1:])
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus}); "
               "sharding across GPUs is not implemented.", file=sys.stderr)

@@ -353,22 +353,43 @@ __device__ inline void iluk_sweep(const OpDev &op, const SubInfo &sd, const Iluk
       const int np = min(kPhaseChunks, c1 - cp);
       for (int cc = 0; cc < np; ++cc) {
         const IlukChunk ch = load_uniform(chs + cp + cc);
-        const bool valid = lane < ch.rows;
-        const int n = valid ? (int)cnt[ch.pos0 + lane] : 0;
+        // a chunk of rp <= 32 rows (rp a power of two >= its rows) is swept by
+        // 64 / rp lane groups that take alternate entries
+        const int rp = ch.rows > 32 ? 64 : ch.rows > 16 ? 32 : ch.rows > 8 ? 16 : 8;
+        const int grp = lane / rp, ngrp = 64 / rp, row = lane % rp;
+        const bool valid = row < ch.rows;
+        const int n = valid ? (int)cnt[ch.pos0 + row] : 0;
         const int base = kFwd ? 0 : ch.lmax;                       // column block of the entries
         const int rs = ch.rows;
         const int64_t fo = ch.foff + (kFwd ? 0 : (int64_t)(ch.lmax + 1) * 9 * rs);
         const int emax = kFwd ? ch.lmax : ch.umax;
+        const int estep = kWaves * ngrp;
         T a0 = 0, a1 = 0, a2 = 0;
-        for (int e = wave; e < emax; e += kWaves) {
-          if (e < n) {
-            const int col = cl[ch.coff + (int64_t)(base + e) * rs + lane];
-            const T *f = Fb + fo + (int64_t)e * 9 * rs + lane;
-            const T *y = Yb + 3 * (int64_t)col;
-            const T y0 = y[0], y1 = y[1], y2 = y[2];
-            a0 += f[0] * y0 + f[rs] * y1 + f[2 * rs] * y2;
-            a1 += f[3 * rs] * y0 + f[4 * rs] * y1 + f[5 * rs] * y2;
-            a2 += f[6 * rs] * y0 + f[7 * rs] * y1 + f[8 * rs] * y2;
+        // four entries per step, all their loads issued before the products
+        for (int e0 = wave + kWaves * grp; e0 < emax; e0 += 4 * estep) {
+          int col[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * estep;
+            col[u] = e < n ? cl[ch.coff + (int64_t)(base + e) * rs + row] : -1;
+          }
+          T f[4][9], yv[4][3];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * estep;
+            const bool has = col[u] >= 0;
+            const T *fp = Fb + fo + (int64_t)(has ? e : 0) * 9 * rs + row;
+            const T *yp = Yb + 3 * (int64_t)(has ? col[u] : 0);
+#pragma unroll
+            for (int v = 0; v < 9; ++v) f[u][v] = has ? fp[(int64_t)v * rs] : (T)0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) yv[u][k] = has ? yp[k] : (T)0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            a0 += f[u][0] * yv[u][0] + f[u][1] * yv[u][1] + f[u][2] * yv[u][2];
+            a1 += f[u][3] * yv[u][0] + f[u][4] * yv[u][1] + f[u][5] * yv[u][2];
+            a2 += f[u][6] * yv[u][0] + f[u][7] * yv[u][1] + f[u][8] * yv[u][2];
           }
         }
         part[wave][cc * 64 + lane][0] = a0;
@@ -381,10 +402,13 @@ __device__ inline void iluk_sweep(const OpDev &op, const SubInfo &sd, const Iluk
         const int q = tq & 63;
         if (q < ch.rows) {
           const int pi = ch.pos0 + q;
+          const int rp = ch.rows > 32 ? 64 : ch.rows > 16 ? 32 : ch.rows > 8 ? 16 : 8;
+          const int base = tq & ~63;
           T s[3];
           for (int k = 0; k < 3; ++k) {
             T acc = 0;
-            for (int w = 0; w < kWaves; ++w) acc += part[w][tq][k];
+            for (int w = 0; w < kWaves; ++w)
+              for (int g = 0; g < 64; g += rp) acc += part[w][base + g + q][k];
             s[k] = acc;
           }
           int x, y, zc, t;
