@@ -1,7 +1,6 @@
 // Operator assembly, right-hand side and the matrix-free space-time matvec.
 #include <algorithm>
 #include <climits>
-#include <cmath>
 #include <mutex>
 #include <string>
 
@@ -152,22 +151,17 @@ void stiff_table(const OpDev &d, double *tab, hipStream_t s) {
 // are identity rows.
 //
 // One workgroup owns a TX x TY x TZ tile of spatial nodes over a chunk of
-// consecutive time levels and marches through them.  Per level: every thread
-// keeps the raw (c, g, f) of up to KH halo nodes for levels n-1, n, n+1 in
-// registers (level n+2 in flight), and writes the six combined fields of its
-// halo nodes to LDS.  B, K and N are tensor products of 1-D mass, stiffness
-// and convection factors, so they are applied by sum factorisation, one axis
-// per pass through LDS: the x pass contracts the six fields with the x
-// factors on every (y, z) line of the halo (nine products), the y pass
-// combines those with the y factors on the tile's (x, y) and the halo's z
-// (six products), and the z pass finishes the three rows of every owned node.
-// The variable diffusion A = sum_e a_e K_e has no tensor structure; it is
-// applied point by point from the per-node 27-entry table, read once per
-// chunk into registers.
+// consecutive time levels and marches through them: every thread keeps the
+// raw (c, g, f) of up to KH halo nodes for levels n-1 and n in registers,
+// loads level n+1 once, writes the six combined fields of its halo nodes to
+// LDS, and after a barrier evaluates the 27-point sums of its own node from
+// LDS.  The spatial 1-D factors of B, K and N are rebuilt from the node's
+// position (end-node rules); the variable-coefficient diffusion A comes from
+// the per-node table, read once per chunk into registers.
+// --------------------------------------------------------------------------
 namespace {
 
-constexpr int kMvThreads = 512;
-constexpr size_t kMvLdsMax = 160 * 1024;   // LDS of one gfx950 workgroup
+constexpr int kMvThreads = 256;
 
 // Mesh and time constants of the matvec, formed on the host so that the
 // kernel never evaluates a product of uniform values in vector registers.
@@ -216,19 +210,16 @@ MvConst make_mv_const(const OpDev &d) {
   return c;
 }
 
-// Centre entries of the 1-D mass, stiffness and convection factors of axis a
-// at a node with position code 0 (interior), 1 (first node) or 2 (last node).
 struct Centre {
-  double m, k, c;
+  double m, k, c;   // centre mass, stiffness and convection entries of the node on one axis
 };
 
-__device__ inline int pos_code(int i, int nn) { return i == 0 ? 1 : (i == nn - 1 ? 2 : 0); }
-
-__device__ inline Centre axis_centre(const MvConst &mc, int a, int code) {
+__device__ inline Centre axis_centre(const MvConst &mc, int a, int i, int nn) {
+  const bool end = (i == 0) || (i == nn - 1);
   Centre r;
-  r.m = code ? 2.0 * mc.h6[a] : 4.0 * mc.h6[a];
-  r.k = code ? mc.hinv[a] : 2.0 * mc.hinv[a];
-  r.c = code == 1 ? -0.5 : (code == 2 ? 0.5 : 0.0);
+  r.m = end ? 2.0 * mc.h6[a] : 4.0 * mc.h6[a];
+  r.k = end ? mc.hinv[a] : 2.0 * mc.hinv[a];
+  r.c = (i == 0) ? -0.5 : ((i == nn - 1) ? 0.5 : 0.0);
   return r;
 }
 
@@ -240,68 +231,37 @@ __device__ inline int xcd_work_index() {
   return xcd * q + min(xcd, r) + (b >> 3);
 }
 
-// LDS doubles of a tile: the diffusion table of the owned nodes, the six
-// fields on the halo, nine x products on the halo's (y, z) lines, six y
-// products on the tile's (x, y) and the halo's z.
-__host__ __device__ inline size_t mv_lds_doubles(const MvTile &tl) {
-  const size_t hy = tl.t[1] + 2, hz = tl.t[2] + 2;
-  return 27 * (size_t)tl.t[0] * tl.t[1] * tl.t[2] + 6 * (size_t)tl.halo + 9 * (size_t)tl.t[0] * hy * hz +
-         6 * (size_t)tl.t[0] * tl.t[1] * hz;
-}
-
 // One (tile, time chunk) work item w of one operator.
 template <int KH>
 __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const MvConst &mc,
                                         const double *__restrict__ Atab, const double *__restrict__ x,
                                         double *__restrict__ y, int w) {
-  extern __shared__ double mv_lds[];
+  // per halo node: {U1, S1}, {U2, S2}, {U3, T3} side by side (48 B)
+  extern __shared__ double2 mv_lds[];
   const int tile = w % tl.ntiles, chunk = w / tl.ntiles;
   const int M = op.M;
   const int n0 = chunk * tl.clen, n1 = min(n0 + tl.clen, M + 1);
-  const int TX = tl.t[0], TY = tl.t[1], TZ = tl.t[2];
   const int tix = tile % tl.nt[0], tiy = (tile / tl.nt[0]) % tl.nt[1], tiz = tile / (tl.nt[0] * tl.nt[1]);
-  const int ox = tix * TX, oy = tiy * TY, oz = tiz * TZ;
-  const int hx = TX + 2, hy = TY + 2, hz = TZ + 2;
-  const int halo = tl.halo, nX = TX * hy * hz, nY = TX * TY * hz, nown = TX * TY * TZ;
-  double *Al = mv_lds;             // [27][nown]: diffusion table of the owned nodes
-  double *F = Al + 27 * nown;      // [6][halo]: U1, S1, U2, S2, U3, T3
-  double *Xp = F + 6 * halo;       // [9][nX]
-  double *Yp = Xp + 9 * nX;        // [6][nY]
+  const int ox = tix * tl.t[0], oy = tiy * tl.t[1], oz = tiz * tl.t[2];
+  const int hx = tl.t[0] + 2, hy = tl.t[1] + 2;
   const int nn0 = op.nn[0], nn1 = op.nn[1], nn2 = op.nn[2];
   const long long N = op.N;
   const double ht = mc.ht;
   const bool dto = op.variant == STKKT_DTO;
-  const int t = threadIdx.x;
 
-  // own node (z pass)
-  const int lx = t % TX, ly = (t / TX) % TY, lz = t / (TX * TY);
+  // own node
+  const int t = threadIdx.x;
+  const int lx = t % tl.t[0], ly = (t / tl.t[0]) % tl.t[1], lz = t / (tl.t[0] * tl.t[1]);
   const int jx = ox + lx, jy = oy + ly, jz = oz + lz;
-  const bool own = t < nown && jx < nn0 && jy < nn1 && jz < nn2;
+  const bool own = t < tl.t[0] * tl.t[1] * tl.t[2] && jx < nn0 && jy < nn1 && jz < nn2;
   const long long j = own ? jx + (long long)nn0 * (jy + (long long)nn1 * jz) : 0;
-  if (t < nown)
-    for (int k = 0; k < 27; ++k) Al[k * nown + t] = own ? Atab[27 * j + k] : 0.0;   // read by this thread only
-  const int zc = own ? pos_code(jz, nn2) : 0;
+  double A[27];
+#pragma unroll
+  for (int k = 0; k < 27; ++k) A[k] = own ? Atab[27 * j + k] : 0.0;
+  Centre cx = axis_centre(mc, 0, jx, nn0), cy = axis_centre(mc, 1, jy, nn1), cz = axis_centre(mc, 2, jz, nn2);
   const bool Pj = own && !on_dirichlet(op, jx, jy, jz);
   const double sens = own ? op.sensor[j] : 0.0;
   const int hc = (lx + 1) + hx * ((ly + 1) + hy * (lz + 1));
-  const int yc = lx + TX * (ly + TY * (lz + 1));
-
-  // x-pass and y-pass items of this thread (at most two each)
-  int xh[2], xo[2], xcode[2], yo[2], ycode[2];
-  bool xv[2], yv[2];
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const int i = t + kMvThreads * s;
-    xv[s] = i < nX;
-    const int ax = i % TX, ayh = (i / TX) % hy, azh = i / (TX * hy);
-    xh[s] = (ax + 1) + hx * (ayh + hy * azh);
-    xo[s] = i;
-    xcode[s] = pos_code(min(ox + ax, nn0 - 1), nn0);
-    yv[s] = i < nY;
-    const int bx = i % TX, by = (i / TX) % TY, bzh = i / (TX * TY);
-    yo[s] = bx + TX * ((by + 1) + hy * bzh);   // centre row of the item in the x products
-    ycode[s] = pos_code(min(oy + by, nn1 - 1), nn1);
-  }
 
   // halo nodes loaded by this thread
   long long hoff[KH];
@@ -310,7 +270,7 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
 #pragma unroll
   for (int s = 0; s < KH; ++s) {
     const int h = t + kMvThreads * s;
-    hact[s] = h < halo;
+    hact[s] = h < tl.halo;
     hin[s] = false;
     hoff[s] = 0;
     hP[s] = 0.0;
@@ -370,7 +330,6 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
         f2[s] = p[2];
       }
     }
-    // the six combined fields of the halo nodes
 #pragma unroll
     for (int s = 0; s < KH; ++s) {
       const double cp = hp ? c1[s] : 0.0, gp = hp ? g1[s] : 0.0, fp = hp ? f1[s] : 0.0;
@@ -382,12 +341,9 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
         const double stf = stm * fm[s] + st0 * f0[s] + stp * fp;
         const double ttf = ttm * fm[s] + tt0 * f0[s] + ttp * fp;
         const double U3 = mc.beta1 * stf - (dto ? ht * S2 : P * (ttm * gm[s] + tt0 * g0[s] + ttp * gp));
-        F[h] = P * (c0[s] - cm[s]) - ht * (fm[s] + f0[s]);
-        F[halo + h] = P * (c0[s] + cm[s]);
-        F[2 * halo + h] = P * (gn - gp);
-        F[3 * halo + h] = S2;
-        F[4 * halo + h] = mc.l2 ? U3 + mc.beta2 * ttf : U3;
-        F[5 * halo + h] = mc.l2 ? 0.0 : mc.beta2 * ttf;
+        mv_lds[3 * h] = make_double2(P * (c0[s] - cm[s]) - ht * (fm[s] + f0[s]), P * (c0[s] + cm[s]));
+        mv_lds[3 * h + 1] = make_double2(P * (gn - gp), S2);
+        mv_lds[3 * h + 2] = mc.l2 ? make_double2(U3 + mc.beta2 * ttf, 0.0) : make_double2(U3, mc.beta2 * ttf);
       }
       cm[s] = c0[s];
       c0[s] = cp;
@@ -400,89 +356,88 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
       f1[s] = f2[s];
     }
     __syncthreads();
-    // x pass: M, D, D^T and K along x on every (y, z) line of the halo
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      if (!xv[s]) continue;
-      const Centre c = axis_centre(mc, 0, xcode[s]);
-      const double hm6 = mc.h6[0], hk = mc.hinv[0];
-      const double *u = F + xh[s];
-      const double U1m = u[-1], U1c = u[0], U1p = u[1];
-      const double S1m = u[halo - 1], S1c = u[halo], S1p = u[halo + 1];
-      const double U2m = u[2 * halo - 1], U2c = u[2 * halo], U2p = u[2 * halo + 1];
-      const double S2m = u[3 * halo - 1], S2c = u[3 * halo], S2p = u[3 * halo + 1];
-      const double U3m = u[4 * halo - 1], U3c = u[4 * halo], U3p = u[4 * halo + 1];
-      const double T3m = u[5 * halo - 1], T3c = u[5 * halo], T3p = u[5 * halo + 1];
-      double *o = Xp + xo[s];
-      o[0] = hm6 * (U1m + U1p) + c.m * U1c;                 // a1 = Mx U1
-      o[nX] = hm6 * (S1m + S1p) + c.m * S1c;                // b1 = Mx S1
-      o[2 * nX] = 0.5 * (S1p - S1m) + c.c * S1c;            // d1 = Dx S1
-      o[3 * nX] = hm6 * (U2m + U2p) + c.m * U2c;            // a2 = Mx U2
-      o[4 * nX] = hm6 * (S2m + S2p) + c.m * S2c;            // b2 = Mx S2
-      o[5 * nX] = 0.5 * (S2m - S2p) + c.c * S2c;            // d2 = Dx^T S2
-      o[6 * nX] = hm6 * (U3m + U3p) + c.m * U3c;            // a3 = Mx U3
-      o[7 * nX] = hm6 * (T3m + T3p) + c.m * T3c;            // b3 = Mx T3
-      o[8 * nX] = c.k * T3c - hk * (T3m + T3p);             // k3 = Kx T3
-    }
-    __syncthreads();
-    // y pass
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      if (!yv[s]) continue;
-      const Centre c = axis_centre(mc, 1, ycode[s]);
-      const double hm6 = mc.h6[1], hk = mc.hinv[1];
-      const double *u = Xp + yo[s];
-      auto My = [&](int f) { return hm6 * (u[f * nX - TX] + u[f * nX + TX]) + c.m * u[f * nX]; };
-      const double Dyb1 = 0.5 * (u[nX + TX] - u[nX - TX]) + c.c * u[nX];
-      const double Dytb2 = 0.5 * (u[4 * nX - TX] - u[4 * nX + TX]) + c.c * u[4 * nX];
-      const double Kyb3 = c.k * u[7 * nX] - hk * (u[7 * nX - TX] + u[7 * nX + TX]);
-      const int i = t + kMvThreads * s;
-      double *o = Yp + i;
-      o[0] = My(0) + ht * (mc.v[0] * My(2) + mc.v[1] * Dyb1);   // Z1, Mz next
-      o[nY] = My(1);                                              // Z1b, Dz next
-      o[2 * nY] = My(3) + ht * (mc.v[0] * My(5) + mc.v[1] * Dytb2);
-      o[3 * nY] = My(4);
-      o[4 * nY] = My(6) + Kyb3 + My(8);                           // Z3, Mz next
-      o[5 * nY] = My(7);                                          // Z3b, Kz next
-    }
-    __syncthreads();
+    // rebuild the node's stencil weights every level instead of keeping them live
+    asm volatile("" : "+v"(cx.m), "+v"(cx.k), "+v"(cx.c), "+v"(cy.m), "+v"(cy.k), "+v"(cy.c));
+    asm volatile("" : "+v"(cz.m), "+v"(cz.k), "+v"(cz.c));
     if (own) {
-      const Centre c = axis_centre(mc, 2, zc);
-      const double hm6 = mc.h6[2], hk = mc.hinv[2];
-      const int sz = TX * TY;
-      const double *u = Yp + yc;
-      auto Mz = [&](int f) { return hm6 * (u[f * nY - sz] + u[f * nY + sz]) + c.m * u[f * nY]; };
-      const double Dz1 = 0.5 * (u[nY + sz] - u[nY - sz]) + c.c * u[nY];
-      const double Dzt2 = 0.5 * (u[3 * nY - sz] - u[3 * nY + sz]) + c.c * u[3 * nY];
-      const double Kz3 = c.k * u[5 * nY] - hk * (u[5 * nY - sz] + u[5 * nY + sz]);
-      // the variable diffusion, point by point
-      double aS1 = 0.0, aS2 = 0.0;
-#pragma unroll 9
-      for (int k = 0; k < 27; ++k) {
-        const int d = (k % 3 - 1) + hx * ((k / 3) % 3 - 1 + hy * (k / 9 - 1));
-        const double a = Al[k * nown + t];
-        aS1 += a * F[halo + hc + d];
-        aS2 += a * F[3 * halo + hc + d];
+      // Sum factorisation: B, K and N are tensor products of 1-D factors, so
+      // each row of three x-neighbours is first contracted with the x factors
+      // (off-centre entries are the same for every node, the centre ones are
+      // the node's), then weighted by the (y, z) factors of the row.  The
+      // variable diffusion A is applied point by point.
+      double aC = 0.0, sC = 0.0, aG = 0.0, sG = 0.0, aF = 0.0;
+#pragma unroll
+      for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+          double myz, kyz, nyz, vmyz;
+          if (dy != 0 && dz != 0) {
+            const double *c4 = mc.cyz[dy > 0][dz > 0];
+            myz = c4[0];
+            kyz = c4[1];
+            nyz = c4[2];
+            vmyz = c4[3];
+          } else if (dy == 0 && dz != 0) {
+            myz = cy.m * mc.h6[2];
+            kyz = cy.k * mc.h6[2] - cy.m * mc.hinv[2];
+            nyz = mc.v[1] * mc.h6[2] * cy.c + (0.5 * dz) * mc.v[2] * cy.m;
+            vmyz = mc.v[0] * myz;
+          } else if (dy != 0 && dz == 0) {
+            myz = mc.h6[1] * cz.m;
+            kyz = -mc.hinv[1] * cz.m + mc.h6[1] * cz.k;
+            nyz = (0.5 * dy) * mc.v[1] * cz.m + mc.v[2] * mc.h6[1] * cz.c;
+            vmyz = mc.v[0] * myz;
+          } else {
+            myz = cy.m * cz.m;
+            kyz = cy.k * cz.m + cy.m * cz.k;
+            nyz = mc.v[1] * cy.c * cz.m + mc.v[2] * cy.m * cz.c;
+            vmyz = mc.v[0] * myz;
+          }
+          // N^T differs from N only in the sign of the off-centre convection entries
+          double ntyz;
+          if (dy != 0 && dz != 0) ntyz = -nyz;
+          else if (dy == 0 && dz != 0) ntyz = mc.v[1] * mc.h6[2] * cy.c - (0.5 * dz) * mc.v[2] * cy.m;
+          else if (dy != 0 && dz == 0) ntyz = -(0.5 * dy) * mc.v[1] * cz.m + mc.v[2] * mc.h6[1] * cz.c;
+          else ntyz = nyz;
+          const double2 *row = mv_lds + 3 * (hc + hx * (dy + hy * dz));
+          const double2 w1 = row[-3], w2 = row[-2], w3 = row[-1];   // x - 1
+          const double2 c1 = row[0], c2 = row[1], c3 = row[2];      // x
+          const double2 e1 = row[3], e2 = row[4], e3 = row[5];      // x + 1
+          const int k0 = 3 * (dy + 1) + 9 * (dz + 1);
+          const double mU1 = mc.h6[0] * (w1.x + e1.x) + cx.m * c1.x;
+          const double mU2 = mc.h6[0] * (w2.x + e2.x) + cx.m * c2.x;
+          const double mU3 = mc.h6[0] * (w3.x + e3.x) + cx.m * c3.x;
+          const double mT = mc.h6[0] * (w3.y + e3.y) + cx.m * c3.y;
+          const double kT = cx.k * c3.y - mc.hinv[0] * (w3.y + e3.y);
+          const double mS1 = mc.h6[0] * (w1.y + e1.y) + cx.m * c1.y;
+          const double cS1 = 0.5 * (e1.y - w1.y) + cx.c * c1.y;
+          const double aS1 = A[k0] * w1.y + A[k0 + 1] * c1.y + A[k0 + 2] * e1.y;
+          const double mS2 = mc.h6[0] * (w2.y + e2.y) + cx.m * c2.y;
+          const double cS2 = 0.5 * (w2.y - e2.y) + cx.c * c2.y;
+          const double aS2 = A[k0] * w2.y + A[k0 + 1] * c2.y + A[k0 + 2] * e2.y;
+          aC += myz * mU1;
+          aG += myz * mU2;
+          aF += myz * (mU3 + kT) + kyz * mT;
+          sC += aS1 + vmyz * cS1 + nyz * mS1;
+          sG += aS2 + vmyz * cS2 + ntyz * mS2;
+        }
       }
-      const double Cv = Mz(0) + ht * (mc.v[2] * Dz1 + aS1);
-      const double Gv = Mz(2) + ht * (mc.v[2] * Dzt2 + aS2);
-      const double Fv = Mz(4) + Kz3;
       const long long idx = (long long)n * N + j;
       const double *xs = x + 3 * idx;
       double *ys = y + 3 * idx;
       const double cj = xs[0], gj = xs[1];
-      ys[0] = (n == 0 || !Pj) ? cj : Cv;
+      ys[0] = (n == 0 || !Pj) ? cj : aC + ht * sC;
       double g;
       if (!Pj) {
         g = gj;
       } else if (dto) {
         const double wn = tend ? ht : 2.0 * ht;   // trapezoid weight of level n
-        g = Gv + (n == 0 ? gj : 0.0) + wn * sens * cj;
+        g = aG + ht * sG + (n == 0 ? gj : 0.0) + wn * sens * cj;
       } else {
-        g = hp ? Gv + ht * sens * (cj + xs[3 * N]) : gj;
+        g = hp ? aG + ht * sG + ht * sens * (cj + xs[3 * N]) : gj;
       }
       ys[1] = g;
-      ys[2] = Fv;
+      ys[2] = aF;
     }
     __syncthreads();
   }
@@ -520,36 +475,27 @@ __global__ void __launch_bounds__(kMvThreads) matvec_batch_kernel(const MvBatchD
 }  // namespace
 
 MvTile choose_matvec_tile(const OpDev &d) {
-  // Tiles of at most kMvThreads owned nodes whose halo and pass products fit
-  // two items per thread and the LDS; cost = per-thread item rounds of the
-  // halo load and the three passes, summed over the tiles.
   MvTile best{};
   double best_cost = 1e300;
   const int cap = kMvThreads;
   for (int tx = 1; tx <= std::min(d.nn[0], cap); ++tx)
     for (int ty = 1; ty <= std::min(d.nn[1], cap / tx); ++ty)
       for (int tz = 1; tz <= std::min(d.nn[2], cap / (tx * ty)); ++tz) {
-        MvTile c{};
-        c.t[0] = tx;
-        c.t[1] = ty;
-        c.t[2] = tz;
-        c.halo = (tx + 2) * (ty + 2) * (tz + 2);
-        const int nX = tx * (ty + 2) * (tz + 2), nY = tx * ty * (tz + 2);
-        if (c.halo > 2 * cap || nX > 2 * cap || nY > 2 * cap) continue;
-        if (sizeof(double) * mv_lds_doubles(c) > kMvLdsMax) continue;
+        const int halo = (tx + 2) * (ty + 2) * (tz + 2);
+        if (halo > 3 * kMvThreads) continue;
         const long long ntiles = (long long)((d.nn[0] + tx - 1) / tx) * ((d.nn[1] + ty - 1) / ty) *
                                  ((d.nn[2] + tz - 1) / tz);
-        // halo loads in 128-byte lines (a halo x line of 24-byte nodes touches
-        // about one line more than it fills), as node-equivalents
-        const double lines = (double)(ty + 2) * (tz + 2) * (std::ceil(24.0 * (tx + 2) / 128.0) + 1.0) * 128.0 / 24.0;
-        const double cost = (double)ntiles * (3.0 * lines + nX + nY + tx * ty * tz);
+        const double cost = (double)ntiles * (halo + kMvThreads);
         if (cost < best_cost) {
           best_cost = cost;
-          best = c;
+          best.t[0] = tx;
+          best.t[1] = ty;
+          best.t[2] = tz;
         }
       }
   for (int a = 0; a < 3; ++a) best.nt[a] = (d.nn[a] + best.t[a] - 1) / best.t[a];
   best.ntiles = best.nt[0] * best.nt[1] * best.nt[2];
+  best.halo = (best.t[0] + 2) * (best.t[1] + 2) * (best.t[2] + 2);
   const int levels = d.M + 1;
   int chunks = std::max(1, std::min(levels, (1024 + best.ntiles - 1) / best.ntiles));
   best.clen = (levels + chunks - 1) / chunks;
@@ -562,22 +508,16 @@ void matvec_device(const kkt_op *op, const double *x, double *y, hipStream_t s) 
   const MvTile &tl = op->mv;
   const long long grid = (long long)tl.ntiles * tl.nchunks;
   if (grid > INT32_MAX) throw Error(STKKT_EINVAL, "kkt_matvec: mesh too large");
-  const size_t lds = sizeof(double) * mv_lds_doubles(tl);
+  const size_t lds = sizeof(double2) * 3 * (size_t)tl.halo;   // 48 B per halo node
   const int kh = (tl.halo + kMvThreads - 1) / kMvThreads;
   const double *atab = op->atab.as<double>();
   const MvConst mc = make_mv_const(d);
-  static bool attr_set = false;
-  if (!attr_set) {
-    STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&matvec_tile_kernel<1>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMvLdsMax));
-    STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&matvec_tile_kernel<2>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMvLdsMax));
-    attr_set = true;
-  }
   if (kh == 1)
     hipLaunchKernelGGL(matvec_tile_kernel<1>, dim3((unsigned)grid), dim3(kMvThreads), lds, s, d, tl, mc, atab, x, y);
-  else
+  else if (kh == 2)
     hipLaunchKernelGGL(matvec_tile_kernel<2>, dim3((unsigned)grid), dim3(kMvThreads), lds, s, d, tl, mc, atab, x, y);
+  else
+    hipLaunchKernelGGL(matvec_tile_kernel<3>, dim3((unsigned)grid), dim3(kMvThreads), lds, s, d, tl, mc, atab, x, y);
   STKKT_HIP(hipGetLastError());
 }
 
@@ -586,7 +526,6 @@ void matvec_batch_prepare(const kkt_op *const *ops, const long long *voff, int c
   std::vector<MvBatchDesc> d(count);
   long long w = 0;
   int halo = 0;
-  size_t lds = 0;
   for (int i = 0; i < count; ++i) {
     d[i] = MvBatchDesc{};
     d[i].w0 = (int32_t)w;
@@ -599,7 +538,6 @@ void matvec_batch_prepare(const kkt_op *const *ops, const long long *voff, int c
     d[i].nw = ops[i]->mv.ntiles * ops[i]->mv.nchunks;
     w += d[i].nw;
     halo = std::max(halo, ops[i]->mv.halo);
-    lds = std::max(lds, sizeof(double) * mv_lds_doubles(ops[i]->mv));
   }
   STKKT_REQUIRE(w <= INT32_MAX, "batched matvec: too many work items");
   out.desc = DevBuf(al, sizeof(MvBatchDesc) * (size_t)count);
@@ -608,7 +546,7 @@ void matvec_batch_prepare(const kkt_op *const *ops, const long long *voff, int c
   STKKT_HIP(hipStreamSynchronize(s));   // d is released on return
   out.count = count;
   out.items = w;
-  out.lds = std::max<size_t>(lds, 256);
+  out.lds = sizeof(double2) * 3 * (size_t)halo;
   out.kh = (halo + kMvThreads - 1) / kMvThreads;
 }
 
@@ -616,18 +554,12 @@ void matvec_batch_run(const MvBatch &b, const double *x, double *y, const int *a
   if (b.items == 0) return;
   const MvBatchDesc *dd = b.desc.as<MvBatchDesc>();
   const dim3 grid((unsigned)b.items);
-  static bool attr_set = false;
-  if (!attr_set) {
-    STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&matvec_batch_kernel<1>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMvLdsMax));
-    STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&matvec_batch_kernel<2>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMvLdsMax));
-    attr_set = true;
-  }
   if (b.kh == 1)
     hipLaunchKernelGGL(matvec_batch_kernel<1>, grid, dim3(kMvThreads), b.lds, s, dd, b.count, act, x, y);
-  else
+  else if (b.kh == 2)
     hipLaunchKernelGGL(matvec_batch_kernel<2>, grid, dim3(kMvThreads), b.lds, s, dd, b.count, act, x, y);
+  else
+    hipLaunchKernelGGL(matvec_batch_kernel<3>, grid, dim3(kMvThreads), b.lds, s, dd, b.count, act, x, y);
   STKKT_HIP(hipGetLastError());
 }
 
