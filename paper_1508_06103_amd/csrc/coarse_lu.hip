@@ -19,6 +19,7 @@
 // itself.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "coarse_lu.hpp"
@@ -246,6 +247,190 @@ __global__ void __launch_bounds__(256) gje_elim_kernel(int n, int k, int c, doub
   *x = (q == j) ? -f * pq : *x - f * pq;
 }
 
+// ---------------------------------------------------------------------------
+// The same Gauss-Jordan steps for all columns of a panel in one cooperative
+// launch.  Workgroup g keeps the panel segments of rows [g R, g R + R) in LDS
+// (column-major, padded: L[t (R + 1) + r]) for the whole panel; step c:
+//  1. every workgroup finds its largest |entry| in column c over its rows
+//     >= c (smallest row on ties) and publishes it, with that row's segment,
+//     in slot (c & 1) of the candidate tables; the owner of row c publishes
+//     row c's segment;
+//  2. grid barrier;
+//  3. every workgroup picks the same pivot row p from the candidates (largest
+//     value, smallest row on ties: the choice of gje_pivot_kernel), forms the
+//     scaled pivot row and eliminates column c from its own rows; the owner
+//     of row p puts row c's old segment in its place (the swap), the owner of
+//     row c the scaled pivot row.
+// The two candidate slots alternate, so a slot is rewritten only after every
+// workgroup has passed the barrier that follows its reads.  The barrier
+// counter grows by the number of workgroups per step and is zeroed once per
+// inversion; bar0 is the number of steps taken by earlier launches.  A
+// barrier that has not completed after about a second sets the abort flag
+// and status 2, and every workgroup leaves at its next barrier, so the launch
+// always ends.
+// ---------------------------------------------------------------------------
+constexpr int kGjThreads = 1024;
+constexpr unsigned kGjSpinLimit = 1u << 20;
+
+struct GjSync {
+  double *candv;     // [2][nwg] largest |entry|
+  int32_t *candi;    // [2][nwg] its row
+  double *candrow;   // [2][nwg][kPanel] that row's panel segment
+  double *crow;      // [2][kPanel] row c's panel segment
+  unsigned *count;   // barrier arrivals
+  int *abort;        // set by a barrier that timed out
+};
+
+// All threads of the workgroup; false if the barrier was abandoned.  Every
+// global write a step makes before its barrier (candidate tables, row c,
+// pivot records) comes from wavefront 0, so thread 0's release ordering of its
+// arrival covers them; the wait polls with relaxed loads and ends with one
+// acquire fence, whose cache invalidation the other wavefronts of the
+// compute unit see after the workgroup barrier.
+__device__ inline bool gj_grid_barrier(const GjSync &gs, unsigned target) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(gs.count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int good = 1;
+    unsigned spins = 0;
+    while (__hip_atomic_load(gs.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(gs.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kGjSpinLimit) {
+        __hip_atomic_store(gs.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ok = good;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// loads of values other workgroups wrote during the launch
+template <typename T> __device__ inline T ld_agent(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void gj_reset_kernel(GjSync gs) {
+  if (threadIdx.x == 0) {
+    *gs.count = 0u;
+    *gs.abort = 0;
+  }
+}
+
+__global__ void __launch_bounds__(kGjThreads) gje_panel_kernel(int n, int k, int e, int R, double *__restrict__ A,
+                                                              int32_t *__restrict__ piv, int32_t *__restrict__ swp,
+                                                              GjSync gs, unsigned bar0, int *__restrict__ status) {
+  extern __shared__ double gj_lds[];
+  __shared__ double wv[kGjThreads / 64], prow_s[kPanel], crow_s[kPanel];
+  __shared__ int wi[kGjThreads / 64];
+  if (*status) return;
+  const int tid = threadIdx.x, g = blockIdx.x, nwg = gridDim.x;
+  const int w = e - k, LD = R + 1;
+  const int r0 = g * R, rows = min(R, n - r0);
+  double *L = gj_lds;
+  for (int q = tid; q < R * w; q += kGjThreads) {
+    const int r = q / w, t = q % w;
+    L[t * LD + r] = r < rows ? A[(long long)(r0 + r) * n + k + t] : 0.0;
+  }
+  __syncthreads();
+  // this thread's row and first column in the elimination
+  const int rr = tid % R, t0 = tid / R, tstep = kGjThreads / R;
+  for (int j = 0; j < w; ++j) {
+    const int c = k + j, par = j & 1;
+    // 1. local candidate
+    double best = -1.0;
+    int bi = n;
+    for (int r = tid; r < rows; r += kGjThreads) {
+      const int i = r0 + r;
+      if (i < c) continue;
+      const double v = fabs(L[j * LD + r]);
+      if (v > best || (v == best && i < bi)) {
+        best = v;
+        bi = i;
+      }
+    }
+    block_argmax(best, bi, wv, wi);
+    {
+      const double lv = wv[0];
+      const int li = wi[0];
+      if (tid == 0) {
+        gs.candv[par * nwg + g] = lv;
+        gs.candi[par * nwg + g] = li;
+      }
+      if (tid < w) {
+        gs.candrow[((long long)par * nwg + g) * kPanel + tid] = li < n ? L[tid * LD + (li - r0)] : 0.0;
+        if (c >= r0 && c < r0 + rows) gs.crow[par * kPanel + tid] = L[tid * LD + (c - r0)];
+      }
+    }
+    // 2. all candidates published
+    if (!gj_grid_barrier(gs, (unsigned)nwg * (bar0 + (unsigned)j + 1u))) {
+      if (tid == 0) __hip_atomic_store(status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    // 3. the pivot
+    {
+      double v = -1.0;
+      int i = n;
+      for (int q = tid; q < nwg; q += kGjThreads) {
+        const double cv = ld_agent(gs.candv + par * nwg + q);
+        const int ci = ld_agent(gs.candi + par * nwg + q);
+        if (cv > v || (cv == v && ci < i)) {
+          v = cv;
+          i = ci;
+        }
+      }
+      block_argmax(v, i, wv, wi);
+    }
+    const double pv = wv[0];
+    const int p = wi[0];
+    if (!(pv > 0.0) || !std::isfinite(pv)) {
+      if (tid == 0) *status = 1;
+      return;
+    }
+    const int gp = p / R;
+    if (tid < w) {
+      const double a = ld_agent(gs.candrow + ((long long)par * nwg + gp) * kPanel + j);
+      const double x = ld_agent(gs.candrow + ((long long)par * nwg + gp) * kPanel + tid);
+      prow_s[tid] = (tid == j ? 1.0 : x) / a;
+      crow_s[tid] = ld_agent(gs.crow + par * kPanel + tid);
+    }
+    if (g == 0 && tid == 0) {
+      swp[j] = p;
+      if (p != c) {
+        const int32_t t = piv[c];
+        piv[c] = piv[p];
+        piv[p] = t;
+      }
+    }
+    __syncthreads();
+    const int i = r0 + rr;
+    const bool valid = rr < rows, isc = i == c, isp = i == p && p != c;
+    const double f = valid ? (isp ? crow_s[j] : L[j * LD + rr]) : 0.0;
+    __syncthreads();
+    if (valid) {
+      for (int t = t0; t < w; t += tstep) {
+        double nv;
+        if (isc) {
+          nv = prow_s[t];
+        } else {
+          const double cur = isp ? crow_s[t] : L[t * LD + rr];
+          nv = (t == j) ? -f * prow_s[j] : cur - f * prow_s[t];
+        }
+        L[t * LD + rr] = nv;
+      }
+    }
+    __syncthreads();
+  }
+  for (int q = tid; q < R * w; q += kGjThreads) {
+    const int r = q / w, t = q % w;
+    if (r < rows) A[(long long)(r0 + r) * n + k + t] = L[t * LD + r];
+  }
+}
+
 // The panel's row swaps, in order, on the columns outside the panel (one
 // thread per column).  Skipped after a failed pivot (swp is then incomplete).
 __global__ void gje_laswp_kernel(int n, int k, int e, double *__restrict__ A, const int32_t *__restrict__ swp,
@@ -276,27 +461,31 @@ __global__ void gje_copy_rows_kernel(int n, int k, int e, const double *__restri
 // on the FP64 matrix cores (v_mfma_f64_16x16x4: lane l supplies a = A[l%16][l/16]
 // and b = B[l/16][l%16] and holds D[l/16 + 4r][l%16], r = 0..3).  A workgroup
 // of 8 wavefronts owns a 128 x 128 output tile; wavefront (wr, wc) a 64 x 32
-// part of it, as 4 x 2 blocks of 16 x 16.  The A panel slice (128 rows x 64,
-// rows padded against bank conflicts) and the R slice (64 x 128) sit in LDS.
+// part of it, as 4 x 2 blocks of 16 x 16.  The accumulators start from the
+// tile's current values (0 for panel rows), requested first so that their
+// latency overlaps the staging; the panel is taken in two passes of 32
+// columns, each staging the A panel slice (128 rows x 32, rows padded against
+// bank conflicts) and the R slice (32 x 128) in LDS.  About 67 KB of LDS and
+// at most 128 registers let two workgroups share a compute unit, one loading
+// while the other multiplies.
 constexpr int kUpdTile = 128;
 constexpr int kUpdThreads = 512;
-constexpr size_t kUpdLds = sizeof(double) * ((size_t)kUpdTile * (kPanel + 1) + (size_t)kPanel * kUpdTile);
+constexpr int kUpdK = 32;
+constexpr size_t kUpdLds = sizeof(double) * ((size_t)kUpdTile * (kUpdK + 1) + (size_t)kUpdK * kUpdTile);
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(kUpdThreads) gje_update_kernel(int n, int k, int e, double *__restrict__ A,
-                                                                 const double *__restrict__ R) {
+__global__ void __launch_bounds__(kUpdThreads, 4) gje_update_kernel(int n, int k, int e, double *__restrict__ A,
+                                                                    const double *__restrict__ R) {
   extern __shared__ double upd_lds[];
-  double(*As)[kPanel + 1] = reinterpret_cast<double(*)[kPanel + 1]>(upd_lds);              // [row][t]
-  double(*Rs)[kUpdTile] = reinterpret_cast<double(*)[kUpdTile]>(upd_lds + kUpdTile * (kPanel + 1));   // [t][col]
+  double(*As)[kUpdK + 1] = reinterpret_cast<double(*)[kUpdK + 1]>(upd_lds);              // [row][t]
+  double(*Rs)[kUpdTile] = reinterpret_cast<double(*)[kUpdTile]>(upd_lds + kUpdTile * (kUpdK + 1));   // [t][col]
   const int row0 = blockIdx.y * kUpdTile, col0 = blockIdx.x * kUpdTile;
   const int w = e - k;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 2, wc = wave & 3;
   const int li = lane & 15, lk = lane >> 4;
-  // the tile's current values are requested first, so that their latency
-  // overlaps the staging and the products
-  double old[4][2][4];
+  f64x4 acc[4][2];
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
@@ -306,34 +495,33 @@ __global__ void __launch_bounds__(kUpdThreads) gje_update_kernel(int n, int k, i
       for (int r = 0; r < 4; ++r) {
         const int i = row0 + wr * 64 + bi * 16 + lk + 4 * r;
         const bool acc_row = i < n && !(i >= k && i < e) && col < n && !(col >= k && col < e);
-        old[bi][bj][r] = acc_row ? A[(long long)i * n + col] : 0.0;
+        acc[bi][bj][r] = acc_row ? A[(long long)i * n + col] : 0.0;
       }
     }
-  for (int q = tid; q < kUpdTile * kPanel; q += kUpdThreads) {
-    const int rr = q / kPanel, t = q % kPanel;
-    const int i = row0 + rr;
-    As[rr][t] = (i < n && t < w) ? A[(long long)i * n + k + t] : 0.0;
-    const int t2 = q / kUpdTile, cc = q % kUpdTile;
-    const int col = col0 + cc;
-    Rs[t2][cc] = (col < n && t2 < w) ? R[(long long)t2 * n + col] : 0.0;
-  }
-  __syncthreads();
-  f64x4 acc[4][2];
-#pragma unroll
-  for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int kb = 0; kb < w; kb += kUpdK) {
+    if (kb > 0) __syncthreads();
+    for (int q = tid; q < kUpdTile * kUpdK; q += kUpdThreads) {
+      const int rr = q / kUpdK, t = q % kUpdK;
+      const int i = row0 + rr;
+      As[rr][t] = (i < n && kb + t < w) ? A[(long long)i * n + k + kb + t] : 0.0;
+      const int t2 = q / kUpdTile, cc = q % kUpdTile;
+      const int col = col0 + cc;
+      Rs[t2][cc] = (col < n && kb + t2 < w) ? R[(long long)(kb + t2) * n + col] : 0.0;
+    }
+    __syncthreads();
 #pragma unroll 4
-  for (int t0 = 0; t0 < kPanel; t0 += 4) {
-    double a[4], b[2];
+    for (int t0 = 0; t0 < kUpdK; t0 += 4) {
+      double a[4], b[2];
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) a[bi] = As[wr * 64 + bi * 16 + li][t0 + lk];
+      for (int bi = 0; bi < 4; ++bi) a[bi] = As[wr * 64 + bi * 16 + li][t0 + lk];
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) b[bj] = Rs[t0 + lk][wc * 32 + bj * 16 + li];
+      for (int bj = 0; bj < 2; ++bj) b[bj] = Rs[t0 + lk][wc * 32 + bj * 16 + li];
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+      for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+        for (int bj = 0; bj < 2; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
@@ -345,8 +533,7 @@ __global__ void __launch_bounds__(kUpdThreads) gje_update_kernel(int n, int k, i
       for (int r = 0; r < 4; ++r) {
         const int i = row0 + wr * 64 + bi * 16 + lk + 4 * r;
         if (i >= n) continue;
-        // panel rows are assigned (their old value is 0 here), other rows accumulate
-        A[(long long)i * n + col] = old[bi][bj][r] + acc[bi][bj][r];
+        A[(long long)i * n + col] = acc[bi][bj][r];
       }
     }
 }
@@ -553,29 +740,65 @@ __global__ void gemm_reduce_kernel(int nb, int ld, int q, int nchunk, const doub
 
 }  // namespace
 
+// Rows per workgroup of the cooperative panel elimination (64, 128 or 256;
+// STKKT_COARSE_PANEL_ROWS overrides, 0 selects the launch-per-column path),
+// or 0 if its workgroups cannot all be resident at once.
+static int panel_rows(int n) {
+  const char *env = std::getenv("STKKT_COARSE_PANEL_ROWS");
+  const int forced = env ? std::atoi(env) : -1;
+  int dev = 0, cus = 0, coop = 0;
+  STKKT_HIP(hipGetDevice(&dev));
+  STKKT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  STKKT_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  if (!coop || forced == 0) return 0;
+  for (int R : {128, 256, 64}) {
+    if (forced > 0 && R != forced) continue;
+    const size_t lds = sizeof(double) * (size_t)kPanel * (R + 1);
+    STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&gje_panel_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    STKKT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gje_panel_kernel, kGjThreads, lds));
+    if ((n + R - 1) / R <= per_cu * cus) return R;
+  }
+  return 0;
+}
+
 // Explicit inverse of the n x n row-major matrix in A (overwritten with the
-// inverse).  tmp: n x n scratch; rows: kPanel x n scratch; piv: n int32.
+// inverse).  tmp: n x n scratch; rows: kPanel x n scratch; piv: n int32;
+// gs: candidate tables for ceil(n / 64) workgroups.
 static void gje_invert(int n, double *A, double *tmp, double *rows, double *pan, double *fcol, int32_t *piv,
-                       int32_t *swp, double *prow, int *status, hipStream_t s) {
+                       int32_t *swp, double *prow, const GjSync &gs, int *status, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
     STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&gje_update_kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kUpdLds));
     attr_set = true;
   }
+  const int R = panel_rows(n);
   hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(n, 256, 64)), dim3(256), 0, s, n, piv);
+  if (R > 0) hipLaunchKernelGGL(gj_reset_kernel, dim3(1), dim3(64), 0, s, gs);
   const int nt = (n + kUpdTile - 1) / kUpdTile;
   for (int k = 0; k < n; k += kPanel) {
     const int e = std::min(n, k + kPanel);
-    const int nrb = (n + 63) / 64;
-    hipLaunchKernelGGL(gje_panel_gather_kernel, dim3(nrb), dim3(256), 0, s, n, k, e - k, A, pan);
-    for (int c = k; c < e; ++c) {
-      hipLaunchKernelGGL(gje_pivot_kernel, dim3(1), dim3(1024), 0, s, n, k, e, c, pan, piv, swp, prow, fcol,
-                         status);
-      hipLaunchKernelGGL(gje_elim_kernel, dim3((n + 255) / 256, e - k), dim3(256), 0, s, n, k, c, pan, prow, fcol,
-                         status);
+    if (R > 0) {
+      int n_ = n, k_ = k, e_ = e, R_ = R;
+      GjSync gs_ = gs;
+      unsigned bar0 = (unsigned)k;
+      void *args[] = {&n_, &k_, &e_, &R_, &A, &piv, &swp, &gs_, &bar0, &status};
+      STKKT_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&gje_panel_kernel),
+                                           dim3((n + R - 1) / R), dim3(kGjThreads), args,
+                                           (unsigned)(sizeof(double) * (size_t)kPanel * (R + 1)), s));
+    } else {
+      const int nrb = (n + 63) / 64;
+      hipLaunchKernelGGL(gje_panel_gather_kernel, dim3(nrb), dim3(256), 0, s, n, k, e - k, A, pan);
+      for (int c = k; c < e; ++c) {
+        hipLaunchKernelGGL(gje_pivot_kernel, dim3(1), dim3(1024), 0, s, n, k, e, c, pan, piv, swp, prow, fcol,
+                           status);
+        hipLaunchKernelGGL(gje_elim_kernel, dim3((n + 255) / 256, e - k), dim3(256), 0, s, n, k, c, pan, prow,
+                           fcol, status);
+      }
+      hipLaunchKernelGGL(gje_panel_scatter_kernel, dim3(nrb), dim3(256), 0, s, n, k, e - k, pan, A);
     }
-    hipLaunchKernelGGL(gje_panel_scatter_kernel, dim3(nrb), dim3(256), 0, s, n, k, e - k, pan, A);
     hipLaunchKernelGGL(gje_laswp_kernel, dim3(blocks_for(n, 256, 64)), dim3(256), 0, s, n, k, e, A, swp, status);
     hipLaunchKernelGGL(gje_copy_rows_kernel, dim3(blocks_for(n, 256, 64), e - k), dim3(256), 0, s, n, k, e, A,
                        rows);
@@ -616,6 +839,12 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
       fcol(al, sizeof(double) * nb_),
       status(al, 256), ridx(al, sizeof(int32_t) * (size_t)nb_ * 81), rval(al, sizeof(double) * (size_t)nb_ * 81),
       cidx(al, sizeof(int32_t) * (size_t)nb_ * 81), cval(al, sizeof(double) * (size_t)nb_ * 81);
+  const int nwg_max = (nb_ + 63) / 64;
+  DevBuf candv(al, sizeof(double) * 2 * nwg_max), candi(al, sizeof(int32_t) * 2 * nwg_max),
+      candrow(al, sizeof(double) * 2 * (size_t)nwg_max * kPanel), crow(al, sizeof(double) * 2 * kPanel),
+      bar(al, 256);
+  const GjSync gs{candv.as<double>(), candi.as<int32_t>(), candrow.as<double>(), crow.as<double>(),
+                  bar.as<unsigned>(), reinterpret_cast<int *>(bar.as<unsigned char>() + 128)};
   STKKT_HIP(hipMemsetAsync(status.ptr, 0, sizeof(int), s));
   std::vector<int32_t> hidx((size_t)nb_ * 81), hcidx;
   std::vector<double> hval((size_t)nb_ * 81), hcval;
@@ -638,7 +867,7 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
     STKKT_HIP(hipGetLastError());
     // S_k^{-1} (column-major S is the row-major transpose: invert it as is)
     gje_invert(nb_, S.as<double>(), tmp.as<double>(), rows.as<double>(), pan.as<double>(), fcol.as<double>(),
-               piv.as<int32_t>(), swp.as<int32_t>(), prow.as<double>(), status.as<int>(), s);
+               piv.as<int32_t>(), swp.as<int32_t>(), prow.as<double>(), gs, status.as<int>(), s);
     // E_k = S_k^{-1} U_k
     if (k + 1 < nlev_) {
       hipLaunchKernelGGL(coupling_rows_kernel, dim3(G), dim3(128), 0, s, d, k, +1, ridx.as<int32_t>(),
@@ -673,6 +902,7 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
   int st = 0;
   STKKT_HIP(hipMemcpyAsync(&st, status.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
   STKKT_HIP(hipStreamSynchronize(s));   // the setup buffers are released on return
+  if (st == 2) throw Error(STKKT_EHIP, "coarse LU: panel elimination barrier timed out");
   if (st) throw Error(STKKT_EBREAKDOWN, "coarse LU: singular Schur complement block");
 }
 

@@ -281,3 +281,32 @@ def test_coarse_lu_multi_rhs_injection(st):
     for i in range(3):
         assert _rel(Y[i].cpu().numpy(), tl.coarse_correction(X[i])) <= 1e-9
         assert torch.equal(Y[i], C.apply(Xd[i].contiguous()))
+
+
+@pytest.mark.parametrize("name", ["aniso", "mid"])
+def test_coarse_lu_panel_paths(st, name, monkeypatch):
+    """The Gauss-Jordan inversion of the Schur blocks, with the panel
+    eliminated by one cooperative launch (64, 128 or 256 rows per workgroup)
+    or by two launches per column: all give the same coarse correction, and
+    it matches the oracle's block LU.  The mid case (2187 rows per block)
+    spans 35 panels and 9 to 35 workgroups with ragged tails."""
+    prob, fac = _mid_case() if name == "mid" else case(name)[:2]
+    op = st.KKTOperator(prob)
+    x = np.random.default_rng(77).standard_normal(prob.unknowns)
+    xd = _dev(x)
+    ys = {}
+    for rows in ("0", "64", "128", "256"):
+        monkeypatch.setenv("STKKT_COARSE_PANEL_ROWS", rows)
+        _say(f"case {name}: coarse LU, panel rows {rows}")
+        C = st.Coarse(op, fac, method=st.COARSE_LU)
+        ys[rows] = C.apply(xd).cpu().numpy()
+        del C
+    monkeypatch.delenv("STKKT_COARSE_PANEL_ROWS")
+    y_ref = twolevel.TwoLevel(prob, None, None, fac, coarse="lu").coarse_correction(x)
+    err = _rel(ys["128"], y_ref)
+    _say(f"  rel err vs oracle {err:.2e}")
+    assert err <= 1e-9
+    for rows in ("0", "64", "256"):
+        d = _rel(ys[rows], ys["128"])
+        _say(f"  panel rows {rows} vs 128: rel diff {d:.2e}")
+        assert d <= 1e-12
