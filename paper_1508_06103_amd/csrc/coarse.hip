@@ -50,59 +50,97 @@ __device__ inline double hat(int i, int I, int f, double rf) {
 }
 
 // y_fine = I_c^h x_coarse: every fine node interpolates the (up to 16) coarse
-// nodes of the coarse space-time cell that contains it.  One wavefront per
-// fine line (nodes (., i1, i2, n), components innermost; four lines per
-// workgroup).  The line's y, z, t interpolation is done once per coarse x
-// node, u[I0][c] = sum over the (up to 8) coarse (I1, I2, I3) of
-// hat_y hat_z hat_t xc[I0, I1, I2, I3, c], kept in LDS; then every fine entry
-// is hat_x(lo) u[lo][c] + hat_x(lo + 1) u[lo + 1][c].
-__global__ void __launch_bounds__(256) prolong_kernel(OpDev fo, OpDev co, int fx, int fy, int fz, int ft,
+// nodes of the coarse space-time cell that contains it (the interpolation is
+// the tensor product of the 1-D hat functions).  A workgroup owns the fine
+// lines (nodes (., i1, i2, n), components innermost) of one coarse (y, z)
+// cell group at one time level: i1 in [g1 fy, g1 fy + fy), i2 in
+// [g2 fz, g2 fz + fz) (the last group of an axis is its last node alone).
+// Such lines need the coarse lines (lo1 + b1, lo2 + b2) of levels lo3 + b3,
+// b = 0, 1 (lo = g, lo3 = n / ft), and the work is done in three passes over
+// LDS:
+//   V[b1][b2][t] = sum_b3 hat_t(n, lo3 + b3) xc[lo3 + b3, lo1 + b1, lo2 + b2][t]
+//   U[line][t]   = sum_b2 hat_z(i2, lo2 + b2) sum_b1 hat_y(i1, lo1 + b1) V[b1][b2][t]
+//   y[line][3 i0 + c] = hat_x(i0, lo0) U[line][3 lo0 + c] + hat_x(i0, lo0 + 1) U[line][3 lo0 + 3 + c]
+// (t runs over the 3 x coarse-x entries of a coarse line).  The x weights and
+// U positions of the 3 nn0 fine entries, and the y / z weights of the lines,
+// are tabulated in LDS first.  The output pass runs over (line, entry) pairs
+// with the entry innermost, so that lines of consecutive i1 (adjacent in
+// memory) are written as one stream.  Lines go through U in batches of at
+// most `lb` lines.
+struct ProlongEntry {
+  double w0, w1;   // hat_x(i0, lo0), hat_x(i0, lo0 + 1) (0 when i0 sits on a coarse node)
+  int u0, pad;     // 3 lo0 + c
+};
+static_assert(sizeof(ProlongEntry) == 3 * sizeof(double), "ProlongEntry takes three doubles of LDS");
+
+__global__ void __launch_bounds__(256) prolong_kernel(OpDev fo, OpDev co, int fx, int fy, int fz, int ft, int lb,
                                                       const double *__restrict__ xc, double *__restrict__ y) {
   extern __shared__ double pro_lds[];
-  const int rows = fo.nn[1] * fo.nn[2] * (fo.M + 1);
-  const int len = 3 * fo.nn[0], clen = 3 * co.nn[0];
+  const int gy = (fo.nn[1] - 1) / fy + 1, gz = (fo.nn[2] - 1) / fz + 1;
+  const int g1 = blockIdx.x % gy, g2 = (blockIdx.x / gy) % gz, n = blockIdx.x / (gy * gz);
+  const int clen = 3 * co.nn[0], len = 3 * fo.nn[0];
+  const int ly = min(fy, fo.nn[1] - g1 * fy), lz = min(fz, fo.nn[2] - g2 * fz);
+  const int cy = ly > 1 ? 2 : 1, cz = lz > 1 ? 2 : 1;   // coarse y / z lines in use
+  const int nl = ly * lz;
+  const int lo3 = n / ft, ct = n % ft == 0 ? 1 : 2;
   const double rx = 1.0 / fx, ry = 1.0 / fy, rz = 1.0 / fz, rt = 1.0 / ft;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double *u = pro_lds + wave * clen;
-  // every wavefront of a workgroup makes the same number of passes (barriers)
-  for (int grp = blockIdx.x; grp * 4 < rows; grp += gridDim.x) {
-    const int row = grp * 4 + wave;
-    const bool live = row < rows;
-    if (live) {
-      const int i1 = row % fo.nn[1], i2 = (row / fo.nn[1]) % fo.nn[2], n = row / (fo.nn[1] * fo.nn[2]);
-      const int lo1 = i1 / fy, c1 = i1 % fy == 0 ? 1 : 2;
-      const int lo2 = i2 / fz, c2 = i2 % fz == 0 ? 1 : 2;
-      const int lo3 = n / ft, c3 = n % ft == 0 ? 1 : 2;
-      const double w1[2] = {hat(i1, lo1, fy, ry), hat(i1, lo1 + 1, fy, ry)};
-      const double w2[2] = {hat(i2, lo2, fz, rz), hat(i2, lo2 + 1, fz, rz)};
-      const double w3[2] = {hat(n, lo3, ft, rt), hat(n, lo3 + 1, ft, rt)};
-      for (int t = lane; t < clen; t += 64) {
-        double a = 0.0;
-#pragma unroll
-        for (int b3 = 0; b3 < 2; ++b3)
-#pragma unroll
-          for (int b2 = 0; b2 < 2; ++b2)
-#pragma unroll
-            for (int b1 = 0; b1 < 2; ++b1) {
-              if (b3 >= c3 || b2 >= c2 || b1 >= c1) continue;
-              const long long cg = (long long)(lo3 + b3) * co.N + co.nn[0] * ((lo1 + b1) + co.nn[1] * (lo2 + b2));
-              a += w1[b1] * w2[b2] * w3[b3] * xc[3 * cg + t];
-            }
-        u[t] = a;
-      }
+  const double wt0 = hat(n, lo3, ft, rt), wt1 = ct > 1 ? hat(n, lo3 + 1, ft, rt) : 0.0;
+  ProlongEntry *ent = reinterpret_cast<ProlongEntry *>(pro_lds);   // [len]
+  double *wl = pro_lds + 3 * len;   // [nl][4]: hat_y(i1, lo1 + b1), hat_z(i2, lo2 + b2)
+  double *V = wl + 4 * nl;          // [4][clen]
+  double *U = V + 4 * clen;         // [lb][clen]
+  for (int t = threadIdx.x; t < len; t += blockDim.x) {
+    const int i0 = t / 3, c = t - 3 * i0, lo0 = i0 / fx;
+    ProlongEntry e;
+    e.w0 = hat(i0, lo0, fx, rx);
+    e.w1 = i0 % fx != 0 ? hat(i0, lo0 + 1, fx, rx) : 0.0;
+    e.u0 = 3 * lo0 + c;
+    e.pad = 0;
+    ent[t] = e;
+  }
+  for (int l = threadIdx.x; l < nl; l += blockDim.x) {
+    const int i1 = g1 * fy + l % ly, i2 = g2 * fz + l / ly;
+    wl[4 * l] = hat(i1, g1, fy, ry);
+    wl[4 * l + 1] = cy > 1 ? hat(i1, g1 + 1, fy, ry) : 0.0;
+    wl[4 * l + 2] = hat(i2, g2, fz, rz);
+    wl[4 * l + 3] = cz > 1 ? hat(i2, g2 + 1, fz, rz) : 0.0;
+  }
+  for (int k = threadIdx.x; k < cy * cz * clen; k += blockDim.x) {
+    const int t = k % clen, b = k / clen, b1 = b % cy, b2 = b / cy;
+    const long long cl = (long long)co.nn[0] * ((g1 + b1) + (long long)co.nn[1] * (g2 + b2));
+    double v = wt0 * xc[3 * ((long long)lo3 * co.N + cl) + t];
+    if (ct > 1) v += wt1 * xc[3 * ((long long)(lo3 + 1) * co.N + cl) + t];
+    V[(b2 * 2 + b1) * clen + t] = v;
+  }
+  for (int l0 = 0; l0 < nl; l0 += lb) {
+    const int nb = min(lb, nl - l0);
+    __syncthreads();   // tables and V written (first batch), U free (later batches)
+    for (int k = threadIdx.x; k < nb * clen; k += blockDim.x) {
+      const int lq = k / clen, t = k - lq * clen;
+      const double *w = wl + 4 * (l0 + lq);
+      double u = w[2] * (w[0] * V[t] + (cy > 1 ? w[1] * V[clen + t] : 0.0));
+      if (cz > 1) u += w[3] * (w[0] * V[2 * clen + t] + (cy > 1 ? w[1] * V[3 * clen + t] : 0.0));
+      U[k] = u;
     }
     __syncthreads();
-    if (live) {
-      double *yrow = y + (long long)row * len;
-      for (int t = lane; t < len; t += 64) {
-        const int i0 = t / 3, c = t - 3 * i0;
-        const int lo0 = i0 / fx;
-        double a = hat(i0, lo0, fx, rx) * u[3 * lo0 + c];
-        if (i0 % fx != 0) a += hat(i0, lo0 + 1, fx, rx) * u[3 * (lo0 + 1) + c];
-        yrow[t] = a;
+    // (line, entry) pairs of this thread, advanced without divisions
+    const int dq = blockDim.x / len, dt = blockDim.x - dq * len;
+    int lq = threadIdx.x / len, t = threadIdx.x - lq * len;
+    for (; lq < nb;) {
+      const int l = l0 + lq;
+      const int i1 = g1 * fy + l % ly, i2 = g2 * fz + l / ly;
+      const ProlongEntry e = ent[t];
+      const double *u = U + lq * clen;
+      double v = e.w0 * u[e.u0];
+      if (e.w1 != 0.0) v += e.w1 * u[e.u0 + 3];
+      y[(((long long)n * fo.nn[2] + i2) * fo.nn[1] + i1) * len + t] = v;
+      lq += dq;
+      t += dt;
+      if (t >= len) {
+        t -= len;
+        ++lq;
       }
     }
-    __syncthreads();   // u is rewritten by the next pass
   }
 }
 
@@ -173,8 +211,29 @@ __global__ void __launch_bounds__(256) restrict_axis_kernel(Dims4 din, int d, in
 
 }  // namespace
 
-static int prolong_blocks(const OpDev &fo) { return std::min((fo.nn[1] * fo.nn[2] * (fo.M + 1) + 3) / 4, 1 << 20); }
-static size_t prolong_lds(const OpDev &co) { return sizeof(double) * 4 * 3 * (size_t)co.nn[0]; }
+// Prolongation launch: one workgroup per (y group, z group, time level); U
+// batches sized so that V and U take at most 32 KB of LDS (the x-entry and
+// line tables come on top: 24 B per fine x entry, 32 B per line).
+static void prolong(const coarse *C, const double *xc, double *y, hipStream_t s) {
+  const OpDev &fo = C->fine, &co = C->cop->d;
+  const int fy = C->fac[1], fz = C->fac[2];
+  const int gy = (fo.nn[1] - 1) / fy + 1, gz = (fo.nn[2] - 1) / fz + 1;
+  const long long blocks = (long long)gy * gz * (fo.M + 1);
+  STKKT_REQUIRE(blocks < (1LL << 31), "coarse_apply: fine mesh too large for the prolongation grid");
+  const int clen = 3 * co.nn[0], len = 3 * fo.nn[0];
+  const int lb = std::max(1, std::min(fy * fz, (int)(4096 / clen) - 4));
+  const size_t lds = sizeof(double) * ((size_t)3 * len + 4 * (size_t)fy * fz + (size_t)(4 + lb) * clen);
+  constexpr size_t kLdsMax = 160 * 1024;
+  STKKT_REQUIRE(lds <= kLdsMax, "coarse_apply: fine x line too long for the prolongation kernel");
+  static bool attr_set = false;
+  if (!attr_set) {
+    STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&prolong_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(prolong_kernel, dim3((unsigned)blocks), dim3(256), lds, s, fo, co, C->fac[0], fy, fz, C->fac[3],
+                     lb, xc, y);
+}
 
 // xc = (I_c^h)^T x, axis by axis (x, y, z, t; axes with factor 1 are skipped)
 static void restrict_transpose(const coarse *C, const double *x, double *xc, hipStream_t s) {
@@ -319,8 +378,7 @@ void coarse_apply_device(const coarse *C, const double *x, double *y, hipStream_
                                C->work.get());
     if (st != STKKT_OK && st != STKKT_NOT_CONVERGED) throw Error(st, "coarse solve failed");
   }
-  hipLaunchKernelGGL(prolong_kernel, dim3(prolong_blocks(fo)), dim3(256), prolong_lds(co), s, fo, co, C->fac[0],
-                     C->fac[1], C->fac[2], C->fac[3], C->yc.as<double>(), y);
+  prolong(C, C->yc.as<double>(), y, s);
   STKKT_HIP(hipGetLastError());
 }
 
@@ -341,9 +399,7 @@ void coarse_apply_multi_device(const coarse *C, int q, const double *const *x, d
   double *xc = C->xcm.as<double>(), *yc = C->ycm.as<double>();
   for (int i = 0; i < q; ++i) restrict_to_coarse(C, x[i], xc + i * nvc, s);
   C->lu->solve_multi(q, xc, nvc, yc, nvc, s);
-  for (int i = 0; i < q; ++i)
-    hipLaunchKernelGGL(prolong_kernel, dim3(prolong_blocks(fo)), dim3(256), prolong_lds(co), s, fo, co, C->fac[0],
-                       C->fac[1], C->fac[2], C->fac[3], yc + i * nvc, y[i]);
+  for (int i = 0; i < q; ++i) prolong(C, yc + i * nvc, y[i], s);
   STKKT_HIP(hipGetLastError());
 }
 

@@ -824,12 +824,11 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
   Lval_ = DevBuf(al, sizeof(double) * (size_t)nb_ * 81 * nlev_);
   partial_ = DevBuf(al, sizeof(double) * (size_t)nb_ * ((nb_ + kGvCols - 1) / kGvCols));
   t_ = DevBuf(al, sizeof(double) * nb_);
-  // multi-RHS products: about 1024 workgroups (64 rows x a column chunk of at
-  // least 256 columns) per block
-  {
-    const int tiles = ld_ / kMrRows, chunks = (nb_ + 255) / 256;
-    nsplit_ = std::min(chunks, std::max(1, (1024 + tiles - 1) / tiles));
-  }
+  // multi-RHS products: workgroups of 64 rows x 256 columns (two rounds of
+  // the load pipeline).  At nb 6591 (103 x 26 workgroups) a block product
+  // took 41 us in FP32 and 65 us in FP64, against 47 / 70 us with 10 column
+  // chunks and 56 / 81 us with 3.
+  nsplit_ = (nb_ + 255) / 256;
   mpartial_ = DevBuf(al, sizeof(double) * (size_t)nsplit_ * kMrRhs * ld_);
   mt_ = DevBuf(al, sizeof(double) * (size_t)3 * kMrRhs * nb_);   // tT, xT[0], xT[1]
   // setup work buffers (FP64)
