@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(256) restrict_axis_kernel(Dims4 din, int d, in
   const int lane = threadIdx.x & 63;
   for (int line = blockIdx.x * 4 + (threadIdx.x >> 6); line < lines; line += gridDim.x * 4) {
     double *orow = out + (long long)line * lout;
-    if (d == 0) {
+    if (d == 0) {   // (x lines too long for restrict_x_kernel's LDS)
       const double *irow = in + (long long)line * lin;   // axes 1..3 unchanged
       for (int t = lane; t < lout; t += 64) {
         const int I = t / 3, c = t - 3 * I;
@@ -193,19 +193,46 @@ __global__ void __launch_bounds__(256) restrict_axis_kernel(Dims4 din, int d, in
         for (int p = lo; p <= hi; ++p) acc += hat(p, I, f, rf) * irow[3 * p + c];
         orow[t] = acc;
       }
-    } else {
-      // input line of node p on axis d: the output line's coordinates with axis d set to p
-      const int o1 = line % dout[1], o2 = (line / dout[1]) % dout[2], o3 = line / (dout[1] * dout[2]);
-      const int I = d == 1 ? o1 : d == 2 ? o2 : o3;
-      const long long step = d == 1 ? 1 : d == 2 ? din.n[1] : (long long)din.n[1] * din.n[2];
-      const long long line0 = o1 + (long long)din.n[1] * (o2 + (long long)din.n[2] * o3) - (long long)I * step;
-      const int lo = max(0, I * f - f + 1), hi = min(din.n[d] - 1, I * f + f - 1);
-      for (int t = lane; t < lout; t += 64) {
-        double acc = 0.0;
-        for (int p = lo; p <= hi; ++p) acc += hat(p, I, f, rf) * in[(line0 + p * step) * lin + t];
-        orow[t] = acc;
-      }
+      continue;
     }
+    // input line of node p on axis d: the output line's coordinates with axis d set to p
+    const int o1 = line % dout[1], o2 = (line / dout[1]) % dout[2], o3 = line / (dout[1] * dout[2]);
+    const int I = d == 1 ? o1 : d == 2 ? o2 : o3;
+    const long long step = d == 1 ? 1 : d == 2 ? din.n[1] : (long long)din.n[1] * din.n[2];
+    const long long line0 = o1 + (long long)din.n[1] * (o2 + (long long)din.n[2] * o3) - (long long)I * step;
+    const int lo = max(0, I * f - f + 1), hi = min(din.n[d] - 1, I * f + f - 1);
+    for (int t = lane; t < lout; t += 64) {
+      double acc = 0.0;
+      for (int p = lo; p <= hi; ++p) acc += hat(p, I, f, rf) * in[(line0 + p * step) * lin + t];
+      orow[t] = acc;
+    }
+  }
+}
+
+// The x axis of the restriction (d = 0 above): lines are unchanged and
+// contiguous, so a workgroup reads kRxLines consecutive input lines into LDS
+// with one coalesced stream and forms all their outputs from there,
+// out[line][3 I + c] = sum over p of hat(p, I, f) in[line][3 p + c].
+constexpr int kRxLines = 16;
+
+__global__ void __launch_bounds__(256) restrict_x_kernel(int nx, int lines, int f, const double *__restrict__ in,
+                                                         double *__restrict__ out) {
+  extern __shared__ double rx_lds[];
+  const int lin = 3 * nx, cx = (nx - 1) / f + 1, lout = 3 * cx;
+  const double rf = 1.0 / f;
+  const int l0 = blockIdx.x * kRxLines, nl = min(kRxLines, lines - l0);
+  const double *src = in + (long long)l0 * lin;
+  for (int k = threadIdx.x; k < nl * lin; k += blockDim.x) rx_lds[k] = src[k];
+  __syncthreads();
+  double *dst = out + (long long)l0 * lout;
+  for (int k = threadIdx.x; k < nl * lout; k += blockDim.x) {
+    const int lq = k / lout, t = k - lq * lout;
+    const int I = t / 3, c = t - 3 * I;
+    const int lo = max(0, I * f - f + 1), hi = min(nx - 1, I * f + f - 1);
+    const double *row = rx_lds + lq * lin + c;
+    double acc = 0.0;
+    for (int p = lo; p <= hi; ++p) acc += hat(p, I, f, rf) * row[3 * p];
+    dst[k] = acc;
   }
 }
 
@@ -253,8 +280,13 @@ static void restrict_transpose(const coarse *C, const double *x, double *xc, hip
     Dims4 out = dm;
     out.n[d] = (dm.n[d] - 1) / C->fac[d] + 1;
     const int lines = out.n[1] * out.n[2] * out.n[3];
-    hipLaunchKernelGGL(restrict_axis_kernel, dim3(std::min((lines + 3) / 4, 1 << 20)), dim3(256), 0, s, dm, d,
-                       C->fac[d], src, dst);
+    const size_t xlds = sizeof(double) * kRxLines * 3 * (size_t)dm.n[0];
+    if (d == 0 && xlds <= 64 * 1024)
+      hipLaunchKernelGGL(restrict_x_kernel, dim3((lines + kRxLines - 1) / kRxLines), dim3(256), xlds, s, dm.n[0], lines,
+                         C->fac[0], src, dst);
+    else
+      hipLaunchKernelGGL(restrict_axis_kernel, dim3(std::min((lines + 3) / 4, 1 << 20)), dim3(256), 0, s, dm, d,
+                         C->fac[d], src, dst);
     dm = out;
     src = dst;
   }
