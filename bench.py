@@ -232,6 +232,11 @@ def time_kernels(op, pre, reps, coarse=None):
            "kkt_matvec": timed(lambda: op.matvec(r, z, stream=stream))}
     if coarse is not None:
         out["coarse_apply"] = timed(lambda: coarse.apply(r, z, stream=stream))
+    # a plain device-to-device copy of 1 GiB: the measured streaming peak
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    out["copy_1gib"] = timed(lambda: dst.copy_(src))
+    del src, dst
     return out
 
 
@@ -700,12 +705,19 @@ def apply_kernel_name(pre, prec_name):
     return f"apply_ring_kernel<{t}, {rows}>" if rows else f"apply_kernel<{t}>"
 
 
-def roofline_of(prob, pre, apply_ms, config, prec_name):
+def roofline_of(prob, pre, apply_ms, config, prec_name, copy_ms=None):
+    """Roofline entry of the apply; with copy_ms (a 1 GiB device copy, read
+    plus write) also the fraction of that measured streaming rate."""
     apply_bytes = algorithmic_apply_bytes(pre, prob)
     achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
-    return {"kernel": f"ras_apply ({apply_kernel_name(pre, prec_name)})", "bound": "hbm", "achieved": achieved,
-            "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
-            "traffic": counted_traffic(config, prec_name), "algorithmic_bytes": apply_bytes}
+    out = {"kernel": f"ras_apply ({apply_kernel_name(pre, prec_name)})", "bound": "hbm", "achieved": achieved,
+           "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+           "traffic": counted_traffic(config, prec_name), "algorithmic_bytes": apply_bytes}
+    if copy_ms:
+        copy_gbps = 2.0 * (1 << 30) / (copy_ms * 1e-3) / 1e9
+        out["measured_copy_GBps"] = copy_gbps
+        out["frac_of_measured_copy"] = achieved / copy_gbps
+    return out
 
 
 def mixed_precision_extra(st, prob, cfg, args, op, pre, coarse):
@@ -744,7 +756,7 @@ def mixed_precision_extra(st, prob, cfg, args, op, pre, coarse):
                 "gmres_iters": float(np.mean(its)), "setup_ms": setup})
     km = time_kernels(op, pre, args.apply_reps, coarse)
     out["kernels_ms"] = km
-    out["roofline"] = roofline_of(prob, pre, km["ras_apply"], args.config, "f32")
+    out["roofline"] = roofline_of(prob, pre, km["ras_apply"], args.config, "f32", km.get("copy_1gib"))
     pre.close()
     if coarse is not None:
         coarse.close()
@@ -773,7 +785,7 @@ def one_level_extra(st, args):
     km = time_kernels(op, pre, args.apply_reps)
     out = {"workload": "cube32x64: " + WORKLOADS["cube32x64"], "value": 3 / total, "unit": "solves/s",
            "ms_per_step": 1e3 * total / 3, "gmres_iters": float(np.mean(its)), "setup_ms": setup, "kernels_ms": km,
-           "roofline": roofline_of(prob, pre, km["ras_apply"], "cube32x64", "f64")}
+           "roofline": roofline_of(prob, pre, km["ras_apply"], "cube32x64", "f64", km.get("copy_1gib"))}
     pre.close()
     op.close()
     torch.cuda.empty_cache()
@@ -818,7 +830,7 @@ def run_single(args):
                    "unknowns": prob.unknowns, "subdomains": pre.nsub, "precision": args.precision},
         "p50_ms": 1e3 * percentile(times, 50), "p99_ms": 1e3 * percentile(times, 99),
         "gmres_iters": mean_its, "setup_ms": setup, "kernels_ms": km,
-        "roofline": roofline_of(prob, pre, km["ras_apply"], args.config, args.precision),
+        "roofline": roofline_of(prob, pre, km["ras_apply"], args.config, args.precision, km.get("copy_1gib")),
     }
     if not args.no_extras and args.config == "cube48x96" and args.precision == "f64":
         res["mixed_f32_preconditioner"] = mixed_precision_extra(st, prob, cfg, args, op, pre, coarse)

@@ -265,12 +265,12 @@ __global__ void __launch_bounds__(256) gje_elim_kernel(int n, int k, int c, doub
 // workgroup has passed the barrier that follows its reads.  The barrier
 // counter grows by the number of workgroups per step and is zeroed once per
 // inversion; bar0 is the number of steps taken by earlier launches.  A
-// barrier that has not completed after about a second sets the abort flag
-// and status 2, and every workgroup leaves at its next barrier, so the launch
-// always ends.
+// barrier that has not completed after `spin_limit` polls (the default is
+// about a second) sets the abort flag and status 2, and every workgroup
+// leaves at its next barrier, so the launch always ends.
 // ---------------------------------------------------------------------------
 constexpr int kGjThreads = 1024;
-constexpr unsigned kGjSpinLimit = 1u << 20;
+constexpr unsigned kGjSpinLimit = 1u << 20;   // default bound on the polls of one barrier
 
 struct GjSync {
   double *candv;     // [2][nwg] largest |entry|
@@ -279,6 +279,7 @@ struct GjSync {
   double *crow;      // [2][kPanel] row c's panel segment
   unsigned *count;   // barrier arrivals
   int *abort;        // set by a barrier that timed out
+  unsigned spin_limit;
 };
 
 // All threads of the workgroup; false if the barrier was abandoned.  Every
@@ -295,7 +296,7 @@ __device__ inline bool gj_grid_barrier(const GjSync &gs, unsigned target) {
     int good = 1;
     unsigned spins = 0;
     while (__hip_atomic_load(gs.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(gs.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kGjSpinLimit) {
+      if (__hip_atomic_load(gs.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > gs.spin_limit) {
         __hip_atomic_store(gs.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         good = 0;
         break;
@@ -842,8 +843,12 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
   DevBuf candv(al, sizeof(double) * 2 * nwg_max), candi(al, sizeof(int32_t) * 2 * nwg_max),
       candrow(al, sizeof(double) * 2 * (size_t)nwg_max * kPanel), crow(al, sizeof(double) * 2 * kPanel),
       bar(al, 256);
+  // STKKT_COARSE_SPIN_LIMIT lowers the barrier's poll bound (a test forces the
+  // time-out path with it)
+  const char *spin_env = std::getenv("STKKT_COARSE_SPIN_LIMIT");
+  const unsigned spin = spin_env ? (unsigned)std::max(0, std::atoi(spin_env)) : kGjSpinLimit;
   const GjSync gs{candv.as<double>(), candi.as<int32_t>(), candrow.as<double>(), crow.as<double>(),
-                  bar.as<unsigned>(), reinterpret_cast<int *>(bar.as<unsigned char>() + 128)};
+                  bar.as<unsigned>(), reinterpret_cast<int *>(bar.as<unsigned char>() + 128), spin};
   STKKT_HIP(hipMemsetAsync(status.ptr, 0, sizeof(int), s));
   std::vector<int32_t> hidx((size_t)nb_ * 81), hcidx;
   std::vector<double> hval((size_t)nb_ * 81), hcval;

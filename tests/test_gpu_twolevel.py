@@ -310,3 +310,26 @@ def test_coarse_lu_panel_paths(st, name, monkeypatch):
         d = _rel(ys[rows], ys["128"])
         _say(f"  panel rows {rows} vs 128: rel diff {d:.2e}")
         assert d <= 1e-12
+
+
+def test_coarse_lu_panel_barrier_timeout_is_reported(st, monkeypatch):
+    """The cooperative panel elimination bounds every grid-barrier wait.  With
+    the bound forced to zero polls from the host, a workgroup that has to wait
+    gives up at once, the launch ends on every workgroup, and coarse_setup
+    reports the failure; the next setup, with the default bound, is correct."""
+    prob, fac = _mid_case()
+    op = st.KKTOperator(prob)
+    monkeypatch.setenv("STKKT_COARSE_PANEL_ROWS", "128")
+    monkeypatch.setenv("STKKT_COARSE_SPIN_LIMIT", "0")
+    _say("case mid: coarse LU with a zero barrier wait bound")
+    with pytest.raises(st.StkktError) as ei:
+        st.Coarse(op, fac, method=st.COARSE_LU)
+    _say(f"  error: {ei.value}")
+    assert "timed out" in str(ei.value)
+    monkeypatch.delenv("STKKT_COARSE_SPIN_LIMIT")
+    C = st.Coarse(op, fac, method=st.COARSE_LU)
+    x = np.random.default_rng(78).standard_normal(prob.unknowns)
+    y = C.apply(_dev(x)).cpu().numpy()
+    err = _rel(y, twolevel.TwoLevel(prob, None, None, fac, coarse="lu").coarse_correction(x))
+    _say(f"  default bound: rel err vs oracle {err:.2e}")
+    assert err <= 1e-9
