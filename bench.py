@@ -362,7 +362,8 @@ def run_coarse(args):
     the one-vector path against the multi-right-hand-side path (one pass over
     the dense blocks for q vectors), for the coarse levels of the served
     32^3 x 64 requests (8^3 x 16) and of cube48x96 (12^3 x 24), FP32 and FP64
-    blocks.  Times are HIP-event averages on the stream of the launches."""
+    blocks, and the wall time of each coarse setup.  Apply times are
+    HIP-event averages on the stream of the launches."""
     import torch
     import paper_1508_06103_amd as st
     from workloads.generate import make_problem
@@ -374,7 +375,11 @@ def run_coarse(args):
         nb = 3 * (prob.n[0] // 4 + 1) ** 3
         nlev = prob.M // 4 + 1
         for prec, esz in ((st.F32, 4), (st.F64, 8)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             C = st.Coarse(op, fac, method=st.COARSE_LU, precision=prec)
+            torch.cuda.synchronize()
+            setup_ms = 1e3 * (time.perf_counter() - t0)
             blocks = esz * nb * nb * (2 * nlev - 1)
             x = torch.randn(16, op.n, dtype=torch.float64, device="cuda")
             y = torch.empty_like(x)
@@ -391,7 +396,8 @@ def run_coarse(args):
                 torch.cuda.synchronize()
                 return ev[0].elapsed_time(ev[1]) / reps
 
-            rec = {"nb": nb, "levels": nlev, "block_bytes": blocks, "one_vector_ms": timed(lambda: C.apply(x0, y0))}
+            rec = {"nb": nb, "levels": nlev, "block_bytes": blocks, "setup_ms": setup_ms,
+                   "one_vector_ms": timed(lambda: C.apply(x0, y0))}
             for q in (1, 2, 4, 8, 16):
                 rec[f"multi_q{q}_ms"] = timed(lambda: C.apply_multi(x[:q], y[:q]))
             key = f"{name}_coarse_{'f32' if esz == 4 else 'f64'}"
