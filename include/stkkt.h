@@ -267,8 +267,15 @@ int ras_export_factors_csr(const ras_t *ras, int32_t sub, int32_t *indptr, int32
 int ras_export_factors(const ras_t *ras, int32_t sub, double *host_out);
 
 /* Coarse level: build F_c on the coarse mesh, its one-level RAS (ILU(0)
- * factors) and the inner GMRES workspace.  Fails with STKKT_EINVAL when a
- * factor does not divide the mesh or a sensor is not on a coarse node. */
+ * factors) and the inner GMRES workspace, or, with STKKT_COARSE_LU, the
+ * explicit inverses S_k^{-1} and E_k of the block elimination in time.  Fails
+ * with STKKT_EINVAL when a factor does not divide the mesh or a sensor is not
+ * on a coarse node, STKKT_EBREAKDOWN for a singular Schur block.  The
+ * STKKT_COARSE_LU setup eliminates each 64-column panel in one cooperative
+ * launch whose workgroups must all be resident at once; every grid-barrier
+ * wait is bounded (about a second), so if other work on the device keeps
+ * some of them from starting the setup fails with STKKT_EHIP instead of
+ * waiting.  The call synchronises `stream`. */
 int coarse_setup(const kkt_op_t *fine, const coarse_params_t *cp, void *stream, coarse_t **out);
 
 /* y = I_c^h F_c^{-1} I_h^c x (device vectors of the fine size).  F_c^{-1} is
