@@ -264,11 +264,12 @@ def auto_parts(prob, box=8):
 
 def batch_parts(prob, how):
     """(parts, overlap) of an uneven-batch instance: the autotuned table
-    (paper_1508_06103_amd/parts_table.json), or boxes of about 8 nodes with overlap 1."""
+    (paper_1508_06103_amd/parts_table.json), or boxes of about 8, 12 or 16
+    nodes per axis ("box8", "box12", "box16") with overlap 1."""
     if how == "tuned":
         from paper_1508_06103_amd.tune import parts_for
         return parts_for(prob)
-    return auto_parts(prob), 1
+    return auto_parts(prob, box=int(how[3:])), 1
 
 
 def run_batch(args):
@@ -883,8 +884,9 @@ def main():
     ap.add_argument("--ilu-levels-f32", default="0,1,2", help="ilu mode: fill levels k run with FP32 factors")
     ap.add_argument("--ilu-levels-f64", default="0,1", help="ilu mode: fill levels k run with FP64 factors")
     ap.add_argument("--instances", type=int, default=64)
-    ap.add_argument("--parts", default="tuned", choices=["tuned", "box8"],
-                    help="batch/serve partitions: the autotuned table, or boxes of about 8 nodes with overlap 1")
+    ap.add_argument("--parts", default="tuned", choices=["tuned", "box8", "box12", "box16"],
+                    help="batch/serve partitions: the autotuned table, or boxes of about 8, 12 or 16 nodes per "
+                         "axis with overlap 1")
     ap.add_argument("--requests", type=int, default=100)
     ap.add_argument("--rate", type=float, default=50.0, help="serve mode: arrivals per second")
     args = ap.parse_args()

@@ -756,7 +756,7 @@ void BatchEngine::cycle(std::vector<int> &finished) {
   // v_0 = r / beta: |r|^2 of every running member is in hd (last residual)
   hipLaunchKernelGGL(bnormalize_kernel, dim3(nch_), dim3(kBT), 0, s_, Vd, Rd, hd, hs, chd, act_a_.as<int>());
   STKKT_HIP(hipGetLastError());
-  bool graph = sp_.graph != 0 && rb_.ring;
+  bool graph = sp_.graph != 0 && ras_batch_single_launch(rb_);
   for (int i = 0; i < S && graph; ++i)
     if (h_cyc[i] && slots_[i].C) graph = false;
   int nstep = graph ? 0 : ncyc;

@@ -1190,14 +1190,14 @@ void ras_apply_device(const ras *R, const double *r, double *z, hipStream_t s, v
 
 template <typename T>
 static void ras_batch_prepare_t(const ras *const *R, const long long *voff, void *const *local, int count,
-                                const Allocator *al, RasBatch &out, hipStream_t s) {
+                                const std::vector<char> &solo, const Allocator *al, RasBatch &out, hipStream_t s) {
   std::vector<RasBatchDesc<T>> d(count);
   std::vector<std::pair<int64_t, int2>> items;
   size_t lds = 0;
   for (int i = 0; i < count; ++i) {
     const ras *q = R[i];
     d[i] = RasBatchDesc<T>{};
-    if (!q) continue;   // empty slot
+    if (!q || solo[i]) continue;   // empty slot, or launched on its own
     d[i].op = q->d;
     d[i].subs = q->d_subs.as<SubInfo>();
     d[i].shapes = q->d_shapes.as<ShapeInfo>();
@@ -1211,7 +1211,7 @@ static void ras_batch_prepare_t(const ras *const *R, const long long *voff, void
     d[i].yzero = q->scratch_elems;
     d[i].voff = voff[i];
     d[i].rg = Ring{q->ring_rmax, q->ring_ltlz};
-    lds = std::max(lds, ring_lds_bytes<T, 256>(q));
+    lds = std::max(lds, out.kr == 256 ? ring_lds_bytes<T, 256>(q) : ring_lds_bytes<T, 64>(q));
     for (int k = 0; k < q->nsub; ++k)
       items.push_back({q->shapes[q->subs[k].shape].nblocks, make_int2(i, k)});
   }
@@ -1227,24 +1227,49 @@ static void ras_batch_prepare_t(const ras *const *R, const long long *voff, void
   out.lds = lds;
 }
 
+// One launch covers every member whose LDS ring fits: with 256 rows per phase
+// when all of them allow it, else with 64 (the per-row sums, and so the
+// results, are the same).  Members without a ring (or with ILU(k) factors)
+// are launched on their own after it; members of different precisions make
+// every member its own launch.
 void ras_batch_prepare(const ras *const *R, const long long *voff, void *const *local, int count,
                        const Allocator *al, RasBatch &out, hipStream_t s) {
   out = RasBatch{};
   out.count = count;
   out.precision = -1;
-  out.ring = true;
+  bool uniform = true;
   for (int i = 0; i < count; ++i) {
     out.members.push_back(R[i]);
     out.voff.push_back(voff[i]);
     out.local.push_back(local ? local[i] : nullptr);
     if (!R[i]) continue;
     if (out.precision < 0) out.precision = R[i]->params.precision;
-    out.ring = out.ring && ras_uses_ring(R[i]) && R[i]->params.precision == out.precision;
+    uniform = uniform && R[i]->params.precision == out.precision;
   }
   if (out.precision < 0) out.precision = STKKT_F64;
-  if (!out.ring) return;   // per-preconditioner launches
-  if (out.precision == STKKT_F32) ras_batch_prepare_t<float>(R, voff, local, count, al, out, s);
-  else ras_batch_prepare_t<double>(R, voff, local, count, al, out, s);
+  if (!uniform) return;   // per-preconditioner launches
+  std::vector<char> solo(count, 0);
+  int kr = 256;
+  bool any = false;
+  for (int i = 0; i < count; ++i) {
+    if (!R[i]) continue;
+    const int rows = ras_apply_rows_per_phase(R[i]);   // 256, 64, or 0 (no ring, ILU(k))
+    if (rows == 0) {
+      solo[i] = 1;
+      out.solo.push_back(i);
+    } else {
+      any = true;
+      kr = std::min(kr, rows);
+    }
+  }
+  if (!any) {   // every member on its own
+    out.solo.clear();
+    return;
+  }
+  out.ring = true;
+  out.kr = kr;
+  if (out.precision == STKKT_F32) ras_batch_prepare_t<float>(R, voff, local, count, solo, al, out, s);
+  else ras_batch_prepare_t<double>(R, voff, local, count, solo, al, out, s);
 }
 
 template <typename T>
@@ -1254,10 +1279,16 @@ static void ras_batch_launch(const RasBatch &b, const double *r, const double *r
   if (!attr_set) {
     STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_ring_batch_kernel<T, 256>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRingLdsLimit));
+    STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_ring_batch_kernel<T, 64>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRingLdsLimit));
     attr_set = true;
   }
-  hipLaunchKernelGGL((apply_ring_batch_kernel<T, 256>), dim3(b.blocks), dim3(kApplyThreads), b.lds, s,
-                     b.desc.as<RasBatchDesc<T>>(), b.work.as<int2>(), act, r, r2 ? r2 : r, z);
+  if (b.kr == 256)
+    hipLaunchKernelGGL((apply_ring_batch_kernel<T, 256>), dim3(b.blocks), dim3(kApplyThreads), b.lds, s,
+                       b.desc.as<RasBatchDesc<T>>(), b.work.as<int2>(), act, r, r2 ? r2 : r, z);
+  else
+    hipLaunchKernelGGL((apply_ring_batch_kernel<T, 64>), dim3(b.blocks), dim3(kApplyThreads), b.lds, s,
+                       b.desc.as<RasBatchDesc<T>>(), b.work.as<int2>(), act, r, r2 ? r2 : r, z);
 }
 
 void ras_batch_run(const RasBatch &b, const double *r, double *z, const int *act, const int *act_host,
@@ -1269,10 +1300,14 @@ void ras_batch_run(const RasBatch &b, const double *r, double *z, const int *act
                          b.local[i]);
     return;
   }
-  if (b.blocks == 0) return;
-  if (b.precision == STKKT_F32) ras_batch_launch<float>(b, r, r2, z, act, s);
-  else ras_batch_launch<double>(b, r, r2, z, act, s);
-  STKKT_HIP(hipGetLastError());
+  if (b.blocks > 0) {
+    if (b.precision == STKKT_F32) ras_batch_launch<float>(b, r, r2, z, act, s);
+    else ras_batch_launch<double>(b, r, r2, z, act, s);
+    STKKT_HIP(hipGetLastError());
+  }
+  for (const int i : b.solo)
+    if (act_host[i])
+      ras_apply_device(b.members[i], (act_host[i] == 2 && r2 ? r2 : r) + b.voff[i], z + b.voff[i], s, b.local[i]);
 }
 
 static std::vector<int> split(int L, int p) {

@@ -83,7 +83,9 @@ size_t ras_local_bytes(const ras *R);
 struct RasBatch {
   DevBuf desc, work;
   int count = 0, blocks = 0, precision = STKKT_F64;
-  bool ring = false;
+  bool ring = false;     // one launch over the (member, subdomain) work list of the ring members
+  int kr = 256;          // rows per phase of that launch (64 when a member's 256-row ring does not fit)
+  std::vector<int> solo; // members launched on their own (no LDS ring, or ILU(k))
   size_t lds = 0;
   std::vector<const ras *> members;
   std::vector<long long> voff;
@@ -91,6 +93,8 @@ struct RasBatch {
 };
 void ras_batch_prepare(const ras *const *R, const long long *voff, void *const *local, int count,
                        const Allocator *al, RasBatch &out, hipStream_t s);
+// true when the whole batch is one launch (no member of its own)
+inline bool ras_batch_single_launch(const RasBatch &b) { return b.ring && b.solo.empty(); }
 // act: device flags (members with 0 are skipped; members with 2 read their
 // input from r2 instead of r, at the same offset), act_host: the same flags on
 // the host

@@ -147,3 +147,30 @@ def test_batch_errors(st):
     other = st.KKTOperator(prob)
     with pytest.raises(st.StkktError):
         st.solve_batch([op, other], [pre, pre])
+
+
+def test_batch_mixed_phase_sizes_and_solo_members(st):
+    """One batched launch serves members with different LDS needs: a single
+    14^4-node box in FP64 (its ring fits only with 64-row phases) makes the
+    whole launch use 64-row phases, and a member with ILU(1) factors (which
+    have no ring) is launched on its own beside it.  Each member's result
+    equals its solve alone, bit for bit, and meets the tolerance on the
+    assembled operator."""
+    mix = [("big14", dict(n=(13, 13, 13), M=13, seed=9, lattice=2), (1, 1, 1, 1), 0), MIX[0], MIX[1]]
+    built = [build(st, *m, precision=st.F64) for m in mix[:2]]
+    prob, op, _ = build(st, *mix[2], precision=st.F64)
+    built.append((prob, op, st.RAS(op, mix[2][2], mix[2][3], precision=st.F64, ilu_level=1)))
+    assert built[0][2].apply_rows == 64 and built[1][2].apply_rows == 256 and built[2][2].apply_rows == 0
+    ops = [b[1] for b in built]
+    pres = [b[2] for b in built]
+    xs, sts = st.solve_batch(ops, pres, restart=20, rtol=1e-6)
+    for (name, *_), (prob, op, pre), x, s in zip(mix, built, xs, sts):
+        xg = x.cpu().numpy()
+        F = kkt.assemble(prob)
+        b = kkt.rhs(prob)
+        res = np.linalg.norm(b - F @ xg) / np.linalg.norm(b)
+        x1, s1 = st.solve_batch([op], [pre], restart=20, rtol=1e-6)
+        _say(f"  {name}: {s.iters} its in the mix, {s1[0].iters} alone, true res {res:.2e}")
+        assert s.converged and res <= 1e-6
+        assert s1[0].iters == s.iters
+        assert np.array_equal(x1[0].cpu().numpy(), xg), name
