@@ -1,17 +1,27 @@
 """Subdomain-partition autotuner for the uneven batched instances.
 
-For every size class (n, M) of the uneven batch (n in {8, 12, 16, 20, 24}
-elements per axis, M in {16, 24, 32, 48} time steps) the tuner times batched
-FGMRES(50) solves (FP32 preconditioners, rtol 1e-6) of a few seeded
-instances of that class under candidate partitions: owned boxes of about 6,
-8 or 12 nodes per spatial axis and 8 or 16 time levels, overlap 1 or 2.  The
-fastest candidate per class goes into ``parts_table.json`` beside this file,
-with its time and mean iteration count; ``parts_for`` reads the table.
+Two modes, both writing ``parts_table.json`` beside this file (``parts_for``
+reads it; the batched and served benchmarks use it):
 
-    python -m paper_1508_06103_amd.tune [--out FILE] [--instances K]
+* in the mix (``--in-mix``, the default table): a tuning batch of 64
+  instances drawn like the benchmark's uneven batch but with other seeds is
+  solved as one batched FGMRES(50) (FP32 preconditioners, rtol 1e-6), and the
+  partition of each size class (n, M) present is chosen by coordinate
+  descent on the batch's solve time: starting from owned boxes of about 12
+  nodes per axis, each class in turn tries boxes of about 8, 12 or 16 nodes
+  per spatial axis and 8, 12 or 16 time levels (overlap 1) and keeps a
+  candidate that shortens the whole batch by more than 0.5%.  In a full
+  batch the GPU is busy anyway, so the partition that wins is the one with
+  the fewest, largest boxes that still converge fast.
+* per class (without ``--in-mix``): a few seeded instances of each class
+  are timed alone as a batch under candidate partitions (owned boxes of
+  about 6, 8, 12 or 16 nodes per spatial axis and 8 or 16 time levels,
+  overlap 1 or 2), and the fastest wins.  Alone, a class favours more,
+  smaller boxes, which keep the GPU busy.
 
-The table is what the batched and served benchmarks use, and it records the
-partition of every class so that each run can be reproduced.
+    python -m paper_1508_06103_amd.tune [--in-mix] [--out FILE] [--instances K]
+
+The table records every class's partition, so each run can be reproduced.
 """
 import json
 import os
@@ -19,13 +29,34 @@ import sys
 import time
 
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "parts_table.json")
-SPACE_BOXES = (6, 8, 12)
+SPACE_BOXES = (6, 8, 12, 16)
 TIME_BOXES = (8, 16)
 OVERLAPS = (1, 2)
 
 
 def _parts(nodes, box):
     return max(1, int(round(nodes / box)))
+
+
+MIX_SPACE_BOXES = (8, 12, 16)
+MIX_TIME_BOXES = (8, 12, 16)
+
+
+def box_parts(n, M, box, tbox=None):
+    """Parts (px, py, pz, pt) for owned boxes of about `box` nodes per spatial
+    axis and `tbox` (default `box`) time levels."""
+    p = _parts(n + 1, box)
+    return (p, p, p, _parts(M + 1, tbox or box))
+
+
+def mix_candidates(n, M):
+    out = []
+    for bs in MIX_SPACE_BOXES:
+        for bt in MIX_TIME_BOXES:
+            parts = box_parts(n, M, bs, bt)
+            if parts not in out:
+                out.append(parts)
+    return out
 
 
 def candidates(n, M):
@@ -76,6 +107,71 @@ def _time_candidate(st, torch, probs, ops, parts, overlap):
     return ms, its, ok
 
 
+def _tune_in_mix(st, torch, args):
+    """Coordinate descent of the classes' partitions on the time of one
+    batched solve of a whole tuning batch (see the module docstring)."""
+    from workloads.generate import BATCH_M, BATCH_N, batch_instances
+    probs = batch_instances(count=args.count, base_seed=args.seed)
+    cls = [(p.n[0], p.M) for p in probs]
+    ops = [st.KKTOperator(p) for p in probs]
+    work = {}
+    for p, c in zip(probs, cls):
+        work[c] = work.get(c, 0) + p.unknowns
+    order = sorted(work, key=lambda c: -work[c])
+    choice = {c: box_parts(c[0], c[1], 12) for c in order}
+    pres = [st.RAS(op, choice[c], 1, precision=st.F32) for op, c in zip(ops, cls)]
+
+    def run():
+        xs = [torch.zeros(op.n, dtype=torch.float64, device="cuda") for op in ops]
+        st.solve_batch(ops, pres, None, xs, restart=50, rtol=1e-6)   # engine and graphs
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, stats = st.solve_batch(ops, pres, None, xs, restart=50, rtol=1e-6)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, all(s.converged for s in stats), [s.iters for s in stats]
+
+    best, ok, its = run()
+    print(f"[tune] mix of {len(probs)}: start (boxes of ~12 nodes) {best:.1f} ms", flush=True)
+    for c in order:
+        idx = [i for i in range(len(probs)) if cls[i] == c]
+        for parts in mix_candidates(*c):
+            if parts == choice[c]:
+                continue
+            old = [pres[i] for i in idx]
+            for i in idx:
+                pres[i] = st.RAS(ops[i], parts, 1, precision=st.F32)
+            ms, ok, its_c = run()
+            keep = ok and ms < best * 0.995
+            print(f"[tune] {c[0]}x{c[1]} parts {parts}: batch {ms:.1f} ms{' (kept)' if keep else ''}", flush=True)
+            if keep:
+                best, choice[c], its = ms, parts, its_c
+                for q in old:
+                    q.close()
+            else:
+                for i, q in zip(idx, old):
+                    pres[i].close()
+                    pres[i] = q
+    classes = {}
+    for n in BATCH_N:
+        for M in BATCH_M:
+            c = (n, M)
+            mine = [its[i] for i in range(len(probs)) if cls[i] == c]
+            classes[f"{n}x{M}"] = {"parts": list(choice.get(c, box_parts(n, M, 12))), "overlap": 1,
+                                   "in_tuning_batch": len(mine),
+                                   "iters": round(sum(mine) / len(mine), 1) if mine else None}
+    for q in pres:
+        q.close()
+    for op in ops:
+        op.close()
+    return {"what": "partition per class chosen in the mix: coordinate descent on the batched FGMRES(50) solve "
+                    "time of a whole tuning batch (FP32 RAS(ILU(0)), rtol 1e-6); classes absent from it keep "
+                    "boxes of about 12 nodes",
+            "tuning_batch": {"count": args.count, "base_seed": args.seed, "batch_ms": round(best, 1)},
+            "device": torch.cuda.get_device_name(0), "classes": classes}
+
+
 def main(argv=None):
     import argparse
     import torch
@@ -85,7 +181,16 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--out", default=TABLE)
     ap.add_argument("--instances", type=int, default=4)
+    ap.add_argument("--in-mix", action="store_true", help="tune on one batched solve of a whole tuning batch")
+    ap.add_argument("--count", type=int, default=64, help="--in-mix: instances in the tuning batch")
+    ap.add_argument("--seed", type=int, default=5000, help="--in-mix: base seed of the tuning batch")
     args = ap.parse_args(argv)
+    if args.in_mix:
+        out = _tune_in_mix(st, torch, args)
+        with open(args.out, "w") as f:
+            json.dump(out, f, indent=1)
+        print(f"[tune] wrote {args.out}", flush=True)
+        return 0
     classes = {}
     for n in BATCH_N:
         for M in BATCH_M:
