@@ -1135,12 +1135,13 @@ static void launch_ring(const ras *R, const double *r, double *z, T *Y, size_t l
 }
 
 // Rows per phase of the ring kernel for this preconditioner: 256 when the ring
-// fits with them, else 64 (boxes with more rows per level, e.g. 14^4 nodes in
+// fits with them, else 128 (e.g. 13^4 boxes in FP64), else 64 (14^4 boxes in
 // FP64), else 0 (no ring: the kernel with the local vector in global memory).
 template <typename T>
 static int ring_rows(const ras *R) {
   if (R->ring_ltlz > kApplyThreads) return 0;
   if (ring_lds_bytes<T, 256>(R) <= kRingLdsLimit) return 256;
+  if (ring_lds_bytes<T, 128>(R) <= kRingLdsLimit) return 128;
   if (ring_lds_bytes<T, 64>(R) <= kRingLdsLimit) return 64;
   return 0;
 }
@@ -1150,6 +1151,8 @@ static void launch_apply(const ras *R, const double *r, double *z, T *Y, hipStre
   const int kr = ring_rows<T>(R);
   if (kr == 256) {
     launch_ring<T, 256>(R, r, z, Y, ring_lds_bytes<T, 256>(R), s);
+  } else if (kr == 128) {
+    launch_ring<T, 128>(R, r, z, Y, ring_lds_bytes<T, 128>(R), s);
   } else if (kr == 64) {
     launch_ring<T, 64>(R, r, z, Y, ring_lds_bytes<T, 64>(R), s);
   } else {
@@ -1211,7 +1214,9 @@ static void ras_batch_prepare_t(const ras *const *R, const long long *voff, void
     d[i].yzero = q->scratch_elems;
     d[i].voff = voff[i];
     d[i].rg = Ring{q->ring_rmax, q->ring_ltlz};
-    lds = std::max(lds, out.kr == 256 ? ring_lds_bytes<T, 256>(q) : ring_lds_bytes<T, 64>(q));
+    lds = std::max(lds, out.kr == 256   ? ring_lds_bytes<T, 256>(q)
+                        : out.kr == 128 ? ring_lds_bytes<T, 128>(q)
+                                        : ring_lds_bytes<T, 64>(q));
     for (int k = 0; k < q->nsub; ++k)
       items.push_back({q->shapes[q->subs[k].shape].nblocks, make_int2(i, k)});
   }
@@ -1227,9 +1232,9 @@ static void ras_batch_prepare_t(const ras *const *R, const long long *voff, void
   out.lds = lds;
 }
 
-// One launch covers every member whose LDS ring fits: with 256 rows per phase
-// when all of them allow it, else with 64 (the per-row sums, and so the
-// results, are the same).  Members without a ring (or with ILU(k) factors)
+// One launch covers every member whose LDS ring fits, with the largest rows
+// per phase (256, 128 or 64) that all of them allow (the per-row sums, and
+// so the results, are the same for every phase size).  Members without a ring (or with ILU(k) factors)
 // are launched on their own after it; members of different precisions make
 // every member its own launch.
 void ras_batch_prepare(const ras *const *R, const long long *voff, void *const *local, int count,
@@ -1253,7 +1258,7 @@ void ras_batch_prepare(const ras *const *R, const long long *voff, void *const *
   bool any = false;
   for (int i = 0; i < count; ++i) {
     if (!R[i]) continue;
-    const int rows = ras_apply_rows_per_phase(R[i]);   // 256, 64, or 0 (no ring, ILU(k))
+    const int rows = ras_apply_rows_per_phase(R[i]);   // 256, 128, 64, or 0 (no ring, ILU(k))
     if (rows == 0) {
       solo[i] = 1;
       out.solo.push_back(i);
@@ -1279,12 +1284,17 @@ static void ras_batch_launch(const RasBatch &b, const double *r, const double *r
   if (!attr_set) {
     STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_ring_batch_kernel<T, 256>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRingLdsLimit));
+    STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_ring_batch_kernel<T, 128>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRingLdsLimit));
     STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_ring_batch_kernel<T, 64>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRingLdsLimit));
     attr_set = true;
   }
   if (b.kr == 256)
     hipLaunchKernelGGL((apply_ring_batch_kernel<T, 256>), dim3(b.blocks), dim3(kApplyThreads), b.lds, s,
+                       b.desc.as<RasBatchDesc<T>>(), b.work.as<int2>(), act, r, r2 ? r2 : r, z);
+  else if (b.kr == 128)
+    hipLaunchKernelGGL((apply_ring_batch_kernel<T, 128>), dim3(b.blocks), dim3(kApplyThreads), b.lds, s,
                        b.desc.as<RasBatchDesc<T>>(), b.work.as<int2>(), act, r, r2 ? r2 : r, z);
   else
     hipLaunchKernelGGL((apply_ring_batch_kernel<T, 64>), dim3(b.blocks), dim3(kApplyThreads), b.lds, s,

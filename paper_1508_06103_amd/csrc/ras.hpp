@@ -84,7 +84,7 @@ struct RasBatch {
   DevBuf desc, work;
   int count = 0, blocks = 0, precision = STKKT_F64;
   bool ring = false;     // one launch over the (member, subdomain) work list of the ring members
-  int kr = 256;          // rows per phase of that launch (64 when a member's 256-row ring does not fit)
+  int kr = 256;          // rows per phase of that launch (the largest of 256, 128, 64 every member allows)
   std::vector<int> solo; // members launched on their own (no LDS ring, or ILU(k))
   size_t lds = 0;
   std::vector<const ras *> members;

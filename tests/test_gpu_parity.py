@@ -35,8 +35,10 @@ SMALL = [
     ("neumann_all", dict(n=(4, 4, 4), M=5, seed=5, lattice=2, faces=0)),
     # one long box: (t, z) groups per level exceed the LDS-ring limits of the apply kernel
     ("tall", dict(n=(2, 2, 40), M=24, seed=6, lattice=1)),
-    # two 13^4 boxes: with FP64 factors the LDS ring only fits with 64 rows per phase
+    # two 13^4 boxes: with FP64 factors the LDS ring only fits with 128 rows per phase
     ("ring64", dict(n=(12, 12, 12), M=25, seed=8, lattice=2)),
+    # one 14^4 box: with FP64 factors the LDS ring only fits with 64 rows per phase
+    ("ring14", dict(n=(13, 13, 13), M=13, seed=9, lattice=2)),
     # the H1-L2 regularisation of Example 2
     ("h1l2", dict(n=(4, 5, 3), M=6, seed=7, lattice=2, reg=H1L2)),
 ]
@@ -96,7 +98,7 @@ def test_rhs_and_matvec(st, name):
                                               ("neumann_all", (1, 2, 2, 1), 0), ("tall", (1, 1, 1, 1), 0),
                                               ("tall", (1, 1, 2, 2), 1), ("cube8x16", (2, 2, 2, 2), 4),
                                               ("ragged", (2, 3, 2, 3), 3), ("h1l2", (2, 2, 1, 2), 1),
-                                              ("ring64", (1, 1, 1, 2), 0)])
+                                              ("ring64", (1, 1, 1, 2), 0), ("ring14", (1, 1, 1, 1), 0)])
 def test_boxes_factors_and_apply(st, name, parts, delta):
     prob = small_problem(name)
     _say(f"case {name}: parts={parts} overlap={delta}")
@@ -281,10 +283,12 @@ def test_allocator_failure_is_enomem(st):
 
 def test_apply_kernel_choice(st):
     """The sweep kernel ras_apply picks: the 256-row LDS ring for 12^4 boxes,
-    the 64-row ring for 13^4 boxes in FP64 (the 256-row one does not fit the
-    LDS), the 256-row ring for the same boxes in FP32, and the global-memory
-    form for a box whose levels hold more (t, z) groups than the ring allows."""
-    cases = [("ring64", (1, 1, 1, 2), 0, "f64", 64), ("ring64", (1, 1, 1, 2), 0, "f32", 256),
+    the 128-row ring for 13^4 boxes and the 64-row ring for 14^4 boxes in FP64
+    (the larger ones do not fit the LDS), the 256-row ring for those boxes in
+    FP32, and the global-memory form for a box whose levels hold more (t, z)
+    groups than the ring allows."""
+    cases = [("ring64", (1, 1, 1, 2), 0, "f64", 128), ("ring64", (1, 1, 1, 2), 0, "f32", 256),
+             ("ring14", (1, 1, 1, 1), 0, "f64", 64), ("ring14", (1, 1, 1, 1), 0, "f32", 256),
              ("tall", (1, 1, 1, 1), 0, "f64", 0), ("cube8x16", (2, 2, 2, 2), 1, "f64", 256)]
     for name, parts, delta, prec, rows in cases:
         op = st.KKTOperator(small_problem(name))
