@@ -152,10 +152,11 @@ void stiff_table(const OpDev &d, double *tab, hipStream_t s) {
 //
 // One workgroup owns a TX x TY x TZ tile of spatial nodes over a chunk of
 // consecutive time levels and marches through them: every thread keeps the
-// raw (c, g, f) of up to KH halo nodes for levels n-1 and n in registers,
-// loads level n+1 once, writes the six combined fields of its halo nodes to
-// LDS, and after a barrier evaluates the 27-point sums of its own node from
-// LDS.  The spatial 1-D factors of B, K and N are rebuilt from the node's
+// raw (c, g, f) of up to KH halo nodes for three consecutive levels in
+// registers, loads each level once, writes the six combined fields of its
+// halo nodes to LDS, and evaluates the 27-point sums of its own node from
+// LDS.  The fields of level n + 1 go to a second buffer while level n's
+// sums read the first, so one barrier per level suffices.  The spatial 1-D factors of B, K and N are rebuilt from the node's
 // position (end-node rules); the variable-coefficient diffusion A comes from
 // the per-node table, read once per chunk into registers.
 // --------------------------------------------------------------------------
@@ -284,8 +285,8 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
       }
     }
   }
-  // halo values of levels n - 1, n, n + 1 (c, g, f), and level n + 2 in
-  // flight: the loads of a level are issued one level before it is used
+  // halo values (c, g, f) of three consecutive levels and a fourth in flight:
+  // the loads of a level are issued one level before its fields are formed
   double cm[KH], c0[KH], gm[KH], g0[KH], fm[KH], f0[KH], c1[KH], g1[KH], f1[KH], c2[KH], g2[KH], f2[KH];
 #pragma unroll
   for (int s = 0; s < KH; ++s) {
@@ -310,26 +311,17 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
     }
   }
 
-  for (int n = n0; n < n1; ++n) {
-    const bool hm = n >= 1, hp = n < M;
-    const bool tend = (n == 0) || (n == M);
-    // rows of the time stiffness St and mass Tt at level n
+  // Fields of level L from the held levels L - 1 (cm), L (c0) and L + 1 (c1)
+  // into buffer buf; then the held levels move on by one, level L + 2 (c2,
+  // requested one level earlier) taking the place of L + 1.
+  auto fields = [&](int L, double2 *buf) {
+    const bool hm = L >= 1, hp = L < M;
+    const bool tend = (L == 0) || (L == M);
+    // rows of the time stiffness St and mass Tt at level L
     const double stm = hm ? -mc.inv_tau : 0.0, st0 = tend ? mc.inv_tau : 2.0 * mc.inv_tau,
                  stp = hp ? -mc.inv_tau : 0.0;
     const double ttm = hm ? mc.tau6 : 0.0, tt0 = tend ? mc.tau3 : 2.0 * mc.tau3, ttp = hp ? mc.tau6 : 0.0;
     const bool mflag = !dto || hm;
-    // level n + 2, used by the next level (only while that level is in this chunk)
-    const bool pre = n + 2 <= M && n + 1 < n1;
-#pragma unroll
-    for (int s = 0; s < KH; ++s) {
-      c2[s] = g2[s] = f2[s] = 0.0;
-      if (hin[s] && pre) {
-        const double *p = x + 3LL * (n + 2) * N + hoff[s];
-        c2[s] = p[0];
-        g2[s] = p[1];
-        f2[s] = p[2];
-      }
-    }
 #pragma unroll
     for (int s = 0; s < KH; ++s) {
       const double cp = hp ? c1[s] : 0.0, gp = hp ? g1[s] : 0.0, fp = hp ? f1[s] : 0.0;
@@ -341,9 +333,9 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
         const double stf = stm * fm[s] + st0 * f0[s] + stp * fp;
         const double ttf = ttm * fm[s] + tt0 * f0[s] + ttp * fp;
         const double U3 = mc.beta1 * stf - (dto ? ht * S2 : P * (ttm * gm[s] + tt0 * g0[s] + ttp * gp));
-        mv_lds[3 * h] = make_double2(P * (c0[s] - cm[s]) - ht * (fm[s] + f0[s]), P * (c0[s] + cm[s]));
-        mv_lds[3 * h + 1] = make_double2(P * (gn - gp), S2);
-        mv_lds[3 * h + 2] = mc.l2 ? make_double2(U3 + mc.beta2 * ttf, 0.0) : make_double2(U3, mc.beta2 * ttf);
+        buf[3 * h] = make_double2(P * (c0[s] - cm[s]) - ht * (fm[s] + f0[s]), P * (c0[s] + cm[s]));
+        buf[3 * h + 1] = make_double2(P * (gn - gp), S2);
+        buf[3 * h + 2] = mc.l2 ? make_double2(U3 + mc.beta2 * ttf, 0.0) : make_double2(U3, mc.beta2 * ttf);
       }
       cm[s] = c0[s];
       c0[s] = cp;
@@ -355,7 +347,36 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
       f0[s] = fp;
       f1[s] = f2[s];
     }
-    __syncthreads();
+  };
+  // level L of the halo into c2 (zero unless wanted)
+  auto request = [&](int L, bool want) {
+#pragma unroll
+    for (int s = 0; s < KH; ++s) {
+      c2[s] = g2[s] = f2[s] = 0.0;
+      if (hin[s] && want) {
+        const double *p = x + 3LL * L * N + hoff[s];
+        c2[s] = p[0];
+        g2[s] = p[1];
+        f2[s] = p[2];
+      }
+    }
+  };
+  // Two field buffers: the fields of level n + 1 are written while the
+  // outputs of level n read those of level n, so one barrier per level
+  // separates the writes of a buffer from its reads.
+  double2 *const buf0 = mv_lds, *const buf1 = mv_lds + 3 * tl.halo;
+  request(n0 + 2, n0 + 2 <= M && n0 + 1 < n1);
+  fields(n0, buf0);
+  __syncthreads();
+  for (int n = n0; n < n1; ++n) {
+    const bool hp = n < M;
+    const bool tend = (n == 0) || (n == M);
+    const double2 *const cur = ((n - n0) & 1) ? buf1 : buf0;
+    if (n + 1 < n1) {
+      // level n + 3 feeds the fields of level n + 2 (formed only while that level is in this chunk)
+      request(n + 3, n + 3 <= M && n + 2 < n1);
+      fields(n + 1, ((n - n0) & 1) ? buf0 : buf1);
+    }
     // rebuild the node's stencil weights every level instead of keeping them live
     asm volatile("" : "+v"(cx.m), "+v"(cx.k), "+v"(cx.c), "+v"(cy.m), "+v"(cy.k), "+v"(cy.c));
     asm volatile("" : "+v"(cz.m), "+v"(cz.k), "+v"(cz.c));
@@ -404,7 +425,7 @@ __device__ inline void matvec_tile_body(const OpDev &op, const MvTile &tl, const
           else if (dy == 0 && dz != 0) ntyz = mc.v[1] * mc.h6[2] * cy.c - (0.5 * dz) * mc.v[2] * cy.m;
           else if (dy != 0 && dz == 0) ntyz = -(0.5 * dy) * mc.v[1] * cz.m + mc.v[2] * mc.h6[1] * cz.c;
           else ntyz = nyz;
-          const double2 *row = mv_lds + 3 * (hc + hx * (dy + hy * dz));
+          const double2 *row = cur + 3 * (hc + hx * (dy + hy * dz));
           const double2 w1 = row[-3], w2 = row[-2], w3 = row[-1];   // x - 1
           const double2 c1 = row[0], c2 = row[1], c3 = row[2];      // x
           const double2 e1 = row[3], e2 = row[4], e3 = row[5];      // x + 1
@@ -487,11 +508,13 @@ MvTile choose_matvec_tile(const OpDev &d) {
     for (int ty = 1; ty <= std::min(d.nn[1], cap / tx); ++ty)
       for (int tz = 1; tz <= std::min(d.nn[2], cap / (tx * ty)); ++tz) {
         const int halo = (tx + 2) * (ty + 2) * (tz + 2);
-        if (halo > 3 * kMvThreads) continue;
+        // at most three halo nodes per thread; two field buffers within 64 KB of LDS
+        if (halo > 3 * kMvThreads || sizeof(double2) * 6 * (size_t)halo > 65536) continue;
         const long long ntiles = (long long)((d.nn[0] + tx - 1) / tx) * ((d.nn[1] + ty - 1) / ty) *
                                  ((d.nn[2] + tz - 1) / tz);
         const double cost = (double)ntiles * (halo + kMvThreads);
-        if (cost < best_cost) {
+        // ties go to the widest x extent (longer contiguous rows of x and y)
+        if (cost <= best_cost) {
           best_cost = cost;
           best.t[0] = tx;
           best.t[1] = ty;
@@ -513,7 +536,7 @@ void matvec_device(const kkt_op *op, const double *x, double *y, hipStream_t s) 
   const MvTile &tl = op->mv;
   const long long grid = (long long)tl.ntiles * tl.nchunks;
   if (grid > INT32_MAX) throw Error(STKKT_EINVAL, "kkt_matvec: mesh too large");
-  const size_t lds = sizeof(double2) * 3 * (size_t)tl.halo;   // 48 B per halo node
+  const size_t lds = sizeof(double2) * 6 * (size_t)tl.halo;   // two buffers of 48 B per halo node
   const int kh = (tl.halo + kMvThreads - 1) / kMvThreads;
   const double *atab = op->atab.as<double>();
   const MvConst mc = make_mv_const(d);
@@ -551,7 +574,7 @@ void matvec_batch_prepare(const kkt_op *const *ops, const long long *voff, int c
   STKKT_HIP(hipStreamSynchronize(s));   // d is released on return
   out.count = count;
   out.items = w;
-  out.lds = sizeof(double2) * 3 * (size_t)halo;
+  out.lds = sizeof(double2) * 6 * (size_t)halo;
   out.kh = (halo + kMvThreads - 1) / kMvThreads;
 }
 

@@ -12,7 +12,13 @@ reads it; the batched and served benchmarks use it):
   per spatial axis and 8, 12 or 16 time levels (overlap 1) and keeps a
   candidate that shortens the whole batch by more than 0.5%.  In a full
   batch the GPU is busy anyway, so the partition that wins is the one with
-  the fewest, largest boxes that still converge fast.
+  the fewest, largest boxes that still converge fast.  One workgroup
+  applies a box, streaming its factors at about 20-28 GB/s, so a box with
+  more than a compute unit's share of a full batch's factor bytes outlasts
+  the rest of the launch: candidates whose largest box holds more FP32
+  factor bytes than ``--max-box-mb`` (150 MB: 38 GB of factors over 256
+  compute units) are not tried, and a class whose boxes of about 12 nodes
+  exceed it starts from its candidate with the fewest boxes under it.
 * per class (without ``--in-mix``): a few seeded instances of each class
   are timed alone as a batch under candidate partitions (owned boxes of
   about 6, 8, 12 or 16 nodes per spatial axis and 8 or 16 time levels,
@@ -57,6 +63,34 @@ def mix_candidates(n, M):
             if parts not in out:
                 out.append(parts)
     return out
+
+
+MAX_BOX_MB = 150.0
+
+
+def max_box_bytes(n, M, parts, overlap=1, elem=4):
+    """Factor bytes of the largest subdomain box of a partition: on every axis
+    the longest range of a part (the even split, the first parts one node
+    longer) grown by the overlap and clipped to the mesh; RAS(ILU(0)) stores
+    a 3 x 3 block for every pair of box nodes at most one apart on every axis."""
+    size = 9 * elem
+    for L, p in zip((n + 1, n + 1, n + 1, M + 1), parts):
+        q, r = divmod(L, p)
+        cuts = [k * q + min(k, r) for k in range(p + 1)]
+        ext = max(min(L, cuts[k + 1] + overlap) - max(0, cuts[k] - overlap) for k in range(p))
+        size *= 3 * ext - 2
+    return size
+
+
+def mix_start(n, M, cap_mb=MAX_BOX_MB):
+    """Starting partition of a class in the mix: boxes of about 12 nodes, or,
+    if their largest box exceeds the cap, the candidate under it with the
+    fewest boxes."""
+    start = box_parts(n, M, 12)
+    if max_box_bytes(n, M, start) <= cap_mb * 1e6:
+        return start
+    under = [p for p in mix_candidates(n, M) if max_box_bytes(n, M, p) <= cap_mb * 1e6]
+    return min(under, key=lambda p: (p[0] * p[1] * p[2] * p[3], p)) if under else start
 
 
 def candidates(n, M):
@@ -118,7 +152,8 @@ def _tune_in_mix(st, torch, args):
     for p, c in zip(probs, cls):
         work[c] = work.get(c, 0) + p.unknowns
     order = sorted(work, key=lambda c: -work[c])
-    choice = {c: box_parts(c[0], c[1], 12) for c in order}
+    cap = args.max_box_mb * 1e6
+    choice = {c: mix_start(c[0], c[1], args.max_box_mb) for c in order}
     pres = [st.RAS(op, choice[c], 1, precision=st.F32) for op, c in zip(ops, cls)]
 
     def run():
@@ -137,7 +172,7 @@ def _tune_in_mix(st, torch, args):
     for c in order:
         idx = [i for i in range(len(probs)) if cls[i] == c]
         for parts in mix_candidates(*c):
-            if parts == choice[c]:
+            if parts == choice[c] or max_box_bytes(c[0], c[1], parts) > cap:
                 continue
             old = [pres[i] for i in idx]
             for i in idx:
@@ -158,7 +193,7 @@ def _tune_in_mix(st, torch, args):
         for M in BATCH_M:
             c = (n, M)
             mine = [its[i] for i in range(len(probs)) if cls[i] == c]
-            classes[f"{n}x{M}"] = {"parts": list(choice.get(c, box_parts(n, M, 12))), "overlap": 1,
+            classes[f"{n}x{M}"] = {"parts": list(choice.get(c, mix_start(n, M, args.max_box_mb))), "overlap": 1,
                                    "in_tuning_batch": len(mine),
                                    "iters": round(sum(mine) / len(mine), 1) if mine else None}
     for q in pres:
@@ -166,9 +201,10 @@ def _tune_in_mix(st, torch, args):
     for op in ops:
         op.close()
     return {"what": "partition per class chosen in the mix: coordinate descent on the batched FGMRES(50) solve "
-                    "time of a whole tuning batch (FP32 RAS(ILU(0)), rtol 1e-6); classes absent from it keep "
-                    "boxes of about 12 nodes",
+                    "time of a whole tuning batch (FP32 RAS(ILU(0)), rtol 1e-6), no box above max_box_mb of "
+                    "FP32 factors; classes absent from it keep their starting partition",
             "tuning_batch": {"count": args.count, "base_seed": args.seed, "batch_ms": round(best, 1)},
+            "max_box_mb": args.max_box_mb,
             "device": torch.cuda.get_device_name(0), "classes": classes}
 
 
@@ -184,6 +220,8 @@ def main(argv=None):
     ap.add_argument("--in-mix", action="store_true", help="tune on one batched solve of a whole tuning batch")
     ap.add_argument("--count", type=int, default=64, help="--in-mix: instances in the tuning batch")
     ap.add_argument("--seed", type=int, default=5000, help="--in-mix: base seed of the tuning batch")
+    ap.add_argument("--max-box-mb", type=float, default=MAX_BOX_MB,
+                    help="--in-mix: largest box's FP32 factor bytes (MB) a candidate may have")
     args = ap.parse_args(argv)
     if args.in_mix:
         out = _tune_in_mix(st, torch, args)

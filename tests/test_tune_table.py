@@ -18,6 +18,9 @@ def test_table_covers_every_class_with_valid_partitions():
             if "tuning_batch" in tune._load():
                 assert d == 1
                 assert tuple(parts) in tune.mix_candidates(n, M) or tuple(parts) == tune.box_parts(n, M, 12)
+                cap = tune._load().get("max_box_mb")
+                if cap is not None:
+                    assert tune.max_box_bytes(n, M, tuple(parts)) <= cap * 1e6
             else:
                 assert (tuple(parts), d) in tune.candidates(n, M)
 
@@ -28,3 +31,24 @@ def test_parts_for_reads_the_class(n, M):
     parts, d = tune.parts_for(prob)
     rec = tune._load()["classes"][f"{n}x{M}"]
     assert list(parts) == rec["parts"] and d == rec["overlap"]
+
+
+@pytest.mark.parametrize("n,M", [(8, 24), (12, 32), (16, 16), (16, 48), (20, 16), (24, 48)])
+def test_max_box_bytes_matches_the_partition(n, M):
+    """The tuner's largest-box size equals the largest FP32 factor size over
+    the boxes the partition really has (3 x 3 blocks of 4-byte values for
+    every pair of box nodes at most one apart on every axis)."""
+    from oracle.ras import subdomains
+
+    class Mesh:
+        nodes = (n + 1, n + 1, n + 1)
+
+    Mesh.M = M
+    for parts in tune.mix_candidates(n, M) + [tune.box_parts(n, M, 12)]:
+        sizes = []
+        for sd in subdomains(Mesh, parts, 1):
+            b = 36
+            for ext in sd.dims:
+                b *= 3 * ext - 2
+            sizes.append(b)
+        assert tune.max_box_bytes(n, M, parts) == max(sizes)
