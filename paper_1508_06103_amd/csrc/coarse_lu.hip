@@ -459,6 +459,8 @@ __global__ void gje_copy_rows_kernel(int n, int k, int e, const double *__restri
 // Trailing update outside the panel columns, a rank-(e - k) product:
 //   rows outside the panel:  A[i][col] += sum_t A[i][k+t] R[t][col]
 //   panel rows:              A[i][col]  = sum_t A[i][k+t] R[t][col]
+// for the columns in [cb, ce) outside [xb, xe) (the tiles of column blocks
+// ct0, ct0 + 1, ...), so that the next panel's columns can be updated first.
 // on the FP64 matrix cores (v_mfma_f64_16x16x4: lane l supplies a = A[l%16][l/16]
 // and b = B[l/16][l%16] and holds D[l/16 + 4r][l%16], r = 0..3).  A workgroup
 // of 8 wavefronts owns a 128 x 128 output tile; wavefront (wr, wc) a 64 x 32
@@ -475,12 +477,17 @@ constexpr int kUpdK = 32;
 constexpr size_t kUpdLds = sizeof(double) * ((size_t)kUpdTile * (kUpdK + 1) + (size_t)kUpdK * kUpdTile);
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(kUpdThreads, 4) gje_update_kernel(int n, int k, int e, double *__restrict__ A,
+__global__ void __launch_bounds__(kUpdThreads, 4) gje_update_kernel(int n, int k, int e, int cb, int ce, int xb,
+                                                                    int xe, int ct0, double *__restrict__ A,
                                                                     const double *__restrict__ R) {
   extern __shared__ double upd_lds[];
   double(*As)[kUpdK + 1] = reinterpret_cast<double(*)[kUpdK + 1]>(upd_lds);              // [row][t]
   double(*Rs)[kUpdTile] = reinterpret_cast<double(*)[kUpdTile]>(upd_lds + kUpdTile * (kUpdK + 1));   // [t][col]
-  const int row0 = blockIdx.y * kUpdTile, col0 = blockIdx.x * kUpdTile;
+  const int row0 = blockIdx.y * kUpdTile, col0 = (ct0 + blockIdx.x) * kUpdTile;
+  // columns this launch updates
+  auto mine = [&](int col) {
+    return col >= cb && col < ce && col < n && !(col >= k && col < e) && !(col >= xb && col < xe);
+  };
   const int w = e - k;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -495,7 +502,7 @@ __global__ void __launch_bounds__(kUpdThreads, 4) gje_update_kernel(int n, int k
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = row0 + wr * 64 + bi * 16 + lk + 4 * r;
-        const bool acc_row = i < n && !(i >= k && i < e) && col < n && !(col >= k && col < e);
+        const bool acc_row = i < n && !(i >= k && i < e) && mine(col);
         acc[bi][bj][r] = acc_row ? A[(long long)i * n + col] : 0.0;
       }
     }
@@ -529,7 +536,7 @@ __global__ void __launch_bounds__(kUpdThreads, 4) gje_update_kernel(int n, int k
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
       const int col = col0 + wc * 32 + bj * 16 + li;
-      if (col >= n || (col >= k && col < e)) continue;
+      if (!mine(col)) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = row0 + wr * 64 + bi * 16 + lk + 4 * r;
@@ -764,11 +771,40 @@ static int panel_rows(int n) {
   return 0;
 }
 
+// Second stream and events of the panel look-ahead (default priority).
+struct LookAhead {
+  hipStream_t side = nullptr;
+  hipEvent_t rows_ready = nullptr, rest_done = nullptr;
+  LookAhead() {
+    try {
+      STKKT_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+      STKKT_HIP(hipEventCreateWithFlags(&rows_ready, hipEventDisableTiming));
+      STKKT_HIP(hipEventCreateWithFlags(&rest_done, hipEventDisableTiming));
+    } catch (...) {
+      release();
+      throw;
+    }
+  }
+  ~LookAhead() { release(); }
+  void release() {
+    if (side) (void)hipStreamSynchronize(side);
+    if (rest_done) (void)hipEventDestroy(rest_done);
+    if (rows_ready) (void)hipEventDestroy(rows_ready);
+    if (side) (void)hipStreamDestroy(side);
+    side = nullptr;
+    rows_ready = rest_done = nullptr;
+  }
+  LookAhead(const LookAhead &) = delete;
+  LookAhead &operator=(const LookAhead &) = delete;
+};
+
 // Explicit inverse of the n x n row-major matrix in A (overwritten with the
-// inverse).  tmp: n x n scratch; rows: kPanel x n scratch; piv: n int32;
-// gs: candidate tables for ceil(n / 64) workgroups.
+// inverse).  tmp: n x n scratch; rows: 2 x kPanel x n scratch (the rows of
+// two consecutive panels); piv: n int32; gs: candidate tables for
+// ceil(n / 64) workgroups; la: the look-ahead's side stream and events.
 static void gje_invert(int n, double *A, double *tmp, double *rows, double *pan, double *fcol, int32_t *piv,
-                       int32_t *swp, double *prow, const GjSync &gs, int *status, hipStream_t s) {
+                       int32_t *swp, double *prow, const GjSync &gs, int *status, const LookAhead &la,
+                       hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
     STKKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&gje_update_kernel),
@@ -779,9 +815,25 @@ static void gje_invert(int n, double *A, double *tmp, double *rows, double *pan,
   hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(n, 256, 64)), dim3(256), 0, s, n, piv);
   if (R > 0) hipLaunchKernelGGL(gj_reset_kernel, dim3(1), dim3(64), 0, s, gs);
   const int nt = (n + kUpdTile - 1) / kUpdTile;
-  for (int k = 0; k < n; k += kPanel) {
-    const int e = std::min(n, k + kPanel);
-    if (R > 0) {
+  // rank-(e - k) update of the columns [cb, ce) outside [xb, xe) on stream st
+  auto update = [&](int k, int e, int cb, int ce, int xb, int xe, const double *Rk, hipStream_t st) {
+    const int t0 = cb / kUpdTile, t1 = (ce + kUpdTile - 1) / kUpdTile;
+    hipLaunchKernelGGL(gje_update_kernel, dim3(t1 - t0, nt), dim3(kUpdThreads), kUpdLds, st, n, k, e, cb, ce, xb, xe,
+                       t0, A, Rk);
+  };
+  // the panel's swaps on the other columns, then its rows into Rk
+  auto close_panel = [&](int k, int e, double *Rk) {
+    hipLaunchKernelGGL(gje_laswp_kernel, dim3(blocks_for(n, 256, 64)), dim3(256), 0, s, n, k, e, A, swp, status);
+    hipLaunchKernelGGL(gje_copy_rows_kernel, dim3(blocks_for(n, 256, 64), e - k), dim3(256), 0, s, n, k, e, A, Rk);
+  };
+  if (R > 0) {
+    // Cooperative elimination of each panel with a look-ahead: the update by
+    // panel p first brings the next panel's columns up to date, then the
+    // next panel is eliminated on s while the rest of the update runs on the
+    // side stream.  The two touch different columns, and the next panel's
+    // swaps on the other columns wait for the rest of the update.  Every
+    // entry gets the same updates as without the look-ahead, bit for bit.
+    auto eliminate = [&](int k, int e) {
       int n_ = n, k_ = k, e_ = e, R_ = R;
       GjSync gs_ = gs;
       unsigned bar0 = (unsigned)k;
@@ -789,7 +841,29 @@ static void gje_invert(int n, double *A, double *tmp, double *rows, double *pan,
       STKKT_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&gje_panel_kernel),
                                            dim3((n + R - 1) / R), dim3(kGjThreads), args,
                                            (unsigned)(sizeof(double) * (size_t)kPanel * (R + 1)), s));
-    } else {
+    };
+    eliminate(0, std::min(n, kPanel));
+    close_panel(0, std::min(n, kPanel), rows);
+    for (int k = 0, p = 0; k < n; k += kPanel, ++p) {
+      const int e = std::min(n, k + kPanel);
+      double *Rk = rows + (size_t)(p & 1) * kPanel * n;
+      if (e >= n) {
+        update(k, e, 0, n, 0, 0, Rk, s);
+        break;
+      }
+      const int e2 = std::min(n, e + kPanel);
+      STKKT_HIP(hipEventRecord(la.rows_ready, s));
+      update(k, e, e, e2, 0, 0, Rk, s);
+      STKKT_HIP(hipStreamWaitEvent(la.side, la.rows_ready, 0));
+      update(k, e, 0, n, e, e2, Rk, la.side);
+      STKKT_HIP(hipEventRecord(la.rest_done, la.side));
+      eliminate(e, e2);
+      STKKT_HIP(hipStreamWaitEvent(s, la.rest_done, 0));
+      close_panel(e, e2, rows + (size_t)((p + 1) & 1) * kPanel * n);
+    }
+  } else {
+    for (int k = 0; k < n; k += kPanel) {
+      const int e = std::min(n, k + kPanel);
       const int nrb = (n + 63) / 64;
       hipLaunchKernelGGL(gje_panel_gather_kernel, dim3(nrb), dim3(256), 0, s, n, k, e - k, A, pan);
       for (int c = k; c < e; ++c) {
@@ -799,11 +873,9 @@ static void gje_invert(int n, double *A, double *tmp, double *rows, double *pan,
                            fcol, status);
       }
       hipLaunchKernelGGL(gje_panel_scatter_kernel, dim3(nrb), dim3(256), 0, s, n, k, e - k, pan, A);
+      close_panel(k, e, rows);
+      update(k, e, 0, n, 0, 0, rows, s);
     }
-    hipLaunchKernelGGL(gje_laswp_kernel, dim3(blocks_for(n, 256, 64)), dim3(256), 0, s, n, k, e, A, swp, status);
-    hipLaunchKernelGGL(gje_copy_rows_kernel, dim3(blocks_for(n, 256, 64), e - k), dim3(256), 0, s, n, k, e, A,
-                       rows);
-    hipLaunchKernelGGL(gje_update_kernel, dim3(nt, nt), dim3(kUpdThreads), kUpdLds, s, n, k, e, A, rows);
   }
   hipLaunchKernelGGL(gje_unpermute_kernel, dim3(blocks_for(n, 256, 64), n), dim3(256), 0, s, n, A, piv, tmp);
   STKKT_HIP(hipGetLastError());
@@ -834,7 +906,7 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
   mt_ = DevBuf(al, sizeof(double) * (size_t)3 * kMrRhs * nb_);   // tT, xT[0], xT[1]
   // setup work buffers (FP64)
   DevBuf S(al, sizeof(double) * nn), Ed(al, sizeof(double) * nn),
-      tmp(al, sizeof(double) * nn), rows(al, sizeof(double) * (size_t)kPanel * nb_), piv(al, sizeof(int32_t) * nb_),
+      tmp(al, sizeof(double) * nn), rows(al, sizeof(double) * 2 * (size_t)kPanel * nb_), piv(al, sizeof(int32_t) * nb_),
       prow(al, sizeof(double) * kPanel), swp(al, sizeof(int32_t) * kPanel), pan(al, sizeof(double) * kPanel * nb_),
       fcol(al, sizeof(double) * nb_),
       status(al, 256), ridx(al, sizeof(int32_t) * (size_t)nb_ * 81), rval(al, sizeof(double) * (size_t)nb_ * 81),
@@ -854,6 +926,7 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
   std::vector<double> hval((size_t)nb_ * 81), hcval;
   const int G = blocks_for(d.N, 128, 1024);
   const dim3 g2(blocks_for(nb_, 256, 64), nb_);
+  const LookAhead la;
   for (int k = 0; k < nlev_; ++k) {
     // lower coupling of level k (to level k-1), kept for the application
     int32_t *Lk_idx = Lidx_.as<int32_t>() + (size_t)k * nb_ * 81;
@@ -871,7 +944,7 @@ CoarseLU::CoarseLU(const Allocator *al, const kkt_op *cop, int precision, hipStr
     STKKT_HIP(hipGetLastError());
     // S_k^{-1} (column-major S is the row-major transpose: invert it as is)
     gje_invert(nb_, S.as<double>(), tmp.as<double>(), rows.as<double>(), pan.as<double>(), fcol.as<double>(),
-               piv.as<int32_t>(), swp.as<int32_t>(), prow.as<double>(), gs, status.as<int>(), s);
+               piv.as<int32_t>(), swp.as<int32_t>(), prow.as<double>(), gs, status.as<int>(), la, s);
     // E_k = S_k^{-1} U_k
     if (k + 1 < nlev_) {
       hipLaunchKernelGGL(coupling_rows_kernel, dim3(G), dim3(128), 0, s, d, k, +1, ridx.as<int32_t>(),
