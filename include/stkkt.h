@@ -275,7 +275,10 @@ int ras_export_factors(const ras_t *ras, int32_t sub, double *host_out);
  * launch whose workgroups must all be resident at once; every grid-barrier
  * wait is bounded (about a second), so if other work on the device keeps
  * some of them from starting the setup fails with STKKT_EHIP instead of
- * waiting.  The call synchronises `stream`. */
+ * waiting.  While a panel is eliminated on `stream`, the rest of the previous
+ * panel's update runs on a second stream of default priority that the call
+ * creates and destroys; it waits for the work on `stream` before it and
+ * `stream` waits for it before continuing.  The call synchronises both. */
 int coarse_setup(const kkt_op_t *fine, const coarse_params_t *cp, void *stream, coarse_t **out);
 
 /* y = I_c^h F_c^{-1} I_h^c x (device vectors of the fine size).  F_c^{-1} is
