@@ -432,6 +432,142 @@ __global__ void __launch_bounds__(kGjThreads) gje_panel_kernel(int n, int k, int
   }
 }
 
+// Panel elimination with the pivots searched among the panel's own rows
+// (block pivoting).  The Schur blocks of the coarse solve need no row
+// exchanges across panels: with the pivots restricted to each 64-row
+// diagonal block the inverse agrees with partial pivoting over all rows to
+// about 1e-14 (and with LAPACK's inverse), so a panel needs no device-wide
+// exchange per column.
+//
+// Step 1, one workgroup of four wavefronts (lane l on column l, wavefront v
+// on rows 16 v ..): Gauss-Jordan inversion of the diagonal block D = A[K][K]
+// (K = [k, e), w = e - k <= 64) in LDS.  Each step reads the rows'
+// multipliers into registers first, so the row updates are independent and
+// their LDS accesses pipeline.  Step j takes the largest
+// |entry| of column j over the block rows j.. (smallest row on ties), swaps
+// the two rows, records the pivot row in swp[j] (global index) and swaps the
+// two entries of piv, then eliminates column j from the other rows with the
+// in-place steps of gje_panel_kernel.  A[K][K] and Dinv (w x w, row stride
+// kPanel) receive (P D)^{-1}; a zero or non-finite pivot sets status 1.
+constexpr int kDiagThreads = 256;   // four wavefronts, 16 rows of the block each
+__global__ void __launch_bounds__(kDiagThreads) gje_diag_kernel(int n, int k, int e, double *__restrict__ A,
+                                                                double *__restrict__ Dinv,
+                                                                int32_t *__restrict__ piv,
+                                                                int32_t *__restrict__ swp,
+                                                                int *__restrict__ status) {
+  __shared__ double M[kPanel][kPanel + 1];
+  __shared__ int32_t pv[kPanel], sw[kPanel];   // piv[k..e) and the pivot rows, kept in LDS
+  __shared__ double pval;
+  __shared__ int prow_i;
+  if (*status) return;
+  const int w = e - k, tid = (int)threadIdx.x, l = tid & 63, wv = tid >> 6;   // lane l: column l
+  for (int r = wv; r < w; r += kDiagThreads / 64) M[r][l] = l < w ? A[(long long)(k + r) * n + k + l] : 0.0;
+  if (tid < w) pv[tid] = piv[k + tid];
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    // pivot (wavefront 0; lane l looks at row l of column j)
+    if (wv == 0) {
+      double v = (l >= j && l < w) ? fabs(M[l][j]) : -1.0;
+      int i = l;
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int oi = __shfl_xor(i, off, 64);
+        if (ov > v || (ov == v && oi < i)) {
+          v = ov;
+          i = oi;
+        }
+      }
+      if (l == 0) {
+        pval = v;
+        prow_i = i;
+      }
+    }
+    __syncthreads();
+    const int p = prow_i;
+    if (!(pval > 0.0) || !std::isfinite(pval)) {
+      if (tid == 0) *status = 1;
+      return;
+    }
+    // the swap; the pivot bookkeeping stays in LDS (a global access would
+    // make every step's barrier wait for a memory round trip)
+    if (wv == 0) {
+      if (p != j && l < w) {
+        const double t = M[j][l];
+        M[j][l] = M[p][l];
+        M[p][l] = t;
+      }
+      if (l == 0) {
+        sw[j] = p;
+        if (p != j) {
+          const int32_t t = pv[j];
+          pv[j] = pv[p];
+          pv[p] = t;
+        }
+      }
+    }
+    __syncthreads();
+    // the scaled pivot row (lane l: entry l) and the multipliers of this
+    // wavefront's rows, read before any row changes; then its rows
+    const double a = M[j][j];
+    const double pr = l < w ? (l == j ? 1.0 : M[j][l]) / a : 0.0;
+    const double pj = 1.0 / a;
+    double f[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) f[q] = M[16 * wv + q][j];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = 16 * wv + q;
+      if (r < w && l < w) M[r][l] = (r == j) ? pr : ((l == j) ? -f[q] * pj : M[r][l] - f[q] * pr);
+    }
+    __syncthreads();
+  }
+  for (int r = wv; r < w; r += kDiagThreads / 64)
+    if (l < w) {
+      A[(long long)(k + r) * n + k + l] = M[r][l];
+      Dinv[r * kPanel + l] = M[r][l];
+    }
+  if (tid < w) {
+    piv[k + tid] = pv[tid];
+    swp[tid] = k + sw[tid];
+  }
+}
+
+// Step 2: the panel columns of the rows outside the block,
+// A[i][K] <- -A[i][K] Dinv (the rows of K already hold Dinv).  64 rows per
+// workgroup of 256 threads with their panel segments (transposed) and Dinv in
+// LDS; thread (row r, column group g) forms 16 of the row's w outputs.
+__global__ void __launch_bounds__(256) gje_pmul_kernel(int n, int k, int e, double *__restrict__ A,
+                                                       const double *__restrict__ Dinv,
+                                                       const int *__restrict__ status) {
+  __shared__ double Ds[kPanel][kPanel], St[kPanel][kPanel];   // Dinv[t][c]; segment St[t][row]
+  if (*status) return;
+  const int w = e - k, tid = (int)threadIdx.x, r0 = (int)blockIdx.x * 64;
+  for (int q = tid; q < 64 * kPanel; q += 256) {
+    const int a = q / kPanel, b = q % kPanel;
+    Ds[a][b] = (a < w && b < w) ? Dinv[a * kPanel + b] : 0.0;
+    const int i = r0 + a;
+    St[b][a] = (i < n && b < w) ? A[(long long)i * n + k + b] : 0.0;
+  }
+  __syncthreads();
+  const int r = tid & 63, g = tid >> 6;
+  const int i = r0 + r;
+  if (i >= n || (i >= k && i < e)) return;
+  double acc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+  for (int t = 0; t < w; ++t) {
+    const double sv = St[t][r];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] += sv * Ds[t][g * 16 + c];
+  }
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int col = g * 16 + c;
+    if (col < w) A[(long long)i * n + k + col] = -acc[c];
+  }
+}
+
 // The panel's row swaps, in order, on the columns outside the panel (one
 // thread per column).  Skipped after a failed pivot (swp is then incomplete).
 __global__ void gje_laswp_kernel(int n, int k, int e, double *__restrict__ A, const int32_t *__restrict__ swp,
@@ -748,6 +884,15 @@ __global__ void gemm_reduce_kernel(int nb, int ld, int q, int nchunk, const doub
 
 }  // namespace
 
+// Pivots among each panel's rows (the default) unless STKKT_COARSE_PIVOT is
+// "global" or STKKT_COARSE_PANEL_ROWS selects one of the global-pivoting
+// elimination paths below.
+static bool block_pivoting() {
+  if (std::getenv("STKKT_COARSE_PANEL_ROWS")) return false;
+  const char *e = std::getenv("STKKT_COARSE_PIVOT");
+  return !(e && e[0] == 'g');
+}
+
 // Rows per workgroup of the cooperative panel elimination (64, 128 or 256;
 // STKKT_COARSE_PANEL_ROWS overrides, 0 selects the launch-per-column path),
 // or 0 if its workgroups cannot all be resident at once.
@@ -800,7 +945,9 @@ struct LookAhead {
 
 // Explicit inverse of the n x n row-major matrix in A (overwritten with the
 // inverse).  tmp: n x n scratch; rows: 2 x kPanel x n scratch (the rows of
-// two consecutive panels); piv: n int32; gs: candidate tables for
+// two consecutive panels); pan: kPanel x n scratch (the launch-per-column
+// path's panel; with block pivoting its first kPanel x kPanel doubles hold the
+// diagonal block's inverse); piv: n int32; gs: candidate tables for
 // ceil(n / 64) workgroups; la: the look-ahead's side stream and events.
 static void gje_invert(int n, double *A, double *tmp, double *rows, double *pan, double *fcol, int32_t *piv,
                        int32_t *swp, double *prow, const GjSync &gs, int *status, const LookAhead &la,
@@ -811,7 +958,8 @@ static void gje_invert(int n, double *A, double *tmp, double *rows, double *pan,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kUpdLds));
     attr_set = true;
   }
-  const int R = panel_rows(n);
+  const bool block = block_pivoting();
+  const int R = block ? 0 : panel_rows(n);
   hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(n, 256, 64)), dim3(256), 0, s, n, piv);
   if (R > 0) hipLaunchKernelGGL(gj_reset_kernel, dim3(1), dim3(64), 0, s, gs);
   const int nt = (n + kUpdTile - 1) / kUpdTile;
@@ -826,14 +974,27 @@ static void gje_invert(int n, double *A, double *tmp, double *rows, double *pan,
     hipLaunchKernelGGL(gje_laswp_kernel, dim3(blocks_for(n, 256, 64)), dim3(256), 0, s, n, k, e, A, swp, status);
     hipLaunchKernelGGL(gje_copy_rows_kernel, dim3(blocks_for(n, 256, 64), e - k), dim3(256), 0, s, n, k, e, A, Rk);
   };
-  if (R > 0) {
-    // Cooperative elimination of each panel with a look-ahead: the update by
+  if (block || R > 0) {
+    // Elimination of each panel (block pivoting: the diagonal block's inverse
+    // and the other rows' multipliers; global pivoting: one cooperative
+    // launch) with a look-ahead: the update by
     // panel p first brings the next panel's columns up to date, then the
     // next panel is eliminated on s while the rest of the update runs on the
     // side stream.  The two touch different columns, and the next panel's
     // swaps on the other columns wait for the rest of the update.  Every
     // entry gets the same updates as without the look-ahead, bit for bit.
+    auto diag = [&](int k, int e) {
+      hipLaunchKernelGGL(gje_diag_kernel, dim3(1), dim3(kDiagThreads), 0, s, n, k, e, A, pan, piv, swp, status);
+    };
+    auto pmul = [&](int k, int e) {
+      hipLaunchKernelGGL(gje_pmul_kernel, dim3((n + 63) / 64), dim3(256), 0, s, n, k, e, A, pan, status);
+    };
     auto eliminate = [&](int k, int e) {
+      if (block) {
+        diag(k, e);
+        pmul(k, e);
+        return;
+      }
       int n_ = n, k_ = k, e_ = e, R_ = R;
       GjSync gs_ = gs;
       unsigned bar0 = (unsigned)k;

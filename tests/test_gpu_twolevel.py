@@ -285,11 +285,13 @@ def test_coarse_lu_multi_rhs_injection(st):
 
 @pytest.mark.parametrize("name", ["aniso", "mid"])
 def test_coarse_lu_panel_paths(st, name, monkeypatch):
-    """The Gauss-Jordan inversion of the Schur blocks, with the panel
-    eliminated by one cooperative launch (64, 128 or 256 rows per workgroup)
-    or by two launches per column: all give the same coarse correction, and
-    it matches the oracle's block LU.  The mid case (2187 rows per block)
-    spans 35 panels and 9 to 35 workgroups with ragged tails."""
+    """The Gauss-Jordan inversion of the Schur blocks with partial pivoting
+    over all rows, the panel eliminated by one cooperative launch (64, 128 or
+    256 rows per workgroup) or by two launches per column: all give the same
+    coarse correction, and it matches the oracle's block LU.  The default,
+    pivots searched among each panel's own rows, matches both.  The mid case
+    (2187 rows per block) spans 35 panels and 9 to 35 workgroups with ragged
+    tails."""
     prob, fac = _mid_case() if name == "mid" else case(name)[:2]
     op = st.KKTOperator(prob)
     x = np.random.default_rng(77).standard_normal(prob.unknowns)
@@ -302,6 +304,10 @@ def test_coarse_lu_panel_paths(st, name, monkeypatch):
         ys[rows] = C.apply(xd).cpu().numpy()
         del C
     monkeypatch.delenv("STKKT_COARSE_PANEL_ROWS")
+    _say(f"case {name}: coarse LU, pivots within each panel (default)")
+    C = st.Coarse(op, fac, method=st.COARSE_LU)
+    ys["block"] = C.apply(xd).cpu().numpy()
+    del C
     y_ref = twolevel.TwoLevel(prob, None, None, fac, coarse="lu").coarse_correction(x)
     err = _rel(ys["128"], y_ref)
     _say(f"  rel err vs oracle {err:.2e}")
@@ -310,6 +316,9 @@ def test_coarse_lu_panel_paths(st, name, monkeypatch):
         d = _rel(ys[rows], ys["128"])
         _say(f"  panel rows {rows} vs 128: rel diff {d:.2e}")
         assert d <= 1e-12
+    err_b, d_b = _rel(ys["block"], y_ref), _rel(ys["block"], ys["128"])
+    _say(f"  pivots within panels: rel err vs oracle {err_b:.2e}, vs global pivoting {d_b:.2e}")
+    assert err_b <= 1e-9 and d_b <= 1e-11
 
 
 def test_coarse_lu_panel_barrier_timeout_is_reported(st, monkeypatch):
