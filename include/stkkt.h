@@ -270,15 +270,19 @@ int ras_export_factors(const ras_t *ras, int32_t sub, double *host_out);
  * factors) and the inner GMRES workspace, or, with STKKT_COARSE_LU, the
  * explicit inverses S_k^{-1} and E_k of the block elimination in time.  Fails
  * with STKKT_EINVAL when a factor does not divide the mesh or a sensor is not
- * on a coarse node, STKKT_EBREAKDOWN for a singular Schur block.  The
- * STKKT_COARSE_LU setup eliminates each 64-column panel in one cooperative
- * launch whose workgroups must all be resident at once; every grid-barrier
- * wait is bounded (about a second), so if other work on the device keeps
- * some of them from starting the setup fails with STKKT_EHIP instead of
- * waiting.  While a panel is eliminated on `stream`, the rest of the previous
- * panel's update runs on a second stream of default priority that the call
- * creates and destroys; it waits for the work on `stream` before it and
- * `stream` waits for it before continuing.  The call synchronises both. */
+ * on a coarse node, STKKT_EBREAKDOWN for a singular Schur block (a zero or
+ * non-finite pivot).  The Schur blocks are inverted by Gauss-Jordan
+ * elimination in 64-column panels with the pivots searched among each
+ * panel's own rows (partial pivoting inside the diagonal block); the
+ * environment variable STKKT_COARSE_PIVOT=global selects partial pivoting
+ * over all rows, each panel then eliminated in one cooperative launch whose
+ * workgroups must all be resident at once: every grid-barrier wait there is
+ * bounded (about a second), so if other work on the device keeps some of
+ * them from starting the setup fails with STKKT_EHIP instead of waiting.
+ * While a panel is eliminated on `stream`, the rest of the previous panel's
+ * update runs on a second stream of default priority that the call creates
+ * and destroys; it waits for the work on `stream` before it and `stream`
+ * waits for it before continuing.  The call synchronises both. */
 int coarse_setup(const kkt_op_t *fine, const coarse_params_t *cp, void *stream, coarse_t **out);
 
 /* y = I_c^h F_c^{-1} I_h^c x (device vectors of the fine size).  F_c^{-1} is
