@@ -977,12 +977,12 @@ static void gje_invert(int n, double *A, double *tmp, double *rows, double *pan,
   if (block || R > 0) {
     // Elimination of each panel (block pivoting: the diagonal block's inverse
     // and the other rows' multipliers; global pivoting: one cooperative
-    // launch) with a look-ahead: the update by
-    // panel p first brings the next panel's columns up to date, then the
-    // next panel is eliminated on s while the rest of the update runs on the
-    // side stream.  The two touch different columns, and the next panel's
-    // swaps on the other columns wait for the rest of the update.  Every
-    // entry gets the same updates as without the look-ahead, bit for bit.
+    // launch) with a look-ahead: the update by panel p first brings the next
+    // panel's columns up to date, then the next panel is eliminated on s
+    // while the rest of the update runs on the side stream.  The two touch
+    // different columns, and the next panel's swaps on the other columns wait
+    // for the rest of the update.  Every entry gets the same updates as
+    // without the look-ahead, bit for bit.
     auto diag = [&](int k, int e) {
       hipLaunchKernelGGL(gje_diag_kernel, dim3(1), dim3(kDiagThreads), 0, s, n, k, e, A, pan, piv, swp, status);
     };
