@@ -439,8 +439,8 @@ __global__ void __launch_bounds__(kGjThreads) gje_panel_kernel(int n, int k, int
 // about 1e-14 (and with LAPACK's inverse), so a panel needs no device-wide
 // exchange per column.
 //
-// Step 1, one workgroup of sixteen wavefronts (lane l on column l, wavefront v
-// on rows kDiagRows v ..): Gauss-Jordan inversion of the diagonal block D = A[K][K]
+// Step 1, one workgroup of four wavefronts (lane l on column l, wavefront v
+// on rows 16 v ..): Gauss-Jordan inversion of the diagonal block D = A[K][K]
 // (K = [k, e), w = e - k <= 64) in LDS.  Each step reads the rows'
 // multipliers into registers first, so the row updates are independent and
 // their LDS accesses pipeline.  Step j takes the largest
@@ -449,8 +449,7 @@ __global__ void __launch_bounds__(kGjThreads) gje_panel_kernel(int n, int k, int
 // two entries of piv, then eliminates column j from the other rows with the
 // in-place steps of gje_panel_kernel.  A[K][K] and Dinv (w x w, row stride
 // kPanel) receive (P D)^{-1}; a zero or non-finite pivot sets status 1.
-constexpr int kDiagThreads = 1024;                       // sixteen wavefronts
-constexpr int kDiagRows = kPanel / (kDiagThreads / 64);   // rows of the block per wavefront
+constexpr int kDiagThreads = 256;   // four wavefronts, 16 rows of the block each
 __global__ void __launch_bounds__(kDiagThreads) gje_diag_kernel(int n, int k, int e, double *__restrict__ A,
                                                                 double *__restrict__ Dinv,
                                                                 int32_t *__restrict__ piv,
@@ -512,13 +511,13 @@ __global__ void __launch_bounds__(kDiagThreads) gje_diag_kernel(int n, int k, in
     const double a = M[j][j];
     const double pr = l < w ? (l == j ? 1.0 : M[j][l]) / a : 0.0;
     const double pj = 1.0 / a;
-    double f[kDiagRows];
+    double f[16];
 #pragma unroll
-    for (int q = 0; q < kDiagRows; ++q) f[q] = M[kDiagRows * wv + q][j];
+    for (int q = 0; q < 16; ++q) f[q] = M[16 * wv + q][j];
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kDiagRows; ++q) {
-      const int r = kDiagRows * wv + q;
+    for (int q = 0; q < 16; ++q) {
+      const int r = 16 * wv + q;
       if (r < w && l < w) M[r][l] = (r == j) ? pr : ((l == j) ? -f[q] * pj : M[r][l] - f[q] * pr);
     }
     __syncthreads();
